@@ -1,0 +1,211 @@
+"""Pins of the oracle's LoD cut (Sec. 4.1 Eq. 4, Sec. 4.3, Alg. 1, Alg. 2)
+against plain-Python references and the invariants the paper states."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from scenegen import configs
+
+from _helpers import (ancestors, bfs_cut, culled64, g64, hspt_cut_reference, hspt_roles, leaves_under,
+                      random_tree)
+
+
+def _random_camera(rng, extent=10.0, w=64, h=48):
+    pos = rng.uniform(-3 * extent, 3 * extent, 3)
+    tgt = rng.uniform(-extent, extent, 3)
+    up = np.array([0.0, 0.0, 1.0]) if rng.random() < 0.5 else np.array([0.0, 1.0, 0.0])
+    if abs(np.dot((tgt - pos) / np.linalg.norm(tgt - pos), up)) > 0.99:
+        up = np.array([1.0, 0.0, 0.0])
+    return scenegen.camera_look_at(pos, tgt, up, w, h, hfov_deg=rng.uniform(30, 90))
+
+
+def test_hspt_split_matches_bfs_definition():
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        assert np.array_equal(S.role, hspt_roles(t))
+        for v in range(t.n_nodes):
+            if S.role[v] == 0:
+                assert S.spt_of[v] == -1
+            else:
+                r = v
+                while S.role[r] != 1:
+                    r = t.parent[r]
+                assert S.spt_of[v] == r
+
+
+def test_intervals_are_prefix_minima_of_ancestor_sizes():
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        g32 = g64(t).astype(np.float32)
+        assert np.array_equal(S.g, g32)
+        for v in range(t.n_nodes):
+            if S.role[v] == 0:
+                continue
+            leaf = t.left[v] < 0
+            assert S.r_min[v] == (0.0 if leaf else g32[v])
+            m = np.float32(np.inf)
+            p = v
+            while S.role[p] != 1:
+                p = t.parent[p]
+                m = min(m, g32[p])
+            assert S.r_max[v] == m
+
+
+def test_layout_is_preorder_then_sorted_segments():
+    rng = np.random.default_rng(3)
+    for _ in range(30):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        n = t.n_nodes
+        assert np.array_equal(np.sort(S.perm), np.arange(n))
+        assert np.array_equal(S.pos_of[S.perm], np.arange(n))
+        # upper prefix = left-first preorder of upper nodes
+        pre, roots, st = [], [], [t.root]
+        while st:
+            u = st.pop()
+            if S.role[u] == 0:
+                pre.append(u)
+                st += [t.right[u], t.left[u]]
+            else:
+                roots.append(u)
+        assert list(S.perm[: S.n_upper]) == pre
+        assert S.n_spt == len(roots)
+        for j, r in enumerate(roots):
+            seg = S.perm[S.spt_begin[j]: S.spt_begin[j + 1]]
+            assert seg[0] == r
+            assert set(seg.tolist()) == set(np.nonzero(S.spt_of == r)[0].tolist())
+            keys = [(-S.r_max[v], -S.r_min[v], v) for v in seg]
+            assert keys == sorted(keys)
+
+
+@pytest.mark.parametrize("cull", [False, True])
+def test_cut_matches_python_two_step_reference(cull):
+    rng = np.random.default_rng(4 + cull)
+    for _ in range(150):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 2)))
+        ref = hspt_cut_reference(t, cam, tau, cull)
+        for mode in (0, 1):
+            ids, _ = S.select(cam, tau, cull=cull, mode=mode)
+            assert sorted(ids.tolist()) == ref
+            assert np.all(np.diff(S.pos_of[ids]) > 0)  # layout order
+
+
+def test_all_upper_equals_alg1_bfs_with_own_distances():
+    """With no SPTs below the leaves (threshold -inf) the HSPT cut is the plain
+    BFS cut of Alg. 1 with the per-node size test of Eq. 3/6."""
+    rng = np.random.default_rng(5)
+    for _ in range(60):
+        t = random_tree(rng, int(rng.integers(2, 65)), log_threshold=-math.inf)
+        S = oracle.OracleScene(t)
+        assert np.all(S.role[t.left >= 0] == 0)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 2)))
+        g = g64(t)
+        k = tau / cam.fx
+        pos = cam.pos.astype(np.float64)
+        cond = lambda u: t.left[u] < 0 or g[u] <= np.linalg.norm(t.means[u].astype(np.float64) - pos) * k
+        ids, _ = S.select(cam, tau, cull=False)
+        assert sorted(ids.tolist()) == sorted(bfs_cut(t, cond))
+
+
+def _check_proper_and_covering(t, ids):
+    sel = set(int(i) for i in ids)
+    for v in sel:  # proper: no ancestor of a selected node is selected
+        assert not (set(ancestors(t, v)) & sel)
+    covered = []
+    for v in sel:
+        covered += leaves_under(t, v)
+    assert sorted(covered) == list(range(t.n_leaves))  # every root-leaf path exactly once
+
+
+def test_cut_is_proper_and_covers_every_path_once_random():
+    rng = np.random.default_rng(6)
+    for _ in range(100):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        ids, _ = S.select(cam, float(10 ** rng.uniform(-1, 2)), cull=False)
+        _check_proper_and_covering(t, ids)
+
+
+@pytest.mark.parametrize("tau", [0.5, 1.0, 8.0, 64.0])
+def test_cut_is_proper_and_covers_every_path_once_tiny(tiny_tree, tiny_oracle, tau):
+    ids, st = tiny_oracle.select(configs.tiny_camera(), tau, cull=False)
+    sel = np.zeros(tiny_tree.n_nodes, bool)
+    sel[ids] = True
+    # coverage by counting selected ancestors-or-self of every leaf
+    cnt = np.zeros(tiny_tree.n_leaves, int)
+    for leaf in range(tiny_tree.n_leaves):
+        cnt[leaf] = sel[leaf] + sum(sel[a] for a in ancestors(tiny_tree, leaf))
+    assert np.all(cnt == 1)
+    if tau >= 8:
+        assert np.any(ids >= tiny_tree.n_leaves)  # interior nodes are chosen at coarse tau
+
+
+def test_tau_limits():
+    rng = np.random.default_rng(7)
+    for _ in range(40):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        ids, _ = S.select(cam, 1e30, cull=False)
+        assert ids.tolist() == [t.root]
+        ids, _ = S.select(cam, 0.0, cull=False)
+        assert sorted(ids.tolist()) == list(range(t.n_leaves))
+
+
+def test_cull_drops_exactly_the_culled_subtrees():
+    rng = np.random.default_rng(8)
+    for _ in range(100):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(10 ** rng.uniform(-1, 2))
+        off = set(S.select(cam, tau, cull=False)[0].tolist())
+        on = set(S.select(cam, tau, cull=True)[0].tolist())
+        rho = 3.0 * np.exp(t.log_scales.astype(np.float64)).max(axis=1)
+
+        def tested_path(v):  # nodes whose frustum test gates v: upper ancestors and the SPT root
+            path = [v] + ancestors(t, v)
+            return [u for u in path if S.role[u] in (0, 1)]
+        expect = {v for v in off if not any(culled64(cam, t.means[u], rho[u]) for u in tested_path(v))}
+        assert on == expect
+
+
+def test_exact_ties_follow_eq4_inequalities():
+    """X == g selects (>= in Eq. 4's distance form), X just below g does not."""
+    # one interior node (a single SPT of 3 nodes) at distance exactly 5 from the camera
+    means = np.array([[3.0, 4.0, 0.0], [3.0, 4.0, 0.1], [3.0, 4.0, -0.1]])
+    ls = np.array([[0.0, 0.0, 0.0], [-2.0, -2.0, -2.0], [-2.0, -2.0, -2.0]])
+    q = np.tile([1.0, 0.0, 0.0, 0.0], (3, 1))
+    t = scenegen.tree_from_arrays(means, ls, q, np.zeros(3), np.zeros((3, 1, 3)), [1, -1, -1], [2, -1, -1],
+                                  [-1, 0, 0], 0, 100.0, 0)
+    S = oracle.OracleScene(t)
+    assert S.role.tolist() == [1, 2, 2]
+    cam = scenegen.Camera(np.eye(3, dtype=np.float32), np.zeros(3, np.float32), np.zeros(3, np.float32),
+                          1.0, 1.0, 0.5, 0.5, 1, 1, 0.2)
+    g = S.g[0]
+    # find tau with float32(5 * float32(tau / 1)) == g exactly
+    tau = np.float32(g / np.float32(5.0))
+    for _ in range(8):
+        if np.float32(np.float32(5.0) * tau) == g:
+            break
+        tau = np.nextafter(tau, np.float32(np.inf)) if np.float32(5.0) * tau < g else np.nextafter(tau, np.float32(0))
+    assert np.float32(np.float32(5.0) * tau) == g
+    ids, st = S.select(cam, float(tau), cull=False)
+    assert ids.tolist() == [0] and st["ties_exact"] >= 1
+    below = np.nextafter(tau, np.float32(0))
+    while np.float32(np.float32(5.0) * below) == g:
+        below = np.nextafter(below, np.float32(0))
+    ids, _ = S.select(cam, float(below), cull=False)
+    assert sorted(ids.tolist()) == [1, 2]
