@@ -1,0 +1,222 @@
+/*
+ * lodgs.h -- C ABI of the MI355X LoD-select + Gaussian-splat library
+ * (liblodgs.so).  The calls follow the paper's statement of the per-view
+ * problem ("A LoD of Gaussians", arXiv 2507.01110, Sec. 4 and Alg. 3): cut the
+ * hierarchy for a camera into a set of Gaussian indices, render that set, and
+ * differentiate the rendering.
+ *
+ * Conventions
+ *  - Every pointer named d_* is device memory on the current HIP device; all
+ *    others are host memory.  The caller owns every array it passes in; the
+ *    library owns only the opaque handles and their internal workspaces.
+ *  - Calls that take a stream are asynchronous and stream-ordered (stream may
+ *    be NULL for the default stream).  Nothing blocks except
+ *    lodgs_frame_stats and the host-only builder.
+ *  - Every call returns a status code (0 on success, one of LODGS_E_* on
+ *    failure); lodgs_last_error() returns a thread-local message for the last
+ *    failure.  No exception crosses the ABI.
+ *  - Device errors found while a kernel runs (a capacity overflow) are
+ *    recorded in the frame and reported by lodgs_frame_stats; the outputs of
+ *    the call that overflowed are then incomplete.
+ *  - Node parameters are the raw ones, FP32, indexed by layout position:
+ *    means [n][3], log_scales [n][3], quats [n][4] as (w, x, y, z), not
+ *    necessarily normalised, opacity_logits [n], sh [n][(deg+1)^2][3].
+ *  - Images are float32 [height][width][3], row-major.
+ */
+#ifndef LODGS_H_
+#define LODGS_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LODGS_OK 0
+#define LODGS_E_INVALID (-1)  /* bad argument                                     */
+#define LODGS_E_CAPACITY (-2) /* an output or workspace is too small               */
+#define LODGS_E_HIP (-3)      /* a HIP runtime call failed                         */
+#define LODGS_E_OOM (-4)      /* device or host allocation failed                  */
+#define LODGS_E_STATE (-5)    /* call out of order (backward without a forward)    */
+
+/* lod_select flags */
+#define LODGS_CULL 1u         /* frustum-cull upper nodes and SPT roots (Sec. 4.3) */
+
+typedef void* lodgs_stream; /* a hipStream_t */
+
+/* Pinhole camera.  x_cam = R x_world + t with R row-major and OpenCV axes
+ * (x right, y down, z forward); pos is the camera centre in world space (used
+ * for LoD distances and SH view directions); (cx, cy) the principal point in
+ * pixels; pixels are sampled at their centres (x + 0.5, y + 0.5); splats with
+ * camera depth <= z_near are not drawn and spheres entirely in front of the
+ * near plane are culled. */
+typedef struct lodgs_camera {
+  float R[9];
+  float t[3];
+  float pos[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float z_near;
+} lodgs_camera;
+
+/* ---------------------------------------------------------------- HSPT build
+ * Hierarchical SPT construction (Sec. 4.3 "The Hierarchical SPT
+ * Datastructure"; Sec. 4.1 for the SPT arrays).  Host only, OpenMP.
+ *
+ * Input: a binary hierarchy of n_nodes nodes given by left/right child ids (-1
+ * for leaves) and root, the nodes' FP32 log-scales [n_nodes][3], and the
+ * volume threshold as log(size) (double).  The BFS split puts node i in the
+ * cut set when it is a leaf or when ((double)ls0 + (double)ls1) + (double)ls2
+ * < log_size; cut nodes root SPTs, nodes above them form the upper hierarchy.
+ *
+ * Outputs (caller-allocated host arrays; sizes in brackets):
+ *   perm [n_nodes]          layout position -> tree node id.  Layout: upper
+ *                           nodes in left-first DFS preorder, then one segment
+ *                           per SPT in the order that DFS meets the SPT roots;
+ *                           inside a segment nodes are sorted by r_max
+ *                           descending, then r_min descending, then tree id.
+ *   r_min, r_max [n_nodes]  in layout order.  Size metric g = sqrt(s1 s2 + s1 s3
+ *                           + s2 s3) (Eq. 6's surface measure), evaluated in FP64
+ *                           and rounded once to FP32.  Upper nodes: r_min = g,
+ *                           r_max = +inf.  SPT members: r_min = g (0 for leaves),
+ *                           r_max = +inf for the SPT root, else the minimum of g
+ *                           over the node's ancestors inside its SPT.
+ *   rho [n_nodes]           3 * max_j s_j (the cull-sphere radius), layout order.
+ *   upper_parent [n_nodes]  first n_upper entries: layout position of the parent
+ *                           (-1 for the root).
+ *   spt_begin [n_nodes + 1] first n_spt + 1 entries: segment boundaries.
+ *   spt_parent [n_nodes]    first n_spt entries: layout position of the upper
+ *                           parent of each SPT root (-1 if it is the hierarchy
+ *                           root).
+ *   n_upper, n_spt          counts.
+ * Errors: LODGS_E_INVALID for a malformed tree (cycle, missing child, n_nodes >
+ * 2^31 - 2), LODGS_E_OOM if host memory runs out. */
+int lodgs_hspt_build(int64_t n_nodes, const int32_t* left, const int32_t* right, int32_t root,
+                     const float* log_scales, double log_size, int32_t* perm, float* r_min, float* r_max,
+                     float* rho, int32_t* upper_parent, int32_t* spt_begin, int32_t* spt_parent,
+                     int32_t* n_upper, int32_t* n_spt);
+
+/* ---------------------------------------------------------------- scene
+ * A scene borrows device arrays in layout order (the outputs of
+ * lodgs_hspt_build, uploaded, plus the node parameters permuted by perm).  The
+ * arrays must outlive the scene handle.  rho is indexed by layout position.
+ * sh_degree is 0..3. */
+typedef struct lodgs_scene_desc {
+  int64_t n_nodes;
+  int32_t n_upper, n_spt, sh_degree;
+  const float* d_means;
+  const float* d_log_scales;
+  const float* d_quats;
+  const float* d_opacity_logits;
+  const float* d_sh;
+  const float* d_r_min;
+  const float* d_r_max;
+  const float* d_rho;
+  const int32_t* d_upper_parent; /* [n_upper] */
+  const int32_t* d_spt_begin;    /* [n_spt + 1] */
+  const int32_t* d_spt_parent;   /* [n_spt] */
+} lodgs_scene_desc;
+
+typedef struct lodgs_scene lodgs_scene;
+
+/* Validates sizes (host-side checks only) and stores the descriptor. */
+int lodgs_scene_create(const lodgs_scene_desc* desc, lodgs_scene** out);
+void lodgs_scene_destroy(lodgs_scene* scene);
+
+/* ---------------------------------------------------------------- frame
+ * A frame owns the device workspace of one view in flight: the LoD-cut
+ * scratch, the per-splat projections, the sorted instance lists, the tile
+ * ranges and the 2D gradients.  Capacities bound the selected-node count, the
+ * (splat, tile) instance count and the image size.  A frame is used by one
+ * stream at a time; frames on different streams may overlap. */
+typedef struct lodgs_frame_caps {
+  int64_t max_selected;
+  int64_t max_instances;
+  int32_t max_width, max_height;
+} lodgs_frame_caps;
+
+typedef struct lodgs_frame lodgs_frame;
+
+int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, lodgs_frame** out);
+void lodgs_frame_destroy(lodgs_frame* frame);
+
+/* ---------------------------------------------------------------- calls
+ * lod_select (Sec. 4.3, two-step HSPT cut; Eq. 4 for the SPTs; Alg. 2).
+ * With X = d * tau / fx (the focal-normalised distance of the implementation
+ * appendix; d = |mu - pos| in FP32):
+ *   - an upper node is dropped with its subtree when culled (if LODGS_CULL),
+ *     selected when r_min (= g) <= X at its own distance, else descended;
+ *   - a reached SPT root that is not culled makes its SPT visible; the SPT is
+ *     cut at the root's X: a binary search gives the prefix with r_max > X and
+ *     every prefix node with r_min <= X is selected.
+ * Writes the selected layout positions in ascending order to d_idx[0 ..
+ * min(count, capacity)) and the full count to *d_count (device int32).  If
+ * count > capacity the frame records LODGS_E_CAPACITY (see lodgs_frame_stats).
+ * tau must be finite and >= 0. */
+int lodgs_lod_select(lodgs_frame* frame, const lodgs_camera* cam, float tau, uint32_t flags, int32_t* d_idx,
+                     int64_t capacity, int32_t* d_count, lodgs_stream stream);
+
+/* render (Sec. 3, Eq. 1 front-to-back compositing with Eq. 2 alpha over the
+ * EWA projection; the rasterizer conventions the paper reuses): projects the
+ * d_idx[0 .. *d_count) nodes (count clamped to the frame's max_selected),
+ * evaluates SH colour, sorts (tile, depth) instances over 16x16 tiles and
+ * blends front to back into d_rgb [height][width][3] with background bg (3
+ * floats, host).  alpha = min(0.99, o exp(power)); alpha < 1/255 is skipped;
+ * blending stops before the transmittance would fall below 1e-4.  The frame
+ * keeps d_idx, d_count and d_rgb for render_backward, which reads them: they
+ * must stay unchanged until then. */
+int lodgs_render(lodgs_frame* frame, const int32_t* d_idx, const int32_t* d_count, const lodgs_camera* cam,
+                 const float bg[3], float* d_rgb, lodgs_stream stream);
+
+/* Gradient destinations, one array per parameter group, same layouts as the
+ * parameters.  Any member may be NULL to skip that group. */
+typedef struct lodgs_grads {
+  float* d_means;
+  float* d_log_scales;
+  float* d_quats;
+  float* d_opacity_logits;
+  float* d_sh;
+} lodgs_grads;
+
+/* render_backward: given dL/dimage (d_dL_drgb, [height][width][3]) for the
+ * last render of this frame, computes the gradients of the raw parameters of
+ * the rendered nodes.  Blending state is recomputed per tile (front to back,
+ * using the final colour), nothing per pixel is stored by the forward.
+ *   sel (optional):   written for positions i < count: gradient of node
+ *                     d_idx[i] (zero for nodes that were not drawn);
+ *   nodes (optional): accumulated (+=) into node-indexed arrays at d_idx[i].
+ * Returns LODGS_E_STATE if the frame has not rendered. */
+int lodgs_render_backward(lodgs_frame* frame, const float* d_dL_drgb, const lodgs_grads* sel,
+                          const lodgs_grads* nodes, lodgs_stream stream);
+
+/* Counters of the last calls on this frame (blocks on the stream). */
+typedef struct lodgs_stats {
+  int32_t status;          /* LODGS_OK or LODGS_E_CAPACITY                  */
+  int32_t n_selected;      /* full count of the last lod_select             */
+  int32_t n_upper_selected;
+  int32_t n_spt_visible;
+  int64_t n_spt_candidates; /* sum over visible SPTs of the prefix length    */
+  int32_t n_rendered;      /* nodes given to the last render                */
+  int32_t n_drawn;         /* of which projected in front of z_near, on screen */
+  int64_t n_instances;     /* (splat, tile) pairs of the last render        */
+} lodgs_stats;
+
+int lodgs_frame_stats(lodgs_frame* frame, lodgs_stats* out, lodgs_stream stream);
+
+/* Copies the sorted instance list of the last render (blocks on the stream):
+ * for k < min(n_instances, capacity), d_tile[k] = tile id (row-major over the
+ * 16x16 tile grid) and d_pos[k] = position in d_idx of the splat, in blend
+ * order (tile, FP32 depth bits, selection position).  *n_out (host) receives
+ * the full instance count.  For parity tests and diagnostics. */
+int lodgs_frame_read_instances(lodgs_frame* frame, int32_t* d_tile, int32_t* d_pos, int64_t capacity,
+                               int64_t* n_out, lodgs_stream stream);
+
+/* Clears the recorded device error of the frame. */
+int lodgs_frame_clear_status(lodgs_frame* frame, lodgs_stream stream);
+
+const char* lodgs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LODGS_H_ */

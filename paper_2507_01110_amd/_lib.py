@@ -1,0 +1,92 @@
+"""ctypes declarations of liblodgs.so (include/lodgs.h).  Argument marshalling
+only: every step of the path runs in the library's kernels.  Loading fails
+loudly when the library has not been built; there is no fallback."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblodgs.so")
+
+OK, E_INVALID, E_CAPACITY, E_HIP, E_OOM, E_STATE = 0, -1, -2, -3, -4, -5
+CULL = 1
+
+c_p = ctypes.c_void_p
+i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", f32 * 9), ("t", f32 * 3), ("pos", f32 * 3), ("fx", f32), ("fy", f32), ("cx", f32),
+                ("cy", f32), ("width", i32), ("height", i32), ("z_near", f32)]
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [("n_nodes", i64), ("n_upper", i32), ("n_spt", i32), ("sh_degree", i32),
+                ("d_means", c_p), ("d_log_scales", c_p), ("d_quats", c_p), ("d_opacity_logits", c_p),
+                ("d_sh", c_p), ("d_r_min", c_p), ("d_r_max", c_p), ("d_rho", c_p), ("d_upper_parent", c_p),
+                ("d_spt_begin", c_p), ("d_spt_parent", c_p)]
+
+
+class FrameCaps(ctypes.Structure):
+    _fields_ = [("max_selected", i64), ("max_instances", i64), ("max_width", i32), ("max_height", i32)]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("d_means", c_p), ("d_log_scales", c_p), ("d_quats", c_p), ("d_opacity_logits", c_p),
+                ("d_sh", c_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", i32), ("n_selected", i32), ("n_upper_selected", i32), ("n_spt_visible", i32),
+                ("n_spt_candidates", i64), ("n_rendered", i32), ("n_drawn", i32), ("n_instances", i64)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+EXPORTS = {
+    "lodgs_hspt_build": ([i64, c_p, c_p, i32, c_p, ctypes.c_double, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p],
+                         ctypes.c_int),
+    "lodgs_scene_create": ([ctypes.POINTER(SceneDesc), ctypes.POINTER(c_p)], ctypes.c_int),
+    "lodgs_scene_destroy": ([c_p], None),
+    "lodgs_frame_create": ([c_p, ctypes.POINTER(FrameCaps), ctypes.POINTER(c_p)], ctypes.c_int),
+    "lodgs_frame_destroy": ([c_p], None),
+    "lodgs_lod_select": ([c_p, ctypes.POINTER(Camera), f32, ctypes.c_uint32, c_p, i64, c_p, c_p], ctypes.c_int),
+    "lodgs_render": ([c_p, c_p, c_p, ctypes.POINTER(Camera), c_p, c_p, c_p], ctypes.c_int),
+    "lodgs_render_backward": ([c_p, c_p, ctypes.POINTER(Grads), ctypes.POINTER(Grads), c_p], ctypes.c_int),
+    "lodgs_frame_stats": ([c_p, ctypes.POINTER(Stats), c_p], ctypes.c_int),
+    "lodgs_frame_read_instances": ([c_p, c_p, c_p, i64, ctypes.POINTER(i64), c_p], ctypes.c_int),
+    "lodgs_frame_clear_status": ([c_p, c_p], ctypes.c_int),
+    "lodgs_last_error": ([], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+class LodgsError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+def load():
+    """Loads the in-tree liblodgs.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2507_01110_amd.build` "
+                              "(or __graft_entry__.build()); the path has no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def check(code: int, where: str):
+    if code != OK:
+        msg = load().lodgs_last_error()
+        raise LodgsError(code, where, msg.decode() if msg else "")

@@ -1,0 +1,288 @@
+// C ABI: error reporting, scene and frame objects, argument checks and the
+// per-view constants.  The stage kernels live in lodgs_select.hip,
+// lodgs_render.hip and lodgs_backward.hip.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "lodgs_internal.h"
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+namespace lodgs {
+
+int set_error(int code, const char* msg) {
+  std::snprintf(g_err, sizeof g_err, "%s", msg);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  std::snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
+  return LODGS_E_HIP;
+}
+
+// Per-view constants, FP32 on the host (IEEE single, correctly rounded / and
+// sqrt), identical for every kernel of the view.
+ViewConst make_view(const lodgs_camera& c, float tau) {
+  ViewConst v;
+  std::memcpy(v.R, c.R, sizeof v.R);
+  std::memcpy(v.t, c.t, sizeof v.t);
+  std::memcpy(v.pos, c.pos, sizeof v.pos);
+  v.fx = c.fx;
+  v.fy = c.fy;
+  v.cx = c.cx;
+  v.cy = c.cy;
+  v.width = c.width;
+  v.height = c.height;
+  v.z_near = c.z_near;
+  v.k = tau / c.fx;
+  v.hl = c.cx / c.fx;
+  v.hr = ((float)c.width - c.cx) / c.fx;
+  v.ht = c.cy / c.fy;
+  v.hb = ((float)c.height - c.cy) / c.fy;
+  v.nl = std::sqrt(1.0f + v.hl * v.hl);
+  v.nr = std::sqrt(1.0f + v.hr * v.hr);
+  v.nt = std::sqrt(1.0f + v.ht * v.ht);
+  v.nb = std::sqrt(1.0f + v.hb * v.hb);
+  v.tiles_x = (c.width + kTile - 1) / kTile;
+  v.tiles_y = (c.height + kTile - 1) / kTile;
+  return v;
+}
+
+}  // namespace lodgs
+
+using lodgs::hip_fail;
+using lodgs::set_error;
+
+namespace {
+
+__global__ void k_clear_status(FrameCounters* c) { c->status = LODGS_OK; }
+
+bool camera_ok(const lodgs_camera* c) {
+  if (!c) return false;
+  if (c->width <= 0 || c->height <= 0 || c->width > 16384 || c->height > 16384) return false;
+  if (!(c->fx > 0.0f) || !(c->fy > 0.0f) || !std::isfinite(c->fx) || !std::isfinite(c->fy)) return false;
+  if (!std::isfinite(c->cx) || !std::isfinite(c->cy) || !std::isfinite(c->z_near) || !(c->z_near > 0.0f))
+    return false;
+  for (float x : c->R)
+    if (!std::isfinite(x)) return false;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(c->t[k]) || !std::isfinite(c->pos[k])) return false;
+  return true;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (count > 0 ? count : 1));
+}
+
+void free_frame(lodgs_frame* f) {
+  if (!f) return;
+  void* ptrs[] = {f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->chunk,
+                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->rect,
+                  f->ikey, f->ival, f->ikey2, f->ival2, f->ranges, f->grad2d};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete f;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lodgs_last_error(void) { return g_err; }
+
+int lodgs_scene_create(const lodgs_scene_desc* d, lodgs_scene** out) {
+  if (!d || !out) return set_error(LODGS_E_INVALID, "lodgs_scene_create: null argument");
+  *out = nullptr;
+  if (d->n_nodes <= 0 || d->n_nodes > (int64_t)INT32_MAX - 1)
+    return set_error(LODGS_E_INVALID, "lodgs_scene_create: n_nodes out of range");
+  if (d->n_upper < 0 || d->n_spt <= 0 || (int64_t)d->n_upper + d->n_spt > d->n_nodes)
+    return set_error(LODGS_E_INVALID, "lodgs_scene_create: bad n_upper / n_spt");
+  if (d->sh_degree < 0 || d->sh_degree > 3) return set_error(LODGS_E_INVALID, "lodgs_scene_create: sh_degree 0..3");
+  if (!d->d_means || !d->d_log_scales || !d->d_quats || !d->d_opacity_logits || !d->d_sh || !d->d_r_min ||
+      !d->d_r_max || !d->d_rho || (!d->d_upper_parent && d->n_upper > 0) || !d->d_spt_begin || !d->d_spt_parent)
+    return set_error(LODGS_E_INVALID, "lodgs_scene_create: null device array");
+  if ((reinterpret_cast<uintptr_t>(d->d_quats) & 15u) != 0)
+    return set_error(LODGS_E_INVALID, "lodgs_scene_create: quats must be 16-byte aligned");
+  lodgs_scene* s = new (std::nothrow) lodgs_scene;
+  if (!s) return set_error(LODGS_E_OOM, "lodgs_scene_create: out of host memory");
+  SceneDev& v = s->dev;
+  v.n_nodes = d->n_nodes;
+  v.n_upper = d->n_upper;
+  v.n_spt = d->n_spt;
+  v.sh_degree = d->sh_degree;
+  v.n_coef = 3 * (d->sh_degree + 1) * (d->sh_degree + 1);
+  v.means = d->d_means;
+  v.log_scales = d->d_log_scales;
+  v.quats = d->d_quats;
+  v.opacity_logits = d->d_opacity_logits;
+  v.sh = d->d_sh;
+  v.r_min = d->d_r_min;
+  v.r_max = d->d_r_max;
+  v.rho = d->d_rho;
+  v.upper_parent = d->d_upper_parent;
+  v.spt_begin = d->d_spt_begin;
+  v.spt_parent = d->d_spt_parent;
+  *out = s;
+  return LODGS_OK;
+}
+
+void lodgs_scene_destroy(lodgs_scene* s) { delete s; }
+
+int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, lodgs_frame** out) {
+  if (!scene || !caps || !out) return set_error(LODGS_E_INVALID, "lodgs_frame_create: null argument");
+  *out = nullptr;
+  if (caps->max_selected <= 0 || caps->max_selected > (int64_t)INT32_MAX / 16 || caps->max_instances <= 0 ||
+      caps->max_instances > (int64_t)INT32_MAX - 1 || caps->max_width <= 0 || caps->max_height <= 0 ||
+      caps->max_width > 16384 || caps->max_height > 16384)
+    return set_error(LODGS_E_INVALID, "lodgs_frame_create: capacities out of range");
+  lodgs_frame* f = new (std::nothrow) lodgs_frame();
+  if (!f) return set_error(LODGS_E_OOM, "lodgs_frame_create: out of host memory");
+  f->scene = scene;
+  f->caps = *caps;
+  const SceneDev& S = scene->dev;
+  const size_t ns = (size_t)caps->max_selected, ni = (size_t)caps->max_instances;
+  const size_t nt = (size_t)((caps->max_width + 15) / 16) * ((caps->max_height + 15) / 16);
+  hipError_t e = hipSuccess;
+#define A(ptr, cnt) if (e == hipSuccess) e = dalloc(&f->ptr, cnt)
+  A(ctr, 1);
+  A(block_sums, lodgs::kScanGrid + 1);
+  A(sort_table, (size_t)256 * lodgs::kSortGrid);
+  A(upper_sel, (size_t)S.n_upper);
+  A(spt_high, (size_t)S.n_spt);
+  A(spt_X, (size_t)S.n_spt);
+  A(spt_off, (size_t)S.n_spt);
+  A(chunk, lodgs::kScanGrid + 1);
+  A(splats, ns);
+  A(depth_key, ns);
+  A(depth_key2, ns);
+  A(order, ns);
+  A(order2, ns);
+  A(tiles, ns);
+  A(inst_off, ns);
+  A(rect, ns);
+  A(ikey, ni);
+  A(ival, ni);
+  A(ikey2, ni);
+  A(ival2, ni);
+  A(ranges, nt);
+  A(grad2d, 9 * ns);
+#undef A
+  if (e != hipSuccess) {
+    free_frame(f);
+    (void)hipGetLastError();
+    return set_error(LODGS_E_OOM, "lodgs_frame_create: device allocation failed");
+  }
+  FrameCounters c;
+  std::memset(&c, 0, sizeof c);
+  c.sort_table_n = 256 * lodgs::kSortGrid;
+  c.spt_count = S.n_spt;
+  e = hipMemcpy(f->ctr, &c, sizeof c, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_frame(f);
+    return hip_fail(e, "lodgs_frame_create");
+  }
+  *out = f;
+  return LODGS_OK;
+}
+
+void lodgs_frame_destroy(lodgs_frame* f) { free_frame(f); }
+
+int lodgs_lod_select(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_t flags, int32_t* d_idx,
+                     int64_t capacity, int32_t* d_count, lodgs_stream stream) {
+  if (!f || !d_idx || !d_count) return set_error(LODGS_E_INVALID, "lodgs_lod_select: null argument");
+  if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_lod_select: bad camera");
+  if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_lod_select: tau must be finite, >= 0");
+  if (capacity < 0 || capacity > (int64_t)INT32_MAX) return set_error(LODGS_E_INVALID, "lodgs_lod_select: capacity");
+  if (flags & ~LODGS_CULL) return set_error(LODGS_E_INVALID, "lodgs_lod_select: unknown flag");
+  const lodgs::ViewConst v = lodgs::make_view(*cam, tau);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  lodgs::launch_select(f, v, flags, d_idx, capacity, d_count, st);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_lod_select");
+}
+
+int lodgs_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, const lodgs_camera* cam,
+                 const float bg[3], float* d_rgb, lodgs_stream stream) {
+  if (!f || !d_idx || !d_count || !d_rgb) return set_error(LODGS_E_INVALID, "lodgs_render: null argument");
+  if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_render: bad camera");
+  if (cam->width > f->caps.max_width || cam->height > f->caps.max_height)
+    return set_error(LODGS_E_CAPACITY, "lodgs_render: image larger than the frame's capacity");
+  const lodgs::ViewConst v = lodgs::make_view(*cam, 0.0f);
+  float b[3] = {0.0f, 0.0f, 0.0f};
+  if (bg)
+    for (int k = 0; k < 3; ++k) b[k] = bg[k];
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  lodgs::launch_render(f, d_idx, d_count, v, b, d_rgb, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "lodgs_render");
+  f->rendered = true;
+  f->r_idx = d_idx;
+  f->r_count = d_count;
+  f->r_rgb = d_rgb;
+  std::memcpy(f->bg, b, sizeof b);
+  f->view = v;
+  return LODGS_OK;
+}
+
+int lodgs_render_backward(lodgs_frame* f, const float* d_dL_drgb, const lodgs_grads* sel, const lodgs_grads* nodes,
+                          lodgs_stream stream) {
+  if (!f || !d_dL_drgb) return set_error(LODGS_E_INVALID, "lodgs_render_backward: null argument");
+  if (!f->rendered) return set_error(LODGS_E_STATE, "lodgs_render_backward: no render on this frame");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  lodgs::launch_backward(f, d_dL_drgb, sel, nodes, st);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_render_backward");
+}
+
+int lodgs_frame_stats(lodgs_frame* f, lodgs_stats* out, lodgs_stream stream) {
+  if (!f || !out) return set_error(LODGS_E_INVALID, "lodgs_frame_stats: null argument");
+  FrameCounters c;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&c, f->ctr, sizeof c, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "lodgs_frame_stats");
+  out->status = c.status;
+  out->n_selected = c.n_selected;
+  out->n_upper_selected = c.n_upper_selected;
+  out->n_spt_visible = c.n_spt_visible;
+  out->n_spt_candidates = c.sum_high;
+  out->n_rendered = c.n_render;
+  out->n_drawn = c.n_drawn;
+  out->n_instances = c.n_instances;
+  return LODGS_OK;
+}
+
+int lodgs_frame_read_instances(lodgs_frame* f, int32_t* d_tile, int32_t* d_pos, int64_t capacity, int64_t* n_out,
+                               lodgs_stream stream) {
+  if (!f || !d_tile || !d_pos || !n_out || capacity < 0)
+    return set_error(LODGS_E_INVALID, "lodgs_frame_read_instances: bad argument");
+  if (!f->rendered) return set_error(LODGS_E_STATE, "lodgs_frame_read_instances: no render on this frame");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  FrameCounters c;
+  hipError_t e = hipMemcpyAsync(&c, f->ctr, sizeof c, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "lodgs_frame_read_instances");
+  *n_out = c.n_instances;
+  int64_t m = c.n_inst_clamped < capacity ? c.n_inst_clamped : capacity;
+  if (m > 0) {
+    e = hipMemcpyAsync(d_tile, f->sorted_ikey, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_pos, f->sorted_ival, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "lodgs_frame_read_instances");
+  }
+  return LODGS_OK;
+}
+
+int lodgs_frame_clear_status(lodgs_frame* f, lodgs_stream stream) {
+  if (!f) return set_error(LODGS_E_INVALID, "lodgs_frame_clear_status: null argument");
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, reinterpret_cast<hipStream_t>(stream), f->ctr);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_frame_clear_status");
+}
+
+}  // extern "C"

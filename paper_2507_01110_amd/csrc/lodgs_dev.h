@@ -1,0 +1,174 @@
+// Device-side definitions shared by the library's kernels (gfx950).
+//
+// FP32 arithmetic here follows fixed operation orders: every discrete
+// decision of the path (LoD test, frustum test, near-plane test, tile
+// rectangle, depth key, alpha skip/clamp, early termination) must be
+// reproducible bit for bit.  The library is compiled with -ffp-contract=off,
+// correctly rounded FP32 division and square root, and FP32 denormals kept;
+// fused multiply-adds appear only where written as __builtin_fmaf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lodgs.h"
+
+namespace lodgs {
+
+constexpr int kTile = 16;
+constexpr int kWave = 64;
+
+// Camera plus per-view constants derived on the host in FP32.
+struct ViewConst {
+  float R[9], t[3], pos[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float z_near;
+  // LoD: X = d * k, k = tau / fx
+  float k;
+  // frustum side planes x/z <= hr, -x/z <= hl, y/z <= hb, -y/z <= ht, with
+  // normalisers n* = sqrt(1 + h*^2)
+  float hl, hr, ht, hb, nl, nr, nt, nb;
+  int32_t tiles_x, tiles_y;
+};
+
+ViewConst make_view(const lodgs_camera& c, float tau);
+
+// e^x for the FP32 path: Cody-Waite reduction x = n ln2 + r (ln2 split in a
+// high part with trailing zero bits and a low part), degree-7 Taylor
+// polynomial of e^r by Horner with fused multiply-adds, scaling by 2^n.
+// Returns 0 below -87 and for NaN; clamps the argument at 88.
+__device__ __forceinline__ float fexp(float x) {
+  if (!(x >= -87.0f)) return 0.0f;
+  x = x > 88.0f ? 88.0f : x;
+  const float n = __builtin_rintf(x * 1.44269502f);
+  float r = __builtin_fmaf(-n, 0.693145752f, x);
+  r = __builtin_fmaf(-n, 1.42860677e-06f, r);
+  float p = 1.98412701e-04f;
+  p = __builtin_fmaf(p, r, 1.38888892e-03f);
+  p = __builtin_fmaf(p, r, 8.33333377e-03f);
+  p = __builtin_fmaf(p, r, 4.16666679e-02f);
+  p = __builtin_fmaf(p, r, 1.66666672e-01f);
+  p = __builtin_fmaf(p, r, 0.5f);
+  p = __builtin_fmaf(p, r, 1.0f);
+  p = __builtin_fmaf(p, r, 1.0f);
+  return __builtin_ldexpf(p, (int)n);
+}
+
+// |mu - pos| as sqrt((dx*dx + dy*dy) + dz*dz).
+__device__ __forceinline__ float view_distance(const ViewConst& v, float mx, float my, float mz) {
+  const float dx = mx - v.pos[0], dy = my - v.pos[1], dz = mz - v.pos[2];
+  float s = dx * dx;
+  s = s + dy * dy;
+  s = s + dz * dz;
+  return __builtin_sqrtf(s);
+}
+
+// x_cam row r = ((R[r0] mx + R[r1] my) + R[r2] mz) + t[r].
+__device__ __forceinline__ void to_camera(const ViewConst& v, float mx, float my, float mz, float& cx, float& cy,
+                                          float& cz) {
+  float a = v.R[0] * mx;
+  a = a + v.R[1] * my;
+  a = a + v.R[2] * mz;
+  cx = a + v.t[0];
+  float b = v.R[3] * mx;
+  b = b + v.R[4] * my;
+  b = b + v.R[5] * mz;
+  cy = b + v.t[1];
+  float c = v.R[6] * mx;
+  c = c + v.R[7] * my;
+  c = c + v.R[8] * mz;
+  cz = c + v.t[2];
+}
+
+// Sphere (mu, rho) entirely outside the near plane or one of the side planes.
+__device__ __forceinline__ bool sphere_culled(const ViewConst& v, float mx, float my, float mz, float rho) {
+  float cx, cy, cz;
+  to_camera(v, mx, my, mz, cx, cy, cz);
+  if (cz + rho < v.z_near) return true;
+  if (cx - v.hr * cz > rho * v.nr) return true;
+  if (-cx - v.hl * cz > rho * v.nl) return true;
+  if (cy - v.hb * cz > rho * v.nb) return true;
+  if (-cy - v.ht * cz > rho * v.nt) return true;
+  return false;
+}
+
+// Per-splat record read by the blend kernels (48 bytes, 16-byte aligned):
+// mean2D, power coefficients (na, nb, nc) = (-a/2, -b, -c/2) of the conic
+// (a, b, c), opacity, colour, and the half extents of the box outside which
+// alpha < 1/255 for certain (used only to skip work whose result is known).
+struct alignas(16) Splat {
+  float mx, my, na, nb;
+  float nc, o, r, g;
+  float b, ex, ey, pad;
+};
+
+// Real SH basis constants, l <= 3 (3DGS sign convention).
+constexpr float kSH0 = 0.28209479177387814f;
+constexpr float kSH1 = 0.4886025119029199f;
+constexpr float kSH2_0 = 1.0925484305920792f, kSH2_1 = -1.0925484305920792f, kSH2_2 = 0.31539156525252005f,
+                kSH2_3 = -1.0925484305920792f, kSH2_4 = 0.5462742152960396f;
+constexpr float kSH3_0 = -0.5900435899266435f, kSH3_1 = 2.890611442640554f, kSH3_2 = -0.4570457994644658f,
+                kSH3_3 = 0.3731763325901154f, kSH3_4 = -0.4570457994644658f, kSH3_5 = 1.445305721320277f,
+                kSH3_6 = -0.5900435899266435f;
+
+// Fills Y[0 .. (deg+1)^2) for the unit direction (x, y, z).
+__device__ __forceinline__ void sh_basis(int deg, float x, float y, float z, float* Y) {
+  Y[0] = kSH0;
+  if (deg < 1) return;
+  Y[1] = -kSH1 * y;
+  Y[2] = kSH1 * z;
+  Y[3] = -kSH1 * x;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = kSH2_0 * x * y;
+  Y[5] = kSH2_1 * y * z;
+  Y[6] = kSH2_2 * (2.0f * zz - xx - yy);
+  Y[7] = kSH2_3 * x * z;
+  Y[8] = kSH2_4 * (xx - yy);
+  if (deg < 3) return;
+  Y[9] = kSH3_0 * y * (3.0f * xx - yy);
+  Y[10] = kSH3_1 * x * y * z;
+  Y[11] = kSH3_2 * y * (4.0f * zz - xx - yy);
+  Y[12] = kSH3_3 * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+  Y[13] = kSH3_4 * x * (4.0f * zz - xx - yy);
+  Y[14] = kSH3_5 * z * (xx - yy);
+  Y[15] = kSH3_6 * x * (xx - 3.0f * yy);
+}
+
+// Gradient of the basis polynomials with respect to (x, y, z): dY[k][3].
+__device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z, float (*dY)[3]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) dY[k][0] = dY[k][1] = dY[k][2] = 0.0f;
+  if (deg < 1) return;
+  dY[1][1] = -kSH1;
+  dY[2][2] = kSH1;
+  dY[3][0] = -kSH1;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  dY[4][0] = kSH2_0 * y; dY[4][1] = kSH2_0 * x;
+  dY[5][1] = kSH2_1 * z; dY[5][2] = kSH2_1 * y;
+  dY[6][0] = -2.0f * kSH2_2 * x; dY[6][1] = -2.0f * kSH2_2 * y; dY[6][2] = 4.0f * kSH2_2 * z;
+  dY[7][0] = kSH2_3 * z; dY[7][2] = kSH2_3 * x;
+  dY[8][0] = 2.0f * kSH2_4 * x; dY[8][1] = -2.0f * kSH2_4 * y;
+  if (deg < 3) return;
+  dY[9][0] = 6.0f * kSH3_0 * x * y; dY[9][1] = kSH3_0 * (3.0f * xx - 3.0f * yy);
+  dY[10][0] = kSH3_1 * y * z; dY[10][1] = kSH3_1 * x * z; dY[10][2] = kSH3_1 * x * y;
+  dY[11][0] = -2.0f * kSH3_2 * x * y; dY[11][1] = kSH3_2 * (4.0f * zz - xx - 3.0f * yy);
+  dY[11][2] = 8.0f * kSH3_2 * y * z;
+  dY[12][0] = -6.0f * kSH3_3 * x * z; dY[12][1] = -6.0f * kSH3_3 * y * z;
+  dY[12][2] = kSH3_3 * (6.0f * zz - 3.0f * xx - 3.0f * yy);
+  dY[13][0] = kSH3_4 * (4.0f * zz - 3.0f * xx - yy); dY[13][1] = -2.0f * kSH3_4 * x * y;
+  dY[13][2] = 8.0f * kSH3_4 * x * z;
+  dY[14][0] = 2.0f * kSH3_5 * x * z; dY[14][1] = -2.0f * kSH3_5 * y * z; dY[14][2] = kSH3_5 * (xx - yy);
+  dY[15][0] = kSH3_6 * (3.0f * xx - 3.0f * yy); dY[15][1] = -6.0f * kSH3_6 * x * y;
+}
+
+// Grid-stride bounds for kernels whose element count lives in device memory.
+__device__ __forceinline__ int64_t clamp_count(const int32_t* d_n, int64_t cap) {
+  int64_t n = *d_n;
+  if (n < 0) n = 0;
+  return n < cap ? n : cap;
+}
+
+}  // namespace lodgs

@@ -1,0 +1,100 @@
+// Host-side state of scenes and frames, and the per-stage launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lodgs.h"
+#include "lodgs_dev.h"
+#include "lodgs_error.h"
+#include "lodgs_prims.h"
+
+// Device pointers of a scene, passed to kernels by value.
+struct SceneDev {
+  int64_t n_nodes;
+  int32_t n_upper, n_spt, sh_degree, n_coef;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* sh;
+  const float* r_min;
+  const float* r_max;
+  const float* rho;
+  const int32_t* upper_parent;
+  const int32_t* spt_begin;
+  const int32_t* spt_parent;
+};
+
+struct lodgs_scene {
+  SceneDev dev;
+};
+
+// Device counters of a frame (one struct in device memory).
+struct FrameCounters {
+  int32_t status;
+  int32_t n_selected;
+  int32_t n_upper_selected;
+  int32_t n_spt_visible;
+  int32_t sum_high;
+  int32_t n_render;      // min(count, max_selected) of the last render
+  int32_t n_drawn;
+  int32_t n_instances;   // full count
+  int32_t n_inst_clamped;
+  int32_t sort_table_n;  // constant 256 * kSortGrid
+  int32_t upper_plus_high;
+  int32_t spt_count;     // constant n_spt
+  int32_t pad[4];
+};
+
+struct lodgs_frame {
+  const lodgs_scene* scene;
+  lodgs_frame_caps caps;
+  // device workspace
+  FrameCounters* ctr;
+  uint32_t* block_sums;   // kScanGrid + 1
+  uint32_t* sort_table;   // 256 * kSortGrid
+  // select
+  uint8_t* upper_sel;     // [n_upper]
+  int32_t* spt_high;      // [n_spt]
+  float* spt_X;           // [n_spt]
+  uint32_t* spt_off;      // [n_spt]
+  uint32_t* chunk;        // [kScanGrid + 1]
+  // render
+  lodgs::Splat* splats;   // [max_selected]
+  uint32_t* depth_key;    // [max_selected]
+  uint32_t* depth_key2;
+  uint32_t* order;        // [max_selected]
+  uint32_t* order2;
+  uint32_t* tiles;        // [max_selected]
+  uint32_t* inst_off;     // [max_selected]
+  ushort4* rect;          // [max_selected]
+  uint32_t* ikey;         // [max_instances]
+  uint32_t* ival;
+  uint32_t* ikey2;
+  uint32_t* ival2;
+  uint2* ranges;          // [max tiles]
+  float* grad2d;          // [max_selected][9]
+  // state of the last render
+  bool rendered;
+  const int32_t* r_idx;
+  const int32_t* r_count;
+  const float* r_rgb;
+  float bg[3];
+  lodgs::ViewConst view;
+  const uint32_t* sorted_ival;  // the buffer holding the final instance order
+  const uint32_t* sorted_ikey;
+};
+
+namespace lodgs {
+
+int hip_fail(hipError_t e, const char* what);
+
+// Stage launchers (all stream-ordered, no host synchronisation).
+void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
+                   int32_t* d_count, hipStream_t st);
+void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, const ViewConst& v,
+                   const float bg[3], float* d_rgb, hipStream_t st);
+void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
+                     hipStream_t st);
+
+}  // namespace lodgs

@@ -1,0 +1,109 @@
+// Scan and radix-sort kernels (see lodgs_prims.h).
+#include "lodgs_prims.h"
+
+namespace lodgs {
+
+__global__ void __launch_bounds__(kScanGrid) k_scan_sums(uint32_t* block_sums, int32_t* d_total) {
+  __shared__ uint32_t wt[kScanGrid / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t v = block_sums[threadIdx.x];
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wt[wave] = x;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kScanGrid / 64; ++w) {
+    base += w < wave ? wt[w] : 0u;
+    tot += wt[w];
+  }
+  block_sums[threadIdx.x] = base + x - v;
+  if (threadIdx.x == 0) {
+    block_sums[kScanGrid] = tot;
+    if (d_total) *d_total = (int32_t)tot;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* keys, const int32_t* d_n, int64_t cap,
+                                                       int shift, uint32_t* table) {
+  __shared__ uint32_t h[256];
+  int64_t n = *d_n;
+  n = n < 0 ? 0 : (n > cap ? cap : n);
+  const Segment s = block_segment(n, kSortGrid);
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t i = s.begin + threadIdx.x; i < s.end; i += kBlock) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  __syncthreads();
+  table[(int64_t)threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, const uint32_t* vin,
+                                                          uint32_t* kout, uint32_t* vout, const int32_t* d_n,
+                                                          int64_t cap, int shift, const uint32_t* table) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kBlock / 64][256];
+  int64_t n = *d_n;
+  n = n < 0 ? 0 : (n > cap ? cap : n);
+  const Segment s = block_segment(n, kSortGrid);
+  if (s.begin >= s.end) return;  // uniform across the block
+  const int t = threadIdx.x, wave = t >> 6;
+  base[t] = table[(int64_t)t * kSortGrid + blockIdx.x];
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) wcnt[w][t] = 0;
+  __syncthreads();
+  const uint64_t lt = lanemask_lt();
+  for (int64_t r0 = s.begin; r0 < s.end; r0 += kBlock) {
+    const int64_t i = r0 + t;
+    const bool valid = i < s.end;
+    const uint32_t key = valid ? kin[i] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bm = __ballot(bit);
+      m &= bit ? bm : ~bm;
+    }
+    const uint32_t rank = (uint32_t)__popcll(m & lt);
+    if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = vin[i];
+    }
+    __syncthreads();
+    uint32_t sum = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      sum += wcnt[w][t];
+      wcnt[w][t] = 0;
+    }
+    base[t] += sum;
+    __syncthreads();
+  }
+}
+
+bool sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* k2, uint32_t* v2, const int32_t* d_n, int64_t cap,
+                int bits, const SortScratch& ws, hipStream_t st) {
+  uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
+  bool swapped = false;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(kSortGrid), dim3(kBlock), 0, st, ka, d_n, cap, shift, ws.table);
+    scan_exclusive(LoadArray{ws.table}, ws.d_table_n, (int64_t)256 * kSortGrid, ws.block_sums, ws.table,
+                   (int32_t*)nullptr, st);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(kSortGrid), dim3(kBlock), 0, st, ka, va, kb, vb, d_n, cap, shift,
+                       ws.table);
+    uint32_t* tk = ka; ka = kb; kb = tk;
+    uint32_t* tv = va; va = vb; vb = tv;
+    swapped = !swapped;
+  }
+  return swapped;
+}
+
+}  // namespace lodgs

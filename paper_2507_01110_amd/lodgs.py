@@ -1,0 +1,191 @@
+"""Python front end of liblodgs: scene upload, frames and the three calls of
+the path (lod_select, render, render_backward).  PyTorch provides device
+memory and streams only."""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def camera_struct(cam) -> _lib.Camera:
+    c = _lib.Camera()
+    c.R[:] = [float(v) for v in np.asarray(cam.R, np.float32).reshape(9)]
+    c.t[:] = [float(v) for v in np.asarray(cam.t, np.float32).reshape(3)]
+    c.pos[:] = [float(v) for v in np.asarray(cam.pos, np.float32).reshape(3)]
+    c.fx, c.fy, c.cx, c.cy = cam.fx, cam.fy, cam.cx, cam.cy
+    c.width, c.height, c.z_near = cam.width, cam.height, cam.z_near
+    return c
+
+
+class HSPT:
+    """Host-side HSPT layout of a hierarchy (lodgs_hspt_build)."""
+
+    def __init__(self, n_nodes, left, right, root, log_scales, log_size):
+        L = _lib.load()
+        n = int(n_nodes)
+        self.n_nodes = n
+        self.perm = np.empty(n, np.int32)
+        self.r_min = np.empty(n, np.float32)
+        self.r_max = np.empty(n, np.float32)
+        self.rho = np.empty(n, np.float32)
+        self.upper_parent = np.empty(n, np.int32)
+        self.spt_begin = np.empty(n + 1, np.int32)
+        self.spt_parent = np.empty(n, np.int32)
+        nu, ns = ctypes.c_int32(0), ctypes.c_int32(0)
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        left = np.ascontiguousarray(left, np.int32)
+        right = np.ascontiguousarray(right, np.int32)
+        ls = np.ascontiguousarray(log_scales, np.float32)
+        check(L.lodgs_hspt_build(n, p(left), p(right), int(root), p(ls), float(log_size), p(self.perm),
+                                 p(self.r_min), p(self.r_max), p(self.rho), p(self.upper_parent), p(self.spt_begin),
+                                 p(self.spt_parent), ctypes.byref(nu), ctypes.byref(ns)), "lodgs_hspt_build")
+        self.n_upper, self.n_spt = nu.value, ns.value
+        self.upper_parent = self.upper_parent[: self.n_upper]
+        self.spt_begin = self.spt_begin[: self.n_spt + 1]
+        self.spt_parent = self.spt_parent[: self.n_spt]
+
+
+class Scene:
+    """A hierarchy resident on the device in HSPT layout order.
+
+    params: dict of torch tensors (layout order) means [n,3], log_scales [n,3],
+    quats [n,4], opacity_logits [n], sh [n,K,3]; `perm` maps layout position to
+    the input (tree) node id.
+    """
+
+    def __init__(self, tree, device="cuda", hspt: HSPT | None = None):
+        self.device = torch.device(device)
+        self.hspt = hspt or HSPT(tree.n_nodes, tree.left, tree.right, tree.root, tree.log_scales,
+                                 tree.log_volume_threshold)
+        h = self.hspt
+        self.n_nodes, self.n_upper, self.n_spt = h.n_nodes, h.n_upper, h.n_spt
+        self.sh_degree = int(tree.sh_degree)
+        self.perm = h.perm
+        perm_d = torch.from_numpy(h.perm.astype(np.int64)).to(self.device)
+
+        def up(a):
+            t = torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
+            return t.index_select(0, perm_d).contiguous()
+
+        self.params = {
+            "means": up(tree.means), "log_scales": up(tree.log_scales), "quats": up(tree.quats),
+            "opacity_logits": up(tree.opacity_logits), "sh": up(tree.sh.reshape(tree.n_nodes, -1, 3)),
+        }
+        del perm_d
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
+        self.lod = {"r_min": dev(h.r_min), "r_max": dev(h.r_max), "rho": dev(h.rho),
+                    "upper_parent": dev(h.upper_parent if h.n_upper else np.zeros(1, np.int32)),
+                    "spt_begin": dev(h.spt_begin), "spt_parent": dev(h.spt_parent)}
+        self._create()
+
+    def _create(self):
+        P, Lo = self.params, self.lod
+        d = _lib.SceneDesc(self.n_nodes, self.n_upper, self.n_spt, self.sh_degree,
+                           _ptr(P["means"]), _ptr(P["log_scales"]), _ptr(P["quats"]), _ptr(P["opacity_logits"]),
+                           _ptr(P["sh"]), _ptr(Lo["r_min"]), _ptr(Lo["r_max"]), _ptr(Lo["rho"]),
+                           _ptr(Lo["upper_parent"]), _ptr(Lo["spt_begin"]), _ptr(Lo["spt_parent"]))
+        h = ctypes.c_void_p()
+        check(_lib.load().lodgs_scene_create(ctypes.byref(d), ctypes.byref(h)), "lodgs_scene_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.lodgs_scene_destroy(h)
+            self._h = None
+
+    def param_bytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in self.params.values())
+
+
+class Frame:
+    """Device workspace of one view in flight (lodgs_frame)."""
+
+    def __init__(self, scene: Scene, max_selected: int, max_instances: int, max_width: int, max_height: int):
+        self.scene = scene
+        caps = _lib.FrameCaps(int(max_selected), int(max_instances), int(max_width), int(max_height))
+        self.caps = caps
+        h = ctypes.c_void_p()
+        check(_lib.load().lodgs_frame_create(scene._h, ctypes.byref(caps), ctypes.byref(h)), "lodgs_frame_create")
+        self._h = h
+        dev = scene.device
+        self.idx = torch.zeros(int(max_selected), dtype=torch.int32, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.lodgs_frame_destroy(h)
+            self._h = None
+
+    def lod_select(self, cam, tau: float, cull: bool = True, stream=None):
+        """Runs the cut into self.idx / self.count (device); returns them."""
+        c = camera_struct(cam)
+        check(_lib.load().lodgs_lod_select(self._h, ctypes.byref(c), float(tau), _lib.CULL if cull else 0,
+                                           _ptr(self.idx), self.idx.numel(), _ptr(self.count), _stream(stream)),
+              "lodgs_lod_select")
+        return self.idx, self.count
+
+    def render(self, cam, idx=None, count=None, bg=(0.0, 0.0, 0.0), out=None, stream=None):
+        idx = self.idx if idx is None else idx
+        count = self.count if count is None else count
+        if out is None:
+            out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=self.scene.device)
+        c = camera_struct(cam)
+        b = (ctypes.c_float * 3)(*[float(x) for x in bg])
+        check(_lib.load().lodgs_render(self._h, _ptr(idx), _ptr(count), ctypes.byref(c),
+                                       ctypes.cast(b, ctypes.c_void_p), _ptr(out), _stream(stream)), "lodgs_render")
+        self._last = (idx, count, out)
+        return out
+
+    def backward(self, dL_drgb, sel: dict | None = None, nodes: dict | None = None, stream=None):
+        g = lambda d: _lib.Grads(*[_ptr(d.get(k)) if d else None for k in
+                                   ("means", "log_scales", "quats", "opacity_logits", "sh")])
+        gs, gn = g(sel), g(nodes)
+        check(_lib.load().lodgs_render_backward(self._h, _ptr(dL_drgb), ctypes.byref(gs) if sel else None,
+                                                ctypes.byref(gn) if nodes else None, _stream(stream)),
+              "lodgs_render_backward")
+
+    def stats(self, stream=None) -> dict:
+        s = _lib.Stats()
+        check(_lib.load().lodgs_frame_stats(self._h, ctypes.byref(s), _stream(stream)), "lodgs_frame_stats")
+        return s.as_dict()
+
+    def clear_status(self, stream=None):
+        check(_lib.load().lodgs_frame_clear_status(self._h, _stream(stream)), "lodgs_frame_clear_status")
+
+    def instances(self, stream=None):
+        n_max = int(self.caps.max_instances)
+        tiles = torch.empty(n_max, dtype=torch.int32, device=self.scene.device)
+        pos = torch.empty(n_max, dtype=torch.int32, device=self.scene.device)
+        n = ctypes.c_int64(0)
+        check(_lib.load().lodgs_frame_read_instances(self._h, _ptr(tiles), _ptr(pos), n_max, ctypes.byref(n),
+                                                     _stream(stream)), "lodgs_frame_read_instances")
+        m = min(n.value, n_max)
+        return tiles[:m], pos[:m]
+
+
+def grads_like(scene: Scene, n: int | None = None, zero: bool = True) -> dict:
+    """Gradient arrays shaped like the scene parameters ([n, ...], default all nodes)."""
+    out = {}
+    for k, v in scene.params.items():
+        shape = (v.shape[0] if n is None else n,) + tuple(v.shape[1:])
+        out[k] = (torch.zeros if zero else torch.empty)(shape, dtype=v.dtype, device=v.device)
+    return out

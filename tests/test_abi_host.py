@@ -1,0 +1,85 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and its host HSPT builder reproduces the oracle's layout bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from scenegen import configs
+
+from _helpers import random_tree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2507_01110_amd import _lib
+    return _lib
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    lib = L.load()
+    hdr = open(os.path.join(ROOT, "include", "lodgs.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"\b(lodgs_\w+)\s*\(", hdr))
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(L.EXPORTS), declared ^ set(L.EXPORTS)
+
+
+def _check_layout(tree):
+    from paper_2507_01110_amd.lodgs import HSPT
+    O = oracle.OracleScene(tree)
+    H = HSPT(tree.n_nodes, tree.left, tree.right, tree.root, tree.log_scales, tree.log_volume_threshold)
+    assert (H.n_upper, H.n_spt) == (O.n_upper, O.n_spt)
+    assert np.array_equal(H.perm, O.perm)
+    assert np.array_equal(H.spt_begin, O.spt_begin)
+    upper = O.perm[: O.n_upper]
+    assert np.array_equal(H.r_min[: O.n_upper], O.g[upper])
+    assert np.all(np.isinf(H.r_max[: O.n_upper]))
+    spt = O.perm[O.n_upper:]
+    assert np.array_equal(H.r_min[O.n_upper:], O.r_min[spt])
+    assert np.array_equal(H.r_max[O.n_upper:], O.r_max[spt])
+    assert np.array_equal(H.rho, O.rho[O.perm])
+    par = tree.parent
+    exp_up = np.array([O.pos_of[par[u]] if par[u] >= 0 else -1 for u in upper], np.int32)
+    assert np.array_equal(H.upper_parent, exp_up)
+    roots = O.perm[O.spt_begin[:-1]]
+    exp_sp = np.array([O.pos_of[par[r]] if par[r] >= 0 else -1 for r in roots], np.int32)
+    assert np.array_equal(H.spt_parent, exp_sp)
+
+
+def test_hspt_builder_matches_oracle_layout_random_trees():
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        _check_layout(random_tree(rng, int(rng.integers(1, 65))))
+
+
+def test_hspt_builder_matches_oracle_layout_tiny(tiny_tree):
+    _check_layout(tiny_tree)
+
+
+@pytest.mark.slow
+def test_hspt_builder_matches_oracle_layout_medium_subset():
+    _check_layout(scenegen.build_tree(configs.medium_spec(n=200_000, seed=3)))
+
+
+def test_hspt_builder_rejects_malformed_trees():
+    from paper_2507_01110_amd.lodgs import HSPT
+    from paper_2507_01110_amd._lib import LodgsError
+    ls = np.zeros((3, 3), np.float32)
+    with pytest.raises(LodgsError) as e:  # node with a single child
+        HSPT(3, np.array([1, -1, -1]), np.array([-1, -1, -1]), 0, ls, 0.0)
+    assert e.value.code == -1
+    with pytest.raises(LodgsError):  # child out of range
+        HSPT(3, np.array([1, -1, -1]), np.array([7, -1, -1]), 0, ls, 0.0)
+    with pytest.raises(LodgsError):  # node 2 unreachable from the root
+        HSPT(3, np.array([-1, -1, -1]), np.array([-1, -1, -1]), 0, ls, 0.0)
+    with pytest.raises(LodgsError):  # cycle: 0 -> (1, 2), 1 -> (0, 2) is rejected (two parents)
+        HSPT(3, np.array([1, 0, -1]), np.array([2, 2, -1]), 0, ls, 0.0)

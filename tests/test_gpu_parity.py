@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path through the C ABI against the oracle.
+
+Bars: selected index set and instance (key) order bit-exact; pixels within
+1e-4 max-abs; gradients within 1e-3 relative L2 per parameter group.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from scenegen import configs
+
+from _helpers import random_tree
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = {"means": slice(0, 3), "log_scales": slice(3, 6), "quats": slice(6, 10), "opacity_logits": slice(10, 11),
+          "sh": slice(11, None)}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _scene(tree):
+    from paper_2507_01110_amd.lodgs import Scene
+    return Scene(tree)
+
+
+def _frame(scene, cam, max_sel=None, max_inst=None):
+    from paper_2507_01110_amd.lodgs import Frame
+    n = scene.n_nodes
+    return Frame(scene, max_sel or n, max_inst or max(1 << 16, 64 * n), cam.width, cam.height)
+
+
+def _gpu_select(frame, cam, tau, cull=True):
+    idx, cnt = frame.lod_select(cam, tau, cull=cull)
+    st = frame.stats()
+    n = int(cnt.item())
+    assert st["status"] == 0 and st["n_selected"] == n
+    return idx[:n].cpu().numpy(), st
+
+
+def _check_select(O, frame, cam, tau, cull):
+    ids, ost = O.select(cam, tau, cull=cull)
+    got, st = _gpu_select(frame, cam, tau, cull)
+    expect = O.pos_of[ids]
+    assert np.array_equal(got, expect), (len(got), len(expect))
+    assert st["n_spt_visible"] == ost["spt_visible"]
+    return ids
+
+
+def test_select_tiny_bitexact(torch_cuda):
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    assert np.array_equal(S.perm, O.perm)
+    for cull in (True, False):
+        for tau in (0.25, 1.0, 4.0, 16.0, 64.0):
+            for cam in (configs.tiny_camera(), scenegen.camera_look_at((25, -8, 6), (3, 2, 0), (0, 0, 1), 320, 200)):
+                _say("select tiny", cull, tau, cam.width)
+                _check_select(O, _frame(S, cam), cam, tau, cull)
+
+
+def test_select_random_trees_bitexact(torch_cuda):
+    rng = np.random.default_rng(21)
+    for it in range(30):
+        tree = random_tree(rng, int(rng.integers(1, 65)))
+        O = oracle.OracleScene(tree)
+        S = _scene(tree)
+        pos = rng.uniform(-30, 30, 3)
+        cam = scenegen.camera_look_at(pos, rng.uniform(-10, 10, 3), (0, 0, 1) if abs(pos[2]) < 25 else (0, 1, 0),
+                                      64, 48)
+        _say("select random tree", it, tree.n_nodes)
+        for tau in (0.1, 1.0, 10.0, 100.0):
+            _check_select(O, _frame(S, cam), cam, tau, cull=bool(it % 2))
+
+
+def test_select_capacity_overflow_is_reported(torch_cuda):
+    tree = scenegen.build_tree(configs.tiny_spec())
+    S = _scene(tree)
+    cam = configs.tiny_camera()
+    from paper_2507_01110_amd.lodgs import Frame
+    f = Frame(S, 100, 1 << 16, cam.width, cam.height)
+    idx, cnt = f.lod_select(cam, 1.0)
+    st = f.stats()
+    assert st["status"] == -2 and int(cnt.item()) > 100
+    f.clear_status()
+    assert f.stats()["status"] == 0
+
+
+def _render_pair(tree, O, S, cam, tau, bg=(0.0, 0.0, 0.0)):
+    import torch
+    frame = _frame(S, cam)
+    ids = _check_select(O, frame, cam, tau, True)
+    img = frame.render(cam, bg=bg)
+    F = oracle.OracleFrame(tree, ids, cam, bg=bg)
+    return frame, img, F, ids
+
+
+def _check_image(img, F, tol=1e-4):
+    got = img.cpu().numpy().astype(np.float64)
+    err = np.abs(got - F.image).max()
+    assert err <= tol, err
+    return err
+
+
+def _check_instances(frame, F):
+    t, p = frame.instances()
+    ot, op = F.instances()
+    assert np.array_equal(t.cpu().numpy(), ot)
+    assert np.array_equal(p.cpu().numpy(), op)
+
+
+def test_render_tiny_pixels_and_key_order(torch_cuda):
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    for cam, tau in ((configs.tiny_camera(), 1.0), (configs.tiny_camera(200, 130), 4.0),
+                     (scenegen.camera_look_at((14, -9, 4), (0, 0, 0), (0, 0, 1), 333, 171), 1.0)):
+        _say("render tiny", cam.width, cam.height, tau)
+        frame, img, F, ids = _render_pair(tree, O, S, cam, tau, bg=(0.1, 0.2, 0.3))
+        st = frame.stats()
+        info = F.info()
+        assert st["n_drawn"] == info["n_visible"] and st["n_instances"] == info["n_inst"]
+        _check_instances(frame, F)
+        err = _check_image(img, F)
+        _say("  max abs err", err, "decisions within 1 ulp:", info["skip_1ulp"], info["stop_1ulp"])
+
+
+def test_render_is_deterministic(torch_cuda):
+    import torch
+    tree = scenegen.build_tree(configs.tiny_spec())
+    S = _scene(tree)
+    cam = configs.tiny_camera()
+    f = _frame(S, cam)
+    f.lod_select(cam, 1.0)
+    a = f.render(cam).clone()
+    b = f.render(cam).clone()
+    assert torch.equal(a, b)
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _backward_pair(tree, O, S, cam, tau, seed):
+    import torch
+    frame, img, F, ids = _render_pair(tree, O, S, cam, tau)
+    target = scenegen.target_image(cam.height, cam.width, seed)
+    _, dL = oracle.l1_loss_grad(F.image, target)
+    g2_o, g_o = F.backward(dL)
+    from paper_2507_01110_amd.lodgs import grads_like
+    n = len(ids)
+    sel = grads_like(S, n, zero=False)
+    frame.backward(torch.from_numpy(dL.astype(np.float32)).cuda(), sel=sel)
+    got = np.concatenate([sel[k].reshape(n, -1).cpu().numpy().astype(np.float64)
+                          for k in ("means", "log_scales", "quats", "opacity_logits", "sh")], axis=1)
+    for name, sl in GROUPS.items():
+        e = _rel_l2(got[:, sl], g_o[:, sl])
+        _say("  grad", name, "rel L2", e)
+        assert e <= 1e-3, (name, e)
+    return frame, sel, got, g_o
+
+
+def test_backward_tiny_matches_oracle(torch_cuda):
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    for cam, tau in ((configs.tiny_camera(), 1.0), (configs.tiny_camera(160, 96), 3.0)):
+        _say("backward tiny", cam.width, cam.height, tau)
+        _backward_pair(tree, O, S, cam, tau, 200)
+
+
+def test_backward_accumulates_into_node_arrays(torch_cuda):
+    import torch
+    tree = scenegen.build_tree(configs.tiny_spec(n=4096, seed=3))
+    S = _scene(tree)
+    cam = configs.tiny_camera(128, 128)
+    from paper_2507_01110_amd.lodgs import grads_like
+    f = _frame(S, cam)
+    idx, cnt = f.lod_select(cam, 2.0)
+    img = f.render(cam)
+    dL = torch.randn_like(img)
+    n = int(cnt.item())
+    sel = grads_like(S, n, zero=False)
+    nodes = grads_like(S)
+    for k in nodes:
+        nodes[k].fill_(0.5)
+    f.backward(dL, sel=sel, nodes=nodes)
+    f.backward(dL, nodes=nodes)
+    ii = idx[:n].long()
+    for k in nodes:
+        # two backward passes: float atomics may sum in a different order each time
+        expect = torch.full_like(nodes[k], 0.5)
+        expect[ii] += 2 * sel[k]
+        scale = float(sel[k].abs().max())
+        assert scale > 0, k
+        assert torch.allclose(nodes[k], expect, rtol=1e-4, atol=1e-5 * scale), k
+        untouched = torch.ones(nodes[k].shape[0], dtype=torch.bool, device=ii.device)
+        untouched[ii] = False
+        assert torch.all(nodes[k][untouched] == 0.5), k
+
+
+def test_backward_without_render_is_a_state_error(torch_cuda):
+    import torch
+    from paper_2507_01110_amd._lib import LodgsError
+    tree = scenegen.build_tree(configs.tiny_spec(n=256))
+    S = _scene(tree)
+    cam = configs.tiny_camera(32, 32)
+    f = _frame(S, cam)
+    with pytest.raises(LodgsError) as e:
+        f.backward(torch.zeros(32, 32, 3, device="cuda"))
+    assert e.value.code == -5
+
+
+@pytest.fixture(scope="module")
+def medium(torch_cuda):
+    tree = scenegen.build_tree(configs.medium_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    return tree, O, S
+
+
+def test_medium_view_select_render_backward(medium):
+    tree, O, S = medium
+    cam = configs.medium_camera()
+    _say("medium view", cam.pos)
+    frame, sel, got, g_o = _backward_pair(tree, O, S, cam, 1.0, 201)
+    F = oracle.OracleFrame(tree, O.select(cam, 1.0)[0], cam)
+    _check_instances(frame, F)
+    img = frame.render(cam)
+    err = _check_image(img, F)
+    _say("  medium max abs err", err, frame.stats())
