@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-view LoD-select + splat forward/backward path.
+
+Workload (default "city"): 50M leaf Gaussians over a 4 x 4 km extent (60% on
+the ground plane, 40% in 20,000 boxes of height U(5,150) m), about 100M
+hierarchy nodes with SH degree 3, resident in HBM; views along the 256-pose
+aerial-to-street path at tau in {0.5, 1, 2} (768 views), 1920 x 1080.  One
+step = one view: LoD select, forward render, L1 loss against a seeded random
+target, backward with the gradients accumulated into node-indexed arrays.
+
+Prints one JSON line (metric, value = ms per view, roofline of the dominant
+kernel, CPU baseline of the oracle on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3
+# FP32 operations of one (pixel, splat) evaluation of the blend that reaches
+# the compositing step: offsets 2, power 7 (two fused), exp 21 (ten fused),
+# alpha/skip/termination 6, weight and colour 7 (three fused); fused = 2.
+FLOP_PER_EVAL = 43
+# FP32 operations of one backward (pixel, splat) evaluation: the forward
+# replay (43) plus the colour/alpha/conic/mean gradient terms (about 45).
+FLOP_PER_EVAL_BWD = 88
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name, leaves):
+    from scenegen import configs
+    if name == "city":
+        spec = configs.city_spec(n=leaves or 50_000_000)
+        views = [(configs.city_path_camera(k), tau) for tau in configs.CITY_TAUS for k in range(256)]
+        desc = {"workload": "city-50M-1080p-path", "leaves": spec.n, "extent_m": 4000, "boxes": spec.n_boxes,
+                "resolution": [1920, 1080], "poses": 256, "taus": list(configs.CITY_TAUS), "sh_degree": 3}
+    elif name == "medium":
+        spec = configs.medium_spec(n=leaves or 2_000_000)
+        import numpy as np
+        views = []
+        rng = np.random.default_rng(101)
+        for k in range(32):
+            views.append((configs.medium_camera(seed=101 + k), 1.0))
+        desc = {"workload": "medium-2M-1080p", "leaves": spec.n, "resolution": [1920, 1080], "sh_degree": 3}
+    else:
+        spec = configs.tiny_spec(n=leaves or 16384)
+        views = [(configs.tiny_camera(), 1.0)]
+        desc = {"workload": "tiny-16k-512", "leaves": spec.n, "resolution": [512, 512], "sh_degree": 3}
+    return spec, views, desc
+
+
+def stage_bytes(c, H, W, n_coef):
+    """Algorithmic HBM bytes of one view by stage (FP32 / int32 layouts)."""
+    par = 4 * (3 + 3 + 4 + 1 + n_coef)  # bytes of one node's parameters
+    b = {}
+    b["select"] = c["n_upper"] * 24 + c["n_spt_visible"] * 32 + c["n_spt_candidates"] * 8 + c["n_selected"] * 4
+    b["project"] = c["n_rendered"] * (4 + par) + c["n_drawn"] * 48 + c["n_rendered"] * 24
+    b["depth_sort"] = 4 * c["n_rendered"] * 16
+    b["duplicate"] = c["n_rendered"] * 16 + c["n_instances"] * 8
+    b["tile_sort"] = 2 * c["n_instances"] * 16
+    b["ranges"] = c["n_instances"] * 4 + (H * W // 256) * 8
+    b["blend"] = c["n_instances"] * 52 + H * W * 12
+    b["loss"] = H * W * 36
+    b["blend_bwd"] = c["n_instances"] * 52 + H * W * 24 + c["n_drawn"] * 36 * 2
+    b["project_bwd"] = c["n_rendered"] * (4 + par + 36) + c["n_drawn"] * par * 2
+    return b
+
+
+def cpu_baseline(tree, cam, tau, target):
+    """The oracle on one view of the same workload (select, render, L1, backward)."""
+    import numpy as np
+    import oracle
+    t0 = time.time()
+    O = oracle.OracleScene(tree)
+    setup = time.time() - t0
+    t0 = time.time()
+    ids, _ = O.select(cam, tau)
+    F = oracle.OracleFrame(tree, ids, cam)
+    _, dL = oracle.l1_loss_grad(F.image, target)
+    F.backward(dL)
+    dt = time.time() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    return {"value": round(dt * 1000.0, 1), "unit": "ms per view", "cores": threads, "kind": "oracle",
+            "sample": f"1 view (path pose 128, tau {tau}) of the same scene: select + render + L1 + backward; "
+                      f"per-scene oracle setup ({setup:.1f} s) excluded", "n_selected": int(len(ids))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=768)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--workload", choices=["city", "medium", "tiny"], default="city")
+    ap.add_argument("--leaves", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--targets", type=int, default=8, help="distinct seeded targets resident in HBM")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): the path is a "
+              "single-GPU pipeline here; views would shard across GPUs with a replicated scene.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import scenegen
+    from paper_2507_01110_amd.lodgs import Frame, Scene, camera_struct
+
+    torch.cuda.set_device(0)
+    spec, views, desc = workload(args.workload, args.leaves)
+    t0 = time.time()
+    tree = scenegen.build_tree(spec)
+    log(f"scene: {tree.n_nodes} nodes built in {time.time() - t0:.1f} s")
+    t0 = time.time()
+    scene = Scene(tree)
+    torch.cuda.synchronize()
+    log(f"HSPT {scene.n_upper} upper nodes, {scene.n_spt} SPTs; upload {scene.param_bytes() / 1e9:.1f} GB "
+        f"in {time.time() - t0:.1f} s")
+    W, H = views[0][0].width, views[0][0].height
+    n_coef = 3 * (tree.sh_degree + 1) ** 2
+    K = max(1, args.steps)
+    stride = max(1, len(views) // K) if K < len(views) else 1
+    seq = [(i * stride) % len(views) for i in range(K)]
+
+    # Counting pass (untimed): per-view counts for the byte model and capacities.
+    cap_sel, cap_inst = min(scene.n_nodes, 1 << 24), 1 << 27
+    frame = Frame(scene, cap_sel, cap_inst, W, H)
+    counts = []
+    for v in seq:
+        cam, tau = views[v]
+        while True:
+            frame.lod_select(cam, tau)
+            frame.render(cam)
+            st = frame.stats()
+            if st["status"] == 0:
+                break
+            cap_sel = max(cap_sel, int(st["n_selected"] * 1.25) + 1024)
+            cap_inst = max(cap_inst, int(st["n_instances"] * 1.25) + 1024)
+            log(f"capacity grown to {cap_sel} selected / {cap_inst} instances")
+            del frame
+            torch.cuda.empty_cache()
+            frame = Frame(scene, cap_sel, cap_inst, W, H)
+        ev, co = frame.blend_work()
+        st["evaluations"], st["contributions"] = ev, co
+        counts.append(st)
+    log(f"counting pass done: mean n_selected {np.mean([c['n_selected'] for c in counts]):.0f}, "
+        f"mean instances {np.mean([c['n_instances'] for c in counts]):.0f}")
+
+    targets = [torch.from_numpy(scenegen.target_image(H, W, 202 + k)).cuda() for k in range(args.targets)]
+    grads = {k: torch.zeros_like(v) for k, v in scene.params.items()}
+    img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    dL = torch.empty_like(img)
+
+    cstructs = [camera_struct(c) for c, _ in views]
+
+    def step(i):
+        cam, tau = cstructs[seq[i % K]], views[seq[i % K]][1]
+        frame.lod_select(cam, tau)
+        frame.render(cam, out=img)
+        frame.l1_loss(img, targets[seq[i % K] % len(targets)], grad=dL)
+        frame.backward(dL, nodes=grads)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    frame.timings()  # discard warmup records
+    frame.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    frame.set_timing(False)
+    tm = frame.timings()
+    ms_per_view = elapsed * 1000.0 / K
+    log(f"timed {K} views: {ms_per_view:.3f} ms per view")
+    st_fin = frame.stats()
+    assert st_fin["status"] == 0, st_fin
+
+    # Byte model and per-stage rates.
+    tot_bytes = {}
+    for c in counts:
+        c["n_spt_candidates"] = int(c["n_spt_candidates"])
+        c["n_upper"] = scene.n_upper
+        for k, b in stage_bytes(c, H, W, n_coef).items():
+            tot_bytes[k] = tot_bytes.get(k, 0) + b
+    stages = {}
+    for name, (ms, calls) in tm.items():
+        if calls == 0:
+            continue
+        gb = tot_bytes.get(name, 0) / 1e9
+        stages[name] = {"ms_per_view": round(ms / K, 4), "GB_per_view": round(gb / K, 4),
+                        "GB_s": round(gb / (ms / 1000.0), 1) if ms > 0 else None}
+    all_bytes = sum(tot_bytes.values())
+    hbm_frac = all_bytes / (elapsed * HBM_PEAK_GBS * 1e9)
+    evals = sum(c["evaluations"] for c in counts)
+    dom = max(stages, key=lambda s: stages[s]["ms_per_view"])
+    dom_ms_total = tm[dom][0]
+    if dom in ("blend", "blend_bwd"):
+        flop = evals * (FLOP_PER_EVAL if dom == "blend" else FLOP_PER_EVAL_BWD)
+        ach = flop / (dom_ms_total / 1000.0) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                "evaluations_per_view": int(evals / K)}
+    else:
+        ach = tot_bytes[dom] / (dom_ms_total / 1000.0) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline and args.workload == "city":
+        mid = 256 + 128  # pose 128 at tau = 1
+        cam, tau = views[mid]
+        log("cpu baseline: oracle on one view ...")
+        cpu = cpu_baseline(tree, cam, tau, scenegen.target_image(H, W, 202))
+        log(f"cpu baseline {cpu['value']} ms per view on {cpu['cores']} threads")
+    elif not args.no_cpu_baseline:
+        cam, tau = views[0]
+        cpu = cpu_baseline(tree, cam, tau, scenegen.target_image(H, W, 202))
+
+    mean = lambda k: float(np.mean([c[k] for c in counts]))
+    out = {
+        "metric": "ms per 1080p view (LoD+splat fwd/bwd) @50M Gaussians, %HBM peak; serve p50/p99",
+        "value": round(ms_per_view, 4), "unit": "ms per view", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_view, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic (seeded scene, cameras and targets)",
+        "config": dict(desc, nodes=int(scene.n_nodes), upper_nodes=int(scene.n_upper), spts=int(scene.n_spt),
+                       views_timed=K, parallelism="none"),
+        "hbm_fraction_whole_path": round(hbm_frac, 4),
+        "algorithmic_GB_per_view": round(all_bytes / K / 1e9, 4),
+        "stages": stages,
+        "mean_counts": {k: round(mean(k), 1) for k in ("n_selected", "n_spt_visible", "n_spt_candidates",
+                                                       "n_drawn", "n_instances", "evaluations", "contributions")},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -214,6 +214,57 @@ int lodgs_frame_read_instances(lodgs_frame* frame, int32_t* d_tile, int32_t* d_p
 /* Clears the recorded device error of the frame. */
 int lodgs_frame_clear_status(lodgs_frame* frame, lodgs_stream stream);
 
+/* ---------------------------------------------------------------- timing
+ * Timing mode brackets every stage of lod_select / render / render_backward
+ * with HIP events on the call's stream.  lodgs_frame_timings blocks until
+ * the recorded events complete, returns the summed milliseconds and call
+ * counts per stage since the last read, and clears the record. */
+#define LODGS_STAGE_SELECT 0      /* upper cut, SPT binary search, compaction */
+#define LODGS_STAGE_PROJECT 1     /* gather + EWA + SH                          */
+#define LODGS_STAGE_DEPTH_SORT 2  /* radix sort of splats by depth              */
+#define LODGS_STAGE_DUPLICATE 3   /* tile-count scan + instance emission        */
+#define LODGS_STAGE_TILE_SORT 4   /* radix sort of instances by tile            */
+#define LODGS_STAGE_RANGES 5      /* per-tile ranges                            */
+#define LODGS_STAGE_BLEND 6       /* forward blend                              */
+#define LODGS_STAGE_BLEND_BWD 7   /* backward blend (2D gradients)              */
+#define LODGS_STAGE_PROJECT_BWD 8 /* projection / SH backward + scatter         */
+#define LODGS_STAGE_LOSS 9        /* lodgs_l1_loss                              */
+#define LODGS_N_STAGES 10
+
+typedef struct lodgs_timings {
+  double ms[LODGS_N_STAGES];
+  int64_t calls[LODGS_N_STAGES];
+} lodgs_timings;
+
+int lodgs_frame_set_timing(lodgs_frame* frame, int enable);
+int lodgs_frame_timings(lodgs_frame* frame, lodgs_timings* out);
+
+/* Work counts of the last render's blend (blocks on the stream): replays the
+ * forward blend with counters and returns the number of (pixel, splat)
+ * evaluations, i.e. splats visited by a pixel before it stopped, and of
+ * contributing pairs.  Diagnostics for the roofline; does not change any
+ * output. */
+int lodgs_frame_blend_work(lodgs_frame* frame, int64_t* evaluations, int64_t* contributions,
+                           lodgs_stream stream);
+
+/* Device arithmetic self-test of the operations every decision of the path
+ * relies on being exact (IEEE round-to-nearest FP32 and FP64 division and
+ * square root) and of the FP32 exp of the decision path.  For i < n, with
+ * (a, b) = (d_in32[2i], d_in32[2i+1]) and (c, d) = (d_in64[2i], d_in64[2i+1]):
+ *   d_out32[3i] = a / b, d_out32[3i+1] = sqrt(|a|), d_out32[3i+2] = exp(a),
+ *   d_out64[2i] = c / d, d_out64[2i+1] = sqrt(|c|). */
+int lodgs_selftest_arith(const float* d_in32, const double* d_in64, int64_t n, float* d_out32, double* d_out64,
+                         lodgs_stream stream);
+
+/* ---------------------------------------------------------------- loss
+ * L1 loss of an image against a target (the configs' training objective):
+ * L = sum |img - target| / n and dL/dimg = sign(img - target) / n with
+ * sign(0) = 0, n = number of floats.  d_grad [n] is written; d_loss (one
+ * float, optional) receives L.  Frame-free; records LODGS_STAGE_LOSS when a
+ * frame in timing mode is given (frame may be NULL). */
+int lodgs_l1_loss(lodgs_frame* frame, const float* d_img, const float* d_target, int64_t n, float* d_grad,
+                  float* d_loss, lodgs_stream stream);
+
 const char* lodgs_last_error(void);
 
 #ifdef __cplusplus

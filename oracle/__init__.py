@@ -210,9 +210,9 @@ class OracleFrame:
         depth = np.zeros(n, np.uint32)
         tiles = np.zeros(n, np.int32)
         rect = np.zeros((n, 4), np.int32)
-        f7 = np.zeros((n, 7), np.float32)
-        lib().orc_frame_get_splats(self._h, _p(depth), _p(tiles), _p(rect), _p(f7))
-        return {"depth_bits": depth, "tiles": tiles, "rect": rect, "f32": f7}
+        f10 = np.zeros((n, 10), np.float32)
+        lib().orc_frame_get_splats(self._h, _p(depth), _p(tiles), _p(rect), _p(f10))
+        return {"depth_bits": depth, "tiles": tiles, "rect": rect, "f32": f10}
 
     def instances(self):
         ni = self.info()["n_inst"]

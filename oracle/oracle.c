@@ -432,79 +432,108 @@ void orc_sh_basis(const double* d, double* Y, double* dY /* [16][3] or NULL */) 
  * low-pass is added to the diagonal of the projected covariance; splats with
  * camera depth <= z_near are not drawn; the tile footprint is the square of
  * half-width ceil(3 sqrt(lambda_max)) around the projected mean, 16x16 tiles.
- * FP32 mirror of the decisions: */
+ *
+ * Decision mirror of the projection: the per-splat chain is evaluated in FP64
+ * with a fixed operation order (scales from the FP32 portable exp, opacity as
+ * the FP32 sigmoid), and its results are rounded to the FP32 record that the
+ * per-pixel FP32 alpha uses: the projected mean as a hi/lo pair of floats,
+ * the principal axis (ce, se) of the projected covariance and the power
+ * coefficients h1 = -1/(2 l1), h2 = -1/(2 l2) of its eigenvalues, so that
+ * power = h1 u1^2 + h2 u2^2 with (u1, u2) the pixel offset in that basis. */
 typedef struct {
   int32_t visible, tiles, x0, x1, y0, y1;
-  float depth, mx, my, na, nb, nc, o, radius;
+  float depth, mxh, mxl, myh, myl, ce, se, h1, h2, o, radius;
 } orc_g32;
 
-static int clamp_tile(float v, int hi) {
-  if (v < 0.0f) return 0;
-  if (v > (float)hi) return hi;
+static int clamp_tile_d(double v, int hi) {
+  if (v < 0.0) return 0;
+  if (v > (double)hi) return hi;
   return (int)v;
 }
 
 void orc_project32(const float* mu, const float* ls, const float* q, float theta, const orc_camera* C,
                    int TX, int TY, orc_g32* G) {
   memset(G, 0, sizeof *G);
-  float c[3];
-  cam32(C, mu, c);
-  G->depth = c[2];
-  if (!(c[2] > C->z_near)) return;
-  float s0 = orc_pexp(ls[0]), s1 = orc_pexp(ls[1]), s2 = orc_pexp(ls[2]);
-  float qq = q[0] * q[0];
-  qq = qq + q[1] * q[1];
-  qq = qq + q[2] * q[2];
-  qq = qq + q[3] * q[3];
-  float qn = sqrtf(qq);
-  float w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
-  float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
-  float wx = w * x, wy = w * y, wz = w * z;
-  float r00 = 1.0f - 2.0f * (yy + zz), r01 = 2.0f * (xy - wz), r02 = 2.0f * (xz + wy);
-  float r10 = 2.0f * (xy + wz), r11 = 1.0f - 2.0f * (xx + zz), r12 = 2.0f * (yz - wx);
-  float r20 = 2.0f * (xz - wy), r21 = 2.0f * (yz + wx), r22 = 1.0f - 2.0f * (xx + yy);
-  float m00 = r00 * s0, m01 = r01 * s1, m02 = r02 * s2;
-  float m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
-  float m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
-  float S00 = (m00 * m00 + m01 * m01) + m02 * m02;
-  float S01 = (m00 * m10 + m01 * m11) + m02 * m12;
-  float S02 = (m00 * m20 + m01 * m21) + m02 * m22;
-  float S11 = (m10 * m10 + m11 * m11) + m12 * m12;
-  float S12 = (m10 * m20 + m11 * m21) + m12 * m22;
-  float S22 = (m20 * m20 + m21 * m21) + m22 * m22;
-  float u = c[0] / c[2], v = c[1] / c[2];
-  float jx = C->fx / c[2], jy = C->fy / c[2];
-  float jxz = -(jx * u), jyz = -(jy * v);
-  const float* W = C->R;
-  float T00 = jx * W[0] + jxz * W[6], T01 = jx * W[1] + jxz * W[7], T02 = jx * W[2] + jxz * W[8];
-  float T10 = jy * W[3] + jyz * W[6], T11 = jy * W[4] + jyz * W[7], T12 = jy * W[5] + jyz * W[8];
-  float U00 = (T00 * S00 + T01 * S01) + T02 * S02;
-  float U01 = (T00 * S01 + T01 * S11) + T02 * S12;
-  float U02 = (T00 * S02 + T01 * S12) + T02 * S22;
-  float U10 = (T10 * S00 + T11 * S01) + T12 * S02;
-  float U11 = (T10 * S01 + T11 * S11) + T12 * S12;
-  float U12 = (T10 * S02 + T11 * S12) + T12 * S22;
-  float A = ((U00 * T00 + U01 * T01) + U02 * T02) + 0.3f;
-  float B = (U00 * T10 + U01 * T11) + U02 * T12;
-  float Cc = ((U10 * T10 + U11 * T11) + U12 * T12) + 0.3f;
-  float det = A * Cc - B * B;
-  if (!(det > 0.0f)) return;
-  G->na = -0.5f * (Cc / det);
-  G->nb = B / det;
-  G->nc = -0.5f * (A / det);
-  G->mx = C->fx * u + C->ppx;
-  G->my = C->fy * v + C->ppy;
-  float mid = 0.5f * (A + Cc);
-  float disc = mid * mid - det;
-  float l1 = mid + sqrtf(fmaxf(0.1f, disc));
-  float r = ceilf(3.0f * sqrtf(l1));
-  G->radius = r;
-  G->x0 = clamp_tile(floorf((G->mx - r) * 0.0625f), TX);
-  G->x1 = clamp_tile(floorf((G->mx + r) * 0.0625f) + 1.0f, TX);
-  G->y0 = clamp_tile(floorf((G->my - r) * 0.0625f), TY);
-  G->y1 = clamp_tile(floorf((G->my + r) * 0.0625f) + 1.0f, TY);
+  double W[9], t[3];
+  for (int k = 0; k < 9; ++k) W[k] = (double)C->R[k];
+  for (int k = 0; k < 3; ++k) t[k] = (double)C->t[k];
+  const double m0 = mu[0], m1 = mu[1], m2 = mu[2];
+  double c[3];
+  for (int r = 0; r < 3; ++r) c[r] = ((W[3 * r] * m0 + W[3 * r + 1] * m1) + W[3 * r + 2] * m2) + t[r];
+  G->depth = (float)c[2];
+  if (!(c[2] > (double)C->z_near)) return;
+  const double s0 = (double)orc_pexp(ls[0]), s1 = (double)orc_pexp(ls[1]), s2 = (double)orc_pexp(ls[2]);
+  const double q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+  const double qq = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
+  const double qn = sqrt(qq);
+  const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+  const double xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
+  const double wx = w * x, wy = w * y, wz = w * z;
+  const double r00 = 1.0 - 2.0 * (yy + zz), r01 = 2.0 * (xy - wz), r02 = 2.0 * (xz + wy);
+  const double r10 = 2.0 * (xy + wz), r11 = 1.0 - 2.0 * (xx + zz), r12 = 2.0 * (yz - wx);
+  const double r20 = 2.0 * (xz - wy), r21 = 2.0 * (yz + wx), r22 = 1.0 - 2.0 * (xx + yy);
+  const double m00 = r00 * s0, m01 = r01 * s1, m02 = r02 * s2;
+  const double m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
+  const double m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
+  const double S00 = (m00 * m00 + m01 * m01) + m02 * m02;
+  const double S01 = (m00 * m10 + m01 * m11) + m02 * m12;
+  const double S02 = (m00 * m20 + m01 * m21) + m02 * m22;
+  const double S11 = (m10 * m10 + m11 * m11) + m12 * m12;
+  const double S12 = (m10 * m20 + m11 * m21) + m12 * m22;
+  const double S22 = (m20 * m20 + m21 * m21) + m22 * m22;
+  const double fx = C->fx, fy = C->fy;
+  const double u = c[0] / c[2], v = c[1] / c[2];
+  const double jx = fx / c[2], jy = fy / c[2];
+  const double jxz = -(jx * u), jyz = -(jy * v);
+  const double T00 = jx * W[0] + jxz * W[6], T01 = jx * W[1] + jxz * W[7], T02 = jx * W[2] + jxz * W[8];
+  const double T10 = jy * W[3] + jyz * W[6], T11 = jy * W[4] + jyz * W[7], T12 = jy * W[5] + jyz * W[8];
+  const double U00 = (T00 * S00 + T01 * S01) + T02 * S02;
+  const double U01 = (T00 * S01 + T01 * S11) + T02 * S12;
+  const double U02 = (T00 * S02 + T01 * S12) + T02 * S22;
+  const double U10 = (T10 * S00 + T11 * S01) + T12 * S02;
+  const double U11 = (T10 * S01 + T11 * S11) + T12 * S12;
+  const double U12 = (T10 * S02 + T11 * S12) + T12 * S22;
+  const double A = ((U00 * T00 + U01 * T01) + U02 * T02) + 0.3;
+  const double B = (U00 * T10 + U01 * T11) + U02 * T12;
+  const double Cc = ((U10 * T10 + U11 * T11) + U12 * T12) + 0.3;
+  const double det = A * Cc - B * B;
+  if (!(det > 0.0)) return;
+  const double mx = fx * u + (double)C->ppx, my = fy * v + (double)C->ppy;
+  const double mid = 0.5 * (A + Cc);
+  const double disc = mid * mid - det;
+  const double r = ceil(3.0 * sqrt(mid + sqrt(fmax(0.1, disc))));
+  G->radius = (float)r;
+  G->x0 = clamp_tile_d(floor((mx - r) * 0.0625), TX);
+  G->x1 = clamp_tile_d(floor((mx + r) * 0.0625) + 1.0, TX);
+  G->y0 = clamp_tile_d(floor((my - r) * 0.0625), TY);
+  G->y1 = clamp_tile_d(floor((my + r) * 0.0625) + 1.0, TY);
   G->tiles = (G->x1 > G->x0 && G->y1 > G->y0) ? (G->x1 - G->x0) * (G->y1 - G->y0) : 0;
   G->visible = G->tiles > 0;
+  /* principal axes of the projected covariance */
+  const double l1 = mid + sqrt(fmax(0.0, disc));
+  const double l2 = det / l1;
+  double vx, vy;
+  if (A >= Cc) {
+    vx = l1 - Cc;
+    vy = B;
+  } else {
+    vx = B;
+    vy = l1 - A;
+  }
+  const double nn = sqrt(vx * vx + vy * vy);
+  double ce = 1.0, se = 0.0;
+  if (nn > 0.0) {
+    ce = vx / nn;
+    se = vy / nn;
+  }
+  G->mxh = (float)mx;
+  G->mxl = (float)(mx - (double)G->mxh);
+  G->myh = (float)my;
+  G->myl = (float)(my - (double)G->myh);
+  G->ce = (float)ce;
+  G->se = (float)se;
+  G->h1 = (float)(-0.5 / l1);
+  G->h2 = (float)(-0.5 / l2);
   G->o = 1.0f / (1.0f + orc_pexp(-theta));
 }
 
@@ -622,10 +651,11 @@ static uint32_t fbits(float f) {
 
 /* FP32 mirror of one pixel's compositing decisions; returns the number of
  * contributing splats and, when list != NULL, their selection positions and
- * whether their alpha was clamped at 0.99.  The power of the Gaussian is
- * evaluated as fmaf(na dx + nb dy, dx, nc dy dy) with na = -a/2, nb = -b,
- * nc = -c/2 from the FP32 conic (a, b, c):
- *   t = na*dx; t = fmaf(nb, dy, t); u = nc*dy; u = u*dy; power = fmaf(t, dx, u). */
+ * whether their alpha was clamped at 0.99.  The power of a splat at the
+ * pixel centre (px, py) is evaluated from its FP32 record as
+ *   dx = (px - mxh) - mxl;  dy = (py - myh) - myl;
+ *   u1 = fmaf(se, dy, ce*dx);  u2 = fmaf(-se, dx, ce*dy);
+ *   power = fmaf(h1*u1, u1, (h2*u2)*u2). */
 static int64_t pixel32(const orc_frame* F, int px, int py, int32_t* list, uint8_t* clampf, int64_t* log4) {
   int tile = (py / ORC_TILE) * F->TX + px / ORC_TILE;
   float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
@@ -635,12 +665,14 @@ static int64_t pixel32(const orc_frame* F, int px, int py, int32_t* list, uint8_
   for (int64_t k = F->tile_start[tile]; k < F->tile_start[tile + 1]; ++k) {
     int32_t i = F->inst_pos[k];
     const orc_g32* G = F->g32 + i;
-    float dx = fx - G->mx, dy = fy - G->my;
-    float t = G->na * dx;
-    t = fmaf(G->nb, dy, t);
-    float u = G->nc * dy;
-    u = u * dy;
-    float power = fmaf(t, dx, u);
+    float dx = (fx - G->mxh) - G->mxl, dy = (fy - G->myh) - G->myl;
+    float u1 = G->ce * dx;
+    u1 = fmaf(G->se, dy, u1);
+    float u2 = G->ce * dy;
+    u2 = fmaf(-G->se, dx, u2);
+    float a2 = G->h2 * u2;
+    a2 = a2 * u2;
+    float power = fmaf(G->h1 * u1, u1, a2);
     float oe = G->o * orc_pexp(power);
     float alpha = fminf(0.99f, oe);
     if (log4) {
@@ -995,18 +1027,19 @@ void orc_frame_get_info(const orc_frame* F, orc_frame_info* I) {
   I->stop_1ulp = F->stop_1ulp;
 }
 
-/* Per-splat FP32 mirror outputs: depth bits, tiles, rect [x0,x1,y0,y1],
- * mean2D, (na, nb, nc), opacity, radius. */
+/* Per-splat mirror outputs: depth bits, tiles, rect [x0,x1,y0,y1] and the
+ * FP32 record [mxh, mxl, myh, myl, ce, se, h1, h2, o, radius]. */
 void orc_frame_get_splats(const orc_frame* F, uint32_t* depth_bits, int32_t* tiles, int32_t* rect,
-                          float* f32x7) {
+                          float* f32x10) {
   for (int64_t i = 0; i < F->n; ++i) {
     const orc_g32* G = F->g32 + i;
     if (depth_bits) depth_bits[i] = fbits(G->depth);
     if (tiles) tiles[i] = G->tiles;
     if (rect) { rect[4 * i] = G->x0; rect[4 * i + 1] = G->x1; rect[4 * i + 2] = G->y0; rect[4 * i + 3] = G->y1; }
-    if (f32x7) {
-      float* o = f32x7 + 7 * i;
-      o[0] = G->mx; o[1] = G->my; o[2] = G->na; o[3] = G->nb; o[4] = G->nc; o[5] = G->o; o[6] = G->radius;
+    if (f32x10) {
+      float* o = f32x10 + 10 * i;
+      o[0] = G->mxh; o[1] = G->mxl; o[2] = G->myh; o[3] = G->myl; o[4] = G->ce;
+      o[5] = G->se; o[6] = G->h1; o[7] = G->h2; o[8] = G->o; o[9] = G->radius;
     }
   }
 }

@@ -45,6 +45,17 @@ class Stats(ctypes.Structure):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
+STAGES = ("select", "project", "depth_sort", "duplicate", "tile_sort", "ranges", "blend", "blend_bwd",
+          "project_bwd", "loss")
+
+
+class Timings(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 10), ("calls", i64 * 10)]
+
+    def as_dict(self):
+        return {name: (float(self.ms[k]), int(self.calls[k])) for k, name in enumerate(STAGES)}
+
+
 EXPORTS = {
     "lodgs_hspt_build": ([i64, c_p, c_p, i32, c_p, ctypes.c_double, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p],
                          ctypes.c_int),
@@ -58,6 +69,11 @@ EXPORTS = {
     "lodgs_frame_stats": ([c_p, ctypes.POINTER(Stats), c_p], ctypes.c_int),
     "lodgs_frame_read_instances": ([c_p, c_p, c_p, i64, ctypes.POINTER(i64), c_p], ctypes.c_int),
     "lodgs_frame_clear_status": ([c_p, c_p], ctypes.c_int),
+    "lodgs_frame_set_timing": ([c_p, ctypes.c_int], ctypes.c_int),
+    "lodgs_frame_timings": ([c_p, ctypes.POINTER(Timings)], ctypes.c_int),
+    "lodgs_frame_blend_work": ([c_p, ctypes.POINTER(i64), ctypes.POINTER(i64), c_p], ctypes.c_int),
+    "lodgs_l1_loss": ([c_p, c_p, c_p, i64, c_p, c_p, c_p], ctypes.c_int),
+    "lodgs_selftest_arith": ([c_p, c_p, i64, c_p, c_p, c_p], ctypes.c_int),
     "lodgs_last_error": ([], ctypes.c_char_p),
 }
 

@@ -52,6 +52,27 @@ ViewConst make_view(const lodgs_camera& c, float tau) {
   return v;
 }
 
+void stage_begin(lodgs_frame* f, int stage, hipStream_t st) {
+  if (!f || !f->timing) return;
+  hipEvent_t a;
+  if (hipEventCreate(&a) != hipSuccess) return;
+  (void)hipEventRecord(a, st);
+  f->open_stage = stage;
+  f->open_event = a;
+}
+
+void stage_end(lodgs_frame* f, hipStream_t st) {
+  if (!f || !f->timing || !f->open_event) return;
+  hipEvent_t b;
+  if (hipEventCreate(&b) != hipSuccess) return;
+  (void)hipEventRecord(b, st);
+  f->timed.push_back({f->open_stage, f->open_event, b});
+  f->open_event = nullptr;
+}
+
+void launch_blend_count(lodgs_frame* f, hipStream_t st);
+void launch_l1_loss(const float* img, const float* target, int64_t n, float* grad, float* loss, hipStream_t st);
+
 }  // namespace lodgs
 
 using lodgs::hip_fail;
@@ -60,6 +81,18 @@ using lodgs::set_error;
 namespace {
 
 __global__ void k_clear_status(FrameCounters* c) { c->status = LODGS_OK; }
+
+__global__ void k_selftest(const float* in32, const double* in64, int64_t n, float* out32, double* out64) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float a = in32[2 * i], b = in32[2 * i + 1];
+    out32[3 * i] = a / b;
+    out32[3 * i + 1] = __builtin_sqrtf(fabsf(a));
+    out32[3 * i + 2] = lodgs::fexp(a);
+    const double c = in64[2 * i], d = in64[2 * i + 1];
+    out64[2 * i] = c / d;
+    out64[2 * i + 1] = __builtin_sqrt(fabs(c));
+  }
+}
 
 bool camera_ok(const lodgs_camera* c) {
   if (!c) return false;
@@ -81,7 +114,12 @@ hipError_t dalloc(T** p, size_t count) {
 
 void free_frame(lodgs_frame* f) {
   if (!f) return;
-  void* ptrs[] = {f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->chunk,
+  for (auto& r : f->timed) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  if (f->open_event) (void)hipEventDestroy(f->open_event);
+  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->chunk,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->rect,
                   f->ikey, f->ival, f->ikey2, f->ival2, f->ranges, f->grad2d};
   for (void* p : ptrs)
@@ -171,6 +209,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(ival2, ni);
   A(ranges, nt);
   A(grad2d, 9 * ns);
+  A(work, 2);
 #undef A
   if (e != hipSuccess) {
     free_frame(f);
@@ -276,6 +315,71 @@ int lodgs_frame_read_instances(lodgs_frame* f, int32_t* d_tile, int32_t* d_pos, 
     if (e != hipSuccess) return hip_fail(e, "lodgs_frame_read_instances");
   }
   return LODGS_OK;
+}
+
+int lodgs_frame_set_timing(lodgs_frame* f, int enable) {
+  if (!f) return set_error(LODGS_E_INVALID, "lodgs_frame_set_timing: null frame");
+  f->timing = enable != 0;
+  return LODGS_OK;
+}
+
+int lodgs_frame_timings(lodgs_frame* f, lodgs_timings* out) {
+  if (!f || !out) return set_error(LODGS_E_INVALID, "lodgs_frame_timings: null argument");
+  std::memset(out, 0, sizeof *out);
+  int rc = LODGS_OK;
+  for (auto& r : f->timed) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && rc == LODGS_OK) rc = hip_fail(e, "lodgs_frame_timings");
+    if (r.stage >= 0 && r.stage < LODGS_N_STAGES) {
+      out->ms[r.stage] += ms;
+      out->calls[r.stage] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  f->timed.clear();
+  return rc;
+}
+
+int lodgs_frame_blend_work(lodgs_frame* f, int64_t* evaluations, int64_t* contributions, lodgs_stream stream) {
+  if (!f || !evaluations || !contributions) return set_error(LODGS_E_INVALID, "lodgs_frame_blend_work: null argument");
+  if (!f->rendered) return set_error(LODGS_E_STATE, "lodgs_frame_blend_work: no render on this frame");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  lodgs::launch_blend_count(f, st);
+  unsigned long long w[2] = {0, 0};
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(w, f->work, sizeof w, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "lodgs_frame_blend_work");
+  *evaluations = (int64_t)w[0];
+  *contributions = (int64_t)w[1];
+  return LODGS_OK;
+}
+
+int lodgs_l1_loss(lodgs_frame* f, const float* d_img, const float* d_target, int64_t n, float* d_grad, float* d_loss,
+                  lodgs_stream stream) {
+  if (!d_img || !d_target || !d_grad || n <= 0) return set_error(LODGS_E_INVALID, "lodgs_l1_loss: bad argument");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  lodgs::stage_begin(f, LODGS_STAGE_LOSS, st);
+  lodgs::launch_l1_loss(d_img, d_target, n, d_grad, d_loss, st);
+  lodgs::stage_end(f, st);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_l1_loss");
+}
+
+int lodgs_selftest_arith(const float* d_in32, const double* d_in64, int64_t n, float* d_out32, double* d_out64,
+                         lodgs_stream stream) {
+  if (!d_in32 || !d_in64 || !d_out32 || !d_out64 || n < 0)
+    return set_error(LODGS_E_INVALID, "lodgs_selftest_arith: bad argument");
+  if (n == 0) return LODGS_OK;
+  int64_t g = (n + 255) / 256;
+  g = g > 1024 ? 1024 : g;
+  hipLaunchKernelGGL(k_selftest, dim3((int)g), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), d_in32, d_in64, n,
+                     d_out32, d_out64);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_selftest_arith");
 }
 
 int lodgs_frame_clear_status(lodgs_frame* f, lodgs_stream stream) {

@@ -93,15 +93,32 @@ __device__ __forceinline__ bool sphere_culled(const ViewConst& v, float mx, floa
   return false;
 }
 
-// Per-splat record read by the blend kernels (48 bytes, 16-byte aligned):
-// mean2D, power coefficients (na, nb, nc) = (-a/2, -b, -c/2) of the conic
-// (a, b, c), opacity, colour, and the half extents of the box outside which
+// Per-splat record read by the blend kernels (64 bytes, 16-byte aligned):
+// the projected mean as hi/lo float pairs, the principal axis (ce, se) of the
+// projected covariance and the power coefficients h1 = -1/(2 l1),
+// h2 = -1/(2 l2) of its eigenvalues (power = h1 u1^2 + h2 u2^2 in that
+// basis), opacity, colour, and the half extents of the box outside which
 // alpha < 1/255 for certain (used only to skip work whose result is known).
 struct alignas(16) Splat {
-  float mx, my, na, nb;
-  float nc, o, r, g;
-  float b, ex, ey, pad;
+  float mxh, mxl, myh, myl;
+  float ce, se, h1, h2;
+  float o, r, g, b;
+  float ex, ey, radius, pad;
 };
+
+// Power of a splat at the pixel centre (px, py), FP32, fixed operation order.
+__device__ __forceinline__ float splat_power(const Splat& s, float px, float py, float& dx, float& dy, float& u1,
+                                             float& u2) {
+  dx = (px - s.mxh) - s.mxl;
+  dy = (py - s.myh) - s.myl;
+  u1 = s.ce * dx;
+  u1 = __builtin_fmaf(s.se, dy, u1);
+  u2 = s.ce * dy;
+  u2 = __builtin_fmaf(-s.se, dx, u2);
+  float a2 = s.h2 * u2;
+  a2 = a2 * u2;
+  return __builtin_fmaf(s.h1 * u1, u1, a2);
+}
 
 // Real SH basis constants, l <= 3 (3DGS sign convention).
 constexpr float kSH0 = 0.28209479177387814f;

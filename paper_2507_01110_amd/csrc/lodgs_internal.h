@@ -8,6 +8,8 @@
 #include "lodgs_error.h"
 #include "lodgs_prims.h"
 
+#include <vector>
+
 // Device pointers of a scene, passed to kernels by value.
 struct SceneDev {
   int64_t n_nodes;
@@ -83,11 +85,25 @@ struct lodgs_frame {
   lodgs::ViewConst view;
   const uint32_t* sorted_ival;  // the buffer holding the final instance order
   const uint32_t* sorted_ikey;
+  // timing mode: one (stage, start, end) event pair per stage and call
+  bool timing;
+  struct TimedStage {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<TimedStage> timed;
+  int open_stage;
+  hipEvent_t open_event;
+  unsigned long long* work;  // [2] evaluation / contribution counters (device)
 };
 
 namespace lodgs {
 
 int hip_fail(hipError_t e, const char* what);
+
+// Timing mode: brackets a stage with events on the stream (no-op otherwise).
+void stage_begin(lodgs_frame* f, int stage, hipStream_t st);
+void stage_end(lodgs_frame* f, hipStream_t st);
 
 // Stage launchers (all stream-ordered, no host synchronisation).
 void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,

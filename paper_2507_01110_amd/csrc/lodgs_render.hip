@@ -15,10 +15,14 @@
 //  k_blend    one workgroup per tile, one lane per pixel; splat records are
 //             staged in LDS in batches of 256.
 #include "lodgs_internal.h"
+#include "lodgs_proj.h"
 
 namespace lodgs {
 
-// FP32 projection of one node (the decisions of the path are taken here).
+// Projection of one node.  The per-splat chain runs in FP64 with a fixed
+// operation order (scales from the FP32 exp, opacity as the FP32 sigmoid);
+// its decisions (near plane, positive determinant, footprint radius, tile
+// rectangle) are taken in FP64 and its outputs rounded to the FP32 record.
 struct Proj {
   bool visible;
   float depth;
@@ -26,9 +30,9 @@ struct Proj {
   int x0, x1, y0, y1;
 };
 
-__device__ __forceinline__ int tile_clamp(float v, int hi) {
-  if (v < 0.0f) return 0;
-  if (v > (float)hi) return hi;
+__device__ __forceinline__ int tile_clamp(double v, int hi) {
+  if (v < 0.0) return 0;
+  if (v > (double)hi) return hi;
   return (int)v;
 }
 
@@ -37,84 +41,62 @@ __device__ __forceinline__ Proj project_node(const SceneDev& S, const ViewConst&
   P.visible = false;
   P.x0 = P.x1 = P.y0 = P.y1 = 0;
   const int64_t n = node;
-  const float mx = S.means[3 * n], my = S.means[3 * n + 1], mz = S.means[3 * n + 2];
-  float cx, cy, cz;
-  to_camera(v, mx, my, mz, cx, cy, cz);
-  P.depth = cz;
-  if (!(cz > v.z_near)) return P;
-  const float s0 = fexp(S.log_scales[3 * n]), s1 = fexp(S.log_scales[3 * n + 1]), s2 = fexp(S.log_scales[3 * n + 2]);
-  const float4 q = *reinterpret_cast<const float4*>(S.quats + 4 * n);
-  float qq = q.x * q.x;
-  qq = qq + q.y * q.y;
-  qq = qq + q.z * q.z;
-  qq = qq + q.w * q.w;
-  const float ql = __builtin_sqrtf(qq);
-  const float w = q.x / ql, x = q.y / ql, y = q.z / ql, z = q.w / ql;
-  const float xx = x * x, yy = y * y, zz = z * z, xy = x * y, xz = x * z, yz = y * z;
-  const float wx = w * x, wy = w * y, wz = w * z;
-  const float r00 = 1.0f - 2.0f * (yy + zz), r01 = 2.0f * (xy - wz), r02 = 2.0f * (xz + wy);
-  const float r10 = 2.0f * (xy + wz), r11 = 1.0f - 2.0f * (xx + zz), r12 = 2.0f * (yz - wx);
-  const float r20 = 2.0f * (xz - wy), r21 = 2.0f * (yz + wx), r22 = 1.0f - 2.0f * (xx + yy);
-  const float m00 = r00 * s0, m01 = r01 * s1, m02 = r02 * s2;
-  const float m10 = r10 * s0, m11 = r11 * s1, m12 = r12 * s2;
-  const float m20 = r20 * s0, m21 = r21 * s1, m22 = r22 * s2;
-  const float S00 = (m00 * m00 + m01 * m01) + m02 * m02;
-  const float S01 = (m00 * m10 + m01 * m11) + m02 * m12;
-  const float S02 = (m00 * m20 + m01 * m21) + m02 * m22;
-  const float S11 = (m10 * m10 + m11 * m11) + m12 * m12;
-  const float S12 = (m10 * m20 + m11 * m21) + m12 * m22;
-  const float S22 = (m20 * m20 + m21 * m21) + m22 * m22;
-  const float u = cx / cz, vv = cy / cz;
-  const float jx = v.fx / cz, jy = v.fy / cz;
-  const float jxz = -(jx * u), jyz = -(jy * vv);
-  const float* W = v.R;
-  const float T00 = jx * W[0] + jxz * W[6], T01 = jx * W[1] + jxz * W[7], T02 = jx * W[2] + jxz * W[8];
-  const float T10 = jy * W[3] + jyz * W[6], T11 = jy * W[4] + jyz * W[7], T12 = jy * W[5] + jyz * W[8];
-  const float U00 = (T00 * S00 + T01 * S01) + T02 * S02;
-  const float U01 = (T00 * S01 + T01 * S11) + T02 * S12;
-  const float U02 = (T00 * S02 + T01 * S12) + T02 * S22;
-  const float U10 = (T10 * S00 + T11 * S01) + T12 * S02;
-  const float U11 = (T10 * S01 + T11 * S11) + T12 * S12;
-  const float U12 = (T10 * S02 + T11 * S12) + T12 * S22;
-  const float A = ((U00 * T00 + U01 * T01) + U02 * T02) + 0.3f;
-  const float B = (U00 * T10 + U01 * T11) + U02 * T12;
-  const float C = ((U10 * T10 + U11 * T11) + U12 * T12) + 0.3f;
-  const float det = A * C - B * B;
-  if (!(det > 0.0f)) return P;
-  P.sp.na = -0.5f * (C / det);
-  P.sp.nb = B / det;
-  P.sp.nc = -0.5f * (A / det);
-  P.sp.mx = v.fx * u + v.cx;
-  P.sp.my = v.fy * vv + v.cy;
-  const float mid = 0.5f * (A + C);
-  const float disc = mid * mid - det;
-  const float sq = __builtin_sqrtf(fmaxf(0.1f, disc));
-  const float l1 = mid + sq;
-  const float r = ceilf(3.0f * __builtin_sqrtf(l1));
-  P.x0 = tile_clamp(floorf((P.sp.mx - r) * 0.0625f), v.tiles_x);
-  P.x1 = tile_clamp(floorf((P.sp.mx + r) * 0.0625f) + 1.0f, v.tiles_x);
-  P.y0 = tile_clamp(floorf((P.sp.my - r) * 0.0625f), v.tiles_y);
-  P.y1 = tile_clamp(floorf((P.sp.my + r) * 0.0625f) + 1.0f, v.tiles_y);
+  Proj64 G;
+  const bool ok = proj_chain64(S.means, S.log_scales, S.quats, v, n, G);
+  P.depth = (float)G.c[2];
+  if (!ok) return P;
+  const double A = G.A, B = G.B, C = G.C, det = G.det;
+  const double fx = v.fx, fy = v.fy, u = G.u, vv = G.v;
+  const double mx = fx * u + (double)v.cx, my = fy * vv + (double)v.cy;
+  const double mid = 0.5 * (A + C);
+  const double disc = mid * mid - det;
+  const double r = ceil(3.0 * __builtin_sqrt(mid + __builtin_sqrt(fmax(0.1, disc))));
+  P.x0 = tile_clamp(floor((mx - r) * 0.0625), v.tiles_x);
+  P.x1 = tile_clamp(floor((mx + r) * 0.0625) + 1.0, v.tiles_x);
+  P.y0 = tile_clamp(floor((my - r) * 0.0625), v.tiles_y);
+  P.y1 = tile_clamp(floor((my + r) * 0.0625) + 1.0, v.tiles_y);
   P.visible = P.x1 > P.x0 && P.y1 > P.y0;
+  // principal axes of the projected covariance
+  const double l1 = mid + __builtin_sqrt(fmax(0.0, disc));
+  const double l2 = det / l1;
+  double vx, vy;
+  if (A >= C) {
+    vx = l1 - C;
+    vy = B;
+  } else {
+    vx = B;
+    vy = l1 - A;
+  }
+  const double nn = __builtin_sqrt(vx * vx + vy * vy);
+  double ce = 1.0, se = 0.0;
+  if (nn > 0.0) {
+    ce = vx / nn;
+    se = vy / nn;
+  }
+  P.sp.mxh = (float)mx;
+  P.sp.mxl = (float)(mx - (double)P.sp.mxh);
+  P.sp.myh = (float)my;
+  P.sp.myl = (float)(my - (double)P.sp.myh);
+  P.sp.ce = (float)ce;
+  P.sp.se = (float)se;
+  P.sp.h1 = (float)(-0.5 / l1);
+  P.sp.h2 = (float)(-0.5 / l2);
   const float theta = S.opacity_logits[n];
   P.sp.o = 1.0f / (1.0f + fexp(-theta));
+  P.sp.radius = (float)r;
+  P.sp.pad = 0.0f;
   // Box outside which alpha < 1/255 is certain: alpha >= 1/255 needs
-  // q = x^T Sigma'^-1 x <= 2 ln(255 o); |x| <= sqrt(q_max Sigma'_00) per axis.
-  // Margins cover FP32 rounding of the power; very anisotropic splats get no box.
-  const float l2 = mid - sq;
+  // q = x^T Sigma'^-1 x <= 2 ln(255 o), hence |x| <= sqrt(q_max Sigma'_00) per
+  // axis.  Margins cover the FP32 evaluation of the power.
   const float lo = 255.0f * P.sp.o;
   if (lo < 1.0f) {
     P.sp.ex = -1.0f;
     P.sp.ey = -1.0f;
-  } else if (l2 > 0.0f && l1 < 1e5f * l2) {
-    const float qmax = 1.1f * (2.0f * __logf(lo) + 0.01f);
-    P.sp.ex = __builtin_sqrtf(qmax * A) + 2.0f;
-    P.sp.ey = __builtin_sqrtf(qmax * C) + 2.0f;
   } else {
-    P.sp.ex = 3.0e38f;
-    P.sp.ey = 3.0e38f;
+    const double qmax = 1.05 * (2.0 * (double)__logf(lo) + 0.01);
+    P.sp.ex = (float)(__builtin_sqrt(qmax * A) * 1.001 + 1.0);
+    P.sp.ey = (float)(__builtin_sqrt(qmax * C) * 1.001 + 1.0);
   }
-  P.sp.pad = r;
   return P;
 }
 
@@ -224,9 +206,10 @@ __global__ void __launch_bounds__(kBlock) k_ranges(const FrameCounters* ctr, con
 
 // One workgroup per tile, one lane per pixel.  alpha = min(0.99, o e^power),
 // skipped below 1/255; stop before the transmittance would drop below 1e-4.
+template <bool COUNT>
 __global__ void __launch_bounds__(256) k_blend(ViewConst v, const uint2* ranges, const uint32_t* ival,
                                                const Splat* splats, const FrameCounters* ctr, float bg0, float bg1,
-                                               float bg2, float* rgb) {
+                                               float bg2, float* rgb, unsigned long long* work) {
   __shared__ Splat batch[256];
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
@@ -238,6 +221,7 @@ __global__ void __launch_bounds__(256) k_blend(ViewConst v, const uint2* ranges,
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
   bool done = !inside;
   const float thr = 1.0f / 255.0f;
+  unsigned long long n_eval = 0, n_contrib = 0;
   for (uint32_t b0 = rg.x; b0 < rg.y; b0 += 256) {
     if (__syncthreads_count(done) == 256) break;
     const uint32_t k = b0 + threadIdx.x;
@@ -250,12 +234,9 @@ __global__ void __launch_bounds__(256) k_blend(ViewConst v, const uint2* ranges,
     const int m = (int)min(256u, rg.y - b0);
     for (int j = 0; j < m && !done; ++j) {
       const Splat& s = batch[j];
-      const float dx = fx - s.mx, dy = fy - s.my;
-      float t1 = s.na * dx;
-      t1 = __builtin_fmaf(s.nb, dy, t1);
-      float u = s.nc * dy;
-      u = u * dy;
-      const float power = __builtin_fmaf(t1, dx, u);
+      if (COUNT) ++n_eval;
+      float dx, dy, u1, u2;
+      const float power = splat_power(s, fx, fy, dx, dy, u1, u2);
       const float alpha = fminf(0.99f, s.o * fexp(power));
       if (alpha < thr) continue;
       const float tt = T * (1.0f - alpha);
@@ -268,7 +249,19 @@ __global__ void __launch_bounds__(256) k_blend(ViewConst v, const uint2* ranges,
       cg = __builtin_fmaf(s.g, w, cg);
       cb = __builtin_fmaf(s.b, w, cb);
       T = tt;
+      if (COUNT) ++n_contrib;
     }
+  }
+  if (COUNT) {
+    for (int d = 32; d > 0; d >>= 1) {
+      n_eval += __shfl_xor(n_eval, d, 64);
+      n_contrib += __shfl_xor(n_contrib, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(work, n_eval);
+      atomicAdd(work + 1, n_contrib);
+    }
+    return;
   }
   if (inside) {
     float* o = rgb + 3 * ((int64_t)py * v.width + px);
@@ -282,28 +275,53 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
                    const float bg[3], float* d_rgb, hipStream_t st) {
   const SceneDev& S = f->scene->dev;
   const int64_t cap = f->caps.max_selected, icap = f->caps.max_instances;
+  stage_begin(f, LODGS_STAGE_PROJECT, st);
   hipLaunchKernelGGL(k_render_begin, dim3(1), dim3(1), 0, st, f->ctr, d_count, cap);
   const int pgrid = 2048;
   hipLaunchKernelGGL(k_project, dim3(pgrid), dim3(kBlock), 0, st, S, v, d_idx, d_count, cap, f->splats, f->depth_key,
                      f->order, f->tiles, f->rect, f->ctr);
+  stage_end(f, st);
+  stage_begin(f, LODGS_STAGE_DEPTH_SORT, st);
   SortScratch ws{f->sort_table, f->block_sums, &f->ctr->sort_table_n};
   const bool sw = sort_pairs(f->depth_key, f->order, f->depth_key2, f->order2, &f->ctr->n_render, cap, 32, ws, st);
   const uint32_t* order = sw ? f->order2 : f->order;
+  stage_end(f, st);
+  stage_begin(f, LODGS_STAGE_DUPLICATE, st);
   scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_render, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
   hipLaunchKernelGGL(k_inst_count, dim3(1), dim3(1), 0, st, f->ctr, icap);
   hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->tiles, f->inst_off, f->rect,
                      v.tiles_x, icap, f->ikey, f->ival);
+  stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
   while ((1 << tbits) < ntiles) tbits += 8;
+  stage_begin(f, LODGS_STAGE_TILE_SORT, st);
   const bool sw2 = sort_pairs(f->ikey, f->ival, f->ikey2, f->ival2, &f->ctr->n_inst_clamped, icap, tbits, ws, st);
   f->sorted_ikey = sw2 ? f->ikey2 : f->ikey;
   f->sorted_ival = sw2 ? f->ival2 : f->ival;
+  stage_end(f, st);
+  stage_begin(f, LODGS_STAGE_RANGES, st);
   hipLaunchKernelGGL(k_zero_ranges, dim3((ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, st, f->ranges, ntiles);
   hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_ikey, f->ranges, (uint32_t)ntiles);
-  hipLaunchKernelGGL(k_blend, dim3(ntiles), dim3(256), 0, st, v, f->ranges, f->sorted_ival, f->splats, f->ctr, bg[0],
-                     bg[1], bg[2], d_rgb);
+  stage_end(f, st);
+  stage_begin(f, LODGS_STAGE_BLEND, st);
+  hipLaunchKernelGGL(k_blend<false>, dim3(ntiles), dim3(256), 0, st, v, f->ranges, f->sorted_ival, f->splats, f->ctr,
+                     bg[0], bg[1], bg[2], d_rgb, (unsigned long long*)nullptr);
+  stage_end(f, st);
+}
+
+__global__ void k_zero_work(unsigned long long* w) {
+  w[0] = 0;
+  w[1] = 0;
+}
+
+void launch_blend_count(lodgs_frame* f, hipStream_t st) {
+  const ViewConst& v = f->view;
+  const int ntiles = v.tiles_x * v.tiles_y;
+  hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(1), 0, st, f->work);
+  hipLaunchKernelGGL(k_blend<true>, dim3(ntiles), dim3(256), 0, st, v, f->ranges, f->sorted_ival, f->splats, f->ctr,
+                     0.0f, 0.0f, 0.0f, (float*)nullptr, f->work);
 }
 
 }  // namespace lodgs

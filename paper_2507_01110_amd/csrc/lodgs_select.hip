@@ -163,6 +163,7 @@ struct LoadHigh {
 void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
                    int32_t* d_count, hipStream_t st) {
   const SceneDev& S = f->scene->dev;
+  stage_begin(f, LODGS_STAGE_SELECT, st);
   hipLaunchKernelGGL(k_reset_select, dim3(1), dim3(1), 0, st, f->ctr);
   const int64_t total = (int64_t)S.n_upper + S.n_spt;
   int grid = (int)((total + kBlock - 1) / kBlock);
@@ -183,6 +184,7 @@ void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* 
     g2 = g2 > 1024 ? 1024 : g2;
     hipLaunchKernelGGL(k_count_upper, dim3(g2), dim3(kBlock), 0, st, f->upper_sel, S.n_upper, f->ctr);
   }
+  stage_end(f, st);
 }
 
 }  // namespace lodgs

@@ -25,6 +25,8 @@ def _stream(stream) -> int:
 
 
 def camera_struct(cam) -> _lib.Camera:
+    if isinstance(cam, _lib.Camera):
+        return cam
     c = _lib.Camera()
     c.R[:] = [float(v) for v in np.asarray(cam.R, np.float32).reshape(9)]
     c.t[:] = [float(v) for v in np.asarray(cam.t, np.float32).reshape(3)]
@@ -170,6 +172,29 @@ class Frame:
 
     def clear_status(self, stream=None):
         check(_lib.load().lodgs_frame_clear_status(self._h, _stream(stream)), "lodgs_frame_clear_status")
+
+    def set_timing(self, enable: bool = True):
+        check(_lib.load().lodgs_frame_set_timing(self._h, 1 if enable else 0), "lodgs_frame_set_timing")
+
+    def timings(self) -> dict:
+        """{stage: (total ms, calls)} since the last read (blocks)."""
+        t = _lib.Timings()
+        check(_lib.load().lodgs_frame_timings(self._h, ctypes.byref(t)), "lodgs_frame_timings")
+        return t.as_dict()
+
+    def blend_work(self, stream=None):
+        """(evaluations, contributions) of the last render's forward blend."""
+        e, c = ctypes.c_int64(0), ctypes.c_int64(0)
+        check(_lib.load().lodgs_frame_blend_work(self._h, ctypes.byref(e), ctypes.byref(c), _stream(stream)),
+              "lodgs_frame_blend_work")
+        return e.value, c.value
+
+    def l1_loss(self, img, target, grad=None, loss=None, stream=None):
+        """dL/dimg of the mean absolute error (written to grad) and, optionally, L."""
+        grad = torch.empty_like(img) if grad is None else grad
+        check(_lib.load().lodgs_l1_loss(self._h, _ptr(img), _ptr(target), img.numel(), _ptr(grad), _ptr(loss),
+                                        _stream(stream)), "lodgs_l1_loss")
+        return grad
 
     def instances(self, stream=None):
         n_max = int(self.caps.max_instances)

@@ -62,6 +62,50 @@ def _check_select(O, frame, cam, tau, cull):
     return ids
 
 
+def test_device_arithmetic_is_correctly_rounded(torch_cuda):
+    """The decisions rely on IEEE round-to-nearest / and sqrt (FP32, FP64) and on
+    the portable FP32 exp: the device must agree bit for bit with the host."""
+    import ctypes
+    import torch
+    from paper_2507_01110_amd import _lib
+    rng = np.random.default_rng(5)
+    n = 200000
+    a32 = np.concatenate([rng.uniform(-90, 20, n // 2), rng.normal(0, 1e3, n // 2)]).astype(np.float32)
+    b32 = rng.uniform(1e-3, 1e4, n).astype(np.float32) * np.where(rng.random(n) < 0.5, -1, 1).astype(np.float32)
+    a64 = rng.normal(0, 1e6, n) * 10.0 ** rng.integers(-20, 20, n)
+    b64 = rng.normal(0, 1e3, n) * 10.0 ** rng.integers(-20, 20, n)
+    in32 = torch.from_numpy(np.stack([a32, b32], 1).reshape(-1).copy()).cuda()
+    in64 = torch.from_numpy(np.stack([a64, b64], 1).reshape(-1).copy()).cuda()
+    o32 = torch.empty(3 * n, dtype=torch.float32, device="cuda")
+    o64 = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    _lib.check(_lib.load().lodgs_selftest_arith(in32.data_ptr(), in64.data_ptr(), n, o32.data_ptr(), o64.data_ptr(),
+                                                torch.cuda.current_stream().cuda_stream), "selftest")
+    torch.cuda.synchronize()
+    r32 = o32.cpu().numpy().reshape(n, 3)
+    r64 = o64.cpu().numpy().reshape(n, 2)
+    assert np.array_equal((a32 / b32).view(np.uint32), r32[:, 0].view(np.uint32))
+    assert np.array_equal(np.sqrt(np.abs(a32)).view(np.uint32), r32[:, 1].view(np.uint32))
+    assert np.array_equal(oracle.pexp(a32).view(np.uint32), r32[:, 2].view(np.uint32))
+    assert np.array_equal((a64 / b64).view(np.uint64), r64[:, 0].view(np.uint64))
+    assert np.array_equal(np.sqrt(np.abs(a64)).view(np.uint64), r64[:, 1].view(np.uint64))
+
+
+def test_l1_loss_kernel(torch_cuda):
+    import torch
+    from paper_2507_01110_amd.lodgs import Frame
+    tree = scenegen.build_tree(configs.tiny_spec(n=256))
+    S = _scene(tree)
+    f = Frame(S, 1024, 4096, 64, 64)
+    img = torch.rand(64, 64, 3, device="cuda")
+    tgt = torch.rand(64, 64, 3, device="cuda")
+    tgt[0, 0] = img[0, 0]
+    loss = torch.zeros(1, device="cuda")
+    g = f.l1_loss(img, tgt, loss=loss)
+    d = (img - tgt).double()
+    assert torch.equal(g, (torch.sign(d) / d.numel()).float())
+    assert abs(float(loss) - float(d.abs().mean())) < 1e-6
+
+
 def test_select_tiny_bitexact(torch_cuda):
     tree = scenegen.build_tree(configs.tiny_spec())
     O = oracle.OracleScene(tree)

@@ -128,9 +128,8 @@ def test_tile_rectangle_matches_bruteforce_square_intersection(tiny_tree, tiny_o
     TX = TY = 32
     txs = np.arange(TX)
     for i in range(0, len(ids), 7):
-        if sp["tiles"][i] == 0 and not np.isfinite(sp["f32"][i, 0]):
-            continue
-        mx, my, r = (float(v) for v in sp["f32"][i, [0, 1, 6]])
+        f = sp["f32"][i].astype(np.float64)
+        mx, my, r = f[0] + f[1], f[2] + f[3], f[9]
         if r == 0:
             continue
         xs = txs[(txs * 16 <= mx + r) & ((txs + 1) * 16 > mx - r)]
