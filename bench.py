@@ -77,6 +77,37 @@ def stage_bytes(c, H, W, n_coef):
     return b
 
 
+def serve_bench(scene, n_per_rate, rates=(50.0, 200.0, 800.0), max_slots=8, warmup=50):
+    """Serving on the resident scene: Poisson arrivals at each rate, image size
+    uniform over 360p/720p/1080p/4K, random poses, tau in {0.5, 1, 2}, forward only;
+    the slot server (graph replays on per-slot streams) against the
+    one-request-per-launch loop on the identical arrival trace."""
+    import numpy as np
+    from scenegen import configs
+    from paper_2507_01110_amd.lodgs import Frame
+    from paper_2507_01110_amd.server import RenderServer, baseline_loop, poisson_requests, summarize, Request
+    sizes = list(configs.SERVE_RESOLUTIONS)
+    ext = 2000.0
+    rng0 = np.random.default_rng(303)
+    srv = RenderServer(scene, sizes, 1 << 23, 24 << 20, max_slots=max_slots,
+                       template_cam=lambda w, h: configs.random_pose_camera(rng0, ext, w, h))
+    base_frame = Frame(scene, 1 << 23, 24 << 20, 3840, 2160)
+    out = {"slots": len(srv.slots), "slot_GB": round(srv.slot_bytes_estimate / 1e9, 2), "rates": {}}
+    for k, lam in enumerate(rates):
+        n = n_per_rate[k] if isinstance(n_per_rate, (list, tuple)) else n_per_rate
+        rng = np.random.default_rng(300 + k)
+        make = lambda r: configs.random_pose_camera(r, ext, *sizes[r.integers(len(sizes))])
+        reqs = poisson_requests(rng, lam, n + warmup, make)
+        base = [Request(r.rid, r.arrival, r.cam, r.tau) for r in reqs]
+        got, span, _ = srv.run(reqs)
+        bl, span_b, _ = baseline_loop(base_frame, base)
+        out["rates"][str(int(lam))] = {"server": summarize(got, span, warmup),
+                                       "baseline": summarize(bl, span_b, warmup)}
+        log(f"serve lambda {lam}: server {out['rates'][str(int(lam))]['server']} "
+            f"baseline {out['rates'][str(int(lam))]['baseline']}")
+    return out
+
+
 def cpu_baseline(tree, cam, tau, target):
     """The oracle on one view of the same workload (select, render, L1, backward)."""
     import numpy as np
@@ -105,6 +136,11 @@ def main():
     ap.add_argument("--leaves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--targets", type=int, default=8, help="distinct seeded targets resident in HBM")
+    ap.add_argument("--diag", action="store_true", help="print per-tile load statistics of sampled views")
+    ap.add_argument("--serve-requests", type=str, default="250,500,1000",
+                    help="measured requests per arrival rate 50,200,800 req/s (0 disables serving)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy (HBM byte-counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -133,6 +169,15 @@ def main():
     stride = max(1, len(views) // K) if K < len(views) else 1
     seq = [(i * stride) % len(views) for i in range(K)]
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 x 1 GiB device-to-device copies")
+
     # Counting pass (untimed): per-view counts for the byte model and capacities.
     cap_sel, cap_inst = min(scene.n_nodes, 1 << 24), 1 << 27
     frame = Frame(scene, cap_sel, cap_inst, W, H)
@@ -153,6 +198,12 @@ def main():
             frame = Frame(scene, cap_sel, cap_inst, W, H)
         ev, co = frame.blend_work()
         st["evaluations"], st["contributions"] = ev, co
+        if args.diag and len(counts) % max(1, K // 12) == 0:
+            tl, _ = frame.instances()
+            per_tile = torch.bincount(tl.long(), minlength=(W // 16 + 1) * (H // 16 + 1)).cpu().numpy()
+            log(f"view {v}: tau {tau} selected {st['n_selected']} drawn {st['n_drawn']} instances "
+                f"{st['n_instances']} per-tile max {per_tile.max()} p99 {np.percentile(per_tile, 99):.0f} "
+                f"mean {per_tile.mean():.1f} tiles>1000 {(per_tile > 1000).sum()} evals {ev} contrib {co}")
         counts.append(st)
     log(f"counting pass done: mean n_selected {np.mean([c['n_selected'] for c in counts]):.0f}, "
         f"mean instances {np.mean([c['n_instances'] for c in counts]):.0f}")
@@ -219,6 +270,12 @@ def main():
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
 
+    serving = None
+    nreq = [int(x) for x in args.serve_requests.split(",") if x.strip()]
+    if args.workload == "city" and nreq and all(x > 0 for x in nreq):
+        del frame
+        torch.cuda.empty_cache()
+        serving = serve_bench(scene, nreq)
     cpu = None
     if not args.no_cpu_baseline and args.workload == "city":
         mid = 256 + 128  # pose 128 at tau = 1
@@ -245,6 +302,7 @@ def main():
                                                        "n_drawn", "n_instances", "evaluations", "contributions")},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

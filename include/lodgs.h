@@ -214,6 +214,25 @@ int lodgs_frame_read_instances(lodgs_frame* frame, int32_t* d_tile, int32_t* d_p
 /* Clears the recorded device error of the frame. */
 int lodgs_frame_clear_status(lodgs_frame* frame, lodgs_stream stream);
 
+/* ---------------------------------------------------------------- graphs
+ * A forward view (lod_select + render) captured once into a HIP graph and
+ * replayed for any camera of the same image size and any tau.  All counts
+ * stay on the device, so the graph never needs the host between stages; a
+ * replay updates only the two nodes that load the per-view constants.
+ * Capture requires a non-default stream and a frame not in timing mode; the
+ * graph reuses the frame, d_idx, d_count and d_rgb of the capture (they must
+ * outlive it), so replays of one graph (or graphs of one frame) must not
+ * overlap.  The serving loop keeps one frame, stream and graph set per slot. */
+typedef struct lodgs_graph lodgs_graph;
+
+int lodgs_graph_capture_view(lodgs_frame* frame, const lodgs_camera* cam, float tau, uint32_t flags,
+                             int32_t* d_idx, int64_t capacity, int32_t* d_count, const float bg[3], float* d_rgb,
+                             lodgs_stream stream, lodgs_graph** out);
+/* Replays the graph for cam (same width and height as captured) and tau on
+ * stream; LODGS_E_INVALID for another image size. */
+int lodgs_graph_launch(lodgs_graph* graph, const lodgs_camera* cam, float tau, lodgs_stream stream);
+void lodgs_graph_destroy(lodgs_graph* graph);
+
 /* ---------------------------------------------------------------- timing
  * Timing mode brackets every stage of lod_select / render / render_backward
  * with HIP events on the call's stream.  lodgs_frame_timings blocks until

@@ -83,6 +83,8 @@ def lib():
         L.orc_frame_get_pixel_counts.argtypes = [P, P]
         L.orc_frame_get_values64.argtypes = [P, P]
         L.orc_project64_one.argtypes = [P, ctypes.c_int, ctypes.POINTER(OrcCamera), P]
+        L.orc_fd_directional.argtypes = [P, P, i64, P, ctypes.c_double, P]
+        L.orc_fd_directional.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -242,6 +244,18 @@ class OracleFrame:
         img = np.zeros_like(self.image)
         lib().orc_eval_frozen(self._h, _p(np.ascontiguousarray(P, np.float64)), _p(img))
         return img
+
+    def fd_directional(self, W: np.ndarray, i: int, v: np.ndarray, h: float) -> float:
+        """Central difference along v of sum(W * image) for the parameters of
+        selected splat i (decisions frozen, FP64), recompositing only the
+        pixels that splat contributes to."""
+        out = ctypes.c_double(0.0)
+        self._W = np.ascontiguousarray(W, np.float64)
+        rc = lib().orc_fd_directional(self._h, _p(self._W), int(i), _p(np.ascontiguousarray(v, np.float64)),
+                                      float(h), ctypes.byref(out))
+        if rc != 0:
+            raise RuntimeError(f"orc_fd_directional failed ({rc})")
+        return out.value
 
     def backward(self, dL_dimg: np.ndarray):
         n = len(self.ids)

@@ -632,6 +632,10 @@ typedef struct orc_frame {
   uint8_t* pix_clamp;
   /* decision log */
   int64_t skip_1ulp, stop_1ulp, skip_flip64, stop_flip64, clamp_flip64;
+  /* lazily built for directional finite differences */
+  orc_g64* g64;       /* [n] FP64 values of the unperturbed splats */
+  int64_t* gpix_off;  /* [n + 1] pixels each splat contributes to (CSR) */
+  int64_t* gpix;
 } orc_frame;
 
 typedef struct { uint32_t tile, depth; int32_t pos; } orc_inst;
@@ -698,6 +702,7 @@ void orc_frame_free(orc_frame* F) {
   if (!F) return;
   free(F->P); free(F->g32); free(F->inst_tile); free(F->inst_pos); free(F->tile_start);
   free(F->pix_off); free(F->pix_list); free(F->pix_clamp);
+  free(F->g64); free(F->gpix_off); free(F->gpix);
   free(F);
 }
 
@@ -819,6 +824,70 @@ static void eval64(const orc_frame* F, const double* P, double* image, orc_g64* 
  * frame's decisions frozen; colour clamps are re-derived from P. */
 int orc_eval_frozen(const orc_frame* F, const double* P, double* image) {
   eval64(F, P, image, NULL);
+  return 0;
+}
+
+/* Directional central difference of f(P) = sum(W * image(P)) along v for the
+ * parameters of selected splat i only, decisions frozen, in FP64:
+ *   (f(P + h v) - f(P - h v)) / (2 h).
+ * Only the pixels that splat i contributes to change, so only those are
+ * recomposited.  W: [H][W][3]; v: [11 + n_coef]. */
+static int build_fd_index(orc_frame* F) {
+  const int np = 11 + F->n_coef;
+  const int64_t npx = (int64_t)F->W * F->H, tot = F->pix_off[npx];
+  F->g64 = (orc_g64*)malloc(sizeof(orc_g64) * (size_t)(F->n > 0 ? F->n : 1));
+  F->gpix_off = (int64_t*)calloc((size_t)F->n + 1, sizeof(int64_t));
+  F->gpix = (int64_t*)malloc(sizeof(int64_t) * (size_t)(tot > 0 ? tot : 1));
+  if (!F->g64 || !F->gpix_off || !F->gpix) return -1;
+  for (int64_t i = 0; i < F->n; ++i)
+    if (F->g32[i].visible) orc_project64(F->P + i * np, F->n_coef, &F->cam, F->g64 + i);
+  for (int64_t e = 0; e < tot; ++e) F->gpix_off[F->pix_list[e] + 1]++;
+  for (int64_t i = 0; i < F->n; ++i) F->gpix_off[i + 1] += F->gpix_off[i];
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(F->n > 0 ? F->n : 1));
+  if (!fill) return -1;
+  memcpy(fill, F->gpix_off, sizeof(int64_t) * (size_t)F->n);
+  for (int64_t p = 0; p < npx; ++p)
+    for (int64_t e = F->pix_off[p]; e < F->pix_off[p + 1]; ++e) F->gpix[fill[F->pix_list[e]]++] = p;
+  free(fill);
+  return 0;
+}
+
+static double pixel_dot(const orc_frame* F, int64_t p, int64_t i, const orc_g64* Gi, const double* W) {
+  double px = (double)(p % F->W) + 0.5, py = (double)(p / F->W) + 0.5;
+  double T = 1.0, C[3] = {0, 0, 0};
+  for (int64_t e = F->pix_off[p]; e < F->pix_off[p + 1]; ++e) {
+    const orc_g64* G = F->pix_list[e] == i ? Gi : F->g64 + F->pix_list[e];
+    double dx = px - G->mx, dy = py - G->my;
+    double power = -0.5 * (G->ca * dx * dx + G->cc * dy * dy) - G->cb * dx * dy;
+    double alpha = F->pix_clamp[e] ? 0.99 : G->o * exp(power);
+    for (int ch = 0; ch < 3; ++ch) C[ch] += G->rgb[ch] * alpha * T;
+    T *= 1.0 - alpha;
+  }
+  double acc = 0.0;
+  for (int ch = 0; ch < 3; ++ch) acc += W[3 * p + ch] * (C[ch] + T * F->bg[ch]);
+  return acc;
+}
+
+int orc_fd_directional(orc_frame* F, const double* W, int64_t i, const double* v, double h, double* out) {
+  if (i < 0 || i >= F->n) return -1;
+  if (!F->g64 && build_fd_index(F) != 0) return -2;
+  *out = 0.0;
+  if (!F->g32[i].visible) return 0;
+  const int np = 11 + F->n_coef;
+  double* P = (double*)malloc(sizeof(double) * (size_t)np);
+  if (!P) return -2;
+  orc_g64 Gp, Gm;
+  for (int k = 0; k < np; ++k) P[k] = F->P[i * np + k] + h * v[k];
+  orc_project64(P, F->n_coef, &F->cam, &Gp);
+  for (int k = 0; k < np; ++k) P[k] = F->P[i * np + k] - h * v[k];
+  orc_project64(P, F->n_coef, &F->cam, &Gm);
+  free(P);
+  double acc = 0.0;
+  for (int64_t e = F->gpix_off[i]; e < F->gpix_off[i + 1]; ++e) {
+    const int64_t p = F->gpix[e];
+    acc += pixel_dot(F, p, i, &Gp, W) - pixel_dot(F, p, i, &Gm, W);
+  }
+  *out = acc / (2.0 * h);
   return 0;
 }
 

@@ -74,6 +74,10 @@ EXPORTS = {
     "lodgs_frame_blend_work": ([c_p, ctypes.POINTER(i64), ctypes.POINTER(i64), c_p], ctypes.c_int),
     "lodgs_l1_loss": ([c_p, c_p, c_p, i64, c_p, c_p, c_p], ctypes.c_int),
     "lodgs_selftest_arith": ([c_p, c_p, i64, c_p, c_p, c_p], ctypes.c_int),
+    "lodgs_graph_capture_view": ([c_p, ctypes.POINTER(Camera), f32, ctypes.c_uint32, c_p, i64, c_p, c_p, c_p, c_p,
+                                  ctypes.POINTER(c_p)], ctypes.c_int),
+    "lodgs_graph_launch": ([c_p, ctypes.POINTER(Camera), f32, c_p], ctypes.c_int),
+    "lodgs_graph_destroy": ([c_p], None),
     "lodgs_last_error": ([], ctypes.c_char_p),
 }
 

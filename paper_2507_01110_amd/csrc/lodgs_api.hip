@@ -70,6 +70,14 @@ void stage_end(lodgs_frame* f, hipStream_t st) {
   f->open_event = nullptr;
 }
 
+namespace {
+__global__ void k_set_view(ViewConst v, ViewConst* dst) { *dst = v; }
+}  // namespace
+
+void launch_set_view(const ViewConst& v, ViewConst* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_view, dim3(1), dim3(1), 0, st, v, dst);
+}
+
 void launch_blend_count(lodgs_frame* f, hipStream_t st);
 void launch_l1_loss(const float* img, const float* target, int64_t n, float* grad, float* loss, hipStream_t st);
 
@@ -119,9 +127,9 @@ void free_frame(lodgs_frame* f) {
     (void)hipEventDestroy(r.b);
   }
   if (f->open_event) (void)hipEventDestroy(f->open_event);
-  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->chunk,
+  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->chunk, f->seg,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->rect,
-                  f->ikey, f->ival, f->ikey2, f->ival2, f->ranges, f->grad2d};
+                  f->ikey, f->ival, f->ikey2, f->ival2, f->ranges, f->grad2d, f->d_view_sel, f->d_view_ren};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete f;
@@ -195,6 +203,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(spt_X, (size_t)S.n_spt);
   A(spt_off, (size_t)S.n_spt);
   A(chunk, lodgs::kScanGrid + 1);
+  A(seg, (size_t)(S.n_upper + 63) / 64 + (size_t)S.n_spt + (size_t)S.n_nodes / 512 + 1);
   A(splats, ns);
   A(depth_key, ns);
   A(depth_key2, ns);
@@ -210,6 +219,8 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(ranges, nt);
   A(grad2d, 9 * ns);
   A(work, 2);
+  A(d_view_sel, 1);
+  A(d_view_ren, 1);
 #undef A
   if (e != hipSuccess) {
     free_frame(f);
@@ -380,6 +391,120 @@ int lodgs_selftest_arith(const float* d_in32, const double* d_in64, int64_t n, f
                      d_out32, d_out64);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_selftest_arith");
+}
+
+}  // extern "C"
+
+struct lodgs_graph {
+  lodgs_frame* frame;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipGraphNode_t node_sel, node_ren;
+  hipKernelNodeParams p_sel, p_ren;
+  int32_t width, height;
+};
+
+extern "C" {
+
+void lodgs_graph_destroy(lodgs_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_t flags, int32_t* d_idx,
+                             int64_t capacity, int32_t* d_count, const float bg[3], float* d_rgb,
+                             lodgs_stream stream, lodgs_graph** out) {
+  if (!f || !d_idx || !d_count || !d_rgb || !out || !stream)
+    return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: null argument (a non-default stream is required)");
+  *out = nullptr;
+  if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: bad camera");
+  if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: bad tau");
+  if (capacity < 0 || capacity > (int64_t)INT32_MAX || (flags & ~LODGS_CULL))
+    return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: bad capacity or flags");
+  if (cam->width > f->caps.max_width || cam->height > f->caps.max_height)
+    return set_error(LODGS_E_CAPACITY, "lodgs_graph_capture_view: image larger than the frame's capacity");
+  if (f->timing) return set_error(LODGS_E_STATE, "lodgs_graph_capture_view: frame is in timing mode");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  lodgs_graph* g = new (std::nothrow) lodgs_graph();
+  if (!g) return set_error(LODGS_E_OOM, "lodgs_graph_capture_view: out of host memory");
+  g->frame = f;
+  g->width = cam->width;
+  g->height = cam->height;
+  float b[3] = {0.0f, 0.0f, 0.0f};
+  if (bg)
+    for (int k = 0; k < 3; ++k) b[k] = bg[k];
+  const lodgs::ViewConst vs = lodgs::make_view(*cam, tau), vr = lodgs::make_view(*cam, 0.0f);
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "lodgs_graph_capture_view: begin capture");
+  }
+  lodgs::launch_select(f, vs, flags, d_idx, capacity, d_count, st);
+  lodgs::launch_render(f, d_idx, d_count, vr, b, d_rgb, st);
+  e = hipStreamEndCapture(st, &g->graph);
+  if (e != hipSuccess) {
+    lodgs_graph_destroy(g);
+    return hip_fail(e, "lodgs_graph_capture_view: end capture");
+  }
+  size_t nn = 0;
+  e = hipGraphGetNodes(g->graph, nullptr, &nn);
+  std::vector<hipGraphNode_t> nodes(nn);
+  if (e == hipSuccess && nn) e = hipGraphGetNodes(g->graph, nodes.data(), &nn);
+  for (size_t k = 0; e == hipSuccess && k < nn; ++k) {
+    hipGraphNodeType ty;
+    if (hipGraphNodeGetType(nodes[k], &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams p;
+    if (hipGraphKernelNodeGetParams(nodes[k], &p) != hipSuccess) continue;
+    if (p.func != reinterpret_cast<void*>(&lodgs::k_set_view)) continue;
+    lodgs::ViewConst* dst = *reinterpret_cast<lodgs::ViewConst**>(p.kernelParams[1]);
+    if (dst == f->d_view_sel) {
+      g->node_sel = nodes[k];
+      g->p_sel = p;
+    } else if (dst == f->d_view_ren) {
+      g->node_ren = nodes[k];
+      g->p_ren = p;
+    }
+  }
+  if (e == hipSuccess && (!g->node_sel || !g->node_ren)) {
+    lodgs_graph_destroy(g);
+    return set_error(LODGS_E_STATE, "lodgs_graph_capture_view: view nodes not found in the captured graph");
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    lodgs_graph_destroy(g);
+    return hip_fail(e, "lodgs_graph_capture_view: instantiate");
+  }
+  f->rendered = true;
+  f->r_idx = d_idx;
+  f->r_count = d_count;
+  f->r_rgb = d_rgb;
+  std::memcpy(f->bg, b, sizeof b);
+  f->view = vr;
+  *out = g;
+  return LODGS_OK;
+}
+
+int lodgs_graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, lodgs_stream stream) {
+  if (!g || !camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: bad argument");
+  if (cam->width != g->width || cam->height != g->height)
+    return set_error(LODGS_E_INVALID, "lodgs_graph_launch: image size differs from the captured one");
+  if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: bad tau");
+  lodgs::ViewConst vs = lodgs::make_view(*cam, tau), vr = lodgs::make_view(*cam, 0.0f);
+  lodgs::ViewConst* ds = g->frame->d_view_sel;
+  lodgs::ViewConst* dr = g->frame->d_view_ren;
+  void* args_s[2] = {&vs, &ds};
+  void* args_r[2] = {&vr, &dr};
+  hipKernelNodeParams ps = g->p_sel, pr = g->p_ren;
+  ps.kernelParams = args_s;
+  pr.kernelParams = args_r;
+  hipError_t e = hipGraphExecKernelNodeSetParams(g->exec, g->node_sel, &ps);
+  if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->node_ren, &pr);
+  if (e == hipSuccess) e = hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lodgs_graph_launch");
+  g->frame->view = vr;
+  return LODGS_OK;
 }
 
 int lodgs_frame_clear_status(lodgs_frame* f, lodgs_stream stream) {

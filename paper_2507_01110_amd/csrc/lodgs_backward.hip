@@ -3,9 +3,13 @@
 // gradient of every contributing (splat, pixel) pair is formed on the fly,
 // using the final pixel colour to obtain the colour behind each splat
 // (S_i = C_final - C_prefix_i - c_i alpha_i T_i).  Per-splat sums over the
-// pixels of a wave are reduced with lane shuffles and added with one atomic
-// per wave and value.  Then one thread per rendered node carries the 2D
-// gradients through the conic inverse, the EWA Jacobian, the camera
+// tile's pixels are gathered in LDS for each batch of 256 splats (LDS atomics
+// from the contributing lanes when a wave has at most four of them, else a
+// DPP reduction across the wave and one LDS atomic) and flushed with one
+// global atomic per splat, tile and value.  A wave skips
+// a splat whose alpha >= 1/255 box misses the wave's 16x4 pixels (its result
+// there is known to be "skip").  Then one thread per rendered node carries
+// the 2D gradients through the conic inverse, the EWA Jacobian, the camera
 // transform, the covariance factorisation, the quaternion normalisation, the
 // sigmoid and the SH basis to the raw parameters.
 #include "lodgs_internal.h"
@@ -19,16 +23,21 @@ __device__ __forceinline__ float wave_sum(float x) {
   return x;
 }
 
-__global__ void __launch_bounds__(256) k_blend_bwd(ViewConst v, const uint2* ranges, const uint32_t* ival,
+__global__ void __launch_bounds__(256) k_blend_bwd(const ViewConst* __restrict__ vp, const uint2* ranges, const uint32_t* ival,
                                                    const Splat* splats, const FrameCounters* ctr, const float* rgb,
                                                    const float* dL, float* grad2d) {
+  const ViewConst v = *vp;
   __shared__ Splat batch[256];
   __shared__ uint32_t bid[256];
+  __shared__ float acc[9][256];
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
   const bool inside = px < v.width && py < v.height;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  // pixel-centre rectangle of this wave (16 x 4 pixels)
+  const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + 15.0f;
+  const float wy0 = (float)(ty * kTile + 4 * (threadIdx.x >> 6)) + 0.5f, wy1 = wy0 + 3.0f;
   const uint2 rg = ranges[tile];
   const uint32_t nr = (uint32_t)ctr->n_render;
   float Cf[3] = {0.0f, 0.0f, 0.0f}, G[3] = {0.0f, 0.0f, 0.0f};
@@ -39,6 +48,8 @@ __global__ void __launch_bounds__(256) k_blend_bwd(ViewConst v, const uint2* ran
       G[c] = dL[p + c];
     }
   }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) acc[c][threadIdx.x] = 0.0f;
   float T = 1.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
   bool done = !inside;
   const float thr = 1.0f / 255.0f;
@@ -53,6 +64,7 @@ __global__ void __launch_bounds__(256) k_blend_bwd(ViewConst v, const uint2* ran
       } else {  // only reachable if the instance count overflowed
         bid[threadIdx.x] = 0;
         batch[threadIdx.x].o = 0.0f;
+        batch[threadIdx.x].ex = -1.0f;
       }
     }
     __syncthreads();
@@ -60,7 +72,8 @@ __global__ void __launch_bounds__(256) k_blend_bwd(ViewConst v, const uint2* ran
     for (int j = 0; j < m; ++j) {
       if (__all(done)) break;  // wave-uniform
       const Splat& s = batch[j];
-      float g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      if (splat_misses(s, wx0, wx1, wy0, wy1)) continue;  // wave-uniform
+      float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
       bool contrib = false;
       if (!done) {
         float dx, dy, u1, u2;
@@ -81,13 +94,12 @@ __global__ void __launch_bounds__(256) k_blend_bwd(ViewConst v, const uint2* ran
             P0 = __builtin_fmaf(s.r, w, P0);
             P1 = __builtin_fmaf(s.g, w, P1);
             P2 = __builtin_fmaf(s.b, w, P2);
-            const float ia = 1.0f / (1.0f - alpha);
+            const float ia = __builtin_amdgcn_rcpf(1.0f - alpha);  // gradient values only
             float dA = G[0] * (s.r * T - (Cf[0] - P0) * ia);
             dA = __builtin_fmaf(G[1], s.g * T - (Cf[1] - P1) * ia, dA);
             dA = __builtin_fmaf(G[2], s.b * T - (Cf[2] - P2) * ia, dA);
             if (oe <= 0.99f) {
               const float dpow = dA * alpha;
-              g[5] = dA * e;
               // d power / d mean2D = Sigma'^-1 (x - mean) = -2 (h1 u1 e1 + h2 u2 e2)
               const float k1 = -2.0f * s.h1 * u1, k2 = -2.0f * s.h2 * u2;
               g[0] = dpow * (k1 * s.ce - k2 * s.se);
@@ -95,17 +107,37 @@ __global__ void __launch_bounds__(256) k_blend_bwd(ViewConst v, const uint2* ran
               g[2] = dpow * (-0.5f * dx * dx);
               g[3] = dpow * (-dx * dy);
               g[4] = dpow * (-0.5f * dy * dy);
+              g[5] = dA * e;
             }
             T = tt;
           }
         }
       }
-      if (__ballot(contrib) == 0ull) continue;
-      float* dst = grad2d + 9 * (int64_t)bid[j];
+      const uint64_t who = __ballot(contrib);
+      if (who == 0ull) continue;
+      if (__popcll(who) <= 4) {  // few lanes: LDS atomics, little contention
+        if (contrib) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) atomicAdd(&acc[c][j], g[c]);
+        }
+      } else {  // many lanes: DPP reduction, one LDS atomic per value
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          const float r = wave_sum_to_lane63(g[c]);
+          if ((threadIdx.x & 63) == 63) atomicAdd(&acc[c][j], r);
+        }
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+      float* dst = grad2d + 9 * (int64_t)bid[threadIdx.x];
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
-        const float r = wave_sum(g[c]);
-        if ((threadIdx.x & 63) == 0 && r != 0.0f) atomicAdd(dst + c, r);
+        const float r = acc[c][threadIdx.x];
+        if (r != 0.0f) {
+          atomicAdd(dst + c, r);
+          acc[c][threadIdx.x] = 0.0f;
+        }
       }
     }
   }
@@ -120,19 +152,35 @@ __global__ void __launch_bounds__(kBlock) k_zero_grad2d(float* p, const FrameCou
 // Projection backward, FP64 (per splat): the forward chain is replayed and the
 // 2D gradients (mean2D, conic, opacity, colour) are carried to the raw
 // parameters.
-__global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, ViewConst v, const int32_t* idx,
-                                                        const FrameCounters* ctr, const float* grad2d,
-                                                        lodgs_grads sel, lodgs_grads nodes) {
+// Zeroes the per-selection gradient rows (splats that were not drawn keep 0).
+__global__ void __launch_bounds__(kBlock) k_zero_sel(const FrameCounters* ctr, int nc, lodgs_grads sel) {
   const int64_t n = ctr->n_render;
-  const int nc = S.n_coef;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (sel.d_means) for (int k = 0; k < 3; ++k) sel.d_means[3 * i + k] = 0.0f;
+    if (sel.d_log_scales) for (int k = 0; k < 3; ++k) sel.d_log_scales[3 * i + k] = 0.0f;
+    if (sel.d_quats) for (int k = 0; k < 4; ++k) sel.d_quats[4 * i + k] = 0.0f;
+    if (sel.d_opacity_logits) sel.d_opacity_logits[i] = 0.0f;
+    if (sel.d_sh) for (int k = 0; k < nc; ++k) sel.d_sh[(int64_t)nc * i + k] = 0.0f;
+  }
+}
+
+// One thread per drawn splat: the drawn splats lead the depth order, so
+// order[0 .. n_drawn) lists exactly them (no lanes idle on culled ones).
+__global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
+                                                        const FrameCounters* ctr, const uint32_t* order,
+                                                        const float* grad2d, lodgs_grads sel, lodgs_grads nodes) {
+  const ViewConst v = *vp;
+  const int64_t n = ctr->n_drawn;
+  const int nc = S.n_coef;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = order[r];
     const int64_t node = idx[i];
     double gm[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
-    float gsh[48];
-    for (int k = 0; k < nc; ++k) gsh[k] = 0.0f;
     Proj64 P;
     const bool visible = proj_chain64(S.means, S.log_scales, S.quats, v, node, P);
     const float* g2 = grad2d + 9 * i;
+    float* sel_sh = sel.d_sh ? sel.d_sh + (int64_t)nc * i : nullptr;
+    float* node_sh = nodes.d_sh ? nodes.d_sh + (int64_t)nc * node : nullptr;
     if (visible) {
       // colour -> SH coefficients and view direction
       const double mx = S.means[3 * node], my = S.means[3 * node + 1], mz = S.means[3 * node + 2];
@@ -157,7 +205,9 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, ViewConst v,
       for (int k = 0; k < nb; ++k) {
         double a = 0.0;
         for (int c = 0; c < 3; ++c) {
-          gsh[3 * k + c] = (float)(dRGB[c] * (double)Y[k]);
+          const float gk = (float)(dRGB[c] * (double)Y[k]);
+          if (sel_sh) sel_sh[3 * k + c] = gk;
+          if (node_sh) node_sh[3 * k + c] += gk;
           a += dRGB[c] * (double)shc[3 * k + c];
         }
         dd[0] += a * (double)dY[k][0];
@@ -239,13 +289,11 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, ViewConst v,
     if (sel.d_log_scales) for (int k = 0; k < 3; ++k) sel.d_log_scales[3 * i + k] = (float)gls[k];
     if (sel.d_quats) for (int k = 0; k < 4; ++k) sel.d_quats[4 * i + k] = (float)gq[k];
     if (sel.d_opacity_logits) sel.d_opacity_logits[i] = (float)go;
-    if (sel.d_sh) for (int k = 0; k < nc; ++k) sel.d_sh[(int64_t)nc * i + k] = gsh[k];
     if (!visible) continue;
     if (nodes.d_means) for (int k = 0; k < 3; ++k) nodes.d_means[3 * node + k] += (float)gm[k];
     if (nodes.d_log_scales) for (int k = 0; k < 3; ++k) nodes.d_log_scales[3 * node + k] += (float)gls[k];
     if (nodes.d_quats) for (int k = 0; k < 4; ++k) nodes.d_quats[4 * node + k] += (float)gq[k];
     if (nodes.d_opacity_logits) nodes.d_opacity_logits[node] += (float)go;
-    if (nodes.d_sh) for (int k = 0; k < nc; ++k) nodes.d_sh[(int64_t)nc * node + k] += gsh[k];
   }
 }
 
@@ -256,13 +304,14 @@ void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, 
   stage_begin(f, LODGS_STAGE_BLEND_BWD, st);
   hipLaunchKernelGGL(k_zero_grad2d, dim3(2048), dim3(kBlock), 0, st, f->grad2d, f->ctr);
   const int ntiles = v.tiles_x * v.tiles_y;
-  hipLaunchKernelGGL(k_blend_bwd, dim3(ntiles), dim3(256), 0, st, v, f->ranges, f->sorted_ival, f->splats, f->ctr,
+  hipLaunchKernelGGL(k_blend_bwd, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival, f->splats, f->ctr,
                      f->r_rgb, d_dL, f->grad2d);
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_PROJECT_BWD, st);
   lodgs_grads none{nullptr, nullptr, nullptr, nullptr, nullptr};
-  hipLaunchKernelGGL(k_project_bwd, dim3(2048), dim3(kBlock), 0, st, S, v, f->r_idx, f->ctr, f->grad2d,
-                     sel ? *sel : none, nodes ? *nodes : none);
+  if (sel) hipLaunchKernelGGL(k_zero_sel, dim3(1024), dim3(kBlock), 0, st, f->ctr, S.n_coef, *sel);
+  hipLaunchKernelGGL(k_project_bwd, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
+                     f->sorted_order, f->grad2d, sel ? *sel : none, nodes ? *nodes : none);
   stage_end(f, st);
 }
 

@@ -120,6 +120,14 @@ __device__ __forceinline__ float splat_power(const Splat& s, float px, float py,
   return __builtin_fmaf(s.h1 * u1, u1, a2);
 }
 
+// True when alpha < 1/255 is certain for every pixel centre in [x0, x1] x
+// [y0, y1] (the splat's box, with its margins, misses the rectangle, or the
+// opacity alone is below 1/255).  Skipping such a splat leaves every result
+// unchanged.
+__device__ __forceinline__ bool splat_misses(const Splat& s, float x0, float x1, float y0, float y1) {
+  return s.ex < 0.0f || s.mxh + s.ex < x0 || s.mxh - s.ex > x1 || s.myh + s.ey < y0 || s.myh - s.ey > y1;
+}
+
 // Real SH basis constants, l <= 3 (3DGS sign convention).
 constexpr float kSH0 = 0.28209479177387814f;
 constexpr float kSH1 = 0.4886025119029199f;
@@ -180,6 +188,23 @@ __device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z
   dY[14][0] = 2.0f * kSH3_5 * x * z; dY[14][1] = -2.0f * kSH3_5 * y * z; dY[14][2] = kSH3_5 * (xx - yy);
   dY[15][0] = kSH3_6 * (3.0f * xx - 3.0f * yy); dY[15][1] = -6.0f * kSH3_6 * x * y;
 }
+
+// Sum over the 64 lanes of a wave with DPP lane moves, result in lane 63:
+// swaps inside quads, row rotations by 4 and 8 (every lane then holds its
+// 16-lane row's sum), then the row broadcasts 15 and 31 fold the rows into
+// the last one.  Lanes that do not take part must pass 0.
+#define LODGS_DPP(x, ctrl, row_mask) \
+  __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, row_mask, 0xf, false))
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += LODGS_DPP(v, 0xB1, 0xf);   // quad_perm [1,0,3,2]
+  v += LODGS_DPP(v, 0x4E, 0xf);   // quad_perm [2,3,0,1]
+  v += LODGS_DPP(v, 0x124, 0xf);  // row_ror 4
+  v += LODGS_DPP(v, 0x128, 0xf);  // row_ror 8
+  v += LODGS_DPP(v, 0x142, 0xa);  // row_bcast 15 into rows 1 and 3
+  v += LODGS_DPP(v, 0x143, 0xc);  // row_bcast 31 into rows 2 and 3
+  return v;
+}
+#undef LODGS_DPP
 
 // Grid-stride bounds for kernels whose element count lives in device memory.
 __device__ __forceinline__ int64_t clamp_count(const int32_t* d_n, int64_t cap) {

@@ -45,7 +45,9 @@ struct FrameCounters {
   int32_t sort_table_n;  // constant 256 * kSortGrid
   int32_t upper_plus_high;
   int32_t spt_count;     // constant n_spt
-  int32_t pad[4];
+  int32_t n_chunks;      // SPT candidate chunks of the last select
+  int32_t seg_total;     // compaction segments of the last select
+  int32_t pad[2];
 };
 
 struct lodgs_frame {
@@ -61,6 +63,7 @@ struct lodgs_frame {
   float* spt_X;           // [n_spt]
   uint32_t* spt_off;      // [n_spt]
   uint32_t* chunk;        // [kScanGrid + 1]
+  uint32_t* seg;          // [ceil(n_upper/64) + n_spt + n_nodes/512 + 1]
   // render
   lodgs::Splat* splats;   // [max_selected]
   uint32_t* depth_key;    // [max_selected]
@@ -75,6 +78,8 @@ struct lodgs_frame {
   uint32_t* ikey2;
   uint32_t* ival2;
   uint2* ranges;          // [max tiles]
+  lodgs::ViewConst* d_view_sel;  // view constants of the last lod_select (device)
+  lodgs::ViewConst* d_view_ren;  // view constants of the last render (device)
   float* grad2d;          // [max_selected][9]
   // state of the last render
   bool rendered;
@@ -85,6 +90,7 @@ struct lodgs_frame {
   lodgs::ViewConst view;
   const uint32_t* sorted_ival;  // the buffer holding the final instance order
   const uint32_t* sorted_ikey;
+  const uint32_t* sorted_order;  // selection positions in depth order (drawn ones first)
   // timing mode: one (stage, start, end) event pair per stage and call
   bool timing;
   struct TimedStage {
@@ -98,6 +104,11 @@ struct lodgs_frame {
 };
 
 namespace lodgs {
+
+// Writes the per-view constants to the frame's device slot (one thread): the
+// kernels of a stage read them from there, so a captured graph is replayed
+// for another camera by updating this one node's argument.
+void launch_set_view(const ViewConst& v, ViewConst* dst, hipStream_t st);
 
 int hip_fail(hipError_t e, const char* what);
 

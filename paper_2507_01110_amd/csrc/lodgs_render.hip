@@ -4,7 +4,7 @@
 //  k_project  one thread per selected node: camera transform, near-plane test,
 //             covariance from (scale, rotation), EWA Jacobian, projected
 //             covariance + 0.3 px^2, conic, square footprint, tile rectangle,
-//             opacity, SH colour.  Writes a 48-byte Splat record, the depth key
+//             opacity, SH colour.  Writes a 64-byte Splat record, the depth key
 //             and the tile count.
 //  sort       stable radix sort of the selected splats by FP32 depth bits, then
 //             (k_dup) one (tile, splat) instance per covered tile emitted in
@@ -13,7 +13,8 @@
 //             ties by selection order, with far less key traffic.
 //  k_ranges   first/last instance of every tile.
 //  k_blend    one workgroup per tile, one lane per pixel; splat records are
-//             staged in LDS in batches of 256.
+//             staged in LDS in batches of 256; a wave skips a splat whose
+//             alpha >= 1/255 box misses its 16x4 pixels (known result).
 #include "lodgs_internal.h"
 #include "lodgs_proj.h"
 
@@ -120,10 +121,11 @@ __device__ __forceinline__ void sh_color(const SceneDev& S, const ViewConst& v, 
   raw[2] = b;
 }
 
-__global__ void __launch_bounds__(kBlock) k_project(SceneDev S, ViewConst v, const int32_t* idx,
+__global__ void __launch_bounds__(kBlock) k_project(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
                                                     const int32_t* d_count, int64_t cap, Splat* splats,
                                                     uint32_t* depth_key, uint32_t* order, uint32_t* tiles,
                                                     ushort4* rect, FrameCounters* ctr) {
+  const ViewConst v = *vp;
   const int64_t n = clamp_count(d_count, cap);
   int drawn = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -168,24 +170,33 @@ __global__ void k_inst_count(FrameCounters* ctr, int64_t cap) {
   if (n > cap) ctr->status = LODGS_E_CAPACITY;
 }
 
+// One thread per (splat, tile) instance: the owning splat is found by binary
+// search over the instance offsets of the drawn splats (which lead the depth
+// order), so splats covering thousands of tiles cost no more than small ones.
 __global__ void __launch_bounds__(kBlock) k_dup(const FrameCounters* ctr, const uint32_t* order,
-                                                const uint32_t* tiles, const uint32_t* inst_off,
-                                                const ushort4* rect, int32_t tiles_x, int64_t cap,
+                                                const uint32_t* inst_off, const ushort4* rect, int32_t tiles_x,
                                                 uint32_t* ikey, uint32_t* ival) {
-  const int64_t n = ctr->n_render;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t i = order[r];
-    if (tiles[i] == 0) continue;
-    int64_t o = inst_off[r];
+  const int64_t n = ctr->n_inst_clamped;
+  const int32_t nd = ctr->n_drawn;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = nd;  // largest r < nd with inst_off[r] <= k
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (inst_off[mid] <= (uint32_t)k) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t i = order[lo];
+    const uint32_t l = (uint32_t)k - inst_off[lo];
     const ushort4 q = rect[i];
-    for (int ty = q.z; ty < q.w; ++ty)
-      for (int tx = q.x; tx < q.y; ++tx) {
-        if (o < cap) {
-          ikey[o] = (uint32_t)(ty * tiles_x + tx);
-          ival[o] = i;
-        }
-        ++o;
-      }
+    const uint32_t w = (uint32_t)(q.y - q.x);
+    if (w == 0) {  // only reachable if the instance count overflowed
+      ikey[k] = 0xFFFFFFFFu;
+      ival[k] = i;
+      continue;
+    }
+    const uint32_t ty = q.z + l / w, tx = q.x + l % w;
+    ikey[k] = ty * (uint32_t)tiles_x + tx;
+    ival[k] = i;
   }
 }
 
@@ -207,15 +218,19 @@ __global__ void __launch_bounds__(kBlock) k_ranges(const FrameCounters* ctr, con
 // One workgroup per tile, one lane per pixel.  alpha = min(0.99, o e^power),
 // skipped below 1/255; stop before the transmittance would drop below 1e-4.
 template <bool COUNT>
-__global__ void __launch_bounds__(256) k_blend(ViewConst v, const uint2* ranges, const uint32_t* ival,
+__global__ void __launch_bounds__(256) k_blend(const ViewConst* __restrict__ vp, const uint2* ranges, const uint32_t* ival,
                                                const Splat* splats, const FrameCounters* ctr, float bg0, float bg1,
                                                float bg2, float* rgb, unsigned long long* work) {
+  const ViewConst v = *vp;
   __shared__ Splat batch[256];
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
   const bool inside = px < v.width && py < v.height;
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  // pixel-centre rectangle of this wave (16 x 4 pixels)
+  const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + 15.0f;
+  const float wy0 = (float)(ty * kTile + 4 * (threadIdx.x >> 6)) + 0.5f, wy1 = wy0 + 3.0f;
   const uint2 rg = ranges[tile];
   const uint32_t nr = (uint32_t)ctr->n_render;
   float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
@@ -227,14 +242,19 @@ __global__ void __launch_bounds__(256) k_blend(ViewConst v, const uint2* ranges,
     const uint32_t k = b0 + threadIdx.x;
     if (k < rg.y) {
       const uint32_t i = ival[k];
-      if (i < nr) batch[threadIdx.x] = splats[i];
-      else batch[threadIdx.x].o = 0.0f;  // only reachable if the instance count overflowed
+      if (i < nr) {
+        batch[threadIdx.x] = splats[i];
+      } else {  // only reachable if the instance count overflowed
+        batch[threadIdx.x].o = 0.0f;
+        batch[threadIdx.x].ex = -1.0f;
+      }
     }
     __syncthreads();
     const int m = (int)min(256u, rg.y - b0);
     for (int j = 0; j < m && !done; ++j) {
       const Splat& s = batch[j];
       if (COUNT) ++n_eval;
+      else if (splat_misses(s, wx0, wx1, wy0, wy1)) continue;
       float dx, dy, u1, u2;
       const float power = splat_power(s, fx, fy, dx, dy, u1, u2);
       const float alpha = fminf(0.99f, s.o * fexp(power));
@@ -276,22 +296,24 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   const SceneDev& S = f->scene->dev;
   const int64_t cap = f->caps.max_selected, icap = f->caps.max_instances;
   stage_begin(f, LODGS_STAGE_PROJECT, st);
+  launch_set_view(v, f->d_view_ren, st);
   hipLaunchKernelGGL(k_render_begin, dim3(1), dim3(1), 0, st, f->ctr, d_count, cap);
   const int pgrid = 2048;
-  hipLaunchKernelGGL(k_project, dim3(pgrid), dim3(kBlock), 0, st, S, v, d_idx, d_count, cap, f->splats, f->depth_key,
+  hipLaunchKernelGGL(k_project, dim3(pgrid), dim3(kBlock), 0, st, S, f->d_view_ren, d_idx, d_count, cap, f->splats, f->depth_key,
                      f->order, f->tiles, f->rect, f->ctr);
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_DEPTH_SORT, st);
   SortScratch ws{f->sort_table, f->block_sums, &f->ctr->sort_table_n};
   const bool sw = sort_pairs(f->depth_key, f->order, f->depth_key2, f->order2, &f->ctr->n_render, cap, 32, ws, st);
   const uint32_t* order = sw ? f->order2 : f->order;
+  f->sorted_order = order;
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_DUPLICATE, st);
   scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_render, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
   hipLaunchKernelGGL(k_inst_count, dim3(1), dim3(1), 0, st, f->ctr, icap);
-  hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->tiles, f->inst_off, f->rect,
-                     v.tiles_x, icap, f->ikey, f->ival);
+  hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x,
+                     f->ikey, f->ival);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
@@ -306,7 +328,7 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_ikey, f->ranges, (uint32_t)ntiles);
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_BLEND, st);
-  hipLaunchKernelGGL(k_blend<false>, dim3(ntiles), dim3(256), 0, st, v, f->ranges, f->sorted_ival, f->splats, f->ctr,
+  hipLaunchKernelGGL(k_blend<false>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival, f->splats, f->ctr,
                      bg[0], bg[1], bg[2], d_rgb, (unsigned long long*)nullptr);
   stage_end(f, st);
 }
@@ -320,7 +342,7 @@ void launch_blend_count(lodgs_frame* f, hipStream_t st) {
   const ViewConst& v = f->view;
   const int ntiles = v.tiles_x * v.tiles_y;
   hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(1), 0, st, f->work);
-  hipLaunchKernelGGL(k_blend<true>, dim3(ntiles), dim3(256), 0, st, v, f->ranges, f->sorted_ival, f->splats, f->ctr,
+  hipLaunchKernelGGL(k_blend<true>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival, f->splats, f->ctr,
                      0.0f, 0.0f, 0.0f, (float*)nullptr, f->work);
 }
 

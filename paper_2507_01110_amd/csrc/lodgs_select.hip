@@ -9,9 +9,8 @@
 // enough are selected; reached SPT roots that are not culled make their SPT
 // visible, and a binary search over the SPT's r_max (descending) gives the
 // candidate prefix length high_j = #{r_max > X_j}.
-// Step 2: the candidate space (upper nodes, then the prefixes of the visible
-// SPTs laid end to end) is compacted in order with wave ballots: per block
-// counts, a scan of the counts, and an ordered write.
+// Step 2: the candidates (upper nodes, then the prefixes of the visible SPTs)
+// are compacted in order with wave ballots, one wave per segment.
 #include "lodgs_internal.h"
 
 namespace lodgs {
@@ -32,12 +31,13 @@ __device__ __forceinline__ bool chain_reached(const SceneDev& S, const ViewConst
   return true;
 }
 
-__global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, ViewConst v, uint32_t flags,
+__global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewConst* __restrict__ vp, uint32_t flags,
                                                       uint8_t* upper_sel, int32_t* spt_high, float* spt_X,
                                                       FrameCounters* ctr) {
+  const ViewConst v = *vp;
   const bool cull = (flags & LODGS_CULL) != 0;
   const int64_t total = (int64_t)S.n_upper + S.n_spt;
-  int vis = 0;
+  int vis = 0, hsum = 0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     if (e < S.n_upper) {
@@ -65,6 +65,7 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, ViewConst v, u
             else hi = mid;
           }
           high = lo;
+          hsum += lo;
           ++vis;
         }
       }
@@ -73,90 +74,96 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, ViewConst v, u
     }
   }
   // one atomic per wave
-  for (int d = 32; d > 0; d >>= 1) vis += __shfl_xor(vis, d, 64);
-  if ((threadIdx.x & 63) == 0 && vis) atomicAdd(&ctr->n_spt_visible, vis);
-}
-
-// Candidate e of the concatenated space: upper node e (e < n_upper), else
-// element f = e - n_upper of the SPT prefixes.
-struct Candidate {
-  int32_t node;
-  bool sel;
-};
-
-__device__ __forceinline__ Candidate candidate(const SceneDev& S, const uint8_t* upper_sel, const uint32_t* spt_off,
-                                               const float* spt_X, int64_t e) {
-  if (e < S.n_upper) return {(int32_t)e, upper_sel[e] != 0};
-  const uint32_t f = (uint32_t)(e - S.n_upper);
-  // largest j with spt_off[j] <= f
-  int32_t lo = 0, hi = S.n_spt;
-  while (hi - lo > 1) {
-    const int32_t mid = (lo + hi) >> 1;
-    if (spt_off[mid] <= f) lo = mid;
-    else hi = mid;
+  for (int d = 32; d > 0; d >>= 1) {
+    vis += __shfl_xor(vis, d, 64);
+    hsum += __shfl_xor(hsum, d, 64);
   }
-  const int32_t node = S.spt_begin[lo] + (int32_t)(f - spt_off[lo]);
-  return {node, S.r_min[node] <= spt_X[lo]};
-}
-
-__global__ void k_set_candidates(FrameCounters* ctr, int32_t n_upper) {
-  ctr->upper_plus_high = n_upper + ctr->sum_high;
-}
-
-__global__ void __launch_bounds__(kBlock) k_compact_count(SceneDev S, const uint8_t* upper_sel,
-                                                          const uint32_t* spt_off, const float* spt_X,
-                                                          const FrameCounters* ctr, uint32_t* chunk) {
-  __shared__ uint32_t wt[kBlock / 64];
-  const Segment s = block_segment(ctr->upper_plus_high, kScanGrid);
-  uint32_t c = 0;
-  for (int64_t e = s.begin + threadIdx.x; e < s.end; e += kBlock) c += candidate(S, upper_sel, spt_off, spt_X, e).sel;
-  uint32_t tot;
-  block_exclusive_scan(c, wt, &tot);
-  if (threadIdx.x == 0) chunk[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(kBlock) k_compact_write(SceneDev S, const uint8_t* upper_sel,
-                                                          const uint32_t* spt_off, const float* spt_X,
-                                                          FrameCounters* ctr, const uint32_t* chunk,
-                                                          int32_t* idx, int64_t capacity, int32_t* d_count) {
-  __shared__ uint32_t wt[kBlock / 64];
-  const Segment s = block_segment(ctr->upper_plus_high, kScanGrid);
-  uint32_t base = chunk[blockIdx.x];
-  for (int64_t r0 = s.begin; r0 < s.end; r0 += kBlock) {
-    const int64_t e = r0 + threadIdx.x;
-    Candidate c{0, false};
-    if (e < s.end) c = candidate(S, upper_sel, spt_off, spt_X, e);
-    uint32_t tot;
-    const uint32_t pos = base + block_exclusive_scan(c.sel ? 1u : 0u, wt, &tot);
-    if (c.sel && pos < capacity) idx[pos] = c.node;
-    base += tot;
+  if ((threadIdx.x & 63) == 0 && vis) {
+    atomicAdd(&ctr->n_spt_visible, vis);
+    atomicAdd(&ctr->sum_high, hsum);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const uint32_t n = chunk[kScanGrid];
-    *d_count = (int32_t)n;
-    ctr->n_selected = (int32_t)n;
+}
+
+// Compaction by segments, one wave per segment: segments 0 .. n_up_chunks-1
+// are 64-node chunks of the upper hierarchy (predicate: selected), the rest
+// are chunks of at most kChunk candidates of the visible SPT prefixes
+// (predicate: r_min <= X_j); an SPT contributes ceil(high_j / kChunk)
+// chunks, located through the scan of those counts.  Pass 1 counts each
+// segment with ballots, a scan turns the counts into output offsets, pass 2
+// writes each segment's selected nodes in order with ballot ranks.  Segments
+// follow the layout order, so the output is ascending.
+constexpr int32_t kChunk = 512;
+
+template <bool WRITE>
+__global__ void __launch_bounds__(kBlock) k_segments(SceneDev S, const uint8_t* upper_sel, const int32_t* spt_high,
+                                                     const float* spt_X, const uint32_t* ch_off, int32_t n_up_chunks,
+                                                     uint32_t* seg, int32_t* idx, int64_t capacity,
+                                                     FrameCounters* ctr, int32_t* d_count) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lanemask_lt();
+  const int64_t nseg = (int64_t)n_up_chunks + ctr->n_chunks;
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  if (!WRITE && blockIdx.x == 0 && threadIdx.x == 0) ctr->seg_total = (int32_t)nseg;
+  uint32_t up_count = 0;
+  for (int64_t sg = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); sg < nseg; sg += nw) {
+    const uint32_t base = WRITE ? seg[sg] : 0u;
+    uint32_t c = 0;
+    if (sg < n_up_chunks) {
+      const int64_t u = sg * 64 + lane;
+      const bool p = u < S.n_upper && upper_sel[u] != 0;
+      const uint64_t b = __ballot(p);
+      if (WRITE && p) {
+        const uint32_t pos = base + (uint32_t)__popcll(b & lt);
+        if (pos < capacity) idx[pos] = (int32_t)u;
+      }
+      c = (uint32_t)__popcll(b);
+      up_count += c;
+    } else {
+      const uint32_t t = (uint32_t)(sg - n_up_chunks);
+      int32_t lo = 0, hi = S.n_spt;  // largest j with ch_off[j] <= t
+      while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (ch_off[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      const int32_t j = lo;
+      const int32_t h = spt_high[j];
+      const int32_t e_begin = (int32_t)(t - ch_off[j]) * kChunk;
+      const int32_t e_end = min(h, e_begin + kChunk);
+      const float X = spt_X[j];
+      const int32_t b0 = S.spt_begin[j];
+      for (int32_t e0 = e_begin; e0 < e_end; e0 += 64) {
+        const int32_t e = e0 + lane;
+        const bool p = e < e_end && S.r_min[b0 + e] <= X;
+        const uint64_t b = __ballot(p);
+        if (WRITE && p) {
+          const uint32_t pos = base + c + (uint32_t)__popcll(b & lt);
+          if (pos < capacity) idx[pos] = b0 + e;
+        }
+        c += (uint32_t)__popcll(b);
+      }
+    }
+    if (!WRITE && lane == 0) seg[sg] = c;
+  }
+  if (!WRITE) {
+    if (lane == 0 && up_count) atomicAdd(&ctr->n_upper_selected, (int)up_count);
+  } else if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int32_t n = ctr->n_selected;
+    *d_count = n;
     if ((int64_t)n > capacity) ctr->status = LODGS_E_CAPACITY;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_count_upper(const uint8_t* upper_sel, int32_t n_upper,
-                                                        FrameCounters* ctr) {
-  int c = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_upper; i += (int64_t)gridDim.x * blockDim.x)
-    c += upper_sel[i];
-  for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(&ctr->n_upper_selected, c);
-}
+struct LoadChunks {
+  const int32_t* high;
+  __device__ uint32_t operator()(int64_t j) const { return (uint32_t)((high[j] + kChunk - 1) / kChunk); }
+};
 
 __global__ void k_reset_select(FrameCounters* ctr) {
   ctr->n_spt_visible = 0;
   ctr->n_upper_selected = 0;
+  ctr->sum_high = 0;
 }
-
-struct LoadHigh {
-  const int32_t* h;
-  __device__ uint32_t operator()(int64_t i) const { return (uint32_t)h[i]; }
-};
 
 }  // namespace
 
@@ -164,26 +171,24 @@ void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* 
                    int32_t* d_count, hipStream_t st) {
   const SceneDev& S = f->scene->dev;
   stage_begin(f, LODGS_STAGE_SELECT, st);
+  launch_set_view(v, f->d_view_sel, st);
   hipLaunchKernelGGL(k_reset_select, dim3(1), dim3(1), 0, st, f->ctr);
   const int64_t total = (int64_t)S.n_upper + S.n_spt;
   int grid = (int)((total + kBlock - 1) / kBlock);
   grid = grid < 1 ? 1 : (grid > 4096 ? 4096 : grid);
-  hipLaunchKernelGGL(k_cut_upper, dim3(grid), dim3(kBlock), 0, st, S, v, flags, f->upper_sel, f->spt_high, f->spt_X,
+  hipLaunchKernelGGL(k_cut_upper, dim3(grid), dim3(kBlock), 0, st, S, f->d_view_sel, flags, f->upper_sel, f->spt_high, f->spt_X,
                      f->ctr);
-  // exclusive scan of the prefix lengths; total -> sum_high
-  scan_exclusive(LoadHigh{f->spt_high}, &f->ctr->spt_count, (int64_t)S.n_spt, f->block_sums, f->spt_off,
-                 &f->ctr->sum_high, st);
-  hipLaunchKernelGGL(k_set_candidates, dim3(1), dim3(1), 0, st, f->ctr, S.n_upper);
-  hipLaunchKernelGGL(k_compact_count, dim3(kScanGrid), dim3(kBlock), 0, st, S, f->upper_sel, f->spt_off, f->spt_X,
-                     f->ctr, f->chunk);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanGrid), 0, st, f->chunk, (int32_t*)nullptr);
-  hipLaunchKernelGGL(k_compact_write, dim3(kScanGrid), dim3(kBlock), 0, st, S, f->upper_sel, f->spt_off, f->spt_X,
-                     f->ctr, f->chunk, d_idx, capacity, d_count);
-  if (S.n_upper > 0) {
-    int g2 = (S.n_upper + kBlock - 1) / kBlock;
-    g2 = g2 > 1024 ? 1024 : g2;
-    hipLaunchKernelGGL(k_count_upper, dim3(g2), dim3(kBlock), 0, st, f->upper_sel, S.n_upper, f->ctr);
-  }
+  const int32_t n_up_chunks = (S.n_upper + 63) / 64;
+  // chunks per visible SPT prefix -> offsets, total -> n_chunks
+  scan_exclusive(LoadChunks{f->spt_high}, &f->ctr->spt_count, (int64_t)S.n_spt, f->block_sums, f->spt_off,
+                 &f->ctr->n_chunks, st);
+  const int sgrid = 4096;
+  const int64_t seg_cap = (int64_t)n_up_chunks + S.n_spt + S.n_nodes / kChunk + 1;
+  hipLaunchKernelGGL(k_segments<false>, dim3(sgrid), dim3(kBlock), 0, st, S, f->upper_sel, f->spt_high, f->spt_X,
+                     f->spt_off, n_up_chunks, f->seg, (int32_t*)nullptr, capacity, f->ctr, d_count);
+  scan_exclusive(LoadArray{f->seg}, &f->ctr->seg_total, seg_cap, f->block_sums, f->seg, &f->ctr->n_selected, st);
+  hipLaunchKernelGGL(k_segments<true>, dim3(sgrid), dim3(kBlock), 0, st, S, f->upper_sel, f->spt_high, f->spt_X,
+                     f->spt_off, n_up_chunks, f->seg, d_idx, capacity, f->ctr, d_count);
   stage_end(f, st);
 }
 

@@ -207,6 +207,38 @@ class Frame:
         return tiles[:m], pos[:m]
 
 
+class ViewGraph:
+    """lod_select + render of one image size captured in a HIP graph
+    (lodgs_graph_capture_view); replayed for any camera of that size and any tau.
+    The image is written to ``self.out``; selection to the frame's idx/count."""
+
+    def __init__(self, frame: Frame, cam, tau: float, stream, cull: bool = True, bg=(0.0, 0.0, 0.0)):
+        self.frame = frame
+        self.width, self.height = cam.width, cam.height
+        self.stream = stream
+        self.out = torch.zeros((cam.height, cam.width, 3), dtype=torch.float32, device=frame.scene.device)
+        c = camera_struct(cam)
+        b = (ctypes.c_float * 3)(*[float(x) for x in bg])
+        h = ctypes.c_void_p()
+        check(_lib.load().lodgs_graph_capture_view(frame._h, ctypes.byref(c), float(tau), _lib.CULL if cull else 0,
+                                                   _ptr(frame.idx), frame.idx.numel(), _ptr(frame.count),
+                                                   ctypes.cast(b, ctypes.c_void_p), _ptr(self.out),
+                                                   stream.cuda_stream, ctypes.byref(h)), "lodgs_graph_capture_view")
+        self._h = h
+
+    def launch(self, cam, tau: float, stream=None):
+        s = self.stream if stream is None else stream
+        check(_lib.load().lodgs_graph_launch(self._h, ctypes.byref(camera_struct(cam)), float(tau), s.cuda_stream),
+              "lodgs_graph_launch")
+        return self.out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.lodgs_graph_destroy(h)
+            self._h = None
+
+
 def grads_like(scene: Scene, n: int | None = None, zero: bool = True) -> dict:
     """Gradient arrays shaped like the scene parameters ([n, ...], default all nodes)."""
     out = {}
