@@ -65,15 +65,17 @@ def stage_bytes(c, H, W, n_coef):
     par = 4 * (3 + 3 + 4 + 1 + n_coef)  # bytes of one node's parameters
     b = {}
     b["select"] = c["n_upper"] * 24 + c["n_spt_visible"] * 32 + c["n_spt_candidates"] * 8 + c["n_selected"] * 4
-    b["project"] = c["n_rendered"] * (4 + par) + c["n_drawn"] * 48 + c["n_rendered"] * 24
-    b["depth_sort"] = 4 * c["n_rendered"] * 16
-    b["duplicate"] = c["n_rendered"] * 16 + c["n_instances"] * 8
+    # every selected node: index, mean, scale, rotation (footprint), tile count
+    b["project"] = c["n_rendered"] * (4 + 12 + 12 + 16 + 4) + c["n_drawn"] * (4 + 4 * n_coef + 64 + 4 + 8)
+    # compaction of the drawn splats (two reads of the tile counts), then 4 radix passes
+    b["depth_sort"] = c["n_rendered"] * 8 + c["n_drawn"] * 16 + 4 * c["n_drawn"] * 16
+    b["duplicate"] = c["n_drawn"] * 16 + c["n_instances"] * 12
     b["tile_sort"] = 2 * c["n_instances"] * 16
     b["ranges"] = c["n_instances"] * 4 + (H * W // 256) * 8
-    b["blend"] = c["n_instances"] * 52 + H * W * 12
+    b["blend"] = c["n_instances"] * (8 + 64) + H * W * 12
     b["loss"] = H * W * 36
-    b["blend_bwd"] = c["n_instances"] * 52 + H * W * 24 + c["n_drawn"] * 36 * 2
-    b["project_bwd"] = c["n_rendered"] * (4 + par + 36) + c["n_drawn"] * par * 2
+    b["blend_bwd"] = c["n_instances"] * (8 + 64 + 36) + H * W * 24
+    b["project_bwd"] = c["n_drawn"] * (16 + 3 * par) + c["n_instances"] * 36
     return b
 
 

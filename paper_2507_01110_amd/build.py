@@ -23,6 +23,8 @@ HIP_FLAGS = [
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt", "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # atomics as written: no wave-level rewrite of LDS adds whose lanes are already reduced
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

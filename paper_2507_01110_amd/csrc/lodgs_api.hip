@@ -2,6 +2,7 @@
 // per-view constants.  The stage kernels live in lodgs_select.hip,
 // lodgs_render.hip and lodgs_backward.hip.
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -22,6 +23,12 @@ int set_error(int code, const char* msg) {
 int hip_fail(hipError_t e, const char* what) {
   std::snprintf(g_err, sizeof g_err, "%s: %s", what, hipGetErrorString(e));
   return LODGS_E_HIP;
+}
+
+int blend_pixels_per_lane() {
+  const char* e = std::getenv("LODGS_BLEND_PX");
+  if (e && (e[0] == '1' || e[0] == '2' || e[0] == '4') && e[1] == 0) return e[0] - '0';
+  return 2;
 }
 
 // Per-view constants, FP32 on the host (IEEE single, correctly rounded / and
@@ -71,11 +78,25 @@ void stage_end(lodgs_frame* f, hipStream_t st) {
 }
 
 namespace {
-__global__ void k_set_view(ViewConst v, ViewConst* dst) { *dst = v; }
+__global__ void k_set_view(ViewConst v, ViewConst* dst, FrameCounters* ctr, int mode, const int32_t* d_count,
+                           int64_t cap) {
+  *dst = v;
+  if (mode == kViewSelect) {
+    ctr->n_spt_visible = 0;
+    ctr->n_upper_selected = 0;
+    ctr->sum_high = 0;
+  } else if (mode == kViewRender) {
+    int64_t n = *d_count;
+    n = n < 0 ? 0 : (n > cap ? cap : n);
+    ctr->n_render = (int32_t)n;
+    ctr->n_drawn = 0;
+  }
+}
 }  // namespace
 
-void launch_set_view(const ViewConst& v, ViewConst* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_view, dim3(1), dim3(1), 0, st, v, dst);
+void launch_set_view(const ViewConst& v, ViewConst* dst, FrameCounters* ctr, int mode, const int32_t* d_count,
+                     int64_t cap, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_view, dim3(1), dim3(1), 0, st, v, dst, ctr, mode, d_count, cap);
 }
 
 void launch_blend_count(lodgs_frame* f, hipStream_t st);
@@ -127,12 +148,19 @@ void free_frame(lodgs_frame* f) {
     (void)hipEventDestroy(r.b);
   }
   if (f->open_event) (void)hipEventDestroy(f->open_event);
-  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->chunk, f->seg,
+  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->rect,
-                  f->ikey, f->ival, f->ikey2, f->ival2, f->ranges, f->grad2d, f->d_view_sel, f->d_view_ren};
+                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_splat, f->inst_grad, f->ranges, f->d_view_sel,
+                  f->d_view_ren};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete f;
+}
+
+// Selection position of each instance in tile order.
+__global__ void k_instance_positions(const uint32_t* sorted_e, const uint32_t* inst_splat, int64_t m, int32_t* pos) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
+    pos[k] = (int32_t)inst_splat[sorted_e[k]];
 }
 
 }  // namespace
@@ -190,6 +218,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   if (!f) return set_error(LODGS_E_OOM, "lodgs_frame_create: out of host memory");
   f->scene = scene;
   f->caps = *caps;
+  f->blend_px = lodgs::blend_pixels_per_lane();
   const SceneDev& S = scene->dev;
   const size_t ns = (size_t)caps->max_selected, ni = (size_t)caps->max_instances;
   const size_t nt = (size_t)((caps->max_width + 15) / 16) * ((caps->max_height + 15) / 16);
@@ -202,8 +231,8 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(spt_high, (size_t)S.n_spt);
   A(spt_X, (size_t)S.n_spt);
   A(spt_off, (size_t)S.n_spt);
-  A(chunk, lodgs::kScanGrid + 1);
   A(seg, (size_t)(S.n_upper + 63) / 64 + (size_t)S.n_spt + (size_t)S.n_nodes / 512 + 1);
+  A(chunk_owner, (size_t)S.n_spt + (size_t)S.n_nodes / 512 + 1);
   A(splats, ns);
   A(depth_key, ns);
   A(depth_key2, ns);
@@ -216,8 +245,9 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(ival, ni);
   A(ikey2, ni);
   A(ival2, ni);
+  A(inst_splat, ni);
+  A(inst_grad, 9 * ni);
   A(ranges, nt);
-  A(grad2d, 9 * ns);
   A(work, 2);
   A(d_view_sel, 1);
   A(d_view_ren, 1);
@@ -321,7 +351,12 @@ int lodgs_frame_read_instances(lodgs_frame* f, int32_t* d_tile, int32_t* d_pos, 
   int64_t m = c.n_inst_clamped < capacity ? c.n_inst_clamped : capacity;
   if (m > 0) {
     e = hipMemcpyAsync(d_tile, f->sorted_ikey, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_pos, f->sorted_ival, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+      const int64_t g = (m + lodgs::kBlock - 1) / lodgs::kBlock;
+      hipLaunchKernelGGL(k_instance_positions, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(lodgs::kBlock), 0, st,
+                         f->sorted_ival, f->inst_splat, m, d_pos);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(e, "lodgs_frame_read_instances");
   }
@@ -401,6 +436,15 @@ struct lodgs_graph {
   hipGraphExec_t exec;
   hipGraphNode_t node_sel, node_ren;
   hipKernelNodeParams p_sel, p_ren;
+  // the captured arguments of the two k_set_view nodes other than the view
+  lodgs::ViewConst* dst_sel;
+  lodgs::ViewConst* dst_ren;
+  FrameCounters* ctr_sel;
+  FrameCounters* ctr_ren;
+  int mode_sel, mode_ren;
+  const int32_t* count_sel;
+  const int32_t* count_ren;
+  int64_t cap_sel, cap_ren;
   int32_t width, height;
 };
 
@@ -459,12 +503,26 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
     if (hipGraphKernelNodeGetParams(nodes[k], &p) != hipSuccess) continue;
     if (p.func != reinterpret_cast<void*>(&lodgs::k_set_view)) continue;
     lodgs::ViewConst* dst = *reinterpret_cast<lodgs::ViewConst**>(p.kernelParams[1]);
+    FrameCounters* ctr = *reinterpret_cast<FrameCounters**>(p.kernelParams[2]);
+    const int mode = *reinterpret_cast<int*>(p.kernelParams[3]);
+    const int32_t* cnt = *reinterpret_cast<const int32_t**>(p.kernelParams[4]);
+    const int64_t cap = *reinterpret_cast<int64_t*>(p.kernelParams[5]);
     if (dst == f->d_view_sel) {
       g->node_sel = nodes[k];
       g->p_sel = p;
+      g->dst_sel = dst;
+      g->ctr_sel = ctr;
+      g->mode_sel = mode;
+      g->count_sel = cnt;
+      g->cap_sel = cap;
     } else if (dst == f->d_view_ren) {
       g->node_ren = nodes[k];
       g->p_ren = p;
+      g->dst_ren = dst;
+      g->ctr_ren = ctr;
+      g->mode_ren = mode;
+      g->count_ren = cnt;
+      g->cap_ren = cap;
     }
   }
   if (e == hipSuccess && (!g->node_sel || !g->node_ren)) {
@@ -492,10 +550,8 @@ int lodgs_graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, lodgs
     return set_error(LODGS_E_INVALID, "lodgs_graph_launch: image size differs from the captured one");
   if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: bad tau");
   lodgs::ViewConst vs = lodgs::make_view(*cam, tau), vr = lodgs::make_view(*cam, 0.0f);
-  lodgs::ViewConst* ds = g->frame->d_view_sel;
-  lodgs::ViewConst* dr = g->frame->d_view_ren;
-  void* args_s[2] = {&vs, &ds};
-  void* args_r[2] = {&vr, &dr};
+  void* args_s[6] = {&vs, &g->dst_sel, &g->ctr_sel, &g->mode_sel, &g->count_sel, &g->cap_sel};
+  void* args_r[6] = {&vr, &g->dst_ren, &g->ctr_ren, &g->mode_ren, &g->count_ren, &g->cap_ren};
   hipKernelNodeParams ps = g->p_sel, pr = g->p_ren;
   ps.kernelParams = args_s;
   pr.kernelParams = args_r;

@@ -17,136 +17,210 @@
 
 namespace lodgs {
 
-__device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
-  return x;
-}
+// Reduce-scatter of 9 per-lane values over a wave (all lanes active): four
+// DPP exchange steps inside each 16-lane row pair lane l with l^1, l^2, l^7
+// and l^15; at each step a lane keeps half of its remaining values (chosen by
+// b0^b2, b1^b2, b2^b3 and b3 of l & 15) and adds its partner's copy of that
+// half.  Lane l then holds its row's sum of value
+// slot(l) = (b0^b2) + 2 (b1^b2) + 4 (b2^b3) + 8 b3 (slots 9..15 are zero);
+// two cross-row exchanges complete the sums over the wave.
+#define LODGS_DPP(x, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false))
+#define LODGS_RS_PAIR(out, a, b, k, ctrl)       \
+  do {                                          \
+    const float keep_ = (k) ? (b) : (a);        \
+    const float send_ = (k) ? (a) : (b);        \
+    (out) = keep_ + LODGS_DPP(send_, ctrl);     \
+  } while (0)
 
-__global__ void __launch_bounds__(256) k_blend_bwd(const ViewConst* __restrict__ vp, const uint2* ranges, const uint32_t* ival,
-                                                   const Splat* splats, const FrameCounters* ctr, const float* rgb,
-                                                   const float* dL, float* grad2d) {
+__device__ __forceinline__ float wave_reduce_scatter9(const float* g, int lane, int& slot) {
+  const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  const bool k1 = (b0 ^ b2) != 0, k2 = (b1 ^ b2) != 0, k3 = (b2 ^ b3) != 0, k4 = b3 != 0;
+  float h0, h1, h2, h3, h4;
+  LODGS_RS_PAIR(h0, g[0], g[1], k1, 0xB1);  // quad_perm [1,0,3,2]: l^1
+  LODGS_RS_PAIR(h1, g[2], g[3], k1, 0xB1);
+  LODGS_RS_PAIR(h2, g[4], g[5], k1, 0xB1);
+  LODGS_RS_PAIR(h3, g[6], g[7], k1, 0xB1);
+  LODGS_RS_PAIR(h4, g[8], 0.0f, k1, 0xB1);
+  float q0, q1, q2;
+  LODGS_RS_PAIR(q0, h0, h1, k2, 0x4E);  // quad_perm [2,3,0,1]: l^2
+  LODGS_RS_PAIR(q1, h2, h3, k2, 0x4E);
+  LODGS_RS_PAIR(q2, h4, 0.0f, k2, 0x4E);
+  float r0, r1;
+  LODGS_RS_PAIR(r0, q0, q1, k3, 0x141);  // row_half_mirror: l^7
+  LODGS_RS_PAIR(r1, q2, 0.0f, k3, 0x141);
+  float z;
+  LODGS_RS_PAIR(z, r0, r1, k4, 0x140);  // row_mirror: l^15
+  z += __shfl_xor(z, 16, 64);
+  z += __shfl_xor(z, 32, 64);
+  slot = (int)k1 + 2 * (int)k2 + 4 * (int)k3 + 8 * (int)k4;
+  return z;
+}
+#undef LODGS_RS_PAIR
+#undef LODGS_DPP
+
+// Backward of the blend, same layout and decisions as the forward.  Per
+// batch, each wave reduces the 9 gradient values of a splat over its lanes
+// (only when some lane contributes) and stores them in its own LDS row; the
+// workgroup then sums the rows in wave order and writes one 9-float partial
+// per (splat, tile) instance at the instance's emission index, with zeros for
+// instances that no pixel reached.  No atomics: the result is deterministic.
+template <int PX>
+__global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restrict__ vp,
+                                                        const uint2* __restrict__ ranges,
+                                                        const uint32_t* __restrict__ ival,
+                                                        const uint32_t* __restrict__ inst_splat,
+                                                        const Splat* __restrict__ splats, const FrameCounters* ctr,
+                                                        const float* __restrict__ rgb, const float* __restrict__ dL,
+                                                        float* __restrict__ partial) {
+  constexpr int NT = 256 / PX, NW = 4 / PX;
   const ViewConst v = *vp;
-  __shared__ Splat batch[256];
-  __shared__ uint32_t bid[256];
-  __shared__ float acc[9][256];
+  __shared__ Splat batch[NT];
+  __shared__ uint32_t bid[NT];
+  __shared__ float acc[NW][9][NT];
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
-  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
-  const bool inside = px < v.width && py < v.height;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  // pixel-centre rectangle of this wave (16 x 4 pixels)
-  const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + 15.0f;
-  const float wy0 = (float)(ty * kTile + 4 * (threadIdx.x >> 6)) + 0.5f, wy1 = wy0 + 3.0f;
-  const uint2 rg = ranges[tile];
-  const uint32_t nr = (uint32_t)ctr->n_render;
-  float Cf[3] = {0.0f, 0.0f, 0.0f}, G[3] = {0.0f, 0.0f, 0.0f};
-  if (inside) {
-    const int64_t p = 3 * ((int64_t)py * v.width + px);
-    for (int c = 0; c < 3; ++c) {
-      Cf[c] = rgb[p + c];
-      G[c] = dL[p + c];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int px = tx * kTile + (lane & 15);
+  const int py0 = ty * kTile + 4 * PX * wv + (lane >> 4);
+  const float fx = (float)px + 0.5f;
+  float fy[PX], T[PX], P0[PX], P1[PX], P2[PX], C0[PX], C1[PX], C2[PX], G0[PX], G1[PX], G2[PX];
+  bool live[PX];
+#pragma unroll
+  for (int p = 0; p < PX; ++p) {
+    const int py = py0 + 4 * p;
+    fy[p] = (float)py + 0.5f;
+    live[p] = px < v.width && py < v.height;
+    T[p] = 1.0f;
+    P0[p] = P1[p] = P2[p] = 0.0f;
+    C0[p] = C1[p] = C2[p] = G0[p] = G1[p] = G2[p] = 0.0f;
+    if (live[p]) {
+      const int64_t o = 3 * ((int64_t)py * v.width + px);
+      C0[p] = rgb[o];
+      C1[p] = rgb[o + 1];
+      C2[p] = rgb[o + 2];
+      G0[p] = dL[o];
+      G1[p] = dL[o + 1];
+      G2[p] = dL[o + 2];
     }
   }
-#pragma unroll
-  for (int c = 0; c < 9; ++c) acc[c][threadIdx.x] = 0.0f;
-  float T = 1.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
-  bool done = !inside;
+  const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + 15.0f;
+  const float wy0 = (float)(ty * kTile + 4 * PX * wv) + 0.5f, wy1 = wy0 + (float)(4 * PX - 1);
+  const uint2 rg = ranges[tile];
+  const uint32_t nr = (uint32_t)ctr->n_render;
   const float thr = 1.0f / 255.0f;
-  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += 256) {
-    if (__syncthreads_count(done) == 256) break;
+  for (int t = threadIdx.x; t < NW * 9 * NT; t += NT) (&acc[0][0][0])[t] = 0.0f;
+  uint32_t b0 = rg.x;
+  for (; b0 < rg.y; b0 += NT) {
+    bool active = false;
+#pragma unroll
+    for (int p = 0; p < PX; ++p) active = active || live[p];
+    if (__syncthreads_count(active) == 0) break;
     const uint32_t k = b0 + threadIdx.x;
     if (k < rg.y) {
-      const uint32_t i = ival[k];
+      const uint32_t e = ival[k];
+      const uint32_t i = inst_splat[e];
+      bid[threadIdx.x] = e;
       if (i < nr) {
-        bid[threadIdx.x] = i;
         batch[threadIdx.x] = splats[i];
       } else {  // only reachable if the instance count overflowed
-        bid[threadIdx.x] = 0;
         batch[threadIdx.x].o = 0.0f;
         batch[threadIdx.x].ex = -1.0f;
       }
     }
     __syncthreads();
-    const int m = (int)min(256u, rg.y - b0);
-    for (int j = 0; j < m; ++j) {
-      if (__all(done)) break;  // wave-uniform
-      const Splat& s = batch[j];
-      if (splat_misses(s, wx0, wx1, wy0, wy1)) continue;  // wave-uniform
-      float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-      bool contrib = false;
-      if (!done) {
-        float dx, dy, u1, u2;
-        const float power = splat_power(s, fx, fy, dx, dy, u1, u2);
-        const float e = fexp(power);
-        const float oe = s.o * e;
-        const float alpha = fminf(0.99f, oe);
-        if (alpha >= thr) {
-          const float tt = T * (1.0f - alpha);
-          if (tt < 0.0001f) {
-            done = true;
-          } else {
-            contrib = true;
-            const float w = alpha * T;
-            g[6] = G[0] * w;
-            g[7] = G[1] * w;
-            g[8] = G[2] * w;
-            P0 = __builtin_fmaf(s.r, w, P0);
-            P1 = __builtin_fmaf(s.g, w, P1);
-            P2 = __builtin_fmaf(s.b, w, P2);
+    const int m = (int)min((uint32_t)NT, rg.y - b0);
+    if (__any(active)) {  // wave-uniform
+      // one splat (batch slot j) against the wave's pixels; true when every
+      // pixel has stopped
+      auto step = [&](const Splat& s, int j) -> bool {
+        if (splat_misses(s, wx0, wx1, wy0, wy1)) return false;  // wave-uniform
+        float dxs[PX], dys[PX], u1s[PX], u2s[PX], es[PX], oes[PX], als[PX], tts[PX];
+        bool cons[PX];
+        bool any_con = false, act = false;
+#pragma unroll
+        for (int p = 0; p < PX; ++p) {
+          const float power = splat_power(s, fx, fy[p], dxs[p], dys[p], u1s[p], u2s[p]);
+          es[p] = fexp(power);
+          oes[p] = s.o * es[p];
+          als[p] = fminf(0.99f, oes[p]);
+          tts[p] = T[p] * (1.0f - als[p]);
+          const bool hit = live[p] & (als[p] >= thr);
+          const bool stop = hit & (tts[p] < 0.0001f);
+          cons[p] = hit & !stop;
+          live[p] = live[p] & !stop;
+          any_con = any_con | cons[p];
+          act = act | live[p];
+        }
+        if (__any(any_con)) {  // wave-uniform
+          float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int p = 0; p < PX; ++p) {
+            const float alpha = als[p], Tp = T[p];
+            const float w = alpha * Tp;
+            const float q0 = __builtin_fmaf(s.r, w, P0[p]);
+            const float q1 = __builtin_fmaf(s.g, w, P1[p]);
+            const float q2 = __builtin_fmaf(s.b, w, P2[p]);
             const float ia = __builtin_amdgcn_rcpf(1.0f - alpha);  // gradient values only
-            float dA = G[0] * (s.r * T - (Cf[0] - P0) * ia);
-            dA = __builtin_fmaf(G[1], s.g * T - (Cf[1] - P1) * ia, dA);
-            dA = __builtin_fmaf(G[2], s.b * T - (Cf[2] - P2) * ia, dA);
-            if (oe <= 0.99f) {
-              const float dpow = dA * alpha;
-              // d power / d mean2D = Sigma'^-1 (x - mean) = -2 (h1 u1 e1 + h2 u2 e2)
-              const float k1 = -2.0f * s.h1 * u1, k2 = -2.0f * s.h2 * u2;
-              g[0] = dpow * (k1 * s.ce - k2 * s.se);
-              g[1] = dpow * (k1 * s.se + k2 * s.ce);
-              g[2] = dpow * (-0.5f * dx * dx);
-              g[3] = dpow * (-dx * dy);
-              g[4] = dpow * (-0.5f * dy * dy);
-              g[5] = dA * e;
-            }
-            T = tt;
+            float dA = G0[p] * (s.r * Tp - (C0[p] - q0) * ia);
+            dA = __builtin_fmaf(G1[p], s.g * Tp - (C1[p] - q1) * ia, dA);
+            dA = __builtin_fmaf(G2[p], s.b * Tp - (C2[p] - q2) * ia, dA);
+            const bool con = cons[p];
+            const bool unclamped = con & (oes[p] <= 0.99f);
+            const float dpow = dA * alpha;
+            // d power / d mean2D = -2 (h1 u1 e1 + h2 u2 e2), e1 = (ce, se), e2 = (-se, ce)
+            const float k1 = -2.0f * s.h1 * u1s[p], k2 = -2.0f * s.h2 * u2s[p];
+            const float dx = dxs[p], dy = dys[p];
+            g[0] += unclamped ? dpow * (k1 * s.ce - k2 * s.se) : 0.0f;
+            g[1] += unclamped ? dpow * (k1 * s.se + k2 * s.ce) : 0.0f;
+            g[2] += unclamped ? dpow * (-0.5f * dx * dx) : 0.0f;
+            g[3] += unclamped ? dpow * (-dx * dy) : 0.0f;
+            g[4] += unclamped ? dpow * (-0.5f * dy * dy) : 0.0f;
+            g[5] += unclamped ? dA * es[p] : 0.0f;
+            g[6] += con ? G0[p] * w : 0.0f;
+            g[7] += con ? G1[p] * w : 0.0f;
+            g[8] += con ? G2[p] * w : 0.0f;
+            P0[p] = con ? q0 : P0[p];
+            P1[p] = con ? q1 : P1[p];
+            P2[p] = con ? q2 : P2[p];
+            T[p] = con ? tts[p] : Tp;
           }
+          int slot;
+          const float r = wave_reduce_scatter9(g, lane, slot);
+          if (lane < 16 && slot < 9) acc[wv][slot][j] = r;
         }
-      }
-      const uint64_t who = __ballot(contrib);
-      if (who == 0ull) continue;
-      if (__popcll(who) <= 4) {  // few lanes: LDS atomics, little contention
-        if (contrib) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) atomicAdd(&acc[c][j], g[c]);
-        }
-      } else {  // many lanes: DPP reduction, one LDS atomic per value
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-          const float r = wave_sum_to_lane63(g[c]);
-          if ((threadIdx.x & 63) == 63) atomicAdd(&acc[c][j], r);
-        }
+        return !__any(act);
+      };
+      // two register sets, each loaded one splat ahead of its use
+      Splat sa = batch[0], sb;
+      for (int j = 0;;) {
+        sb = batch[j + 1 < m ? j + 1 : j];
+        if (step(sa, j) || ++j >= m) break;
+        sa = batch[j + 1 < m ? j + 1 : j];
+        if (step(sb, j) || ++j >= m) break;
       }
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
-      float* dst = grad2d + 9 * (int64_t)bid[threadIdx.x];
+      float* dst = partial + 9 * (int64_t)bid[threadIdx.x];
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
-        const float r = acc[c][threadIdx.x];
-        if (r != 0.0f) {
-          atomicAdd(dst + c, r);
-          acc[c][threadIdx.x] = 0.0f;
+        float r = acc[0][c][threadIdx.x];
+        acc[0][c][threadIdx.x] = 0.0f;
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+          r += acc[w][c][threadIdx.x];
+          acc[w][c][threadIdx.x] = 0.0f;
         }
+        dst[c] = r;
       }
     }
   }
-}
-
-__global__ void __launch_bounds__(kBlock) k_zero_grad2d(float* p, const FrameCounters* ctr) {
-  const int64_t n = (int64_t)9 * ctr->n_render;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0f;
+  // instances that no pixel of the tile reached
+  for (uint32_t k = b0 + threadIdx.x; k < rg.y; k += NT) {
+    float* dst = partial + 9 * (int64_t)ival[k];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dst[c] = 0.0f;
+  }
 }
 
 // Projection backward, FP64 (per splat): the forward chain is replayed and the
@@ -164,58 +238,90 @@ __global__ void __launch_bounds__(kBlock) k_zero_sel(const FrameCounters* ctr, i
   }
 }
 
-// One thread per drawn splat: the drawn splats lead the depth order, so
-// order[0 .. n_drawn) lists exactly them (no lanes idle on culled ones).
+// Colour backward for one splat: dL/dRGB (zero where the forward's FP32
+// colour was clamped at 0) to the SH coefficients (written to the optional
+// per-selection row and added to the optional node row) and to the view
+// direction; returns dL/dmean from the direction term.  DEG is the SH degree,
+// so the basis lives in registers.
+template <int DEG>
+__device__ __forceinline__ void sh_backward(const SceneDev& S, const ViewConst& v, int64_t node, const float* g2,
+                                            float* sel_sh, float* node_sh, double* gdir) {
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+  const float* shc = S.sh + (int64_t)(3 * nb) * node;
+  const double mx = S.means[3 * node], my = S.means[3 * node + 1], mz = S.means[3 * node + 2];
+  const double dx = mx - (double)v.pos[0], dy = my - (double)v.pos[1], dz = mz - (double)v.pos[2];
+  // the forward's FP32 colour decides the clamp at 0
+  float raw[3] = {0.5f, 0.5f, 0.5f};
+  {
+    const float il = 1.0f / __builtin_sqrtf((float)dx * (float)dx + (float)dy * (float)dy + (float)dz * (float)dz);
+    float Yf[16];
+    sh_basis(DEG, (float)dx * il, (float)dy * il, (float)dz * il, Yf);
+#pragma unroll
+    for (int k = 0; k < nb; ++k)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) raw[c] = __builtin_fmaf(shc[3 * k + c], Yf[k], raw[c]);
+  }
+  double dRGB[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dRGB[c] = raw[c] < 0.0f ? 0.0 : (double)g2[6 + c];
+  const double dl = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
+  const double d0 = dx / dl, d1 = dy / dl, d2 = dz / dl;
+  float Y[16], dY[16][3];
+  sh_basis(DEG, (float)d0, (float)d1, (float)d2, Y);
+  sh_basis_grad(DEG, (float)d0, (float)d1, (float)d2, dY);
+  double dd[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < nb; ++k) {
+    double a = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float gk = (float)(dRGB[c] * (double)Y[k]);
+      if (sel_sh) sel_sh[3 * k + c] = gk;
+      if (node_sh) node_sh[3 * k + c] += gk;
+      a += dRGB[c] * (double)shc[3 * k + c];
+    }
+    dd[0] += a * (double)dY[k][0];
+    dd[1] += a * (double)dY[k][1];
+    dd[2] += a * (double)dY[k][2];
+  }
+  const double dot = dd[0] * d0 + dd[1] * d1 + dd[2] * d2;
+  gdir[0] = (dd[0] - d0 * dot) / dl;
+  gdir[1] = (dd[1] - d1 * dot) / dl;
+  gdir[2] = (dd[2] - d2 * dot) / dl;
+}
+
+// One thread per drawn splat: order[0 .. n_drawn) lists exactly the drawn
+// splats in depth order (no lanes idle on culled ones).
+// The colour part runs first so that its registers are free before the FP64
+// geometry chain is replayed.
+template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
                                                         const FrameCounters* ctr, const uint32_t* order,
-                                                        const float* grad2d, lodgs_grads sel, lodgs_grads nodes) {
+                                                        const uint32_t* inst_off, const float* partial,
+                                                        lodgs_grads sel, lodgs_grads nodes) {
   const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
-  const int nc = S.n_coef;
+  const int64_t n_inst = ctr->n_instances, n_inst_cl = ctr->n_inst_clamped;
+  constexpr int nc = 3 * (DEG + 1) * (DEG + 1);
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = order[r];
     const int64_t node = idx[i];
+    // 2D gradients: sum of the splat's per-instance partials, in emission order
+    int64_t a = inst_off[r], b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
+    a = a < n_inst_cl ? a : n_inst_cl;
+    b = b < n_inst_cl ? b : n_inst_cl;
+    float g2[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t q = a; q < b; ++q) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) g2[c] += partial[9 * q + c];
+    }
+    double gdir[3];
+    sh_backward<DEG>(S, v, node, g2, sel.d_sh ? sel.d_sh + nc * i : nullptr,
+                     nodes.d_sh ? nodes.d_sh + nc * node : nullptr, gdir);
     double gm[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
     Proj64 P;
     const bool visible = proj_chain64(S.means, S.log_scales, S.quats, v, node, P);
-    const float* g2 = grad2d + 9 * i;
-    float* sel_sh = sel.d_sh ? sel.d_sh + (int64_t)nc * i : nullptr;
-    float* node_sh = nodes.d_sh ? nodes.d_sh + (int64_t)nc * node : nullptr;
     if (visible) {
-      // colour -> SH coefficients and view direction
-      const double mx = S.means[3 * node], my = S.means[3 * node + 1], mz = S.means[3 * node + 2];
-      const double dx = mx - (double)v.pos[0], dy = my - (double)v.pos[1], dz = mz - (double)v.pos[2];
-      const double dl = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
-      const double d0 = dx / dl, d1 = dy / dl, d2 = dz / dl;
-      float Y[16], dY[16][3];
-      sh_basis(S.sh_degree, (float)d0, (float)d1, (float)d2, Y);
-      sh_basis_grad(S.sh_degree, (float)d0, (float)d1, (float)d2, dY);
-      const int nb = nc / 3;
-      const float* shc = S.sh + (int64_t)nc * node;
-      // the forward's FP32 colour decides the clamp at 0
-      const float il = 1.0f / __builtin_sqrtf((float)dx * (float)dx + (float)dy * (float)dy + (float)dz * (float)dz);
-      float Yf[16];
-      sh_basis(S.sh_degree, (float)dx * il, (float)dy * il, (float)dz * il, Yf);
-      float raw[3] = {0.5f, 0.5f, 0.5f};
-      for (int k = 0; k < nb; ++k)
-        for (int c = 0; c < 3; ++c) raw[c] = __builtin_fmaf(shc[3 * k + c], Yf[k], raw[c]);
-      double dRGB[3];
-      for (int c = 0; c < 3; ++c) dRGB[c] = raw[c] < 0.0f ? 0.0 : (double)g2[6 + c];
-      double dd[3] = {0.0, 0.0, 0.0};
-      for (int k = 0; k < nb; ++k) {
-        double a = 0.0;
-        for (int c = 0; c < 3; ++c) {
-          const float gk = (float)(dRGB[c] * (double)Y[k]);
-          if (sel_sh) sel_sh[3 * k + c] = gk;
-          if (node_sh) node_sh[3 * k + c] += gk;
-          a += dRGB[c] * (double)shc[3 * k + c];
-        }
-        dd[0] += a * (double)dY[k][0];
-        dd[1] += a * (double)dY[k][1];
-        dd[2] += a * (double)dY[k][2];
-      }
-      const double dot = dd[0] * d0 + dd[1] * d1 + dd[2] * d2;
-      const double gdir[3] = {(dd[0] - d0 * dot) / dl, (dd[1] - d1 * dot) / dl, (dd[2] - d2 * dot) / dl};
       // opacity
       const double o = 1.0 / (1.0 + (double)fexp(-S.opacity_logits[node]));
       go = (double)g2[5] * o * (1.0 - o);
@@ -297,22 +403,51 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewCo
   }
 }
 
+template <int DEG>
+static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodgs_grads& sel,
+                                   const lodgs_grads& nodes, hipStream_t st) {
+  hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
+                     f->sorted_order, f->inst_off, f->inst_grad, sel, nodes);
+}
+
 void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
                      hipStream_t st) {
   const SceneDev& S = f->scene->dev;
   const ViewConst& v = f->view;
   stage_begin(f, LODGS_STAGE_BLEND_BWD, st);
-  hipLaunchKernelGGL(k_zero_grad2d, dim3(2048), dim3(kBlock), 0, st, f->grad2d, f->ctr);
   const int ntiles = v.tiles_x * v.tiles_y;
-  hipLaunchKernelGGL(k_blend_bwd, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival, f->splats, f->ctr,
-                     f->r_rgb, d_dL, f->grad2d);
+  switch (f->blend_px) {
+    case 1:
+      hipLaunchKernelGGL(k_blend_bwd<1>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
+                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_grad);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_blend_bwd<4>, dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
+                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_grad);
+      break;
+    default:
+      hipLaunchKernelGGL(k_blend_bwd<2>, dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
+                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_grad);
+      break;
+  }
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_PROJECT_BWD, st);
   lodgs_grads none{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (sel) hipLaunchKernelGGL(k_zero_sel, dim3(1024), dim3(kBlock), 0, st, f->ctr, S.n_coef, *sel);
-  hipLaunchKernelGGL(k_project_bwd, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->sorted_order, f->grad2d, sel ? *sel : none, nodes ? *nodes : none);
+  const lodgs_grads gs = sel ? *sel : none, gn = nodes ? *nodes : none;
+  switch (S.sh_degree) {
+    case 0: launch_project_bwd_deg<0>(S, f, gs, gn, st); break;
+    case 1: launch_project_bwd_deg<1>(S, f, gs, gn, st); break;
+    case 2: launch_project_bwd_deg<2>(S, f, gs, gn, st); break;
+    default: launch_project_bwd_deg<3>(S, f, gs, gn, st); break;
+  }
   stage_end(f, st);
+}
+
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
 }
 
 // L1 loss: grad = sign(img - target) / n, loss = sum |img - target| / n.

@@ -38,9 +38,11 @@ ViewConst make_view(const lodgs_camera& c, float tau);
 // high part with trailing zero bits and a low part), degree-7 Taylor
 // polynomial of e^r by Horner with fused multiply-adds, scaling by 2^n.
 // Returns 0 below -87 and for NaN; clamps the argument at 88.
+// Written with selects rather than branches (same arithmetic on live lanes).
 __device__ __forceinline__ float fexp(float x) {
-  if (!(x >= -87.0f)) return 0.0f;
+  const bool live = x >= -87.0f;  // false for NaN
   x = x > 88.0f ? 88.0f : x;
+  x = live ? x : 0.0f;
   const float n = __builtin_rintf(x * 1.44269502f);
   float r = __builtin_fmaf(-n, 0.693145752f, x);
   r = __builtin_fmaf(-n, 1.42860677e-06f, r);
@@ -52,7 +54,7 @@ __device__ __forceinline__ float fexp(float x) {
   p = __builtin_fmaf(p, r, 0.5f);
   p = __builtin_fmaf(p, r, 1.0f);
   p = __builtin_fmaf(p, r, 1.0f);
-  return __builtin_ldexpf(p, (int)n);
+  return live ? __builtin_ldexpf(p, (int)n) : 0.0f;
 }
 
 // |mu - pos| as sqrt((dx*dx + dy*dy) + dz*dz).
@@ -125,7 +127,7 @@ __device__ __forceinline__ float splat_power(const Splat& s, float px, float py,
 // opacity alone is below 1/255).  Skipping such a splat leaves every result
 // unchanged.
 __device__ __forceinline__ bool splat_misses(const Splat& s, float x0, float x1, float y0, float y1) {
-  return s.ex < 0.0f || s.mxh + s.ex < x0 || s.mxh - s.ex > x1 || s.myh + s.ey < y0 || s.myh - s.ey > y1;
+  return (s.ex < 0.0f) | (s.mxh + s.ex < x0) | (s.mxh - s.ex > x1) | (s.myh + s.ey < y0) | (s.myh - s.ey > y1);
 }
 
 // Real SH basis constants, l <= 3 (3DGS sign convention).

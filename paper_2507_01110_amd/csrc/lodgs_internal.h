@@ -62,8 +62,8 @@ struct lodgs_frame {
   int32_t* spt_high;      // [n_spt]
   float* spt_X;           // [n_spt]
   uint32_t* spt_off;      // [n_spt]
-  uint32_t* chunk;        // [kScanGrid + 1]
   uint32_t* seg;          // [ceil(n_upper/64) + n_spt + n_nodes/512 + 1]
+  uint32_t* chunk_owner;  // [n_spt + n_nodes/512 + 1] SPT of each candidate chunk
   // render
   lodgs::Splat* splats;   // [max_selected]
   uint32_t* depth_key;    // [max_selected]
@@ -71,16 +71,17 @@ struct lodgs_frame {
   uint32_t* order;        // [max_selected]
   uint32_t* order2;
   uint32_t* tiles;        // [max_selected]
-  uint32_t* inst_off;     // [max_selected]
+  uint32_t* inst_off;     // [max_selected] drawn ranks, then per-drawn-splat instance offsets
   ushort4* rect;          // [max_selected]
   uint32_t* ikey;         // [max_instances]
   uint32_t* ival;
   uint32_t* ikey2;
   uint32_t* ival2;
+  uint32_t* inst_splat;   // [max_instances] selection position of each instance (emission order)
+  float* inst_grad;       // [max_instances][9] per-instance 2D gradient partials (emission order)
   uint2* ranges;          // [max tiles]
   lodgs::ViewConst* d_view_sel;  // view constants of the last lod_select (device)
   lodgs::ViewConst* d_view_ren;  // view constants of the last render (device)
-  float* grad2d;          // [max_selected][9]
   // state of the last render
   bool rendered;
   const int32_t* r_idx;
@@ -90,7 +91,7 @@ struct lodgs_frame {
   lodgs::ViewConst view;
   const uint32_t* sorted_ival;  // the buffer holding the final instance order
   const uint32_t* sorted_ikey;
-  const uint32_t* sorted_order;  // selection positions in depth order (drawn ones first)
+  const uint32_t* sorted_order;  // selection positions of the drawn splats in depth order
   // timing mode: one (stage, start, end) event pair per stage and call
   bool timing;
   struct TimedStage {
@@ -101,16 +102,26 @@ struct lodgs_frame {
   int open_stage;
   hipEvent_t open_event;
   unsigned long long* work;  // [2] evaluation / contribution counters (device)
+  int blend_px;              // pixels per lane of the blend kernels (1, 2 or 4)
 };
 
 namespace lodgs {
 
 // Writes the per-view constants to the frame's device slot (one thread): the
 // kernels of a stage read them from there, so a captured graph is replayed
-// for another camera by updating this one node's argument.
-void launch_set_view(const ViewConst& v, ViewConst* dst, hipStream_t st);
+// for another camera by updating this one node's argument.  The same thread
+// starts the stage's counters: kViewSelect clears the select counters,
+// kViewRender sets n_render = clamp(*d_count, 0, cap) and clears n_drawn.
+constexpr int kViewOnly = 0, kViewSelect = 1, kViewRender = 2;
+void launch_set_view(const ViewConst& v, ViewConst* dst, FrameCounters* ctr, int mode, const int32_t* d_count,
+                     int64_t cap, hipStream_t st);
 
 int hip_fail(hipError_t e, const char* what);
+
+// Pixels per lane of the blend kernels: 2, or LODGS_BLEND_PX (1, 2 or 4) when
+// set in the environment (a tuning knob: images are identical, gradients equal
+// up to the order of their sums).
+int blend_pixels_per_lane();
 
 // Timing mode: brackets a stage with events on the stream (no-op otherwise).
 void stage_begin(lodgs_frame* f, int stage, hipStream_t st);

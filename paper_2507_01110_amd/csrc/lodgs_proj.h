@@ -26,15 +26,32 @@ __device__ __forceinline__ void to_camera64(const ViewConst& v, double m0, doubl
     c[r] = (((double)v.R[3 * r] * m0 + (double)v.R[3 * r + 1] * m1) + (double)v.R[3 * r + 2] * m2) + (double)v.t[r];
 }
 
+// The raw parameters of one node, loaded together (independent loads).
+struct NodeGeom {
+  float m[3], ls[3];
+  float4 q;
+};
+
+__device__ __forceinline__ NodeGeom load_geom(const float* means, const float* log_scales, const float* quats,
+                                              int64_t n) {
+  NodeGeom g;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g.m[k] = means[3 * n + k];
+    g.ls[k] = log_scales[3 * n + k];
+  }
+  g.q = *reinterpret_cast<const float4*>(quats + 4 * n);
+  return g;
+}
+
 // Returns false when the splat is not drawn (depth <= z_near or a
 // non-positive determinant); P is then only partly filled.
-__device__ __forceinline__ bool proj_chain64(const float* means, const float* log_scales, const float* quats,
-                                             const ViewConst& v, int64_t n, Proj64& P) {
-  to_camera64(v, means[3 * n], means[3 * n + 1], means[3 * n + 2], P.c);
+__device__ __forceinline__ bool proj_chain64(const NodeGeom& g, const ViewConst& v, Proj64& P) {
+  to_camera64(v, g.m[0], g.m[1], g.m[2], P.c);
   if (!(P.c[2] > (double)v.z_near)) return false;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) P.s[k] = fexp(log_scales[3 * n + k]);
-  const float4 qf = *reinterpret_cast<const float4*>(quats + 4 * n);
+  for (int k = 0; k < 3; ++k) P.s[k] = fexp(g.ls[k]);
+  const float4 qf = g.q;
   const double q0 = qf.x, q1 = qf.y, q2 = qf.z, q3 = qf.w;
   const double qq = ((q0 * q0 + q1 * q1) + q2 * q2) + q3 * q3;
   P.ql = __builtin_sqrt(qq);
@@ -79,6 +96,11 @@ __device__ __forceinline__ bool proj_chain64(const float* means, const float* lo
   P.C = ((U10 * T[3] + U11 * T[4]) + U12 * T[5]) + 0.3;
   P.det = P.A * P.C - P.B * P.B;
   return P.det > 0.0;
+}
+
+__device__ __forceinline__ bool proj_chain64(const float* means, const float* log_scales, const float* quats,
+                                             const ViewConst& v, int64_t n, Proj64& P) {
+  return proj_chain64(load_geom(means, log_scales, quats, n), v, P);
 }
 
 }  // namespace lodgs

@@ -5,16 +5,18 @@
 //             covariance from (scale, rotation), EWA Jacobian, projected
 //             covariance + 0.3 px^2, conic, square footprint, tile rectangle,
 //             opacity, SH colour.  Writes a 64-byte Splat record, the depth key
-//             and the tile count.
-//  sort       stable radix sort of the selected splats by FP32 depth bits, then
-//             (k_dup) one (tile, splat) instance per covered tile emitted in
-//             depth order, then a stable radix sort of the instances by tile:
-//             the result is the order of the 64-bit key (tile << 32 | depth),
-//             ties by selection order, with far less key traffic.
+//             and the tile count (0 for a splat that is not drawn).
+//  sort       order-preserving compaction of the drawn splats, stable radix
+//             sort of their FP32 depth bits, then (k_dup) one (tile, splat)
+//             instance per covered tile emitted in depth order, then a stable
+//             radix sort of the instances by tile: the result is the order of
+//             the 64-bit key (tile << 32 | depth), ties by selection order, with
+//             far less key traffic.
 //  k_ranges   first/last instance of every tile.
-//  k_blend    one workgroup per tile, one lane per pixel; splat records are
-//             staged in LDS in batches of 256; a wave skips a splat whose
-//             alpha >= 1/255 box misses its 16x4 pixels (known result).
+//  k_blend    one workgroup per tile, PX pixels per lane; splat records are
+//             staged in LDS one batch per workgroup size; a wave skips a splat
+//             whose alpha >= 1/255 box misses its 16 x 4 PX pixels (known
+//             result).
 #include "lodgs_internal.h"
 #include "lodgs_proj.h"
 
@@ -42,8 +44,12 @@ __device__ __forceinline__ Proj project_node(const SceneDev& S, const ViewConst&
   P.visible = false;
   P.x0 = P.x1 = P.y0 = P.y1 = 0;
   const int64_t n = node;
+  // every parameter but the colour is requested up front, before the
+  // near-plane test needs the mean
+  const NodeGeom geo = load_geom(S.means, S.log_scales, S.quats, n);
+  const float theta = S.opacity_logits[n];
   Proj64 G;
-  const bool ok = proj_chain64(S.means, S.log_scales, S.quats, v, n, G);
+  const bool ok = proj_chain64(geo, v, G);
   P.depth = (float)G.c[2];
   if (!ok) return P;
   const double A = G.A, B = G.B, C = G.C, det = G.det;
@@ -82,7 +88,6 @@ __device__ __forceinline__ Proj project_node(const SceneDev& S, const ViewConst&
   P.sp.se = (float)se;
   P.sp.h1 = (float)(-0.5 / l1);
   P.sp.h2 = (float)(-0.5 / l2);
-  const float theta = S.opacity_logits[n];
   P.sp.o = 1.0f / (1.0f + fexp(-theta));
   P.sp.radius = (float)r;
   P.sp.pad = 0.0f;
@@ -90,27 +95,25 @@ __device__ __forceinline__ Proj project_node(const SceneDev& S, const ViewConst&
   // q = x^T Sigma'^-1 x <= 2 ln(255 o), hence |x| <= sqrt(q_max Sigma'_00) per
   // axis.  Margins cover the FP32 evaluation of the power.
   const float lo = 255.0f * P.sp.o;
-  if (lo < 1.0f) {
-    P.sp.ex = -1.0f;
-    P.sp.ey = -1.0f;
-  } else {
-    const double qmax = 1.05 * (2.0 * (double)__logf(lo) + 0.01);
-    P.sp.ex = (float)(__builtin_sqrt(qmax * A) * 1.001 + 1.0);
-    P.sp.ey = (float)(__builtin_sqrt(qmax * C) * 1.001 + 1.0);
-  }
+  const bool faint = lo < 1.0f;  // alpha < 1/255 everywhere
+  const double qmax = 1.05 * (2.0 * (double)__logf(faint ? 1.0f : lo) + 0.01);
+  P.sp.ex = faint ? -1.0f : (float)(__builtin_sqrt(qmax * A) * 1.001 + 1.0);
+  P.sp.ey = faint ? -1.0f : (float)(__builtin_sqrt(qmax * C) * 1.001 + 1.0);
   return P;
 }
 
 // SH colour for the view direction (mu - pos) / |mu - pos|; returns the
 // unclamped value in raw[3].
+template <int DEG>
 __device__ __forceinline__ void sh_color(const SceneDev& S, const ViewConst& v, int64_t n, float* raw) {
   const float dx = S.means[3 * n] - v.pos[0], dy = S.means[3 * n + 1] - v.pos[1], dz = S.means[3 * n + 2] - v.pos[2];
   const float il = 1.0f / __builtin_sqrtf(dx * dx + dy * dy + dz * dz);
   float Y[16];
-  sh_basis(S.sh_degree, dx * il, dy * il, dz * il, Y);
-  const int nb = (S.sh_degree + 1) * (S.sh_degree + 1);
-  const float* c = S.sh + (int64_t)S.n_coef * n;
+  sh_basis(DEG, dx * il, dy * il, dz * il, Y);
+  constexpr int nb = (DEG + 1) * (DEG + 1);
+  const float* c = S.sh + (int64_t)(3 * nb) * n;
   float r = 0.5f, g = 0.5f, b = 0.5f;
+#pragma unroll
   for (int k = 0; k < nb; ++k) {
     r = __builtin_fmaf(c[3 * k], Y[k], r);
     g = __builtin_fmaf(c[3 * k + 1], Y[k], g);
@@ -121,41 +124,48 @@ __device__ __forceinline__ void sh_color(const SceneDev& S, const ViewConst& v, 
   raw[2] = b;
 }
 
+template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_project(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
                                                     const int32_t* d_count, int64_t cap, Splat* splats,
-                                                    uint32_t* depth_key, uint32_t* order, uint32_t* tiles,
-                                                    ushort4* rect, FrameCounters* ctr) {
+                                                    uint32_t* depth_key, uint32_t* tiles, ushort4* rect) {
   const ViewConst v = *vp;
   const int64_t n = clamp_count(d_count, cap);
-  int drawn = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t node = idx[i];
     Proj P = project_node(S, v, node);
     uint32_t t = 0;
     if (P.visible) {
       float raw[3];
-      sh_color(S, v, node, raw);
+      sh_color<DEG>(S, v, node, raw);
       P.sp.r = fmaxf(raw[0], 0.0f);
       P.sp.g = fmaxf(raw[1], 0.0f);
       P.sp.b = fmaxf(raw[2], 0.0f);
       t = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
       splats[i] = P.sp;
-      ++drawn;
+      depth_key[i] = __float_as_uint(P.depth);
+      rect[i] = make_ushort4((unsigned short)P.x0, (unsigned short)P.x1, (unsigned short)P.y0, (unsigned short)P.y1);
     }
-    depth_key[i] = P.visible ? __float_as_uint(P.depth) : 0xFFFFFFFFu;
-    order[i] = (uint32_t)i;
-    tiles[i] = t;
-    rect[i] = make_ushort4((unsigned short)P.x0, (unsigned short)P.x1, (unsigned short)P.y0, (unsigned short)P.y1);
+    tiles[i] = t;  // 0: not drawn
   }
-  for (int d = 32; d > 0; d >>= 1) drawn += __shfl_xor(drawn, d, 64);
-  if ((threadIdx.x & 63) == 0 && drawn) atomicAdd(&ctr->n_drawn, drawn);
 }
 
-__global__ void k_render_begin(FrameCounters* ctr, const int32_t* d_count, int64_t cap) {
-  int64_t n = *d_count;
-  n = n < 0 ? 0 : (n > cap ? cap : n);
-  ctr->n_render = (int32_t)n;
-  ctr->n_drawn = 0;
+struct LoadDrawn {
+  const uint32_t* tiles;
+  __device__ uint32_t operator()(int64_t i) const { return tiles[i] != 0u ? 1u : 0u; }
+};
+
+// Order-preserving compaction of the drawn splats: (depth key, selection
+// position) at the drawn splat's rank among the drawn ones.
+__global__ void __launch_bounds__(kBlock) k_compact_drawn(const FrameCounters* ctr, const uint32_t* tiles,
+                                                          const uint32_t* rank, const uint32_t* depth_key,
+                                                          uint32_t* key_out, uint32_t* val_out) {
+  const int64_t n = ctr->n_render;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (tiles[i] == 0u) continue;
+    const uint32_t r = rank[i];
+    key_out[r] = depth_key[i];
+    val_out[r] = (uint32_t)i;
+  }
 }
 
 struct LoadTilesInOrder {
@@ -164,19 +174,20 @@ struct LoadTilesInOrder {
   __device__ uint32_t operator()(int64_t r) const { return tiles[order[r]]; }
 };
 
-__global__ void k_inst_count(FrameCounters* ctr, int64_t cap) {
-  const int32_t n = ctr->n_instances;
-  ctr->n_inst_clamped = n > cap ? (int32_t)cap : n;
-  if (n > cap) ctr->status = LODGS_E_CAPACITY;
-}
-
 // One thread per (splat, tile) instance: the owning splat is found by binary
-// search over the instance offsets of the drawn splats (which lead the depth
-// order), so splats covering thousands of tiles cost no more than small ones.
-__global__ void __launch_bounds__(kBlock) k_dup(const FrameCounters* ctr, const uint32_t* order,
+// search over the instance offsets of the drawn splats in depth order, so
+// splats covering thousands of tiles cost no more than small ones.  The
+// instance count is clamped to the capacity here (thread 0 publishes the
+// clamped count for the later kernels and flags an overflow).
+__global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order,
                                                 const uint32_t* inst_off, const ushort4* rect, int32_t tiles_x,
-                                                uint32_t* ikey, uint32_t* ival) {
-  const int64_t n = ctr->n_inst_clamped;
+                                                int64_t cap, uint32_t* ikey, uint32_t* ival, uint32_t* inst_splat) {
+  const uint32_t total = (uint32_t)ctr->n_instances;  // the scan's 32-bit sum
+  const int64_t n = (int64_t)total > cap ? cap : (int64_t)total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctr->n_inst_clamped = (int32_t)n;
+    if ((int64_t)total > cap) ctr->status = LODGS_E_CAPACITY;
+  }
   const int32_t nd = ctr->n_drawn;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     int32_t lo = 0, hi = nd;  // largest r < nd with inst_off[r] <= k
@@ -189,14 +200,14 @@ __global__ void __launch_bounds__(kBlock) k_dup(const FrameCounters* ctr, const 
     const uint32_t l = (uint32_t)k - inst_off[lo];
     const ushort4 q = rect[i];
     const uint32_t w = (uint32_t)(q.y - q.x);
+    ival[k] = (uint32_t)k;  // the tile sort carries the emission index
+    inst_splat[k] = i;
     if (w == 0) {  // only reachable if the instance count overflowed
       ikey[k] = 0xFFFFFFFFu;
-      ival[k] = i;
       continue;
     }
     const uint32_t ty = q.z + l / w, tx = q.x + l % w;
     ikey[k] = ty * (uint32_t)tiles_x + tx;
-    ival[k] = i;
   }
 }
 
@@ -215,33 +226,54 @@ __global__ void __launch_bounds__(kBlock) k_ranges(const FrameCounters* ctr, con
   }
 }
 
-// One workgroup per tile, one lane per pixel.  alpha = min(0.99, o e^power),
-// skipped below 1/255; stop before the transmittance would drop below 1e-4.
-template <bool COUNT>
-__global__ void __launch_bounds__(256) k_blend(const ViewConst* __restrict__ vp, const uint2* ranges, const uint32_t* ival,
-                                               const Splat* splats, const FrameCounters* ctr, float bg0, float bg1,
-                                               float bg2, float* rgb, unsigned long long* work) {
+// One workgroup per tile with 4/PX waves, PX pixels per lane (wave w covers
+// the tile's rows [4 PX w, 4 PX (w + 1)), lane l the column l & 15 and the
+// rows 4 PX w + (l >> 4) + 4p, p < PX).  alpha = min(0.99, o e^power),
+// skipped below 1/255; a pixel stops before its transmittance would drop
+// below 1e-4.  Splat records are staged in LDS one batch per workgroup size
+// and read into registers one splat ahead; the per-pixel steps are written
+// with selects, so the only branches are wave-uniform.
+template <bool COUNT, int PX>
+__global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict__ vp, const uint2* __restrict__ ranges,
+                                                    const uint32_t* __restrict__ ival,
+                                                    const uint32_t* __restrict__ inst_splat,
+                                                    const Splat* __restrict__ splats, const FrameCounters* ctr,
+                                                    float bg0, float bg1, float bg2, float* rgb,
+                                                    unsigned long long* work) {
+  constexpr int NT = 256 / PX;
   const ViewConst v = *vp;
-  __shared__ Splat batch[256];
+  __shared__ Splat batch[NT];
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
-  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
-  const bool inside = px < v.width && py < v.height;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  // pixel-centre rectangle of this wave (16 x 4 pixels)
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int px = tx * kTile + (lane & 15);
+  const int py0 = ty * kTile + 4 * PX * wv + (lane >> 4);
+  const float fx = (float)px + 0.5f;
+  float fy[PX], T[PX], cr[PX], cg[PX], cb[PX];
+  bool inside[PX], live[PX];
+#pragma unroll
+  for (int p = 0; p < PX; ++p) {
+    fy[p] = (float)(py0 + 4 * p) + 0.5f;
+    inside[p] = px < v.width && py0 + 4 * p < v.height;
+    live[p] = inside[p];
+    T[p] = 1.0f;
+    cr[p] = cg[p] = cb[p] = 0.0f;
+  }
+  // pixel-centre rectangle of this wave (16 x 4 PX pixels)
   const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + 15.0f;
-  const float wy0 = (float)(ty * kTile + 4 * (threadIdx.x >> 6)) + 0.5f, wy1 = wy0 + 3.0f;
+  const float wy0 = (float)(ty * kTile + 4 * PX * wv) + 0.5f, wy1 = wy0 + (float)(4 * PX - 1);
   const uint2 rg = ranges[tile];
   const uint32_t nr = (uint32_t)ctr->n_render;
-  float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-  bool done = !inside;
   const float thr = 1.0f / 255.0f;
   unsigned long long n_eval = 0, n_contrib = 0;
-  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += 256) {
-    if (__syncthreads_count(done) == 256) break;
+  for (uint32_t b0 = rg.x; b0 < rg.y; b0 += NT) {
+    bool active = false;
+#pragma unroll
+    for (int p = 0; p < PX; ++p) active = active || live[p];
+    if (__syncthreads_count(active) == 0) break;
     const uint32_t k = b0 + threadIdx.x;
     if (k < rg.y) {
-      const uint32_t i = ival[k];
+      const uint32_t i = inst_splat[ival[k]];
       if (i < nr) {
         batch[threadIdx.x] = splats[i];
       } else {  // only reachable if the instance count overflowed
@@ -250,26 +282,42 @@ __global__ void __launch_bounds__(256) k_blend(const ViewConst* __restrict__ vp,
       }
     }
     __syncthreads();
-    const int m = (int)min(256u, rg.y - b0);
-    for (int j = 0; j < m && !done; ++j) {
-      const Splat& s = batch[j];
-      if (COUNT) ++n_eval;
-      else if (splat_misses(s, wx0, wx1, wy0, wy1)) continue;
-      float dx, dy, u1, u2;
-      const float power = splat_power(s, fx, fy, dx, dy, u1, u2);
-      const float alpha = fminf(0.99f, s.o * fexp(power));
-      if (alpha < thr) continue;
-      const float tt = T * (1.0f - alpha);
-      if (tt < 0.0001f) {
-        done = true;
-        break;
+    const int m = (int)min((uint32_t)NT, rg.y - b0);
+    if (!__any(active)) continue;  // wave-uniform
+    // one splat against the wave's pixels; true when every pixel has stopped
+    auto step = [&](const Splat& s) -> bool {
+      if (!COUNT && splat_misses(s, wx0, wx1, wy0, wy1)) return false;  // wave-uniform
+      bool act = false;
+#pragma unroll
+      for (int p = 0; p < PX; ++p) {
+        float dx, dy, u1, u2;
+        const float power = splat_power(s, fx, fy[p], dx, dy, u1, u2);
+        const float alpha = fminf(0.99f, s.o * fexp(power));
+        const float tt = T[p] * (1.0f - alpha);
+        const bool hit = live[p] & (alpha >= thr);
+        const bool stop = hit & (tt < 0.0001f);
+        const bool con = hit & !stop;
+        if (COUNT) {
+          n_eval += live[p] ? 1 : 0;
+          n_contrib += con ? 1 : 0;
+        }
+        live[p] = live[p] & !stop;
+        const float w = alpha * T[p];
+        cr[p] = con ? __builtin_fmaf(s.r, w, cr[p]) : cr[p];
+        cg[p] = con ? __builtin_fmaf(s.g, w, cg[p]) : cg[p];
+        cb[p] = con ? __builtin_fmaf(s.b, w, cb[p]) : cb[p];
+        T[p] = con ? tt : T[p];
+        act = act | live[p];
       }
-      const float w = alpha * T;
-      cr = __builtin_fmaf(s.r, w, cr);
-      cg = __builtin_fmaf(s.g, w, cg);
-      cb = __builtin_fmaf(s.b, w, cb);
-      T = tt;
-      if (COUNT) ++n_contrib;
+      return !__any(act);
+    };
+    // two register sets, each loaded one splat ahead of its use
+    Splat sa = batch[0], sb;
+    for (int j = 0;;) {
+      sb = batch[j + 1 < m ? j + 1 : j];
+      if (step(sa) || ++j >= m) break;
+      sa = batch[j + 1 < m ? j + 1 : j];
+      if (step(sb) || ++j >= m) break;
     }
   }
   if (COUNT) {
@@ -277,17 +325,39 @@ __global__ void __launch_bounds__(256) k_blend(const ViewConst* __restrict__ vp,
       n_eval += __shfl_xor(n_eval, d, 64);
       n_contrib += __shfl_xor(n_contrib, d, 64);
     }
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
       atomicAdd(work, n_eval);
       atomicAdd(work + 1, n_contrib);
     }
     return;
   }
-  if (inside) {
-    float* o = rgb + 3 * ((int64_t)py * v.width + px);
-    o[0] = __builtin_fmaf(T, bg0, cr);
-    o[1] = __builtin_fmaf(T, bg1, cg);
-    o[2] = __builtin_fmaf(T, bg2, cb);
+#pragma unroll
+  for (int p = 0; p < PX; ++p) {
+    if (!inside[p]) continue;
+    float* o = rgb + 3 * ((int64_t)(py0 + 4 * p) * v.width + px);
+    o[0] = __builtin_fmaf(T[p], bg0, cr[p]);
+    o[1] = __builtin_fmaf(T[p], bg1, cg[p]);
+    o[2] = __builtin_fmaf(T[p], bg2, cb[p]);
+  }
+}
+
+template <bool COUNT>
+static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], float* d_rgb, hipStream_t st) {
+  const int ntiles = v.tiles_x * v.tiles_y;
+  unsigned long long* work = COUNT ? f->work : nullptr;
+  switch (f->blend_px) {
+    case 1:
+      hipLaunchKernelGGL((k_blend<COUNT, 1>), dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges,
+                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, work);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_blend<COUNT, 4>), dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges,
+                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, work);
+      break;
+    default:
+      hipLaunchKernelGGL((k_blend<COUNT, 2>), dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges,
+                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, work);
+      break;
   }
 }
 
@@ -296,24 +366,35 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   const SceneDev& S = f->scene->dev;
   const int64_t cap = f->caps.max_selected, icap = f->caps.max_instances;
   stage_begin(f, LODGS_STAGE_PROJECT, st);
-  launch_set_view(v, f->d_view_ren, st);
-  hipLaunchKernelGGL(k_render_begin, dim3(1), dim3(1), 0, st, f->ctr, d_count, cap);
+  launch_set_view(v, f->d_view_ren, f->ctr, kViewRender, d_count, cap, st);
   const int pgrid = 2048;
-  hipLaunchKernelGGL(k_project, dim3(pgrid), dim3(kBlock), 0, st, S, f->d_view_ren, d_idx, d_count, cap, f->splats, f->depth_key,
-                     f->order, f->tiles, f->rect, f->ctr);
+  switch (S.sh_degree) {
+#define LODGS_PROJECT(D)                                                                                         \
+  hipLaunchKernelGGL(k_project<D>, dim3(pgrid), dim3(kBlock), 0, st, S, f->d_view_ren, d_idx, d_count, cap,   \
+                     f->splats, f->depth_key, f->tiles, f->rect)
+    case 0: LODGS_PROJECT(0); break;
+    case 1: LODGS_PROJECT(1); break;
+    case 2: LODGS_PROJECT(2); break;
+    default: LODGS_PROJECT(3); break;
+#undef LODGS_PROJECT
+  }
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_DEPTH_SORT, st);
+  // drawn splats only: ranks (in inst_off, free until the instance scan), then
+  // a stable sort of their depth keys, ties in selection order
+  scan_exclusive(LoadDrawn{f->tiles}, &f->ctr->n_render, cap, f->block_sums, f->inst_off, &f->ctr->n_drawn, st);
+  hipLaunchKernelGGL(k_compact_drawn, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, f->tiles, f->inst_off, f->depth_key,
+                     f->depth_key2, f->order);
   SortScratch ws{f->sort_table, f->block_sums, &f->ctr->sort_table_n};
-  const bool sw = sort_pairs(f->depth_key, f->order, f->depth_key2, f->order2, &f->ctr->n_render, cap, 32, ws, st);
+  const bool sw = sort_pairs(f->depth_key2, f->order, f->depth_key, f->order2, &f->ctr->n_drawn, cap, 32, ws, st);
   const uint32_t* order = sw ? f->order2 : f->order;
   f->sorted_order = order;
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_DUPLICATE, st);
-  scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_render, cap, f->block_sums, f->inst_off,
+  scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_drawn, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
-  hipLaunchKernelGGL(k_inst_count, dim3(1), dim3(1), 0, st, f->ctr, icap);
-  hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x,
-                     f->ikey, f->ival);
+  hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x, icap,
+                     f->ikey, f->ival, f->inst_splat);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
@@ -328,8 +409,7 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_ikey, f->ranges, (uint32_t)ntiles);
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_BLEND, st);
-  hipLaunchKernelGGL(k_blend<false>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival, f->splats, f->ctr,
-                     bg[0], bg[1], bg[2], d_rgb, (unsigned long long*)nullptr);
+  launch_blend<false>(f, v, bg, d_rgb, st);
   stage_end(f, st);
 }
 
@@ -339,11 +419,9 @@ __global__ void k_zero_work(unsigned long long* w) {
 }
 
 void launch_blend_count(lodgs_frame* f, hipStream_t st) {
-  const ViewConst& v = f->view;
-  const int ntiles = v.tiles_x * v.tiles_y;
   hipLaunchKernelGGL(k_zero_work, dim3(1), dim3(1), 0, st, f->work);
-  hipLaunchKernelGGL(k_blend<true>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival, f->splats, f->ctr,
-                     0.0f, 0.0f, 0.0f, (float*)nullptr, f->work);
+  const float zero[3] = {0.0f, 0.0f, 0.0f};
+  launch_blend<true>(f, f->view, zero, nullptr, st);
 }
 
 }  // namespace lodgs

@@ -88,15 +88,27 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewCons
 // are 64-node chunks of the upper hierarchy (predicate: selected), the rest
 // are chunks of at most kChunk candidates of the visible SPT prefixes
 // (predicate: r_min <= X_j); an SPT contributes ceil(high_j / kChunk)
-// chunks, located through the scan of those counts.  Pass 1 counts each
+// chunks, located through the scan of those counts (k_chunk_owner writes the
+// SPT of every chunk).  Pass 1 counts each
 // segment with ballots, a scan turns the counts into output offsets, pass 2
 // writes each segment's selected nodes in order with ballot ranks.  Segments
 // follow the layout order, so the output is ascending.
 constexpr int32_t kChunk = 512;
 
+// owner[t] = the SPT whose prefix holds candidate chunk t.
+__global__ void __launch_bounds__(kBlock) k_chunk_owner(const int32_t* spt_high, const uint32_t* ch_off, int32_t n_spt,
+                                                        uint32_t* owner) {
+  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_spt; j += gridDim.x * blockDim.x) {
+    const int32_t c = (spt_high[j] + kChunk - 1) / kChunk;
+    const uint32_t o = ch_off[j];
+    for (int32_t t = 0; t < c; ++t) owner[o + t] = (uint32_t)j;
+  }
+}
+
 template <bool WRITE>
 __global__ void __launch_bounds__(kBlock) k_segments(SceneDev S, const uint8_t* upper_sel, const int32_t* spt_high,
-                                                     const float* spt_X, const uint32_t* ch_off, int32_t n_up_chunks,
+                                                     const float* spt_X, const uint32_t* ch_off,
+                                                     const uint32_t* owner, int32_t n_up_chunks,
                                                      uint32_t* seg, int32_t* idx, int64_t capacity,
                                                      FrameCounters* ctr, int32_t* d_count) {
   const int lane = threadIdx.x & 63;
@@ -120,13 +132,7 @@ __global__ void __launch_bounds__(kBlock) k_segments(SceneDev S, const uint8_t* 
       up_count += c;
     } else {
       const uint32_t t = (uint32_t)(sg - n_up_chunks);
-      int32_t lo = 0, hi = S.n_spt;  // largest j with ch_off[j] <= t
-      while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (ch_off[mid] <= t) lo = mid;
-        else hi = mid;
-      }
-      const int32_t j = lo;
+      const int32_t j = (int32_t)owner[t];
       const int32_t h = spt_high[j];
       const int32_t e_begin = (int32_t)(t - ch_off[j]) * kChunk;
       const int32_t e_end = min(h, e_begin + kChunk);
@@ -159,20 +165,13 @@ struct LoadChunks {
   __device__ uint32_t operator()(int64_t j) const { return (uint32_t)((high[j] + kChunk - 1) / kChunk); }
 };
 
-__global__ void k_reset_select(FrameCounters* ctr) {
-  ctr->n_spt_visible = 0;
-  ctr->n_upper_selected = 0;
-  ctr->sum_high = 0;
-}
-
 }  // namespace
 
 void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
                    int32_t* d_count, hipStream_t st) {
   const SceneDev& S = f->scene->dev;
   stage_begin(f, LODGS_STAGE_SELECT, st);
-  launch_set_view(v, f->d_view_sel, st);
-  hipLaunchKernelGGL(k_reset_select, dim3(1), dim3(1), 0, st, f->ctr);
+  launch_set_view(v, f->d_view_sel, f->ctr, kViewSelect, nullptr, 0, st);
   const int64_t total = (int64_t)S.n_upper + S.n_spt;
   int grid = (int)((total + kBlock - 1) / kBlock);
   grid = grid < 1 ? 1 : (grid > 4096 ? 4096 : grid);
@@ -182,13 +181,15 @@ void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* 
   // chunks per visible SPT prefix -> offsets, total -> n_chunks
   scan_exclusive(LoadChunks{f->spt_high}, &f->ctr->spt_count, (int64_t)S.n_spt, f->block_sums, f->spt_off,
                  &f->ctr->n_chunks, st);
+  hipLaunchKernelGGL(k_chunk_owner, dim3((S.n_spt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, f->spt_high,
+                     f->spt_off, S.n_spt, f->chunk_owner);
   const int sgrid = 4096;
   const int64_t seg_cap = (int64_t)n_up_chunks + S.n_spt + S.n_nodes / kChunk + 1;
   hipLaunchKernelGGL(k_segments<false>, dim3(sgrid), dim3(kBlock), 0, st, S, f->upper_sel, f->spt_high, f->spt_X,
-                     f->spt_off, n_up_chunks, f->seg, (int32_t*)nullptr, capacity, f->ctr, d_count);
+                     f->spt_off, f->chunk_owner, n_up_chunks, f->seg, (int32_t*)nullptr, capacity, f->ctr, d_count);
   scan_exclusive(LoadArray{f->seg}, &f->ctr->seg_total, seg_cap, f->block_sums, f->seg, &f->ctr->n_selected, st);
   hipLaunchKernelGGL(k_segments<true>, dim3(sgrid), dim3(kBlock), 0, st, S, f->upper_sel, f->spt_high, f->spt_X,
-                     f->spt_off, n_up_chunks, f->seg, d_idx, capacity, f->ctr, d_count);
+                     f->spt_off, f->chunk_owner, n_up_chunks, f->seg, d_idx, capacity, f->ctr, d_count);
   stage_end(f, st);
 }
 
