@@ -25,10 +25,10 @@ int hip_fail(hipError_t e, const char* what) {
   return LODGS_E_HIP;
 }
 
-int blend_pixels_per_lane() {
-  const char* e = std::getenv("LODGS_BLEND_PX");
+int blend_pixels_per_lane(bool backward) {
+  const char* e = std::getenv(backward ? "LODGS_BLEND_PX_BWD" : "LODGS_BLEND_PX_FWD");
   if (e && (e[0] == '1' || e[0] == '2' || e[0] == '4') && e[1] == 0) return e[0] - '0';
-  return 2;
+  return backward ? 2 : 1;
 }
 
 // Per-view constants, FP32 on the host (IEEE single, correctly rounded / and
@@ -150,7 +150,7 @@ void free_frame(lodgs_frame* f) {
   if (f->open_event) (void)hipEventDestroy(f->open_event);
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->rect,
-                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_splat, f->inst_grad, f->ranges, f->d_view_sel,
+                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_splat, f->inst_grad, f->grad2d, f->ranges, f->d_view_sel,
                   f->d_view_ren};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -218,7 +218,8 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   if (!f) return set_error(LODGS_E_OOM, "lodgs_frame_create: out of host memory");
   f->scene = scene;
   f->caps = *caps;
-  f->blend_px = lodgs::blend_pixels_per_lane();
+  f->blend_px_fwd = lodgs::blend_pixels_per_lane(false);
+  f->blend_px_bwd = lodgs::blend_pixels_per_lane(true);
   const SceneDev& S = scene->dev;
   const size_t ns = (size_t)caps->max_selected, ni = (size_t)caps->max_instances;
   const size_t nt = (size_t)((caps->max_width + 15) / 16) * ((caps->max_height + 15) / 16);
@@ -247,6 +248,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(ival2, ni);
   A(inst_splat, ni);
   A(inst_grad, 9 * ni);
+  A(grad2d, 9 * ns);
   A(ranges, nt);
   A(work, 2);
   A(d_view_sel, 1);

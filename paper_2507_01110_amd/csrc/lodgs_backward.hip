@@ -23,7 +23,7 @@ namespace lodgs {
 // b0^b2, b1^b2, b2^b3 and b3 of l & 15) and adds its partner's copy of that
 // half.  Lane l then holds its row's sum of value
 // slot(l) = (b0^b2) + 2 (b1^b2) + 4 (b2^b3) + 8 b3 (slots 9..15 are zero);
-// two cross-row exchanges complete the sums over the wave.
+// in the wave form two cross-row exchanges complete the sums over the wave.
 #define LODGS_DPP(x, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false))
 #define LODGS_RS_PAIR(out, a, b, k, ctrl)       \
   do {                                          \
@@ -32,7 +32,7 @@ namespace lodgs {
     (out) = keep_ + LODGS_DPP(send_, ctrl);     \
   } while (0)
 
-__device__ __forceinline__ float wave_reduce_scatter9(const float* g, int lane, int& slot) {
+__device__ __forceinline__ float row_reduce_scatter9(const float* g, int lane, int& slot) {
   const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
   const bool k1 = (b0 ^ b2) != 0, k2 = (b1 ^ b2) != 0, k3 = (b2 ^ b3) != 0, k4 = b3 != 0;
   float h0, h1, h2, h3, h4;
@@ -50,9 +50,14 @@ __device__ __forceinline__ float wave_reduce_scatter9(const float* g, int lane, 
   LODGS_RS_PAIR(r1, q2, 0.0f, k3, 0x141);
   float z;
   LODGS_RS_PAIR(z, r0, r1, k4, 0x140);  // row_mirror: l^15
+  slot = (int)k1 + 2 * (int)k2 + 4 * (int)k3 + 8 * (int)k4;
+  return z;
+}
+
+__device__ __forceinline__ float wave_reduce_scatter9(const float* g, int lane, int& slot) {
+  float z = row_reduce_scatter9(g, lane, slot);
   z += __shfl_xor(z, 16, 64);
   z += __shfl_xor(z, 32, 64);
-  slot = (int)k1 + 2 * (int)k2 + 4 * (int)k3 + 8 * (int)k4;
   return z;
 }
 #undef LODGS_RS_PAIR
@@ -238,6 +243,36 @@ __global__ void __launch_bounds__(kBlock) k_zero_sel(const FrameCounters* ctr, i
   }
 }
 
+// Per drawn splat (rank r in depth order), the sum of its instance partials,
+// which are contiguous in emission order: 16 lanes per splat stride over the
+// range, then the in-row reduce-scatter leaves each of the 9 sums in one lane.
+// Fixed order, so deterministic; long ranges (splats covering many tiles) are
+// spread over 16 lanes instead of one thread.
+__global__ void __launch_bounds__(kBlock) k_sum_partials(const FrameCounters* ctr, const uint32_t* inst_off,
+                                                         const float* __restrict__ partial, float* grad2d) {
+  const int64_t n = ctr->n_drawn;
+  const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
+  const int lane = threadIdx.x & 63, sub = lane & 15;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r0 = wave * 4; r0 < n; r0 += waves * 4) {  // wave-uniform
+    const int64_t r = r0 + (lane >> 4);
+    float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (r < n) {
+      int64_t a = inst_off[r], b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
+      a = a < n_cl ? a : n_cl;
+      b = b < n_cl ? b : n_cl;
+      for (int64_t q = a + sub; q < b; q += 16) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) g[c] += partial[9 * q + c];
+      }
+    }
+    int slot;
+    const float z = row_reduce_scatter9(g, lane, slot);  // all lanes active
+    if (r < n && slot < 9) grad2d[9 * r + slot] = z;
+  }
+}
+
 // Colour backward for one splat: dL/dRGB (zero where the forward's FP32
 // colour was clamped at 0) to the SH coefficients (written to the optional
 // per-selection row and added to the optional node row) and to the view
@@ -297,24 +332,16 @@ __device__ __forceinline__ void sh_backward(const SceneDev& S, const ViewConst& 
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
                                                         const FrameCounters* ctr, const uint32_t* order,
-                                                        const uint32_t* inst_off, const float* partial,
-                                                        lodgs_grads sel, lodgs_grads nodes) {
+                                                        const float* grad2d, lodgs_grads sel, lodgs_grads nodes) {
   const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
-  const int64_t n_inst = ctr->n_instances, n_inst_cl = ctr->n_inst_clamped;
   constexpr int nc = 3 * (DEG + 1) * (DEG + 1);
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = order[r];
     const int64_t node = idx[i];
-    // 2D gradients: sum of the splat's per-instance partials, in emission order
-    int64_t a = inst_off[r], b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
-    a = a < n_inst_cl ? a : n_inst_cl;
-    b = b < n_inst_cl ? b : n_inst_cl;
-    float g2[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    for (int64_t q = a; q < b; ++q) {
+    float g2[9];  // 2D gradients of the splat (rank r)
 #pragma unroll
-      for (int c = 0; c < 9; ++c) g2[c] += partial[9 * q + c];
-    }
+    for (int c = 0; c < 9; ++c) g2[c] = grad2d[9 * r + c];
     double gdir[3];
     sh_backward<DEG>(S, v, node, g2, sel.d_sh ? sel.d_sh + nc * i : nullptr,
                      nodes.d_sh ? nodes.d_sh + nc * node : nullptr, gdir);
@@ -407,7 +434,7 @@ template <int DEG>
 static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodgs_grads& sel,
                                    const lodgs_grads& nodes, hipStream_t st) {
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->sorted_order, f->inst_off, f->inst_grad, sel, nodes);
+                     f->sorted_order, f->grad2d, sel, nodes);
 }
 
 void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
@@ -416,7 +443,7 @@ void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, 
   const ViewConst& v = f->view;
   stage_begin(f, LODGS_STAGE_BLEND_BWD, st);
   const int ntiles = v.tiles_x * v.tiles_y;
-  switch (f->blend_px) {
+  switch (f->blend_px_bwd) {
     case 1:
       hipLaunchKernelGGL(k_blend_bwd<1>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
                          f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_grad);
@@ -432,6 +459,7 @@ void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, 
   }
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_PROJECT_BWD, st);
+  hipLaunchKernelGGL(k_sum_partials, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->inst_off, f->inst_grad, f->grad2d);
   lodgs_grads none{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (sel) hipLaunchKernelGGL(k_zero_sel, dim3(1024), dim3(kBlock), 0, st, f->ctr, S.n_coef, *sel);
   const lodgs_grads gs = sel ? *sel : none, gn = nodes ? *nodes : none;

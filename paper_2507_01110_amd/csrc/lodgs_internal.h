@@ -79,6 +79,7 @@ struct lodgs_frame {
   uint32_t* ival2;
   uint32_t* inst_splat;   // [max_instances] selection position of each instance (emission order)
   float* inst_grad;       // [max_instances][9] per-instance 2D gradient partials (emission order)
+  float* grad2d;          // [max_selected][9] per-drawn-splat 2D gradients (depth rank)
   uint2* ranges;          // [max tiles]
   lodgs::ViewConst* d_view_sel;  // view constants of the last lod_select (device)
   lodgs::ViewConst* d_view_ren;  // view constants of the last render (device)
@@ -102,7 +103,8 @@ struct lodgs_frame {
   int open_stage;
   hipEvent_t open_event;
   unsigned long long* work;  // [2] evaluation / contribution counters (device)
-  int blend_px;              // pixels per lane of the blend kernels (1, 2 or 4)
+  int blend_px_fwd;          // pixels per lane of the forward blend (1, 2 or 4)
+  int blend_px_bwd;          // pixels per lane of the blend backward (1, 2 or 4)
 };
 
 namespace lodgs {
@@ -118,10 +120,11 @@ void launch_set_view(const ViewConst& v, ViewConst* dst, FrameCounters* ctr, int
 
 int hip_fail(hipError_t e, const char* what);
 
-// Pixels per lane of the blend kernels: 2, or LODGS_BLEND_PX (1, 2 or 4) when
-// set in the environment (a tuning knob: images are identical, gradients equal
-// up to the order of their sums).
-int blend_pixels_per_lane();
+// Pixels per lane of the forward blend (1) and the blend backward (2), or
+// LODGS_BLEND_PX_FWD / LODGS_BLEND_PX_BWD (1, 2 or 4) when set in the
+// environment (a tuning knob: images are identical, gradients equal up to the
+// order of their sums).
+int blend_pixels_per_lane(bool backward);
 
 // Timing mode: brackets a stage with events on the stream (no-op otherwise).
 void stage_begin(lodgs_frame* f, int stage, hipStream_t st);

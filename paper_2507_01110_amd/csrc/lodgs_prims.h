@@ -72,18 +72,29 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(Load load, const int32_t
   if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
 }
 
-// Single block of kScanGrid threads: exclusive scan of the block sums; writes
-// the grand total to *d_total (if not null).
-__global__ void __launch_bounds__(kScanGrid) k_scan_sums(uint32_t* block_sums, int32_t* d_total);
-
+// Each block first sums the totals of the blocks before it (block 0 also
+// sums all of them and writes the grand total to *d_total, if not null), then
+// scans its own segment.
 template <class Load>
 __global__ void __launch_bounds__(kBlock) k_scan_down(Load load, const int32_t* d_n, int64_t cap,
-                                                      const uint32_t* block_sums, uint32_t* out) {
+                                                      const uint32_t* block_sums, uint32_t* out, int32_t* d_total) {
   __shared__ uint32_t wt[kBlock / 64];
+  uint32_t before = 0, all = 0;
+  for (int t = threadIdx.x; t < kScanGrid; t += kBlock) {
+    const uint32_t x = block_sums[t];
+    before += t < (int)blockIdx.x ? x : 0u;
+    all += x;
+  }
+  uint32_t base;
+  block_exclusive_scan(before, wt, &base);
+  if (blockIdx.x == 0) {
+    uint32_t grand;
+    block_exclusive_scan(all, wt, &grand);
+    if (threadIdx.x == 0 && d_total) *d_total = (int32_t)grand;
+  }
   int64_t n = *d_n;
   n = n < 0 ? 0 : (n > cap ? cap : n);
   const Segment s = block_segment(n, kScanGrid);
-  uint32_t base = block_sums[blockIdx.x];
   for (int64_t t0 = s.begin; t0 < s.end; t0 += kBlock * 4) {
     const int64_t i0 = t0 + (int64_t)threadIdx.x * 4;
     uint32_t v[4];
@@ -106,14 +117,15 @@ struct LoadArray {
 };
 
 // out[i] = sum_{j < i} load(j) for i < min(*d_n, cap); *d_total = sum (may be
-// null).  block_sums: kScanGrid + 1 words of scratch.  out may alias the
-// array read by load.
+// null).  block_sums: kScanGrid words of scratch.  out may alias the array
+// read by load.  Two kernels: per-block totals, then per-block bases and the
+// scan of each segment.
 template <class Load>
 inline void scan_exclusive(Load load, const int32_t* d_n, int64_t cap, uint32_t* block_sums, uint32_t* out,
                            int32_t* d_total, hipStream_t st) {
   hipLaunchKernelGGL(k_scan_reduce<Load>, dim3(kScanGrid), dim3(kBlock), 0, st, load, d_n, cap, block_sums);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanGrid), 0, st, block_sums, d_total);
-  hipLaunchKernelGGL(k_scan_down<Load>, dim3(kScanGrid), dim3(kBlock), 0, st, load, d_n, cap, block_sums, out);
+  hipLaunchKernelGGL(k_scan_down<Load>, dim3(kScanGrid), dim3(kBlock), 0, st, load, d_n, cap, block_sums, out,
+                     d_total);
 }
 
 // ---------------------------------------------------------------- radix sort

@@ -3,31 +3,6 @@
 
 namespace lodgs {
 
-__global__ void __launch_bounds__(kScanGrid) k_scan_sums(uint32_t* block_sums, int32_t* d_total) {
-  __shared__ uint32_t wt[kScanGrid / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t v = block_sums[threadIdx.x];
-  uint32_t x = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t y = __shfl_up(x, d, 64);
-    if (lane >= d) x += y;
-  }
-  if (lane == 63) wt[wave] = x;
-  __syncthreads();
-  uint32_t base = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kScanGrid / 64; ++w) {
-    base += w < wave ? wt[w] : 0u;
-    tot += wt[w];
-  }
-  block_sums[threadIdx.x] = base + x - v;
-  if (threadIdx.x == 0) {
-    block_sums[kScanGrid] = tot;
-    if (d_total) *d_total = (int32_t)tot;
-  }
-}
-
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* keys, const int32_t* d_n, int64_t cap,
                                                        int shift, uint32_t* table) {
   __shared__ uint32_t h[256];

@@ -345,7 +345,7 @@ template <bool COUNT>
 static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], float* d_rgb, hipStream_t st) {
   const int ntiles = v.tiles_x * v.tiles_y;
   unsigned long long* work = COUNT ? f->work : nullptr;
-  switch (f->blend_px) {
+  switch (f->blend_px_fwd) {
     case 1:
       hipLaunchKernelGGL((k_blend<COUNT, 1>), dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges,
                          f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, work);
