@@ -90,6 +90,7 @@ __global__ void k_set_view(ViewConst v, ViewConst* dst, FrameCounters* ctr, int 
     n = n < 0 ? 0 : (n > cap ? cap : n);
     ctr->n_render = (int32_t)n;
     ctr->n_drawn = 0;
+    ctr->n_long = 0;
   }
 }
 }  // namespace
@@ -149,8 +150,8 @@ void free_frame(lodgs_frame* f) {
   }
   if (f->open_event) (void)hipEventDestroy(f->open_event);
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
-                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->rect,
-                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_splat, f->inst_grad, f->grad2d, f->ranges, f->d_view_sel,
+                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->rect,
+                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_splat, f->inst_grad, f->inst_event, f->grad2d, f->long_list, f->ranges, f->d_view_sel,
                   f->d_view_ren};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -241,6 +242,8 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(order2, ns);
   A(tiles, ns);
   A(inst_off, ns);
+  A(drawn_rank, ns);
+  A(drawn_list, ns);
   A(rect, ns);
   A(ikey, ni);
   A(ival, ni);
@@ -248,7 +251,9 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(ival2, ni);
   A(inst_splat, ni);
   A(inst_grad, 9 * ni);
+  A(inst_event, ni);
   A(grad2d, 9 * ns);
+  A(long_list, ns);
   A(ranges, nt);
   A(work, 2);
   A(d_view_sel, 1);

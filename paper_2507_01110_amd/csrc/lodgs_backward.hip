@@ -63,12 +63,23 @@ __device__ __forceinline__ float wave_reduce_scatter9(const float* g, int lane, 
 #undef LODGS_RS_PAIR
 #undef LODGS_DPP
 
-// Backward of the blend, same layout and decisions as the forward.  Per
-// batch, each wave reduces the 9 gradient values of a splat over its lanes
-// (only when some lane contributes) and stores them in its own LDS row; the
-// workgroup then sums the rows in wave order and writes one 9-float partial
-// per (splat, tile) instance at the instance's emission index, with zeros for
-// instances that no pixel reached.  No atomics: the result is deterministic.
+// Backward of the blend: the forward's decisions, pixel layout blend_pixel<PX>.
+// A wave replays only the splats whose forward event bits cover one of its
+// quarters: elsewhere no pixel of the wave blended the splat or stopped on it
+// in the forward, so the replay would leave every value unchanged.
+//
+// Per pixel, dL/dalpha = T (G . c) - (G . (C - Q)) / (1 - alpha), with G =
+// dL/dC, c the splat colour, C the final colour and Q the colour blended up
+// to and including the splat; G . C is fixed per pixel and G . Q is kept as
+// one running scalar.  The per-pixel sums are taken in the splat's eigenbasis
+// (sum of dpow u1, dpow u2) and without constant factors (dpow dx^2,
+// dpow dx dy, dpow dy^2); the per-splat rotation and factors are applied once
+// per instance when the partial is written.  Per batch, each wave reduces
+// these 9 values of a splat over its lanes (only when some lane contributes)
+// and stores them in its own LDS row; the workgroup then sums the rows in wave
+// order and writes one 9-float partial per (splat, tile) instance at the
+// instance's emission index, with zeros for instances that no pixel reached.
+// No atomics: the result is deterministic.
 template <int PX>
 __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restrict__ vp,
                                                         const uint2* __restrict__ ranges,
@@ -76,40 +87,38 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
                                                         const uint32_t* __restrict__ inst_splat,
                                                         const Splat* __restrict__ splats, const FrameCounters* ctr,
                                                         const float* __restrict__ rgb, const float* __restrict__ dL,
+                                                        const uint8_t* __restrict__ event,
                                                         float* __restrict__ partial) {
   constexpr int NT = 256 / PX, NW = 4 / PX;
   const ViewConst v = *vp;
   __shared__ Splat batch[NT];
   __shared__ uint32_t bid[NT];
+  __shared__ uint32_t ev[NT];
+  const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
   __shared__ float acc[NW][9][NT];
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int px = tx * kTile + (lane & 15);
-  const int py0 = ty * kTile + 4 * PX * wv + (lane >> 4);
-  const float fx = (float)px + 0.5f;
-  float fy[PX], T[PX], P0[PX], P1[PX], P2[PX], C0[PX], C1[PX], C2[PX], G0[PX], G1[PX], G2[PX];
+  int px = 0;
+  float fy[PX], T[PX], GQ[PX], GC[PX], G0[PX], G1[PX], G2[PX];
   bool live[PX];
 #pragma unroll
   for (int p = 0; p < PX; ++p) {
-    const int py = py0 + 4 * p;
+    int py;
+    blend_pixel<PX>(tx, ty, wv, lane, p, px, py);
     fy[p] = (float)py + 0.5f;
     live[p] = px < v.width && py < v.height;
     T[p] = 1.0f;
-    P0[p] = P1[p] = P2[p] = 0.0f;
-    C0[p] = C1[p] = C2[p] = G0[p] = G1[p] = G2[p] = 0.0f;
+    GQ[p] = GC[p] = G0[p] = G1[p] = G2[p] = 0.0f;
     if (live[p]) {
       const int64_t o = 3 * ((int64_t)py * v.width + px);
-      C0[p] = rgb[o];
-      C1[p] = rgb[o + 1];
-      C2[p] = rgb[o + 2];
       G0[p] = dL[o];
       G1[p] = dL[o + 1];
       G2[p] = dL[o + 2];
+      GC[p] = __builtin_fmaf(G2[p], rgb[o + 2], __builtin_fmaf(G1[p], rgb[o + 1], G0[p] * rgb[o]));
     }
   }
-  const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + 15.0f;
-  const float wy0 = (float)(ty * kTile + 4 * PX * wv) + 0.5f, wy1 = wy0 + (float)(4 * PX - 1);
+  const float fx = (float)px + 0.5f;
   const uint2 rg = ranges[tile];
   const uint32_t nr = (uint32_t)ctr->n_render;
   const float thr = 1.0f / 255.0f;
@@ -125,11 +134,13 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
       const uint32_t e = ival[k];
       const uint32_t i = inst_splat[e];
       bid[threadIdx.x] = e;
+      ev[threadIdx.x] = event[k];
       if (i < nr) {
         batch[threadIdx.x] = splats[i];
       } else {  // only reachable if the instance count overflowed
-        batch[threadIdx.x].o = 0.0f;
-        batch[threadIdx.x].ex = -1.0f;
+        Splat z = {};
+        z.ex = -1.0f;
+        batch[threadIdx.x] = z;
       }
     }
     __syncthreads();
@@ -138,7 +149,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
       // one splat (batch slot j) against the wave's pixels; true when every
       // pixel has stopped
       auto step = [&](const Splat& s, int j) -> bool {
-        if (splat_misses(s, wx0, wx1, wy0, wy1)) return false;  // wave-uniform
+        if ((ev[j] & qmask) == 0u) return false;  // wave-uniform
         float dxs[PX], dys[PX], u1s[PX], u2s[PX], es[PX], oes[PX], als[PX], tts[PX];
         bool cons[PX];
         bool any_con = false, act = false;
@@ -162,31 +173,28 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
           for (int p = 0; p < PX; ++p) {
             const float alpha = als[p], Tp = T[p];
             const float w = alpha * Tp;
-            const float q0 = __builtin_fmaf(s.r, w, P0[p]);
-            const float q1 = __builtin_fmaf(s.g, w, P1[p]);
-            const float q2 = __builtin_fmaf(s.b, w, P2[p]);
+            const float Gc = __builtin_fmaf(G2[p], s.b, __builtin_fmaf(G1[p], s.g, G0[p] * s.r));
+            const float gq = __builtin_fmaf(w, Gc, GQ[p]);
             const float ia = __builtin_amdgcn_rcpf(1.0f - alpha);  // gradient values only
-            float dA = G0[p] * (s.r * Tp - (C0[p] - q0) * ia);
-            dA = __builtin_fmaf(G1[p], s.g * Tp - (C1[p] - q1) * ia, dA);
-            dA = __builtin_fmaf(G2[p], s.b * Tp - (C2[p] - q2) * ia, dA);
+            const float dA = Tp * Gc - (GC[p] - gq) * ia;
             const bool con = cons[p];
             const bool unclamped = con & (oes[p] <= 0.99f);
-            const float dpow = dA * alpha;
-            // d power / d mean2D = -2 (h1 u1 e1 + h2 u2 e2), e1 = (ce, se), e2 = (-se, ce)
-            const float k1 = -2.0f * s.h1 * u1s[p], k2 = -2.0f * s.h2 * u2s[p];
-            const float dx = dxs[p], dy = dys[p];
-            g[0] += unclamped ? dpow * (k1 * s.ce - k2 * s.se) : 0.0f;
-            g[1] += unclamped ? dpow * (k1 * s.se + k2 * s.ce) : 0.0f;
-            g[2] += unclamped ? dpow * (-0.5f * dx * dx) : 0.0f;
-            g[3] += unclamped ? dpow * (-dx * dy) : 0.0f;
-            g[4] += unclamped ? dpow * (-0.5f * dy * dy) : 0.0f;
-            g[5] += unclamped ? dA * es[p] : 0.0f;
-            g[6] += con ? G0[p] * w : 0.0f;
-            g[7] += con ? G1[p] * w : 0.0f;
-            g[8] += con ? G2[p] * w : 0.0f;
-            P0[p] = con ? q0 : P0[p];
-            P1[p] = con ? q1 : P1[p];
-            P2[p] = con ? q2 : P2[p];
+            // the factors are zeroed for pixels without a contribution (the
+            // other factors are finite), so the sums need no further selects
+            const float dpow = unclamped ? dA * alpha : 0.0f;
+            const float dop = unclamped ? dA * es[p] : 0.0f;
+            const float wc = con ? w : 0.0f;
+            const float tx = dpow * dxs[p], ty = dpow * dys[p];
+            g[0] = __builtin_fmaf(dpow, u1s[p], g[0]);
+            g[1] = __builtin_fmaf(dpow, u2s[p], g[1]);
+            g[2] = __builtin_fmaf(tx, dxs[p], g[2]);
+            g[3] = __builtin_fmaf(tx, dys[p], g[3]);
+            g[4] = __builtin_fmaf(ty, dys[p], g[4]);
+            g[5] += dop;
+            g[6] = __builtin_fmaf(G0[p], wc, g[6]);
+            g[7] = __builtin_fmaf(G1[p], wc, g[7]);
+            g[8] = __builtin_fmaf(G2[p], wc, g[8]);
+            GQ[p] = con ? gq : GQ[p];
             T[p] = con ? tts[p] : Tp;
           }
           int slot;
@@ -206,18 +214,29 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
-      float* dst = partial + 9 * (int64_t)bid[threadIdx.x];
+      float r[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
-        float r = acc[0][c][threadIdx.x];
+        r[c] = acc[0][c][threadIdx.x];
         acc[0][c][threadIdx.x] = 0.0f;
 #pragma unroll
         for (int w = 1; w < NW; ++w) {
-          r += acc[w][c][threadIdx.x];
+          r[c] += acc[w][c][threadIdx.x];
           acc[w][c][threadIdx.x] = 0.0f;
         }
-        dst[c] = r;
       }
+      // d power / d mean2D = -2 (h1 u1 e1 + h2 u2 e2), e1 = (ce, se),
+      // e2 = (-se, ce); d power / d conic = -(dx^2 / 2, dx dy, dy^2 / 2)
+      const Splat& s = batch[threadIdx.x];
+      const float a1 = -2.0f * s.h1 * r[0], a2 = -2.0f * s.h2 * r[1];
+      float* dst = partial + 9 * (int64_t)bid[threadIdx.x];
+      dst[0] = a1 * s.ce - a2 * s.se;
+      dst[1] = a1 * s.se + a2 * s.ce;
+      dst[2] = -0.5f * r[2];
+      dst[3] = -r[3];
+      dst[4] = -0.5f * r[4];
+#pragma unroll
+      for (int c = 5; c < 9; ++c) dst[c] = r[c];
     }
   }
   // instances that no pixel of the tile reached
@@ -243,108 +262,246 @@ __global__ void __launch_bounds__(kBlock) k_zero_sel(const FrameCounters* ctr, i
   }
 }
 
-// Per drawn splat (rank r in depth order), the sum of its instance partials,
-// which are contiguous in emission order: 16 lanes per splat stride over the
-// range, then the in-row reduce-scatter leaves each of the 9 sums in one lane.
-// Fixed order, so deterministic; long ranges (splats covering many tiles) are
-// spread over 16 lanes instead of one thread.
-__global__ void __launch_bounds__(kBlock) k_sum_partials(const FrameCounters* ctr, const uint32_t* inst_off,
-                                                         const float* __restrict__ partial, float* grad2d) {
+// Lane of a row that holds value slot s after row_reduce_scatter9 (inverse of
+// slot(l): b3 = k4, b2 = k3 ^ b3, b1 = k2 ^ b2, b0 = k1 ^ b2).
+__device__ __forceinline__ int rs_lane_of_slot(int s) {
+  const int k1 = s & 1, k2 = (s >> 1) & 1, k3 = (s >> 2) & 1, k4 = (s >> 3) & 1;
+  const int b3 = k4, b2 = k3 ^ b3, b1 = k2 ^ b2, b0 = k1 ^ b2;
+  return b0 | (b1 << 1) | (b2 << 2) | (b3 << 3);
+}
+
+// Sum over a 16-lane row (every lane gets it); all lanes active.
+__device__ __forceinline__ float row_sum(float x) {
+#define LODGS_DPP(v, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, false))
+  x += LODGS_DPP(x, 0xB1);   // l^1
+  x += LODGS_DPP(x, 0x4E);   // l^2
+  x += LODGS_DPP(x, 0x141);  // l^7 inside 8
+  x += LODGS_DPP(x, 0x140);  // l^15 inside 16
+#undef LODGS_DPP
+  return x;
+}
+
+// Basis function k (k < 16) and its gradient at the unit direction (x, y, z):
+// the same expressions as sh_basis / sh_basis_grad, one function per case.
+__device__ __forceinline__ void sh_basis_one(int k, float x, float y, float z, float& Y, float* dY) {
+  const float xx = x * x, yy = y * y, zz = z * z;
+  float a = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  switch (k) {
+    case 0: a = kSH0; break;
+    case 1: a = -kSH1 * y; gy = -kSH1; break;
+    case 2: a = kSH1 * z; gz = kSH1; break;
+    case 3: a = -kSH1 * x; gx = -kSH1; break;
+    case 4: a = kSH2_0 * x * y; gx = kSH2_0 * y; gy = kSH2_0 * x; break;
+    case 5: a = kSH2_1 * y * z; gy = kSH2_1 * z; gz = kSH2_1 * y; break;
+    case 6:
+      a = kSH2_2 * (2.0f * zz - xx - yy);
+      gx = -2.0f * kSH2_2 * x; gy = -2.0f * kSH2_2 * y; gz = 4.0f * kSH2_2 * z;
+      break;
+    case 7: a = kSH2_3 * x * z; gx = kSH2_3 * z; gz = kSH2_3 * x; break;
+    case 8: a = kSH2_4 * (xx - yy); gx = 2.0f * kSH2_4 * x; gy = -2.0f * kSH2_4 * y; break;
+    case 9: a = kSH3_0 * y * (3.0f * xx - yy); gx = 6.0f * kSH3_0 * x * y; gy = kSH3_0 * (3.0f * xx - 3.0f * yy); break;
+    case 10: a = kSH3_1 * x * y * z; gx = kSH3_1 * y * z; gy = kSH3_1 * x * z; gz = kSH3_1 * x * y; break;
+    case 11:
+      a = kSH3_2 * y * (4.0f * zz - xx - yy);
+      gx = -2.0f * kSH3_2 * x * y; gy = kSH3_2 * (4.0f * zz - xx - 3.0f * yy); gz = 8.0f * kSH3_2 * y * z;
+      break;
+    case 12:
+      a = kSH3_3 * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+      gx = -6.0f * kSH3_3 * x * z; gy = -6.0f * kSH3_3 * y * z; gz = kSH3_3 * (6.0f * zz - 3.0f * xx - 3.0f * yy);
+      break;
+    case 13:
+      a = kSH3_4 * x * (4.0f * zz - xx - yy);
+      gx = kSH3_4 * (4.0f * zz - 3.0f * xx - yy); gy = -2.0f * kSH3_4 * x * y; gz = 8.0f * kSH3_4 * x * z;
+      break;
+    case 14: a = kSH3_5 * z * (xx - yy); gx = 2.0f * kSH3_5 * x * z; gy = -2.0f * kSH3_5 * y * z; gz = kSH3_5 * (xx - yy); break;
+    default: a = kSH3_6 * x * (xx - 3.0f * yy); gx = kSH3_6 * (3.0f * xx - 3.0f * yy); gy = -6.0f * kSH3_6 * x * y; break;
+  }
+  Y = a;
+  dY[0] = gx;
+  dY[1] = gy;
+  dY[2] = gz;
+}
+
+// Splats with more than kLongSegment instances: one workgroup per splat sums
+// its instance partials (independent unrolled loads, then a fixed-order
+// reduction: deterministic) into grad2d at the splat's drawn rank.
+__global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, const uint32_t* long_list,
+                                                      const uint32_t* order, const uint32_t* drawn_rank,
+                                                      const uint32_t* inst_off, const float* __restrict__ partial,
+                                                      float* grad2d) {
+  __shared__ float part[kBlock / 64][9];
+  const int64_t n = ctr->n_drawn, nl = ctr->n_long;
+  const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int64_t li = blockIdx.x; li < nl; li += gridDim.x) {  // block-uniform
+    const int64_t r = long_list[li];
+    int64_t a = inst_off[r], b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
+    a = a < n_cl ? a : n_cl;
+    b = b < n_cl ? b : n_cl;
+    float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t q0 = a + threadIdx.x; q0 < b; q0 += 4 * kBlock) {
+      float t[4][9];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t q = q0 + (int64_t)u * kBlock;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) t[u][c] = q < b ? partial[9 * q + c] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) g[c] += t[u][c];
+    }
+    int slot;
+    const float z = wave_reduce_scatter9(g, lane, slot);
+    if (lane < 16 && slot < 9) part[wv][slot] = z;
+    __syncthreads();
+    if (threadIdx.x < 9) {
+      float sum = part[0][threadIdx.x];
+#pragma unroll
+      for (int w = 1; w < kBlock / 64; ++w) sum += part[w][threadIdx.x];
+      grad2d[9 * (int64_t)drawn_rank[order[r]] + threadIdx.x] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// Per drawn splat (rank r in depth order), 16 lanes: (1) the sum of its
+// instance partials, contiguous in emission order (the lanes stride over the
+// range, then the in-row reduce-scatter leaves each of the 9 sums in one
+// lane; fixed order, so deterministic), or, for a splat with more than
+// kLongSegment instances, the sums k_long_sums left in grad2d; (2) the colour
+// backward: dL/dRGB (zero for a channel
+// the forward clamped at 0, a decision the forward recorded) to the SH
+// coefficients, lane k taking basis function k (contiguous reads and writes of
+// the 192-byte coefficient block), and to the view direction, summed over the
+// row.  grad2d at the splat's drawn rank receives the 6 geometric 2D
+// gradients (mean2D, conic, opacity) and dL/dmean through the view direction.
+template <int DEG>
+__global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewConst* __restrict__ vp,
+                                                      const int32_t* idx, const FrameCounters* ctr,
+                                                      const uint32_t* order, const uint32_t* inst_off,
+                                                      const uint32_t* drawn_rank, const float* __restrict__ partial,
+                                                      const Splat* splats, float* grad2d, float* sel_sh,
+                                                      float* node_sh) {
+  constexpr int nb = (DEG + 1) * (DEG + 1), nc = 3 * nb;
+  const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
   const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
-  const int lane = threadIdx.x & 63, sub = lane & 15;
+  const int lane = threadIdx.x & 63, sub = lane & 15, row = lane & ~15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t r0 = wave * 4; r0 < n; r0 += waves * 4) {  // wave-uniform
     const int64_t r = r0 + (lane >> 4);
+    const bool live = r < n;
     float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    if (r < n) {
+    int64_t i = 0, node = 0, dr = 0;
+    // per-splat inputs of the colour part, requested together with the
+    // partials (they depend only on the splat)
+    uint32_t clamp = 0;
+    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, sh3[3] = {0.0f, 0.0f, 0.0f}, acc3[3] = {0.0f, 0.0f, 0.0f};
+    if (live) {
+      i = order[r];
+      node = idx[i];
+      dr = drawn_rank[i];
+      clamp = splats[i].clamp;
+      m0 = S.means[3 * node];
+      m1 = S.means[3 * node + 1];
+      m2 = S.means[3 * node + 2];
+      if (sub < nb) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          sh3[c] = S.sh[(int64_t)nc * node + 3 * sub + c];
+          if (node_sh) acc3[c] = node_sh[(int64_t)nc * node + 3 * sub + c];
+        }
+      }
       int64_t a = inst_off[r], b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
       a = a < n_cl ? a : n_cl;
       b = b < n_cl ? b : n_cl;
-      for (int64_t q = a + sub; q < b; q += 16) {
+      if (b - a > (int64_t)kLongSegment) {  // summed by k_long_sums
+        if (sub == 0) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) g[c] += partial[9 * q + c];
+          for (int c = 0; c < 9; ++c) g[c] = grad2d[9 * dr + c];
+        }
+      } else {  // at most 4 instances per lane, loads issued together
+        float t[4][9];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t q = a + sub + 16 * u;
+#pragma unroll
+          for (int c = 0; c < 9; ++c) t[u][c] = q < b ? partial[9 * q + c] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < 9; ++c) g[c] += t[u][c];
       }
     }
     int slot;
     const float z = row_reduce_scatter9(g, lane, slot);  // all lanes active
-    if (r < n && slot < 9) grad2d[9 * r + slot] = z;
-  }
-}
-
-// Colour backward for one splat: dL/dRGB (zero where the forward's FP32
-// colour was clamped at 0) to the SH coefficients (written to the optional
-// per-selection row and added to the optional node row) and to the view
-// direction; returns dL/dmean from the direction term.  DEG is the SH degree,
-// so the basis lives in registers.
-template <int DEG>
-__device__ __forceinline__ void sh_backward(const SceneDev& S, const ViewConst& v, int64_t node, const float* g2,
-                                            float* sel_sh, float* node_sh, double* gdir) {
-  constexpr int nb = (DEG + 1) * (DEG + 1);
-  const float* shc = S.sh + (int64_t)(3 * nb) * node;
-  const double mx = S.means[3 * node], my = S.means[3 * node + 1], mz = S.means[3 * node + 2];
-  const double dx = mx - (double)v.pos[0], dy = my - (double)v.pos[1], dz = mz - (double)v.pos[2];
-  // the forward's FP32 colour decides the clamp at 0
-  float raw[3] = {0.5f, 0.5f, 0.5f};
-  {
-    const float il = 1.0f / __builtin_sqrtf((float)dx * (float)dx + (float)dy * (float)dy + (float)dz * (float)dz);
-    float Yf[16];
-    sh_basis(DEG, (float)dx * il, (float)dy * il, (float)dz * il, Yf);
+    if (live && slot < 6) grad2d[9 * dr + slot] = z;
+    const float gr = __shfl(z, row + rs_lane_of_slot(6), 64);
+    const float gg = __shfl(z, row + rs_lane_of_slot(7), 64);
+    const float gb = __shfl(z, row + rs_lane_of_slot(8), 64);
+    float ddx = 0.0f, ddy = 0.0f, ddz = 0.0f;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, dl = 1.0;
+    if (live) {
+      const double dRGB[3] = {(clamp & 1u) ? 0.0 : (double)gr, (clamp & 2u) ? 0.0 : (double)gg,
+                              (clamp & 4u) ? 0.0 : (double)gb};
+      const double dx = (double)m0 - (double)v.pos[0];
+      const double dy = (double)m1 - (double)v.pos[1];
+      const double dz = (double)m2 - (double)v.pos[2];
+      dl = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
+      d0 = dx / dl;
+      d1 = dy / dl;
+      d2 = dz / dl;
+      if (sub < nb) {
+        float Yk, dYk[3];
+        sh_basis_one(sub, (float)d0, (float)d1, (float)d2, Yk, dYk);
+        double a = 0.0;
 #pragma unroll
-    for (int k = 0; k < nb; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) raw[c] = __builtin_fmaf(shc[3 * k + c], Yf[k], raw[c]);
-  }
-  double dRGB[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) dRGB[c] = raw[c] < 0.0f ? 0.0 : (double)g2[6 + c];
-  const double dl = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
-  const double d0 = dx / dl, d1 = dy / dl, d2 = dz / dl;
-  float Y[16], dY[16][3];
-  sh_basis(DEG, (float)d0, (float)d1, (float)d2, Y);
-  sh_basis_grad(DEG, (float)d0, (float)d1, (float)d2, dY);
-  double dd[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k = 0; k < nb; ++k) {
-    double a = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float gk = (float)(dRGB[c] * (double)Y[k]);
-      if (sel_sh) sel_sh[3 * k + c] = gk;
-      if (node_sh) node_sh[3 * k + c] += gk;
-      a += dRGB[c] * (double)shc[3 * k + c];
+        for (int c = 0; c < 3; ++c) {
+          const float gk = (float)(dRGB[c] * (double)Yk);
+          if (sel_sh) sel_sh[(int64_t)nc * i + 3 * sub + c] = gk;
+          if (node_sh) node_sh[(int64_t)nc * node + 3 * sub + c] = acc3[c] + gk;
+          a += dRGB[c] * (double)sh3[c];
+        }
+        ddx = (float)(a * (double)dYk[0]);
+        ddy = (float)(a * (double)dYk[1]);
+        ddz = (float)(a * (double)dYk[2]);
+      }
     }
-    dd[0] += a * (double)dY[k][0];
-    dd[1] += a * (double)dY[k][1];
-    dd[2] += a * (double)dY[k][2];
+    ddx = row_sum(ddx);  // all lanes active
+    ddy = row_sum(ddy);
+    ddz = row_sum(ddz);
+    if (live && sub == 0) {
+      const double dot = (double)ddx * d0 + (double)ddy * d1 + (double)ddz * d2;
+      grad2d[9 * dr + 6] = (float)(((double)ddx - d0 * dot) / dl);
+      grad2d[9 * dr + 7] = (float)(((double)ddy - d1 * dot) / dl);
+      grad2d[9 * dr + 8] = (float)(((double)ddz - d2 * dot) / dl);
+    }
   }
-  const double dot = dd[0] * d0 + dd[1] * d1 + dd[2] * d2;
-  gdir[0] = (dd[0] - d0 * dot) / dl;
-  gdir[1] = (dd[1] - d1 * dot) / dl;
-  gdir[2] = (dd[2] - d2 * dot) / dl;
 }
 
-// One thread per drawn splat: order[0 .. n_drawn) lists exactly the drawn
-// splats in depth order (no lanes idle on culled ones).
-// The colour part runs first so that its registers are free before the FP64
-// geometry chain is replayed.
+// One thread per drawn splat, in selection order (ascending node index, so
+// neighbouring lanes touch neighbouring nodes): drawn_list[0 .. n_drawn)
+// lists exactly the drawn splats.  The FP64 geometry chain is replayed and
+// the 2D gradients of grad2d[r] are carried to the mean, scales, rotation and
+// opacity logit; grad2d[r][6..8] already holds dL/dmean through the view
+// direction.
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
-                                                        const FrameCounters* ctr, const uint32_t* order,
+                                                        const FrameCounters* ctr, const uint32_t* drawn_list,
                                                         const float* grad2d, lodgs_grads sel, lodgs_grads nodes) {
   const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
-  constexpr int nc = 3 * (DEG + 1) * (DEG + 1);
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = order[r];
+    const int64_t i = drawn_list[r];
     const int64_t node = idx[i];
-    float g2[9];  // 2D gradients of the splat (rank r)
+    float g2[9];  // 2D gradients of the splat (drawn rank r)
 #pragma unroll
     for (int c = 0; c < 9; ++c) g2[c] = grad2d[9 * r + c];
-    double gdir[3];
-    sh_backward<DEG>(S, v, node, g2, sel.d_sh ? sel.d_sh + nc * i : nullptr,
-                     nodes.d_sh ? nodes.d_sh + nc * node : nullptr, gdir);
+    const double gdir[3] = {g2[6], g2[7], g2[8]};
     double gm[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
     Proj64 P;
     const bool visible = proj_chain64(S.means, S.log_scales, S.quats, v, node, P);
@@ -433,8 +590,15 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewCo
 template <int DEG>
 static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodgs_grads& sel,
                                    const lodgs_grads& nodes, hipStream_t st) {
+  // 16 splats per block: one pass covers 256k drawn splats, so each 16-lane
+  // group runs its latency-bound chain of dependent loads once
+  hipLaunchKernelGGL(k_long_sums, dim3(1024), dim3(kBlock), 0, st, f->ctr, f->long_list, f->sorted_order,
+                     f->drawn_rank, f->inst_off, f->inst_grad, f->grad2d);
+  hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
+                     f->sorted_order, f->inst_off, f->drawn_rank, f->inst_grad, f->splats, f->grad2d, sel.d_sh,
+                     nodes.d_sh);
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->sorted_order, f->grad2d, sel, nodes);
+                     f->drawn_list, f->grad2d, sel, nodes);
 }
 
 void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
@@ -446,20 +610,19 @@ void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, 
   switch (f->blend_px_bwd) {
     case 1:
       hipLaunchKernelGGL(k_blend_bwd<1>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_grad);
+                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->inst_grad);
       break;
     case 4:
       hipLaunchKernelGGL(k_blend_bwd<4>, dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_grad);
+                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->inst_grad);
       break;
     default:
       hipLaunchKernelGGL(k_blend_bwd<2>, dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_grad);
+                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->inst_grad);
       break;
   }
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_PROJECT_BWD, st);
-  hipLaunchKernelGGL(k_sum_partials, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->inst_off, f->inst_grad, f->grad2d);
   lodgs_grads none{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (sel) hipLaunchKernelGGL(k_zero_sel, dim3(1024), dim3(kBlock), 0, st, f->ctr, S.n_coef, *sel);
   const lodgs_grads gs = sel ? *sel : none, gn = nodes ? *nodes : none;

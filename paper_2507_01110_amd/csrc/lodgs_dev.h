@@ -100,12 +100,14 @@ __device__ __forceinline__ bool sphere_culled(const ViewConst& v, float mx, floa
 // projected covariance and the power coefficients h1 = -1/(2 l1),
 // h2 = -1/(2 l2) of its eigenvalues (power = h1 u1^2 + h2 u2^2 in that
 // basis), opacity, colour, and the half extents of the box outside which
-// alpha < 1/255 for certain (used only to skip work whose result is known).
+// alpha < 1/255 for certain (used only to skip work whose result is known),
+// and the colour clamp decisions.
 struct alignas(16) Splat {
   float mxh, mxl, myh, myl;
   float ce, se, h1, h2;
   float o, r, g, b;
-  float ex, ey, radius, pad;
+  float ex, ey, radius;
+  uint32_t clamp;  // bit c: colour channel c was clamped at 0 (read by the backward)
 };
 
 // Power of a splat at the pixel centre (px, py), FP32, fixed operation order.
@@ -189,6 +191,44 @@ __device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z
   dY[13][2] = 8.0f * kSH3_4 * x * z;
   dY[14][0] = 2.0f * kSH3_5 * x * z; dY[14][1] = -2.0f * kSH3_5 * y * z; dY[14][2] = kSH3_5 * (xx - yy);
   dY[15][0] = kSH3_6 * (3.0f * xx - 3.0f * yy); dY[15][1] = -6.0f * kSH3_6 * x * y;
+}
+
+// Pixel layout of the blend kernels: a 16x16 tile is one workgroup of 4/PX
+// waves, PX pixels per lane.  PX = 1: wave w covers the 8x8 quarter
+// (w & 1, w >> 1) of the tile, lane l its pixel (l & 7, l >> 3).  PX = 2, 4:
+// wave w covers the rows [4 PX w, 4 PX (w + 1)), lane l the column l & 15 and
+// the rows 4 PX w + (l >> 4) + 4p, p < PX.  A wave's pixel-centre rectangle is
+// used to skip splats whose result there is known.
+template <int PX>
+__device__ __forceinline__ void blend_pixel(int tx, int ty, int wv, int lane, int p, int& x, int& y) {
+  if (PX == 1) {
+    x = tx * kTile + 8 * (wv & 1) + (lane & 7);
+    y = ty * kTile + 8 * (wv >> 1) + (lane >> 3);
+  } else {
+    x = tx * kTile + (lane & 15);
+    y = ty * kTile + 4 * PX * wv + (lane >> 4) + 4 * p;
+  }
+}
+
+template <int PX>
+__device__ __forceinline__ void blend_wave_box(int tx, int ty, int wv, float& x0, float& x1, float& y0, float& y1) {
+  if (PX == 1) {
+    x0 = (float)(tx * kTile + 8 * (wv & 1)) + 0.5f;
+    x1 = x0 + 7.0f;
+    y0 = (float)(ty * kTile + 8 * (wv >> 1)) + 0.5f;
+    y1 = y0 + 7.0f;
+  } else {
+    x0 = (float)(tx * kTile) + 0.5f;
+    x1 = x0 + 15.0f;
+    y0 = (float)(ty * kTile + 4 * PX * wv) + 0.5f;
+    y1 = y0 + (float)(4 * PX - 1);
+  }
+}
+
+// The 8x8 quarters of the tile (bit qx + 2 qy) that wave w covers.
+template <int PX>
+__device__ __forceinline__ uint32_t blend_wave_quarters(int wv) {
+  return PX == 1 ? (1u << wv) : (PX == 2 ? (3u << (2 * wv)) : 0xFu);
 }
 
 // Sum over the 64 lanes of a wave with DPP lane moves, result in lane 63:

@@ -47,7 +47,8 @@ struct FrameCounters {
   int32_t spt_count;     // constant n_spt
   int32_t n_chunks;      // SPT candidate chunks of the last select
   int32_t seg_total;     // compaction segments of the last select
-  int32_t pad[2];
+  int32_t n_long;        // drawn splats with more than kLongSegment instances
+  int32_t pad;
 };
 
 struct lodgs_frame {
@@ -71,7 +72,9 @@ struct lodgs_frame {
   uint32_t* order;        // [max_selected]
   uint32_t* order2;
   uint32_t* tiles;        // [max_selected]
-  uint32_t* inst_off;     // [max_selected] drawn ranks, then per-drawn-splat instance offsets
+  uint32_t* inst_off;     // [max_selected] instance offsets of the drawn splats in depth order
+  uint32_t* drawn_rank;   // [max_selected] rank of a drawn splat among the drawn ones (selection order)
+  uint32_t* drawn_list;   // [max_selected] selection positions of the drawn splats (selection order)
   ushort4* rect;          // [max_selected]
   uint32_t* ikey;         // [max_instances]
   uint32_t* ival;
@@ -79,7 +82,9 @@ struct lodgs_frame {
   uint32_t* ival2;
   uint32_t* inst_splat;   // [max_instances] selection position of each instance (emission order)
   float* inst_grad;       // [max_instances][9] per-instance 2D gradient partials (emission order)
-  float* grad2d;          // [max_selected][9] per-drawn-splat 2D gradients (depth rank)
+  uint8_t* inst_event;    // [max_instances] forward event bits per tile quarter (tile order)
+  float* grad2d;          // [max_selected][9] per-drawn-splat 2D gradients (drawn rank)
+  uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances
   uint2* ranges;          // [max tiles]
   lodgs::ViewConst* d_view_sel;  // view constants of the last lod_select (device)
   lodgs::ViewConst* d_view_ren;  // view constants of the last render (device)
@@ -108,6 +113,10 @@ struct lodgs_frame {
 };
 
 namespace lodgs {
+
+// A drawn splat with more instances than this has its instance partials
+// summed by a whole workgroup in the backward (listed by the duplication).
+constexpr uint32_t kLongSegment = 64;
 
 // Writes the per-view constants to the frame's device slot (one thread): the
 // kernels of a stage read them from there, so a captured graph is replayed

@@ -90,7 +90,7 @@ __device__ __forceinline__ Proj project_node(const SceneDev& S, const ViewConst&
   P.sp.h2 = (float)(-0.5 / l2);
   P.sp.o = 1.0f / (1.0f + fexp(-theta));
   P.sp.radius = (float)r;
-  P.sp.pad = 0.0f;
+  P.sp.clamp = 0u;
   // Box outside which alpha < 1/255 is certain: alpha >= 1/255 needs
   // q = x^T Sigma'^-1 x <= 2 ln(255 o), hence |x| <= sqrt(q_max Sigma'_00) per
   // axis.  Margins cover the FP32 evaluation of the power.
@@ -140,6 +140,7 @@ __global__ void __launch_bounds__(kBlock) k_project(SceneDev S, const ViewConst*
       P.sp.r = fmaxf(raw[0], 0.0f);
       P.sp.g = fmaxf(raw[1], 0.0f);
       P.sp.b = fmaxf(raw[2], 0.0f);
+      P.sp.clamp = (raw[0] < 0.0f ? 1u : 0u) | (raw[1] < 0.0f ? 2u : 0u) | (raw[2] < 0.0f ? 4u : 0u);
       t = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
       splats[i] = P.sp;
       depth_key[i] = __float_as_uint(P.depth);
@@ -155,16 +156,18 @@ struct LoadDrawn {
 };
 
 // Order-preserving compaction of the drawn splats: (depth key, selection
-// position) at the drawn splat's rank among the drawn ones.
+// position) at the drawn splat's rank among the drawn ones (the sort's input),
+// and the list of drawn selection positions (kept for the backward).
 __global__ void __launch_bounds__(kBlock) k_compact_drawn(const FrameCounters* ctr, const uint32_t* tiles,
                                                           const uint32_t* rank, const uint32_t* depth_key,
-                                                          uint32_t* key_out, uint32_t* val_out) {
+                                                          uint32_t* key_out, uint32_t* val_out, uint32_t* list) {
   const int64_t n = ctr->n_render;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     if (tiles[i] == 0u) continue;
     const uint32_t r = rank[i];
     key_out[r] = depth_key[i];
     val_out[r] = (uint32_t)i;
+    list[r] = (uint32_t)i;
   }
 }
 
@@ -178,10 +181,13 @@ struct LoadTilesInOrder {
 // search over the instance offsets of the drawn splats in depth order, so
 // splats covering thousands of tiles cost no more than small ones.  The
 // instance count is clamped to the capacity here (thread 0 publishes the
-// clamped count for the later kernels and flags an overflow).
+// clamped count for the later kernels and flags an overflow).  The first
+// instance of a splat with more than kLongSegment instances lists the splat's
+// depth rank for the backward.
 __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order,
                                                 const uint32_t* inst_off, const ushort4* rect, int32_t tiles_x,
-                                                int64_t cap, uint32_t* ikey, uint32_t* ival, uint32_t* inst_splat) {
+                                                int64_t cap, uint32_t* ikey, uint32_t* ival, uint32_t* inst_splat,
+                                                uint32_t* long_list) {
   const uint32_t total = (uint32_t)ctr->n_instances;  // the scan's 32-bit sum
   const int64_t n = (int64_t)total > cap ? cap : (int64_t)total;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -200,6 +206,7 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
     const uint32_t l = (uint32_t)k - inst_off[lo];
     const ushort4 q = rect[i];
     const uint32_t w = (uint32_t)(q.y - q.x);
+    if (l == 0 && w * (uint32_t)(q.w - q.z) > kLongSegment) long_list[atomicAdd(&ctr->n_long, 1)] = (uint32_t)lo;
     ival[k] = (uint32_t)k;  // the tile sort carries the emission index
     inst_splat[k] = i;
     if (w == 0) {  // only reachable if the instance count overflowed
@@ -226,9 +233,12 @@ __global__ void __launch_bounds__(kBlock) k_ranges(const FrameCounters* ctr, con
   }
 }
 
-// One workgroup per tile with 4/PX waves, PX pixels per lane (wave w covers
-// the tile's rows [4 PX w, 4 PX (w + 1)), lane l the column l & 15 and the
-// rows 4 PX w + (l >> 4) + 4p, p < PX).  alpha = min(0.99, o e^power),
+// One workgroup per tile with 4/PX waves, PX pixels per lane (the layout of
+// blend_pixel / blend_wave_box).  For every instance of the tile that it
+// reaches, the forward records in event[k] the 8x8 quarters of the tile
+// (blend_wave_quarters) where some pixel blended the splat or stopped on it;
+// elsewhere the splat changed nothing, which lets the backward skip it there.
+// alpha = min(0.99, o e^power),
 // skipped below 1/255; a pixel stops before its transmittance would drop
 // below 1e-4.  Splat records are staged in LDS one batch per workgroup size
 // and read into registers one splat ahead; the per-pixel steps are written
@@ -238,30 +248,32 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
                                                     const uint32_t* __restrict__ ival,
                                                     const uint32_t* __restrict__ inst_splat,
                                                     const Splat* __restrict__ splats, const FrameCounters* ctr,
-                                                    float bg0, float bg1, float bg2, float* rgb,
+                                                    float bg0, float bg1, float bg2, float* rgb, uint8_t* event,
                                                     unsigned long long* work) {
   constexpr int NT = 256 / PX;
   const ViewConst v = *vp;
   __shared__ Splat batch[NT];
+  __shared__ uint32_t ev[NT];
+  const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int px = tx * kTile + (lane & 15);
-  const int py0 = ty * kTile + 4 * PX * wv + (lane >> 4);
-  const float fx = (float)px + 0.5f;
+  int px, pys[PX];
   float fy[PX], T[PX], cr[PX], cg[PX], cb[PX];
   bool inside[PX], live[PX];
 #pragma unroll
   for (int p = 0; p < PX; ++p) {
-    fy[p] = (float)(py0 + 4 * p) + 0.5f;
-    inside[p] = px < v.width && py0 + 4 * p < v.height;
+    blend_pixel<PX>(tx, ty, wv, lane, p, px, pys[p]);
+    fy[p] = (float)pys[p] + 0.5f;
+    inside[p] = px < v.width && pys[p] < v.height;
     live[p] = inside[p];
     T[p] = 1.0f;
     cr[p] = cg[p] = cb[p] = 0.0f;
   }
-  // pixel-centre rectangle of this wave (16 x 4 PX pixels)
-  const float wx0 = (float)(tx * kTile) + 0.5f, wx1 = wx0 + 15.0f;
-  const float wy0 = (float)(ty * kTile + 4 * PX * wv) + 0.5f, wy1 = wy0 + (float)(4 * PX - 1);
+  const float fx = (float)px + 0.5f;
+  // pixel-centre rectangle of this wave
+  float wx0, wx1, wy0, wy1;
+  blend_wave_box<PX>(tx, ty, wv, wx0, wx1, wy0, wy1);
   const uint2 rg = ranges[tile];
   const uint32_t nr = (uint32_t)ctr->n_render;
   const float thr = 1.0f / 255.0f;
@@ -272,6 +284,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     for (int p = 0; p < PX; ++p) active = active || live[p];
     if (__syncthreads_count(active) == 0) break;
     const uint32_t k = b0 + threadIdx.x;
+    ev[threadIdx.x] = 0u;
     if (k < rg.y) {
       const uint32_t i = inst_splat[ival[k]];
       if (i < nr) {
@@ -283,11 +296,11 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     }
     __syncthreads();
     const int m = (int)min((uint32_t)NT, rg.y - b0);
-    if (!__any(active)) continue;  // wave-uniform
-    // one splat against the wave's pixels; true when every pixel has stopped
-    auto step = [&](const Splat& s) -> bool {
+    // one splat (batch slot j) against the wave's pixels; true when every
+    // pixel has stopped
+    auto step = [&](const Splat& s, int j) -> bool {
       if (!COUNT && splat_misses(s, wx0, wx1, wy0, wy1)) return false;  // wave-uniform
-      bool act = false;
+      bool act = false, changed = false;
 #pragma unroll
       for (int p = 0; p < PX; ++p) {
         float dx, dy, u1, u2;
@@ -308,16 +321,24 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
         cb[p] = con ? __builtin_fmaf(s.b, w, cb[p]) : cb[p];
         T[p] = con ? tt : T[p];
         act = act | live[p];
+        changed = changed | hit;
       }
+      if (!COUNT && __any(changed) && lane == 0) atomicOr(&ev[j], qmask);
       return !__any(act);
     };
-    // two register sets, each loaded one splat ahead of its use
-    Splat sa = batch[0], sb;
-    for (int j = 0;;) {
-      sb = batch[j + 1 < m ? j + 1 : j];
-      if (step(sa) || ++j >= m) break;
-      sa = batch[j + 1 < m ? j + 1 : j];
-      if (step(sb) || ++j >= m) break;
+    if (__any(active)) {  // wave-uniform
+      // two register sets, each loaded one splat ahead of its use
+      Splat sa = batch[0], sb;
+      for (int j = 0;;) {
+        sb = batch[j + 1 < m ? j + 1 : j];
+        if (step(sa, j) || ++j >= m) break;
+        sa = batch[j + 1 < m ? j + 1 : j];
+        if (step(sb, j) || ++j >= m) break;
+      }
+    }
+    if (!COUNT) {
+      __syncthreads();
+      if ((int)threadIdx.x < m) event[b0 + threadIdx.x] = (uint8_t)ev[threadIdx.x];
     }
   }
   if (COUNT) {
@@ -334,7 +355,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
 #pragma unroll
   for (int p = 0; p < PX; ++p) {
     if (!inside[p]) continue;
-    float* o = rgb + 3 * ((int64_t)(py0 + 4 * p) * v.width + px);
+    float* o = rgb + 3 * ((int64_t)pys[p] * v.width + px);
     o[0] = __builtin_fmaf(T[p], bg0, cr[p]);
     o[1] = __builtin_fmaf(T[p], bg1, cg[p]);
     o[2] = __builtin_fmaf(T[p], bg2, cb[p]);
@@ -345,18 +366,19 @@ template <bool COUNT>
 static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], float* d_rgb, hipStream_t st) {
   const int ntiles = v.tiles_x * v.tiles_y;
   unsigned long long* work = COUNT ? f->work : nullptr;
+  uint8_t* event = COUNT ? nullptr : f->inst_event;
   switch (f->blend_px_fwd) {
     case 1:
       hipLaunchKernelGGL((k_blend<COUNT, 1>), dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, work);
+                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
       break;
     case 4:
       hipLaunchKernelGGL((k_blend<COUNT, 4>), dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, work);
+                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
       break;
     default:
       hipLaunchKernelGGL((k_blend<COUNT, 2>), dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, work);
+                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
       break;
   }
 }
@@ -380,11 +402,11 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   }
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_DEPTH_SORT, st);
-  // drawn splats only: ranks (in inst_off, free until the instance scan), then
-  // a stable sort of their depth keys, ties in selection order
-  scan_exclusive(LoadDrawn{f->tiles}, &f->ctr->n_render, cap, f->block_sums, f->inst_off, &f->ctr->n_drawn, st);
-  hipLaunchKernelGGL(k_compact_drawn, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, f->tiles, f->inst_off, f->depth_key,
-                     f->depth_key2, f->order);
+  // drawn splats only: ranks among them in selection order, then a stable
+  // sort of their depth keys, ties in selection order
+  scan_exclusive(LoadDrawn{f->tiles}, &f->ctr->n_render, cap, f->block_sums, f->drawn_rank, &f->ctr->n_drawn, st);
+  hipLaunchKernelGGL(k_compact_drawn, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, f->tiles, f->drawn_rank,
+                     f->depth_key, f->depth_key2, f->order, f->drawn_list);
   SortScratch ws{f->sort_table, f->block_sums, &f->ctr->sort_table_n};
   const bool sw = sort_pairs(f->depth_key2, f->order, f->depth_key, f->order2, &f->ctr->n_drawn, cap, 32, ws, st);
   const uint32_t* order = sw ? f->order2 : f->order;
@@ -394,7 +416,7 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_drawn, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
   hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x, icap,
-                     f->ikey, f->ival, f->inst_splat);
+                     f->ikey, f->ival, f->inst_splat, f->long_list);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
