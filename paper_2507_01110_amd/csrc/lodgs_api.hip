@@ -149,7 +149,7 @@ void free_frame(lodgs_frame* f) {
     (void)hipEventDestroy(r.b);
   }
   if (f->open_event) (void)hipEventDestroy(f->open_event);
-  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
+  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->rect,
                   f->ikey, f->ival, f->ikey2, f->ival2, f->inst_splat, f->inst_grad, f->inst_event, f->grad2d, f->long_list, f->ranges, f->d_view_sel,
                   f->d_view_ren};
@@ -229,6 +229,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(ctr, 1);
   A(block_sums, lodgs::kScanGrid + 1);
   A(sort_table, (size_t)256 * lodgs::kSortGrid);
+  A(sort_below, (size_t)256 * lodgs::kSortGrid);
   A(upper_sel, (size_t)S.n_upper);
   A(spt_high, (size_t)S.n_spt);
   A(spt_X, (size_t)S.n_spt);
@@ -266,7 +267,6 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   }
   FrameCounters c;
   std::memset(&c, 0, sizeof c);
-  c.sort_table_n = 256 * lodgs::kSortGrid;
   c.spt_count = S.n_spt;
   e = hipMemcpy(f->ctr, &c, sizeof c, hipMemcpyHostToDevice);
   if (e != hipSuccess) {

@@ -42,7 +42,7 @@ struct FrameCounters {
   int32_t n_drawn;
   int32_t n_instances;   // full count
   int32_t n_inst_clamped;
-  int32_t sort_table_n;  // constant 256 * kSortGrid
+  int32_t pad0;
   int32_t upper_plus_high;
   int32_t spt_count;     // constant n_spt
   int32_t n_chunks;      // SPT candidate chunks of the last select
@@ -58,6 +58,7 @@ struct lodgs_frame {
   FrameCounters* ctr;
   uint32_t* block_sums;   // kScanGrid + 1
   uint32_t* sort_table;   // 256 * kSortGrid
+  uint32_t* sort_below;   // 256 * kSortGrid
   // select
   uint8_t* upper_sel;     // [n_upper]
   int32_t* spt_high;      // [n_spt]

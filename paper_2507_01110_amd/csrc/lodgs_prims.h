@@ -13,6 +13,7 @@ namespace lodgs {
 constexpr int kScanGrid = 512;    // blocks of the multi-block scan
 constexpr int kSortGrid = 512;    // blocks of a radix pass
 constexpr int kBlock = 256;
+static_assert(kSortGrid % kBlock == 0, "a radix offsets workgroup scans a table row in whole chunks");
 
 struct Segment {
   int64_t begin, end;
@@ -74,10 +75,11 @@ __global__ void __launch_bounds__(kBlock) k_scan_reduce(Load load, const int32_t
 
 // Each block first sums the totals of the blocks before it (block 0 also
 // sums all of them and writes the grand total to *d_total, if not null), then
-// scans its own segment.
-template <class Load>
+// scans its own segment, handing each element's exclusive prefix to the
+// store functor: store(i, prefix, value).
+template <class Load, class Store>
 __global__ void __launch_bounds__(kBlock) k_scan_down(Load load, const int32_t* d_n, int64_t cap,
-                                                      const uint32_t* block_sums, uint32_t* out, int32_t* d_total) {
+                                                      const uint32_t* block_sums, Store store, int32_t* d_total) {
   __shared__ uint32_t wt[kBlock / 64];
   uint32_t before = 0, all = 0;
   for (int t = threadIdx.x; t < kScanGrid; t += kBlock) {
@@ -104,7 +106,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(Load load, const int32_t* 
     uint32_t run = base + block_exclusive_scan(v[0] + v[1] + v[2] + v[3], wt, &tot);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (i0 + k < s.end) out[i0 + k] = run;
+      if (i0 + k < s.end) store(i0 + k, run, v[k]);
       run += v[k];
     }
     base += tot;
@@ -116,34 +118,49 @@ struct LoadArray {
   __device__ uint32_t operator()(int64_t i) const { return a[i]; }
 };
 
-// out[i] = sum_{j < i} load(j) for i < min(*d_n, cap); *d_total = sum (may be
-// null).  block_sums: kScanGrid words of scratch.  out may alias the array
-// read by load.  Two kernels: per-block totals, then per-block bases and the
-// scan of each segment.
+struct StoreArray {
+  uint32_t* out;
+  __device__ void operator()(int64_t i, uint32_t prefix, uint32_t) const { out[i] = prefix; }
+};
+
+// store(i, sum_{j < i} load(j), load(i)) for i < min(*d_n, cap); *d_total =
+// sum (may be null).  block_sums: kScanGrid words of scratch.  The store may
+// overwrite the array read by load at index i.  Two kernels: per-block
+// totals, then per-block bases and the scan of each segment.
+template <class Load, class Store>
+inline void scan_exclusive(Load load, const int32_t* d_n, int64_t cap, uint32_t* block_sums, Store store,
+                           int32_t* d_total, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_reduce<Load>, dim3(kScanGrid), dim3(kBlock), 0, st, load, d_n, cap, block_sums);
+  hipLaunchKernelGGL((k_scan_down<Load, Store>), dim3(kScanGrid), dim3(kBlock), 0, st, load, d_n, cap, block_sums,
+                     store, d_total);
+}
+
 template <class Load>
 inline void scan_exclusive(Load load, const int32_t* d_n, int64_t cap, uint32_t* block_sums, uint32_t* out,
                            int32_t* d_total, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan_reduce<Load>, dim3(kScanGrid), dim3(kBlock), 0, st, load, d_n, cap, block_sums);
-  hipLaunchKernelGGL(k_scan_down<Load>, dim3(kScanGrid), dim3(kBlock), 0, st, load, d_n, cap, block_sums, out,
-                     d_total);
+  scan_exclusive(load, d_n, cap, block_sums, StoreArray{out}, d_total, st);
 }
 
 // ---------------------------------------------------------------- radix sort
-// One pass = digit histogram per block (digit-major table [256][kSortGrid]),
-// exclusive scan of the table, stable scatter.  Ranks inside a block come from
-// wave ballots over the digit bits plus per-wave digit counts in LDS, so equal
-// digits keep their input order.
+// One pass = three kernels: per-block digit counts (digit-major table
+// [256][kSortGrid]) together with each block's exclusive prefix over the
+// digits (same layout, in below); the exclusive offsets of every (digit,
+// block), one workgroup per digit (the sum of its row of below gives the
+// count of all smaller digits, the scan of its row of counts the blocks
+// before); the stable scatter.  Ranks inside a block come from wave ballots
+// over the digit bits plus per-wave digit counts in LDS, so equal digits keep
+// their input order.
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* keys, const int32_t* d_n, int64_t cap,
-                                                       int shift, uint32_t* table);
+                                                       int shift, uint32_t* table, uint32_t* below);
+__global__ void __launch_bounds__(kBlock) k_radix_offsets(uint32_t* table, const uint32_t* below);
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, const uint32_t* vin,
                                                           uint32_t* kout, uint32_t* vout, const int32_t* d_n,
                                                           int64_t cap, int shift, const uint32_t* table);
 
-// Workspace for sort_pairs: table [256 * kSortGrid] and scan scratch.
+// Workspace for sort_pairs: two tables of 256 * kSortGrid words.
 struct SortScratch {
   uint32_t* table;
-  uint32_t* block_sums;
-  int32_t* d_table_n;  // device int32 holding 256 * kSortGrid
+  uint32_t* below;
 };
 
 // Sorts (keys, vals) of length min(*d_n, cap) by the key bits [0, bits), stable.

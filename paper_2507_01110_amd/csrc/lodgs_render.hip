@@ -155,21 +155,24 @@ struct LoadDrawn {
   __device__ uint32_t operator()(int64_t i) const { return tiles[i] != 0u ? 1u : 0u; }
 };
 
-// Order-preserving compaction of the drawn splats: (depth key, selection
-// position) at the drawn splat's rank among the drawn ones (the sort's input),
-// and the list of drawn selection positions (kept for the backward).
-__global__ void __launch_bounds__(kBlock) k_compact_drawn(const FrameCounters* ctr, const uint32_t* tiles,
-                                                          const uint32_t* rank, const uint32_t* depth_key,
-                                                          uint32_t* key_out, uint32_t* val_out, uint32_t* list) {
-  const int64_t n = ctr->n_render;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    if (tiles[i] == 0u) continue;
-    const uint32_t r = rank[i];
-    key_out[r] = depth_key[i];
-    val_out[r] = (uint32_t)i;
-    list[r] = (uint32_t)i;
+// Order-preserving compaction of the drawn splats, done by the scan of their
+// flags: the drawn splat at selection position i gets rank = its prefix among
+// the drawn ones; (depth key, i) go to that rank (the sort's input), and so
+// does i in the list of drawn selection positions (kept for the backward).
+struct StoreDrawn {
+  uint32_t* rank;
+  const uint32_t* depth_key;
+  uint32_t* key_out;
+  uint32_t* val_out;
+  uint32_t* list;
+  __device__ void operator()(int64_t i, uint32_t prefix, uint32_t drawn) const {
+    rank[i] = prefix;
+    if (!drawn) return;
+    key_out[prefix] = depth_key[i];
+    val_out[prefix] = (uint32_t)i;
+    list[prefix] = (uint32_t)i;
   }
-}
+};
 
 struct LoadTilesInOrder {
   const uint32_t* tiles;
@@ -218,18 +221,21 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_zero_ranges(uint2* ranges, int32_t n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) ranges[i] = make_uint2(0, 0);
-}
-
+// Tile ranges from the tile-sorted keys, one thread per boundary k in
+// [0, n]: between the keys t0 = key[k - 1] and t1 = key[k] (-1 before the
+// first, ntiles after the last; keys >= ntiles, which only an instance
+// overflow produces, count as ntiles) tile t0 ends at k, tile t1 starts at k,
+// and every tile strictly between them is empty (k, k).
 __global__ void __launch_bounds__(kBlock) k_ranges(const FrameCounters* ctr, const uint32_t* key, uint2* ranges,
                                                    uint32_t ntiles) {
   const int64_t n = ctr->n_inst_clamped;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t t = key[k];
-    if (t >= ntiles) continue;  // only reachable if the instance count overflowed
-    if (k == 0 || key[k - 1] != t) ranges[t].x = (uint32_t)k;
-    if (k == n - 1 || key[k + 1] != t) ranges[t].y = (uint32_t)(k + 1);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t0 = k > 0 ? (int64_t)min(key[k - 1], ntiles) : -1;
+    const int64_t t1 = k < n ? (int64_t)min(key[k], ntiles) : (int64_t)ntiles;
+    if (t0 == t1) continue;
+    if (t0 >= 0 && t0 < ntiles) ranges[t0].y = (uint32_t)k;
+    if (t1 < ntiles) ranges[t1].x = (uint32_t)k;
+    for (int64_t t = t0 + 1; t < t1; ++t) ranges[t] = make_uint2((uint32_t)k, (uint32_t)k);
   }
 }
 
@@ -404,10 +410,10 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   stage_begin(f, LODGS_STAGE_DEPTH_SORT, st);
   // drawn splats only: ranks among them in selection order, then a stable
   // sort of their depth keys, ties in selection order
-  scan_exclusive(LoadDrawn{f->tiles}, &f->ctr->n_render, cap, f->block_sums, f->drawn_rank, &f->ctr->n_drawn, st);
-  hipLaunchKernelGGL(k_compact_drawn, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, f->tiles, f->drawn_rank,
-                     f->depth_key, f->depth_key2, f->order, f->drawn_list);
-  SortScratch ws{f->sort_table, f->block_sums, &f->ctr->sort_table_n};
+  scan_exclusive(LoadDrawn{f->tiles}, &f->ctr->n_render, cap, f->block_sums,
+                 StoreDrawn{f->drawn_rank, f->depth_key, f->depth_key2, f->order, f->drawn_list}, &f->ctr->n_drawn,
+                 st);
+  SortScratch ws{f->sort_table, f->sort_below};
   const bool sw = sort_pairs(f->depth_key2, f->order, f->depth_key, f->order2, &f->ctr->n_drawn, cap, 32, ws, st);
   const uint32_t* order = sw ? f->order2 : f->order;
   f->sorted_order = order;
@@ -427,7 +433,6 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   f->sorted_ival = sw2 ? f->ival2 : f->ival;
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_RANGES, st);
-  hipLaunchKernelGGL(k_zero_ranges, dim3((ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, st, f->ranges, ntiles);
   hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_ikey, f->ranges, (uint32_t)ntiles);
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_BLEND, st);

@@ -88,22 +88,23 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewCons
 // are 64-node chunks of the upper hierarchy (predicate: selected), the rest
 // are chunks of at most kChunk candidates of the visible SPT prefixes
 // (predicate: r_min <= X_j); an SPT contributes ceil(high_j / kChunk)
-// chunks, located through the scan of those counts (k_chunk_owner writes the
+// chunks, located through the scan of those counts (which also writes the
 // SPT of every chunk).  Pass 1 counts each
 // segment with ballots, a scan turns the counts into output offsets, pass 2
 // writes each segment's selected nodes in order with ballot ranks.  Segments
 // follow the layout order, so the output is ascending.
 constexpr int32_t kChunk = 512;
 
-// owner[t] = the SPT whose prefix holds candidate chunk t.
-__global__ void __launch_bounds__(kBlock) k_chunk_owner(const int32_t* spt_high, const uint32_t* ch_off, int32_t n_spt,
-                                                        uint32_t* owner) {
-  for (int32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < n_spt; j += gridDim.x * blockDim.x) {
-    const int32_t c = (spt_high[j] + kChunk - 1) / kChunk;
-    const uint32_t o = ch_off[j];
-    for (int32_t t = 0; t < c; ++t) owner[o + t] = (uint32_t)j;
+// The scan of the chunk counts stores each SPT's first chunk index and the
+// owner table: owner[t] = the SPT whose prefix holds candidate chunk t.
+struct StoreChunks {
+  uint32_t* ch_off;
+  uint32_t* owner;
+  __device__ void operator()(int64_t j, uint32_t first, uint32_t count) const {
+    ch_off[j] = first;
+    for (uint32_t t = 0; t < count; ++t) owner[first + t] = (uint32_t)j;
   }
-}
+};
 
 template <bool WRITE>
 __global__ void __launch_bounds__(kBlock) k_segments(SceneDev S, const uint8_t* upper_sel, const int32_t* spt_high,
@@ -179,10 +180,8 @@ void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* 
                      f->ctr);
   const int32_t n_up_chunks = (S.n_upper + 63) / 64;
   // chunks per visible SPT prefix -> offsets, total -> n_chunks
-  scan_exclusive(LoadChunks{f->spt_high}, &f->ctr->spt_count, (int64_t)S.n_spt, f->block_sums, f->spt_off,
-                 &f->ctr->n_chunks, st);
-  hipLaunchKernelGGL(k_chunk_owner, dim3((S.n_spt + kBlock - 1) / kBlock), dim3(kBlock), 0, st, f->spt_high,
-                     f->spt_off, S.n_spt, f->chunk_owner);
+  scan_exclusive(LoadChunks{f->spt_high}, &f->ctr->spt_count, (int64_t)S.n_spt, f->block_sums,
+                 StoreChunks{f->spt_off, f->chunk_owner}, &f->ctr->n_chunks, st);
   const int sgrid = 4096;
   const int64_t seg_cap = (int64_t)n_up_chunks + S.n_spt + S.n_nodes / kChunk + 1;
   hipLaunchKernelGGL(k_segments<false>, dim3(sgrid), dim3(kBlock), 0, st, S, f->upper_sel, f->spt_high, f->spt_X,
