@@ -150,7 +150,7 @@ void free_frame(lodgs_frame* f) {
   }
   if (f->open_event) (void)hipEventDestroy(f->open_event);
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
-                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->rect,
+                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->depth_rank, f->rect,
                   f->ikey, f->ival, f->ikey2, f->ival2, f->inst_splat, f->inst_grad, f->inst_event, f->grad2d, f->long_list, f->ranges, f->d_view_sel,
                   f->d_view_ren};
   for (void* p : ptrs)
@@ -245,6 +245,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(inst_off, ns);
   A(drawn_rank, ns);
   A(drawn_list, ns);
+  A(depth_rank, ns);
   A(rect, ns);
   A(ikey, ni);
   A(ival, ni);

@@ -281,45 +281,49 @@ __device__ __forceinline__ float row_sum(float x) {
   return x;
 }
 
-// Basis function k (k < 16) and its gradient at the unit direction (x, y, z):
-// the same expressions as sh_basis / sh_basis_grad, one function per case.
+// Every real SH basis function of degree <= 3 is C L Q with a linear
+// monomial L = lx x + ly y + lz z + l1 (one coefficient set) and a quadratic
+// form Q = a xx + b yy + g zz + d xy + e yz + f xz + h; row k holds
+// (C, lx, ly, lz, l1, a, b, g, d, e, f, h) for basis function k (the same
+// functions as sh_basis).  One lane evaluates one function and its gradient
+// without branches.
+__constant__ float kShFactors[16][12] = {
+    {kSH0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 0, 1},
+    {-kSH1, 0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 1},
+    {kSH1, 0, 0, 1, 0, 0, 0, 0, 0, 0, 0, 1},
+    {-kSH1, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 1},
+    {kSH2_0, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0},
+    {kSH2_1, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0},
+    {kSH2_2, 0, 0, 0, 1, -1, -1, 2, 0, 0, 0, 0},
+    {kSH2_3, 0, 0, 0, 1, 0, 0, 0, 0, 0, 1, 0},
+    {kSH2_4, 0, 0, 0, 1, 1, -1, 0, 0, 0, 0, 0},
+    {kSH3_0, 0, 1, 0, 0, 3, -1, 0, 0, 0, 0, 0},
+    {kSH3_1, 0, 0, 1, 0, 0, 0, 0, 1, 0, 0, 0},
+    {kSH3_2, 0, 1, 0, 0, -1, -1, 4, 0, 0, 0, 0},
+    {kSH3_3, 0, 0, 1, 0, -3, -3, 2, 0, 0, 0, 0},
+    {kSH3_4, 1, 0, 0, 0, -1, -1, 4, 0, 0, 0, 0},
+    {kSH3_5, 0, 0, 1, 0, 1, -1, 0, 0, 0, 0, 0},
+    {kSH3_6, 1, 0, 0, 0, 1, -3, 0, 0, 0, 0, 0},
+};
+
+// Basis function k and its gradient with respect to (x, y, z).
 __device__ __forceinline__ void sh_basis_one(int k, float x, float y, float z, float& Y, float* dY) {
-  const float xx = x * x, yy = y * y, zz = z * z;
-  float a = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
-  switch (k) {
-    case 0: a = kSH0; break;
-    case 1: a = -kSH1 * y; gy = -kSH1; break;
-    case 2: a = kSH1 * z; gz = kSH1; break;
-    case 3: a = -kSH1 * x; gx = -kSH1; break;
-    case 4: a = kSH2_0 * x * y; gx = kSH2_0 * y; gy = kSH2_0 * x; break;
-    case 5: a = kSH2_1 * y * z; gy = kSH2_1 * z; gz = kSH2_1 * y; break;
-    case 6:
-      a = kSH2_2 * (2.0f * zz - xx - yy);
-      gx = -2.0f * kSH2_2 * x; gy = -2.0f * kSH2_2 * y; gz = 4.0f * kSH2_2 * z;
-      break;
-    case 7: a = kSH2_3 * x * z; gx = kSH2_3 * z; gz = kSH2_3 * x; break;
-    case 8: a = kSH2_4 * (xx - yy); gx = 2.0f * kSH2_4 * x; gy = -2.0f * kSH2_4 * y; break;
-    case 9: a = kSH3_0 * y * (3.0f * xx - yy); gx = 6.0f * kSH3_0 * x * y; gy = kSH3_0 * (3.0f * xx - 3.0f * yy); break;
-    case 10: a = kSH3_1 * x * y * z; gx = kSH3_1 * y * z; gy = kSH3_1 * x * z; gz = kSH3_1 * x * y; break;
-    case 11:
-      a = kSH3_2 * y * (4.0f * zz - xx - yy);
-      gx = -2.0f * kSH3_2 * x * y; gy = kSH3_2 * (4.0f * zz - xx - 3.0f * yy); gz = 8.0f * kSH3_2 * y * z;
-      break;
-    case 12:
-      a = kSH3_3 * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
-      gx = -6.0f * kSH3_3 * x * z; gy = -6.0f * kSH3_3 * y * z; gz = kSH3_3 * (6.0f * zz - 3.0f * xx - 3.0f * yy);
-      break;
-    case 13:
-      a = kSH3_4 * x * (4.0f * zz - xx - yy);
-      gx = kSH3_4 * (4.0f * zz - 3.0f * xx - yy); gy = -2.0f * kSH3_4 * x * y; gz = 8.0f * kSH3_4 * x * z;
-      break;
-    case 14: a = kSH3_5 * z * (xx - yy); gx = 2.0f * kSH3_5 * x * z; gy = -2.0f * kSH3_5 * y * z; gz = kSH3_5 * (xx - yy); break;
-    default: a = kSH3_6 * x * (xx - 3.0f * yy); gx = kSH3_6 * (3.0f * xx - 3.0f * yy); gy = -6.0f * kSH3_6 * x * y; break;
-  }
-  Y = a;
-  dY[0] = gx;
-  dY[1] = gy;
-  dY[2] = gz;
+  const float* t = kShFactors[k];
+  const float L = __builtin_fmaf(t[1], x, __builtin_fmaf(t[2], y, __builtin_fmaf(t[3], z, t[4])));
+  float Q = t[11];
+  Q = __builtin_fmaf(t[5] * x, x, Q);
+  Q = __builtin_fmaf(t[6] * y, y, Q);
+  Q = __builtin_fmaf(t[7] * z, z, Q);
+  Q = __builtin_fmaf(t[8] * x, y, Q);
+  Q = __builtin_fmaf(t[9] * y, z, Q);
+  Q = __builtin_fmaf(t[10] * x, z, Q);
+  const float qx = __builtin_fmaf(2.0f * t[5], x, __builtin_fmaf(t[8], y, t[10] * z));
+  const float qy = __builtin_fmaf(2.0f * t[6], y, __builtin_fmaf(t[8], x, t[9] * z));
+  const float qz = __builtin_fmaf(2.0f * t[7], z, __builtin_fmaf(t[9], y, t[10] * x));
+  Y = t[0] * L * Q;
+  dY[0] = t[0] * __builtin_fmaf(t[1], Q, L * qx);
+  dY[1] = t[0] * __builtin_fmaf(t[2], Q, L * qy);
+  dY[2] = t[0] * __builtin_fmaf(t[3], Q, L * qz);
 }
 
 // Splats with more than kLongSegment instances: one workgroup per splat sums
@@ -366,7 +370,8 @@ __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, 
   }
 }
 
-// Per drawn splat (rank r in depth order), 16 lanes: (1) the sum of its
+// Per drawn splat, 16 lanes, in selection order (ascending node index, so
+// neighbouring groups read neighbouring nodes): (1) the sum of its
 // instance partials, contiguous in emission order (the lanes stride over the
 // range, then the in-row reduce-scatter leaves each of the 9 sums in one
 // lane; fixed order, so deterministic), or, for a splat with more than
@@ -380,8 +385,8 @@ __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, 
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewConst* __restrict__ vp,
                                                       const int32_t* idx, const FrameCounters* ctr,
-                                                      const uint32_t* order, const uint32_t* inst_off,
-                                                      const uint32_t* drawn_rank, const float* __restrict__ partial,
+                                                      const uint32_t* drawn_list, const uint32_t* depth_rank,
+                                                      const uint32_t* inst_off, const float* __restrict__ partial,
                                                       const Splat* splats, float* grad2d, float* sel_sh,
                                                       float* node_sh) {
   constexpr int nb = (DEG + 1) * (DEG + 1), nc = 3 * nb;
@@ -391,19 +396,19 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
   const int lane = threadIdx.x & 63, sub = lane & 15, row = lane & ~15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t r0 = wave * 4; r0 < n; r0 += waves * 4) {  // wave-uniform
-    const int64_t r = r0 + (lane >> 4);
-    const bool live = r < n;
+  for (int64_t g0 = wave * 4; g0 < n; g0 += waves * 4) {  // wave-uniform
+    const int64_t dr = g0 + (lane >> 4);  // drawn rank
+    const bool live = dr < n;
     float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    int64_t i = 0, node = 0, dr = 0;
+    int64_t i = 0, node = 0;
     // per-splat inputs of the colour part, requested together with the
     // partials (they depend only on the splat)
     uint32_t clamp = 0;
     float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, sh3[3] = {0.0f, 0.0f, 0.0f}, acc3[3] = {0.0f, 0.0f, 0.0f};
     if (live) {
-      i = order[r];
+      i = drawn_list[dr];
       node = idx[i];
-      dr = drawn_rank[i];
+      const int64_t r = depth_rank[dr];  // every drawn splat has an instance, so a rank
       clamp = splats[i].clamp;
       m0 = S.means[3 * node];
       m1 = S.means[3 * node + 1];
@@ -415,7 +420,11 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
           if (node_sh) acc3[c] = node_sh[(int64_t)nc * node + 3 * sub + c];
         }
       }
-      int64_t a = inst_off[r], b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
+      int64_t a = 0, b = 0;  // a rank out of range only follows an instance overflow
+      if (r < n) {
+        a = inst_off[r];
+        b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
+      }
       a = a < n_cl ? a : n_cl;
       b = b < n_cl ? b : n_cl;
       if (b - a > (int64_t)kLongSegment) {  // summed by k_long_sums
@@ -423,16 +432,17 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
 #pragma unroll
           for (int c = 0; c < 9; ++c) g[c] = grad2d[9 * dr + c];
         }
-      } else {  // at most 4 instances per lane, loads issued together
-        float t[4][9];
+      } else {  // at most 2 instances per lane (kLongSegment = 32), loads issued together
+        static_assert(kLongSegment <= 32, "two instances per lane of a 16-lane group");
+        float t[2][9];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2; ++u) {
           const int64_t q = a + sub + 16 * u;
 #pragma unroll
           for (int c = 0; c < 9; ++c) t[u][c] = q < b ? partial[9 * q + c] : 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
           for (int c = 0; c < 9; ++c) g[c] += t[u][c];
       }
@@ -443,42 +453,39 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
     const float gr = __shfl(z, row + rs_lane_of_slot(6), 64);
     const float gg = __shfl(z, row + rs_lane_of_slot(7), 64);
     const float gb = __shfl(z, row + rs_lane_of_slot(8), 64);
-    float ddx = 0.0f, ddy = 0.0f, ddz = 0.0f;
-    double d0 = 0.0, d1 = 0.0, d2 = 0.0, dl = 1.0;
+    // gradient values only: FP32 throughout
+    float ddx = 0.0f, ddy = 0.0f, ddz = 0.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, il = 0.0f;
     if (live) {
-      const double dRGB[3] = {(clamp & 1u) ? 0.0 : (double)gr, (clamp & 2u) ? 0.0 : (double)gg,
-                              (clamp & 4u) ? 0.0 : (double)gb};
-      const double dx = (double)m0 - (double)v.pos[0];
-      const double dy = (double)m1 - (double)v.pos[1];
-      const double dz = (double)m2 - (double)v.pos[2];
-      dl = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
-      d0 = dx / dl;
-      d1 = dy / dl;
-      d2 = dz / dl;
+      const float dRGB[3] = {(clamp & 1u) ? 0.0f : gr, (clamp & 2u) ? 0.0f : gg, (clamp & 4u) ? 0.0f : gb};
+      const float dx = m0 - v.pos[0], dy = m1 - v.pos[1], dz = m2 - v.pos[2];
+      il = 1.0f / __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
+      d0 = dx * il;
+      d1 = dy * il;
+      d2 = dz * il;
       if (sub < nb) {
         float Yk, dYk[3];
-        sh_basis_one(sub, (float)d0, (float)d1, (float)d2, Yk, dYk);
-        double a = 0.0;
+        sh_basis_one(sub, d0, d1, d2, Yk, dYk);
+        float a = 0.0f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const float gk = (float)(dRGB[c] * (double)Yk);
+          const float gk = dRGB[c] * Yk;
           if (sel_sh) sel_sh[(int64_t)nc * i + 3 * sub + c] = gk;
           if (node_sh) node_sh[(int64_t)nc * node + 3 * sub + c] = acc3[c] + gk;
-          a += dRGB[c] * (double)sh3[c];
+          a = __builtin_fmaf(dRGB[c], sh3[c], a);
         }
-        ddx = (float)(a * (double)dYk[0]);
-        ddy = (float)(a * (double)dYk[1]);
-        ddz = (float)(a * (double)dYk[2]);
+        ddx = a * dYk[0];
+        ddy = a * dYk[1];
+        ddz = a * dYk[2];
       }
     }
     ddx = row_sum(ddx);  // all lanes active
     ddy = row_sum(ddy);
     ddz = row_sum(ddz);
-    if (live && sub == 0) {
-      const double dot = (double)ddx * d0 + (double)ddy * d1 + (double)ddz * d2;
-      grad2d[9 * dr + 6] = (float)(((double)ddx - d0 * dot) / dl);
-      grad2d[9 * dr + 7] = (float)(((double)ddy - d1 * dot) / dl);
-      grad2d[9 * dr + 8] = (float)(((double)ddz - d2 * dot) / dl);
+    if (live && sub == 0) {  // projection onto the sphere's tangent plane, / |mu - pos|
+      const float dot = __builtin_fmaf(ddx, d0, __builtin_fmaf(ddy, d1, ddz * d2));
+      grad2d[9 * dr + 6] = (ddx - d0 * dot) * il;
+      grad2d[9 * dr + 7] = (ddy - d1 * dot) * il;
+      grad2d[9 * dr + 8] = (ddz - d2 * dot) * il;
     }
   }
 }
@@ -595,7 +602,7 @@ static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodg
   hipLaunchKernelGGL(k_long_sums, dim3(1024), dim3(kBlock), 0, st, f->ctr, f->long_list, f->sorted_order,
                      f->drawn_rank, f->inst_off, f->inst_grad, f->grad2d);
   hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->sorted_order, f->inst_off, f->drawn_rank, f->inst_grad, f->splats, f->grad2d, sel.d_sh,
+                     f->drawn_list, f->depth_rank, f->inst_off, f->inst_grad, f->splats, f->grad2d, sel.d_sh,
                      nodes.d_sh);
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
                      f->drawn_list, f->grad2d, sel, nodes);

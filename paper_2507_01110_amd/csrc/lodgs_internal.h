@@ -76,6 +76,7 @@ struct lodgs_frame {
   uint32_t* inst_off;     // [max_selected] instance offsets of the drawn splats in depth order
   uint32_t* drawn_rank;   // [max_selected] rank of a drawn splat among the drawn ones (selection order)
   uint32_t* drawn_list;   // [max_selected] selection positions of the drawn splats (selection order)
+  uint32_t* depth_rank;   // [max_selected] depth rank of each drawn splat, by drawn rank
   ushort4* rect;          // [max_selected]
   uint32_t* ikey;         // [max_instances]
   uint32_t* ival;
@@ -117,7 +118,7 @@ namespace lodgs {
 
 // A drawn splat with more instances than this has its instance partials
 // summed by a whole workgroup in the backward (listed by the duplication).
-constexpr uint32_t kLongSegment = 64;
+constexpr uint32_t kLongSegment = 32;
 
 // Writes the per-view constants to the frame's device slot (one thread): the
 // kernels of a stage read them from there, so a captured graph is replayed

@@ -185,12 +185,14 @@ struct LoadTilesInOrder {
 // splats covering thousands of tiles cost no more than small ones.  The
 // instance count is clamped to the capacity here (thread 0 publishes the
 // clamped count for the later kernels and flags an overflow).  The first
-// instance of a splat with more than kLongSegment instances lists the splat's
-// depth rank for the backward.
+// instance of a splat records the splat's depth rank at its drawn rank (for
+// the backward, which walks the drawn splats in selection order), and lists
+// it when it has more than kLongSegment instances.
 __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order,
                                                 const uint32_t* inst_off, const ushort4* rect, int32_t tiles_x,
                                                 int64_t cap, uint32_t* ikey, uint32_t* ival, uint32_t* inst_splat,
-                                                uint32_t* long_list) {
+                                                uint32_t* long_list, const uint32_t* drawn_rank,
+                                                uint32_t* depth_rank) {
   const uint32_t total = (uint32_t)ctr->n_instances;  // the scan's 32-bit sum
   const int64_t n = (int64_t)total > cap ? cap : (int64_t)total;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -209,7 +211,10 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
     const uint32_t l = (uint32_t)k - inst_off[lo];
     const ushort4 q = rect[i];
     const uint32_t w = (uint32_t)(q.y - q.x);
-    if (l == 0 && w * (uint32_t)(q.w - q.z) > kLongSegment) long_list[atomicAdd(&ctr->n_long, 1)] = (uint32_t)lo;
+    if (l == 0) {
+      depth_rank[drawn_rank[i]] = (uint32_t)lo;
+      if (w * (uint32_t)(q.w - q.z) > kLongSegment) long_list[atomicAdd(&ctr->n_long, 1)] = (uint32_t)lo;
+    }
     ival[k] = (uint32_t)k;  // the tile sort carries the emission index
     inst_splat[k] = i;
     if (w == 0) {  // only reachable if the instance count overflowed
@@ -422,7 +427,7 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_drawn, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
   hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x, icap,
-                     f->ikey, f->ival, f->inst_splat, f->long_list);
+                     f->ikey, f->ival, f->inst_splat, f->long_list, f->drawn_rank, f->depth_rank);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
