@@ -149,7 +149,7 @@ void free_frame(lodgs_frame* f) {
     (void)hipEventDestroy(r.b);
   }
   if (f->open_event) (void)hipEventDestroy(f->open_event);
-  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
+  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->upper_test, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->depth_rank, f->rect,
                   f->ikey, f->ival, f->ikey2, f->ival2, f->inst_splat, f->inst_grad, f->inst_event, f->grad2d, f->long_list, f->ranges, f->d_view_sel,
                   f->d_view_ren};
@@ -202,11 +202,23 @@ int lodgs_scene_create(const lodgs_scene_desc* d, lodgs_scene** out) {
   v.upper_parent = d->d_upper_parent;
   v.spt_begin = d->d_spt_begin;
   v.spt_parent = d->d_spt_parent;
+  v.anc = nullptr;
+  v.anc_depth = 0;
+  s->anc_owned = nullptr;
+  const int rc = lodgs::build_ancestor_table(s);
+  if (rc != LODGS_OK) {
+    delete s;
+    return rc;
+  }
   *out = s;
   return LODGS_OK;
 }
 
-void lodgs_scene_destroy(lodgs_scene* s) { delete s; }
+void lodgs_scene_destroy(lodgs_scene* s) {
+  if (!s) return;
+  if (s->anc_owned) (void)hipFree(s->anc_owned);
+  delete s;
+}
 
 int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, lodgs_frame** out) {
   if (!scene || !caps || !out) return set_error(LODGS_E_INVALID, "lodgs_frame_create: null argument");
@@ -231,6 +243,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(sort_table, (size_t)256 * lodgs::kSortGrid);
   A(sort_below, (size_t)256 * lodgs::kSortGrid);
   A(upper_sel, (size_t)S.n_upper);
+  A(upper_test, (size_t)S.n_upper);
   A(spt_high, (size_t)S.n_spt);
   A(spt_X, (size_t)S.n_spt);
   A(spt_off, (size_t)S.n_spt);

@@ -25,11 +25,24 @@ struct SceneDev {
   const int32_t* upper_parent;
   const int32_t* spt_begin;
   const int32_t* spt_parent;
+  // Ancestor table of the upper hierarchy (library-owned, built at scene
+  // creation): row d (d < anc_depth) holds the d-th upper ancestor (the
+  // parent first) of every upper node e and SPT root n_upper + j, -1 past the
+  // root; nullptr when the hierarchy is deeper than kMaxAncDepth.
+  const int32_t* anc;
+  int32_t anc_depth;
 };
 
 struct lodgs_scene {
   SceneDev dev;
+  int32_t* anc_owned;
 };
+
+namespace lodgs {
+constexpr int32_t kMaxAncDepth = 64;
+// Builds the ancestor table (synchronous; scene creation only).
+int build_ancestor_table(lodgs_scene* s);
+}  // namespace lodgs
 
 // Device counters of a frame (one struct in device memory).
 struct FrameCounters {
@@ -61,6 +74,7 @@ struct lodgs_frame {
   uint32_t* sort_below;   // 256 * kSortGrid
   // select
   uint8_t* upper_sel;     // [n_upper]
+  uint8_t* upper_test;    // [n_upper] bit 0 culled, bit 1 fine enough
   int32_t* spt_high;      // [n_spt]
   float* spt_X;           // [n_spt]
   uint32_t* spt_off;      // [n_spt]

@@ -17,23 +17,133 @@ namespace lodgs {
 
 namespace {
 
-__device__ __forceinline__ bool upper_stops(const SceneDev& S, const ViewConst& v, bool cull, int32_t a) {
-  const float mx = S.means[3 * (int64_t)a], my = S.means[3 * (int64_t)a + 1], mz = S.means[3 * (int64_t)a + 2];
-  if (cull && sphere_culled(v, mx, my, mz, S.rho[a])) return true;
-  return S.r_min[a] <= view_distance(v, mx, my, mz) * v.k;
+// Per upper node, the two view tests of the cut, evaluated once per view:
+// bit 0 = culled (its sphere is outside the frustum, when culling), bit 1 =
+// fine enough (r_min <= X at its own distance).  The descent stops at a node
+// with either bit; an upper node is selected when it is reached, not culled
+// and fine enough.
+__global__ void __launch_bounds__(kBlock) k_upper_tests(SceneDev S, const ViewConst* __restrict__ vp, uint32_t flags,
+                                                        uint8_t* utest) {
+  const ViewConst v = *vp;
+  const bool cull = (flags & LODGS_CULL) != 0;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < S.n_upper;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const float mx = S.means[3 * u], my = S.means[3 * u + 1], mz = S.means[3 * u + 2];
+    const bool culled = cull && sphere_culled(v, mx, my, mz, S.rho[u]);
+    const bool fine = S.r_min[u] <= view_distance(v, mx, my, mz) * v.k;
+    utest[u] = (uint8_t)((culled ? 1u : 0u) | (fine ? 2u : 0u));
+  }
 }
 
-__device__ __forceinline__ bool chain_reached(const SceneDev& S, const ViewConst& v, bool cull, int32_t a) {
-  while (a >= 0) {
-    if (upper_stops(S, v, cull, a)) return false;
+// Longest ancestor chain a walk follows (a malformed parent array with a
+// cycle then reads as "not reached" instead of looping).
+constexpr int32_t kMaxWalk = 4096;
+
+// Walk up from a (the first upper ancestor, -1 for none): reached iff no
+// upper ancestor stops the descent.
+__device__ __forceinline__ bool chain_reached(const SceneDev& S, const uint8_t* utest, int32_t a) {
+  for (int32_t steps = 0; a >= 0; ++steps) {
+    if (steps >= kMaxWalk || a >= S.n_upper) return false;
+    if (utest[a]) return false;
     a = S.upper_parent[a];
   }
   return true;
 }
 
+// The same from the ancestor table of element e: sixteen ancestors' tests are
+// requested together instead of one dependent load per level.
+__device__ __forceinline__ bool table_reached(const SceneDev& S, const uint8_t* utest, int64_t e, int64_t total) {
+  constexpr int W = 16;
+  for (int32_t d0 = 0; d0 < S.anc_depth; d0 += W) {
+    int32_t a[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) a[k] = d0 + k < S.anc_depth ? S.anc[(int64_t)(d0 + k) * total + e] : -1;
+    uint32_t t[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) t[k] = utest[a[k] < 0 ? 0 : a[k]];  // node 0 stands in for missing entries
+    bool stop = false, end = false;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      end = end || a[k] < 0;
+      stop = stop || (!end && t[k] != 0u);
+    }
+    if (stop) return false;
+    if (end) return true;
+  }
+  return true;
+}
+
+// high = #{i < m : r[i] > X} for r descending, by an 8-ary search: each
+// round requests 8 evenly spaced samples together and keeps the interval
+// between the last sample above X and the first one not above it.
+__device__ __forceinline__ int32_t count_above(const float* r, int32_t m, float X) {
+  int32_t lo = 0, hi = m;  // the answer lies in [lo, hi]
+  while (hi - lo > 8) {
+    const int32_t span = hi - lo;
+    int32_t p[8];
+    float rv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      p[k] = lo + (int32_t)(((int64_t)(k + 1) * span) / 9);
+      rv[k] = r[p[k]];
+    }
+    int32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c += rv[k] > X ? 1 : 0;
+    const int32_t nlo = c > 0 ? p[c > 0 ? c - 1 : 0] + 1 : lo;
+    const int32_t nhi = c < 8 ? p[c < 8 ? c : 7] : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  float rv[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) rv[k] = lo + k < hi ? r[lo + k] : 0.0f;
+  int32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) c += (lo + k < hi && rv[k] > X) ? 1 : 0;
+  return lo + c;
+}
+
+__device__ __forceinline__ bool reached(const SceneDev& S, const uint8_t* utest, int64_t e, int64_t total,
+                                        int32_t first) {
+  return S.anc ? table_reached(S, utest, e, total) : chain_reached(S, utest, first);
+}
+
+// Ancestor-table construction: chain lengths (the maximum, or kMaxAncDepth + 1
+// for a chain that is too long or leaves the upper node range), then the rows.
+__global__ void __launch_bounds__(kBlock) k_anc_depth(SceneDev S, int32_t* depth) {
+  const int64_t total = (int64_t)S.n_upper + S.n_spt;
+  int32_t dmax = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t a = e < S.n_upper ? S.upper_parent[e] : S.spt_parent[e - S.n_upper];
+    int32_t d = 0;
+    while (a >= 0 && d <= kMaxAncDepth) {
+      if (a >= S.n_upper) {
+        d = kMaxAncDepth + 1;
+        break;
+      }
+      ++d;
+      a = S.upper_parent[a];
+    }
+    dmax = d > dmax ? d : dmax;
+  }
+  if (dmax) atomicMax(depth, dmax);
+}
+
+__global__ void __launch_bounds__(kBlock) k_anc_fill(SceneDev S, int32_t D, int32_t* anc) {
+  const int64_t total = (int64_t)S.n_upper + S.n_spt;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int32_t a = e < S.n_upper ? S.upper_parent[e] : S.spt_parent[e - S.n_upper];
+    for (int32_t d = 0; d < D; ++d) {
+      anc[(int64_t)d * total + e] = a;
+      if (a >= 0) a = S.upper_parent[a];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewConst* __restrict__ vp, uint32_t flags,
-                                                      uint8_t* upper_sel, int32_t* spt_high, float* spt_X,
-                                                      FrameCounters* ctr) {
+                                                      const uint8_t* utest, uint8_t* upper_sel, int32_t* spt_high,
+                                                      float* spt_X, FrameCounters* ctr) {
   const ViewConst v = *vp;
   const bool cull = (flags & LODGS_CULL) != 0;
   const int64_t total = (int64_t)S.n_upper + S.n_spt;
@@ -42,30 +152,18 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewCons
        e += (int64_t)gridDim.x * blockDim.x) {
     if (e < S.n_upper) {
       const int32_t u = (int32_t)e;
-      uint8_t sel = 0;
-      if (chain_reached(S, v, cull, S.upper_parent[u])) {
-        const float mx = S.means[3 * e], my = S.means[3 * e + 1], mz = S.means[3 * e + 2];
-        const bool culled = cull && sphere_culled(v, mx, my, mz, S.rho[u]);
-        sel = (!culled && S.r_min[u] <= view_distance(v, mx, my, mz) * v.k) ? 1 : 0;
-      }
-      upper_sel[u] = sel;
+      upper_sel[u] = (utest[u] == 2u && reached(S, utest, e, total, S.upper_parent[u])) ? 1 : 0;
     } else {
       const int32_t j = (int32_t)(e - S.n_upper);
       const int32_t b = S.spt_begin[j], m = S.spt_begin[j + 1] - b;
       int32_t high = 0;
       float X = 0.0f;
-      if (chain_reached(S, v, cull, S.spt_parent[j])) {
+      if (reached(S, utest, e, total, S.spt_parent[j])) {
         const float mx = S.means[3 * (int64_t)b], my = S.means[3 * (int64_t)b + 1], mz = S.means[3 * (int64_t)b + 2];
         if (!(cull && sphere_culled(v, mx, my, mz, S.rho[b]))) {
           X = view_distance(v, mx, my, mz) * v.k;
-          int32_t lo = 0, hi = m;
-          while (lo < hi) {
-            const int32_t mid = (lo + hi) >> 1;
-            if (S.r_max[b + mid] > X) lo = mid + 1;
-            else hi = mid;
-          }
-          high = lo;
-          hsum += lo;
+          high = count_above(S.r_max + b, m, X);
+          hsum += high;
           ++vis;
         }
       }
@@ -73,14 +171,27 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewCons
       spt_X[j] = X;
     }
   }
-  // one atomic per wave
+  // one pair of atomics per workgroup (same-address atomics serialise)
+  __shared__ int wsum[kBlock / 64][2];
   for (int d = 32; d > 0; d >>= 1) {
     vis += __shfl_xor(vis, d, 64);
     hsum += __shfl_xor(hsum, d, 64);
   }
-  if ((threadIdx.x & 63) == 0 && vis) {
-    atomicAdd(&ctr->n_spt_visible, vis);
-    atomicAdd(&ctr->sum_high, hsum);
+  if ((threadIdx.x & 63) == 0) {
+    wsum[threadIdx.x >> 6][0] = vis;
+    wsum[threadIdx.x >> 6][1] = hsum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0, b = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+      a += wsum[w][0];
+      b += wsum[w][1];
+    }
+    if (a) {
+      atomicAdd(&ctr->n_spt_visible, a);
+      atomicAdd(&ctr->sum_high, b);
+    }
   }
 }
 
@@ -139,9 +250,18 @@ __global__ void __launch_bounds__(kBlock) k_segments(SceneDev S, const uint8_t* 
       const int32_t e_end = min(h, e_begin + kChunk);
       const float X = spt_X[j];
       const int32_t b0 = S.spt_begin[j];
-      for (int32_t e0 = e_begin; e0 < e_end; e0 += 64) {
-        const int32_t e = e0 + lane;
-        const bool p = e < e_end && S.r_min[b0 + e] <= X;
+      // the chunk's candidates (at most kChunk = 8 x 64) are requested together
+      static_assert(kChunk == 8 * 64, "eight wave-wide loads per chunk");
+      float rm[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t e = e_begin + 64 * q + lane;
+        rm[q] = e < e_end ? S.r_min[b0 + e] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t e = e_begin + 64 * q + lane;
+        const bool p = e < e_end && rm[q] <= X;
         const uint64_t b = __ballot(p);
         if (WRITE && p) {
           const uint32_t pos = base + c + (uint32_t)__popcll(b & lt);
@@ -152,8 +272,15 @@ __global__ void __launch_bounds__(kBlock) k_segments(SceneDev S, const uint8_t* 
     }
     if (!WRITE && lane == 0) seg[sg] = c;
   }
-  if (!WRITE) {
-    if (lane == 0 && up_count) atomicAdd(&ctr->n_upper_selected, (int)up_count);
+  if (!WRITE) {  // one atomic per workgroup
+    __shared__ uint32_t wup[kBlock / 64];
+    if (lane == 0) wup[threadIdx.x >> 6] = up_count;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (int w = 0; w < kBlock / 64; ++w) t += wup[w];
+      if (t) atomicAdd(&ctr->n_upper_selected, (int)t);
+    }
   } else if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int32_t n = ctr->n_selected;
     *d_count = n;
@@ -168,6 +295,43 @@ struct LoadChunks {
 
 }  // namespace
 
+int build_ancestor_table(lodgs_scene* s) {
+  SceneDev& S = s->dev;
+  const int64_t total = (int64_t)S.n_upper + S.n_spt;
+  if (S.n_upper <= 0 || total <= 0) return LODGS_OK;
+  int32_t* d_depth = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&d_depth), sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemset(d_depth, 0, sizeof(int32_t));
+  int grid = (int)((total + kBlock - 1) / kBlock);
+  grid = grid > 4096 ? 4096 : grid;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_anc_depth, dim3(grid), dim3(kBlock), 0, 0, S, d_depth);
+    e = hipGetLastError();
+  }
+  int32_t D = 0;
+  if (e == hipSuccess) e = hipMemcpy(&D, d_depth, sizeof D, hipMemcpyDeviceToHost);
+  if (d_depth) (void)hipFree(d_depth);
+  if (e != hipSuccess) return hip_fail(e, "lodgs_scene_create: ancestor table");
+  if (D <= 0 || D > kMaxAncDepth) return LODGS_OK;  // the cut walks the parent array instead
+  int32_t* anc = nullptr;
+  e = hipMalloc(reinterpret_cast<void**>(&anc), sizeof(int32_t) * (size_t)D * (size_t)total);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return LODGS_OK;  // no room: the cut walks the parent array instead
+  }
+  hipLaunchKernelGGL(k_anc_fill, dim3(grid), dim3(kBlock), 0, 0, S, D, anc);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(anc);
+    return hip_fail(e, "lodgs_scene_create: ancestor table");
+  }
+  s->anc_owned = anc;
+  S.anc = anc;
+  S.anc_depth = D;
+  return LODGS_OK;
+}
+
 void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
                    int32_t* d_count, hipStream_t st) {
   const SceneDev& S = f->scene->dev;
@@ -176,8 +340,11 @@ void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* 
   const int64_t total = (int64_t)S.n_upper + S.n_spt;
   int grid = (int)((total + kBlock - 1) / kBlock);
   grid = grid < 1 ? 1 : (grid > 4096 ? 4096 : grid);
-  hipLaunchKernelGGL(k_cut_upper, dim3(grid), dim3(kBlock), 0, st, S, f->d_view_sel, flags, f->upper_sel, f->spt_high, f->spt_X,
-                     f->ctr);
+  int ugrid = (int)((S.n_upper + kBlock - 1) / kBlock);
+  ugrid = ugrid < 1 ? 1 : (ugrid > 4096 ? 4096 : ugrid);
+  hipLaunchKernelGGL(k_upper_tests, dim3(ugrid), dim3(kBlock), 0, st, S, f->d_view_sel, flags, f->upper_test);
+  hipLaunchKernelGGL(k_cut_upper, dim3(grid), dim3(kBlock), 0, st, S, f->d_view_sel, flags, f->upper_test,
+                     f->upper_sel, f->spt_high, f->spt_X, f->ctr);
   const int32_t n_up_chunks = (S.n_upper + 63) / 64;
   // chunks per visible SPT prefix -> offsets, total -> n_chunks
   scan_exclusive(LoadChunks{f->spt_high}, &f->ctr->spt_count, (int64_t)S.n_spt, f->block_sums,
