@@ -47,6 +47,30 @@ def random_tree(rng: np.random.Generator, n_leaves: int, sh_degree: int = 1, ext
     return scenegen.tree_from_arrays(means, ls, q, op, sh, left, right, parent, root, log_threshold, sh_degree)
 
 
+def caterpillar_tree(rng: np.random.Generator, n_leaves: int, sh_degree: int = 1, extent: float = 10.0):
+    """Each internal node joins the previous root with a new leaf: depth
+    n_leaves - 1.  With a very low volume threshold every internal node is in
+    the upper hierarchy, which is then a chain of n_leaves - 1 nodes."""
+    n = 2 * n_leaves - 1
+    left = -np.ones(n, np.int32)
+    right = -np.ones(n, np.int32)
+    parent = -np.ones(n, np.int32)
+    root = 0
+    for k in range(1, n_leaves):
+        nxt = n_leaves + k - 1
+        left[nxt], right[nxt] = root, k
+        parent[root] = parent[k] = nxt
+        root = nxt
+    means = rng.uniform(-extent, extent, (n, 3))
+    ls = rng.normal(-1.0, 1.0, (n, 3))
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    op = rng.normal(size=n)
+    nb = (sh_degree + 1) ** 2
+    sh = rng.normal(0, 0.2, (n, nb, 3))
+    return scenegen.tree_from_arrays(means, ls, q, op, sh, left, right, parent, root, -1e30, sh_degree)
+
+
 def g64(tree) -> np.ndarray:
     s = np.exp(tree.log_scales.astype(np.float64))
     return np.sqrt(s[:, 0] * s[:, 1] + s[:, 0] * s[:, 2] + s[:, 1] * s[:, 2])

@@ -13,7 +13,7 @@ import oracle
 import scenegen
 from scenegen import configs
 
-from _helpers import random_tree
+from _helpers import caterpillar_tree, random_tree
 
 pytestmark = pytest.mark.gpu
 
@@ -130,6 +130,23 @@ def test_select_random_trees_bitexact(torch_cuda):
         _say("select random tree", it, tree.n_nodes)
         for tau in (0.1, 1.0, 10.0, 100.0):
             _check_select(O, _frame(S, cam), cam, tau, cull=bool(it % 2))
+
+
+def test_select_deep_upper_hierarchy_bitexact(torch_cuda):
+    # an upper hierarchy deeper than the ancestor table holds: the cut walks the
+    # parent array instead, with the same decisions
+    rng = np.random.default_rng(23)
+    for it, n in enumerate((100, 300)):
+        tree = caterpillar_tree(rng, n)
+        O = oracle.OracleScene(tree)
+        assert O.n_upper == n - 1  # every internal node is an upper node: depth n - 1 > 64
+        S = _scene(tree)
+        for k in range(3):
+            pos = rng.uniform(-30, 30, 3)
+            cam = scenegen.camera_look_at(pos, rng.uniform(-10, 10, 3), (0, 0, 1), 64, 48)
+            _say("select deep hierarchy", n, k)
+            for tau in (0.1, 1.0, 10.0):
+                _check_select(O, _frame(S, cam), cam, tau, cull=bool(k % 2))
 
 
 def test_select_capacity_overflow_is_reported(torch_cuda):
