@@ -138,9 +138,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
       if (i < nr) {
         batch[threadIdx.x] = splats[i];
       } else {  // only reachable if the instance count overflowed
-        Splat z = {};
-        z.ex = -1.0f;
-        batch[threadIdx.x] = z;
+        batch[threadIdx.x] = Splat{};  // no event bits: never replayed
       }
     }
     __syncthreads();

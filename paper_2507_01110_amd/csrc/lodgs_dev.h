@@ -99,15 +99,14 @@ __device__ __forceinline__ bool sphere_culled(const ViewConst& v, float mx, floa
 // the projected mean as hi/lo float pairs, the principal axis (ce, se) of the
 // projected covariance and the power coefficients h1 = -1/(2 l1),
 // h2 = -1/(2 l2) of its eigenvalues (power = h1 u1^2 + h2 u2^2 in that
-// basis), opacity, colour, and the half extents of the box outside which
-// alpha < 1/255 for certain (used only to skip work whose result is known),
-// and the colour clamp decisions.
+// basis), opacity, colour, footprint radius and the colour clamp decisions.
 struct alignas(16) Splat {
   float mxh, mxl, myh, myl;
   float ce, se, h1, h2;
   float o, r, g, b;
-  float ex, ey, radius;
+  float radius;
   uint32_t clamp;  // bit c: colour channel c was clamped at 0 (read by the backward)
+  float pad0, pad1;
 };
 
 // Power of a splat at the pixel centre (px, py), FP32, fixed operation order.
@@ -122,14 +121,6 @@ __device__ __forceinline__ float splat_power(const Splat& s, float px, float py,
   float a2 = s.h2 * u2;
   a2 = a2 * u2;
   return __builtin_fmaf(s.h1 * u1, u1, a2);
-}
-
-// True when alpha < 1/255 is certain for every pixel centre in [x0, x1] x
-// [y0, y1] (the splat's box, with its margins, misses the rectangle, or the
-// opacity alone is below 1/255).  Skipping such a splat leaves every result
-// unchanged.
-__device__ __forceinline__ bool splat_misses(const Splat& s, float x0, float x1, float y0, float y1) {
-  return (s.ex < 0.0f) | (s.mxh + s.ex < x0) | (s.mxh - s.ex > x1) | (s.myh + s.ey < y0) | (s.myh - s.ey > y1);
 }
 
 // Real SH basis constants, l <= 3 (3DGS sign convention).
@@ -193,12 +184,56 @@ __device__ __forceinline__ void sh_basis_grad(int deg, float x, float y, float z
   dY[15][0] = kSH3_6 * (3.0f * xx - 3.0f * yy); dY[15][1] = -6.0f * kSH3_6 * x * y;
 }
 
+// Smallest value of -power = a1 u1^2 + a2 u2^2 (a = -h > 0, u the splat's
+// eigenbasis coordinates of the offset from its mean) over the pixel-centre
+// rectangle [x0, x1] x [y0, y1]: zero when the mean lies inside, otherwise
+// the smallest of the four edge minima (a convex quadratic on a segment).
+__device__ __forceinline__ float splat_rect_min(const Splat& s, float x0, float x1, float y0, float y1) {
+  const float a1 = -s.h1, a2 = -s.h2;
+  const float mx = s.mxh + s.mxl, my = s.myh + s.myl;
+  if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return 0.0f;
+  float best = 3.0e38f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    // edges: bottom/top (along x) and left/right (along y)
+    const bool along_x = k < 2;
+    const float px = (k == 3) ? x1 : x0, py = (k == 1) ? y1 : y0;
+    const float len = along_x ? x1 - x0 : y1 - y0;
+    const float dx = (px - s.mxh) - s.mxl, dy = (py - s.myh) - s.myl;
+    const float c1 = __builtin_fmaf(s.se, dy, s.ce * dx), c2 = __builtin_fmaf(-s.se, dx, s.ce * dy);
+    const float e1 = along_x ? s.ce : s.se, e2 = along_x ? -s.se : s.ce;
+    const float den = __builtin_fmaf(a1 * e1, e1, a2 * e2 * e2);
+    float t = den > 0.0f ? -__builtin_fmaf(a1 * c1, e1, a2 * c2 * e2) / den : 0.0f;
+    t = fminf(fmaxf(t, 0.0f), len);
+    const float u1 = __builtin_fmaf(t, e1, c1), u2 = __builtin_fmaf(t, e2, c2);
+    best = fminf(best, __builtin_fmaf(a1 * u1, u1, a2 * u2 * u2));
+  }
+  return best;
+}
+
+// Bit q (quarter (q & 1, q >> 1) of the 16x16 tile at (tx, ty)) is set unless
+// alpha < 1/255 is certain at every pixel centre of that 8x8 quarter:
+// alpha >= 1/255 needs -power <= ln(255 o), and the quarter's minimum of
+// -power exceeds that bound by a margin (1% + 0.02) far above the FP32
+// evaluation error of the power, so a cleared bit only skips known results.
+__device__ __forceinline__ uint32_t splat_quarter_mask(const Splat& s, int tx, int ty) {
+  const float lo = 255.0f * s.o;
+  if (!(lo >= 1.0f)) return 0u;
+  const float qmax = __builtin_fmaf(0.01f, __logf(lo), __logf(lo)) + 0.02f;
+  uint32_t m = 0u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float x0 = (float)(tx * kTile + 8 * (q & 1)) + 0.5f, y0 = (float)(ty * kTile + 8 * (q >> 1)) + 0.5f;
+    if (splat_rect_min(s, x0, x0 + 7.0f, y0, y0 + 7.0f) <= qmax) m |= 1u << q;
+  }
+  return m;
+}
+
 // Pixel layout of the blend kernels: a 16x16 tile is one workgroup of 4/PX
 // waves, PX pixels per lane.  PX = 1: wave w covers the 8x8 quarter
 // (w & 1, w >> 1) of the tile, lane l its pixel (l & 7, l >> 3).  PX = 2, 4:
 // wave w covers the rows [4 PX w, 4 PX (w + 1)), lane l the column l & 15 and
-// the rows 4 PX w + (l >> 4) + 4p, p < PX.  A wave's pixel-centre rectangle is
-// used to skip splats whose result there is known.
+// the rows 4 PX w + (l >> 4) + 4p, p < PX.
 template <int PX>
 __device__ __forceinline__ void blend_pixel(int tx, int ty, int wv, int lane, int p, int& x, int& y) {
   if (PX == 1) {
@@ -207,21 +242,6 @@ __device__ __forceinline__ void blend_pixel(int tx, int ty, int wv, int lane, in
   } else {
     x = tx * kTile + (lane & 15);
     y = ty * kTile + 4 * PX * wv + (lane >> 4) + 4 * p;
-  }
-}
-
-template <int PX>
-__device__ __forceinline__ void blend_wave_box(int tx, int ty, int wv, float& x0, float& x1, float& y0, float& y1) {
-  if (PX == 1) {
-    x0 = (float)(tx * kTile + 8 * (wv & 1)) + 0.5f;
-    x1 = x0 + 7.0f;
-    y0 = (float)(ty * kTile + 8 * (wv >> 1)) + 0.5f;
-    y1 = y0 + 7.0f;
-  } else {
-    x0 = (float)(tx * kTile) + 0.5f;
-    x1 = x0 + 15.0f;
-    y0 = (float)(ty * kTile + 4 * PX * wv) + 0.5f;
-    y1 = y0 + (float)(4 * PX - 1);
   }
 }
 

@@ -99,6 +99,7 @@ struct lodgs_frame {
   uint32_t* inst_splat;   // [max_instances] selection position of each instance (emission order)
   float* inst_grad;       // [max_instances][9] per-instance 2D gradient partials (emission order)
   uint8_t* inst_event;    // [max_instances] forward event bits per tile quarter (tile order)
+  uint8_t* inst_quarters; // [max_instances] quarters the splat's alpha >= 1/255 ellipse reaches (emission order)
   float* grad2d;          // [max_selected][9] per-drawn-splat 2D gradients (drawn rank)
   uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances
   uint2* ranges;          // [max tiles]

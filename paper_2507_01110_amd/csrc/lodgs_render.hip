@@ -15,8 +15,8 @@
 //  k_ranges   first/last instance of every tile.
 //  k_blend    one workgroup per tile, PX pixels per lane; splat records are
 //             staged in LDS one batch per workgroup size; a wave skips a splat
-//             whose alpha >= 1/255 box misses its 16 x 4 PX pixels (known
-//             result).
+//             whose alpha >= 1/255 ellipse reaches none of its 8x8 quarters of
+//             the tile (known result).
 #include "lodgs_internal.h"
 #include "lodgs_proj.h"
 
@@ -91,14 +91,7 @@ __device__ __forceinline__ Proj project_node(const SceneDev& S, const ViewConst&
   P.sp.o = 1.0f / (1.0f + fexp(-theta));
   P.sp.radius = (float)r;
   P.sp.clamp = 0u;
-  // Box outside which alpha < 1/255 is certain: alpha >= 1/255 needs
-  // q = x^T Sigma'^-1 x <= 2 ln(255 o), hence |x| <= sqrt(q_max Sigma'_00) per
-  // axis.  Margins cover the FP32 evaluation of the power.
-  const float lo = 255.0f * P.sp.o;
-  const bool faint = lo < 1.0f;  // alpha < 1/255 everywhere
-  const double qmax = 1.05 * (2.0 * (double)__logf(faint ? 1.0f : lo) + 0.01);
-  P.sp.ex = faint ? -1.0f : (float)(__builtin_sqrt(qmax * A) * 1.001 + 1.0);
-  P.sp.ey = faint ? -1.0f : (float)(__builtin_sqrt(qmax * C) * 1.001 + 1.0);
+  P.sp.pad0 = P.sp.pad1 = 0.0f;
   return P;
 }
 
@@ -187,12 +180,15 @@ struct LoadTilesInOrder {
 // clamped count for the later kernels and flags an overflow).  The first
 // instance of a splat records the splat's depth rank at its drawn rank (for
 // the backward, which walks the drawn splats in selection order), and lists
-// it when it has more than kLongSegment instances.
+// it when it has more than kLongSegment instances.  Each instance also gets
+// the quarters of its tile that the splat's alpha >= 1/255 ellipse can reach
+// (splat_quarter_mask); the forward skips the others.
 __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order,
                                                 const uint32_t* inst_off, const ushort4* rect, int32_t tiles_x,
                                                 int64_t cap, uint32_t* ikey, uint32_t* ival, uint32_t* inst_splat,
                                                 uint32_t* long_list, const uint32_t* drawn_rank,
-                                                uint32_t* depth_rank) {
+                                                uint32_t* depth_rank, const Splat* __restrict__ splats,
+                                                uint8_t* inst_quarters) {
   const uint32_t total = (uint32_t)ctr->n_instances;  // the scan's 32-bit sum
   const int64_t n = (int64_t)total > cap ? cap : (int64_t)total;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -219,10 +215,12 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
     inst_splat[k] = i;
     if (w == 0) {  // only reachable if the instance count overflowed
       ikey[k] = 0xFFFFFFFFu;
+      inst_quarters[k] = 0;
       continue;
     }
     const uint32_t ty = q.z + l / w, tx = q.x + l % w;
     ikey[k] = ty * (uint32_t)tiles_x + tx;
+    inst_quarters[k] = (uint8_t)splat_quarter_mask(splats[i], (int)tx, (int)ty);
   }
 }
 
@@ -245,7 +243,9 @@ __global__ void __launch_bounds__(kBlock) k_ranges(const FrameCounters* ctr, con
 }
 
 // One workgroup per tile with 4/PX waves, PX pixels per lane (the layout of
-// blend_pixel / blend_wave_box).  For every instance of the tile that it
+// blend_pixel / blend_wave_box).  A wave skips an instance whose quarter mask
+// (k_dup) covers none of its quarters: there alpha < 1/255 at every pixel.
+// For every instance of the tile that it
 // reaches, the forward records in event[k] the 8x8 quarters of the tile
 // (blend_wave_quarters) where some pixel blended the splat or stopped on it;
 // elsewhere the splat changed nothing, which lets the backward skip it there.
@@ -258,13 +258,15 @@ template <bool COUNT, int PX>
 __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict__ vp, const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ ival,
                                                     const uint32_t* __restrict__ inst_splat,
-                                                    const Splat* __restrict__ splats, const FrameCounters* ctr,
+                                                    const Splat* __restrict__ splats,
+                                                    const uint8_t* __restrict__ quarters, const FrameCounters* ctr,
                                                     float bg0, float bg1, float bg2, float* rgb, uint8_t* event,
                                                     unsigned long long* work) {
   constexpr int NT = 256 / PX;
   const ViewConst v = *vp;
   __shared__ Splat batch[NT];
   __shared__ uint32_t ev[NT];
+  __shared__ uint32_t qm[NT];
   const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
   const int tile = blockIdx.x;
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
@@ -282,9 +284,6 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     cr[p] = cg[p] = cb[p] = 0.0f;
   }
   const float fx = (float)px + 0.5f;
-  // pixel-centre rectangle of this wave
-  float wx0, wx1, wy0, wy1;
-  blend_wave_box<PX>(tx, ty, wv, wx0, wx1, wy0, wy1);
   const uint2 rg = ranges[tile];
   const uint32_t nr = (uint32_t)ctr->n_render;
   const float thr = 1.0f / 255.0f;
@@ -297,12 +296,13 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     const uint32_t k = b0 + threadIdx.x;
     ev[threadIdx.x] = 0u;
     if (k < rg.y) {
-      const uint32_t i = inst_splat[ival[k]];
+      const uint32_t e = ival[k];
+      const uint32_t i = inst_splat[e];
+      qm[threadIdx.x] = quarters[e];
       if (i < nr) {
         batch[threadIdx.x] = splats[i];
-      } else {  // only reachable if the instance count overflowed
+      } else {  // only reachable if the instance count overflowed (its quarter mask is 0)
         batch[threadIdx.x].o = 0.0f;
-        batch[threadIdx.x].ex = -1.0f;
       }
     }
     __syncthreads();
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     // one splat (batch slot j) against the wave's pixels; true when every
     // pixel has stopped
     auto step = [&](const Splat& s, int j) -> bool {
-      if (!COUNT && splat_misses(s, wx0, wx1, wy0, wy1)) return false;  // wave-uniform
+      if (!COUNT && (qm[j] & qmask) == 0u) return false;  // wave-uniform
       bool act = false, changed = false;
 #pragma unroll
       for (int p = 0; p < PX; ++p) {
@@ -381,15 +381,15 @@ static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], 
   switch (f->blend_px_fwd) {
     case 1:
       hipLaunchKernelGGL((k_blend<COUNT, 1>), dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
+                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
       break;
     case 4:
       hipLaunchKernelGGL((k_blend<COUNT, 4>), dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
+                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
       break;
     default:
       hipLaunchKernelGGL((k_blend<COUNT, 2>), dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
+                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
       break;
   }
 }
@@ -427,7 +427,8 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_drawn, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
   hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x, icap,
-                     f->ikey, f->ival, f->inst_splat, f->long_list, f->drawn_rank, f->depth_rank);
+                     f->ikey, f->ival, f->inst_splat, f->long_list, f->drawn_rank, f->depth_rank, f->splats,
+                     f->inst_quarters);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
