@@ -88,6 +88,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
                                                         const Splat* __restrict__ splats, const FrameCounters* ctr,
                                                         const float* __restrict__ rgb, const float* __restrict__ dL,
                                                         const uint8_t* __restrict__ event,
+                                                        const uint32_t* __restrict__ tile_order,
                                                         float* __restrict__ partial) {
   constexpr int NT = 256 / PX, NW = 4 / PX;
   const ViewConst v = *vp;
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   __shared__ uint32_t ev[NT];
   const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
   __shared__ float acc[NW][9][NT];
-  const int tile = blockIdx.x;
+  const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int px = 0;
@@ -615,15 +616,15 @@ void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, 
   switch (f->blend_px_bwd) {
     case 1:
       hipLaunchKernelGGL(k_blend_bwd<1>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->inst_grad);
+                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
       break;
     case 4:
       hipLaunchKernelGGL(k_blend_bwd<4>, dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->inst_grad);
+                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
       break;
     default:
       hipLaunchKernelGGL(k_blend_bwd<2>, dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->inst_grad);
+                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
       break;
   }
   stage_end(f, st);

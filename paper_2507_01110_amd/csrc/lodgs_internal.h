@@ -40,6 +40,7 @@ struct lodgs_scene {
 
 namespace lodgs {
 constexpr int32_t kMaxAncDepth = 64;
+constexpr int kTileClasses = 128;  // blend tile-order classes (quarter octaves of the instance count)
 // Builds the ancestor table (synchronous; scene creation only).
 int build_ancestor_table(lodgs_scene* s);
 }  // namespace lodgs
@@ -103,6 +104,7 @@ struct lodgs_frame {
   float* grad2d;          // [max_selected][9] per-drawn-splat 2D gradients (drawn rank)
   uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances
   uint2* ranges;          // [max tiles]
+  uint32_t* tile_order;   // [max tiles] tiles, heaviest first
   lodgs::ViewConst* d_view_sel;  // view constants of the last lod_select (device)
   lodgs::ViewConst* d_view_ren;  // view constants of the last render (device)
   // state of the last render

@@ -242,6 +242,73 @@ __global__ void __launch_bounds__(kBlock) k_ranges(const FrameCounters* ctr, con
   }
 }
 
+// Workgroup order of the blend kernels: tiles by descending class of their
+// instance count n (the bit length of n and the two bits below its leading
+// one, so classes are a quarter octave wide), so the longest workgroups start
+// early; results do not depend on the order of the tiles.  Workgroup b orders
+// the chunk of kOrderChunk tiles starting at b * kOrderChunk (a 1080p frame
+// has one chunk): each tile takes its rank within its class from an LDS
+// counter, and a scan over the classes gives each class its start.  The
+// order within a class is whatever the LDS atomics give.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBatch = 8;  // tiles per thread
+constexpr int32_t kOrderChunk = kOrderThreads * kOrderBatch;
+static_assert(kTileClasses == 128, "one thread per class in waves 0 and 1");
+
+__device__ __forceinline__ int tile_class(uint2 r) {
+  const uint32_t n = r.y - r.x;
+  const int bl = min(31, 32 - __clz((int)n));  // 0 for an empty tile
+  const int sub = bl >= 3 ? (int)((n >> (bl - 3)) & 3u) : 0;
+  return bl * 4 + sub;  // < kTileClasses
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* ranges, int32_t ntiles, uint32_t* order) {
+  __shared__ uint32_t cnt[kTileClasses];
+  __shared__ uint32_t half[2];
+  const int32_t lo = blockIdx.x * kOrderChunk;
+  const int32_t n = min(kOrderChunk, ntiles - lo);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint2 r[kOrderBatch];
+#pragma unroll
+  for (int k = 0; k < kOrderBatch; ++k) {
+    const int32_t t = k * kOrderThreads + (int32_t)threadIdx.x;
+    r[k] = t < n ? ranges[lo + t] : make_uint2(0u, 0u);
+  }
+  if (threadIdx.x < kTileClasses) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t key[kOrderBatch];  // class << 16 | rank within the class (rank < kOrderChunk)
+#pragma unroll
+  for (int k = 0; k < kOrderBatch; ++k) {
+    const int32_t t = k * kOrderThreads + (int32_t)threadIdx.x;
+    key[k] = 0;
+    if (t < n) {
+      const int c = tile_class(r[k]);
+      key[k] = ((uint32_t)c << 16) | atomicAdd(&cnt[c], 1u);
+    }
+  }
+  __syncthreads();
+  // cnt[c] becomes the tiles of all classes above c (waves 0 and 1, whole waves)
+  const int c = threadIdx.x;
+  uint32_t incl = 0;
+  if (c < kTileClasses) {
+    incl = cnt[c];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    if (lane == 63) half[wv] = incl;
+  }
+  __syncthreads();
+  if (c < kTileClasses) cnt[c] = half[0] + half[1] - (incl + (wv == 1 ? half[0] : 0u));
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kOrderBatch; ++k) {
+    const int32_t t = k * kOrderThreads + (int32_t)threadIdx.x;
+    if (t < n) order[lo + cnt[key[k] >> 16] + (key[k] & 0xFFFFu)] = (uint32_t)(lo + t);
+  }
+}
+
 // One workgroup per tile with 4/PX waves, PX pixels per lane (the layout of
 // blend_pixel / blend_wave_box).  A wave skips an instance whose quarter mask
 // (k_dup) covers none of its quarters: there alpha < 1/255 at every pixel.
@@ -260,15 +327,15 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
                                                     const uint32_t* __restrict__ inst_splat,
                                                     const Splat* __restrict__ splats,
                                                     const uint8_t* __restrict__ quarters, const FrameCounters* ctr,
-                                                    float bg0, float bg1, float bg2, float* rgb, uint8_t* event,
-                                                    unsigned long long* work) {
+                                                    const uint32_t* __restrict__ tile_order, float bg0, float bg1,
+                                                    float bg2, float* rgb, uint8_t* event, unsigned long long* work) {
   constexpr int NT = 256 / PX;
   const ViewConst v = *vp;
   __shared__ Splat batch[NT];
   __shared__ uint32_t ev[NT];
   __shared__ uint32_t qm[NT];
   const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
-  const int tile = blockIdx.x;
+  const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int px, pys[PX];
@@ -381,15 +448,18 @@ static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], 
   switch (f->blend_px_fwd) {
     case 1:
       hipLaunchKernelGGL((k_blend<COUNT, 1>), dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
+                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         d_rgb, event, work);
       break;
     case 4:
       hipLaunchKernelGGL((k_blend<COUNT, 4>), dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
+                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         d_rgb, event, work);
       break;
     default:
       hipLaunchKernelGGL((k_blend<COUNT, 2>), dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, bg[0], bg[1], bg[2], d_rgb, event, work);
+                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         d_rgb, event, work);
       break;
   }
 }
@@ -440,6 +510,9 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_RANGES, st);
   hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_ikey, f->ranges, (uint32_t)ntiles);
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_tile_order, dim3((ntiles + kOrderChunk - 1) / kOrderChunk), dim3(kOrderThreads), 0, st,
+                       f->ranges, ntiles, f->tile_order);
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_BLEND, st);
   launch_blend<false>(f, v, bg, d_rgb, st);
