@@ -265,7 +265,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(ikey2, ni);
   A(ival2, ni);
   A(inst_splat, ni);
-  A(inst_grad, 9 * ni);
+  A(inst_grad, (size_t)lodgs::kPartial * ni);
   A(inst_event, ni);
   A(inst_quarters, ni);
   A(grad2d, 9 * ns);

@@ -1,29 +1,26 @@
 // Backward of the render (recompute-based): per tile, the forward
 // front-to-back pass is replayed with identical FP32 decisions and the
 // gradient of every contributing (splat, pixel) pair is formed on the fly,
-// using the final pixel colour to obtain the colour behind each splat
-// (S_i = C_final - C_prefix_i - c_i alpha_i T_i).  Per-splat sums over the
-// tile's pixels are gathered in LDS for each batch of 256 splats (LDS atomics
-// from the contributing lanes when a wave has at most four of them, else a
-// DPP reduction across the wave and one LDS atomic) and flushed with one
-// global atomic per splat, tile and value.  A wave skips
-// a splat whose alpha >= 1/255 box misses the wave's 16x4 pixels (its result
-// there is known to be "skip").  Then one thread per rendered node carries
-// the 2D gradients through the conic inverse, the EWA Jacobian, the camera
-// transform, the covariance factorisation, the quaternion normalisation, the
-// sigmoid and the SH basis to the raw parameters.
+// using the final pixel colour to obtain the colour behind each splat.  Each
+// (splat, tile) instance gets one partial of per-pixel sums (moments about the
+// tile centre, dL/do, dL/dRGB), written at its emission index without
+// atomics.  The projection backward then forms each drawn splat's 2D sums
+// from its partials in FP64 and carries them through the conic inverse, the
+// EWA Jacobian, the camera transform, the covariance factorisation, the
+// quaternion normalisation, the sigmoid and the SH basis to the raw
+// parameters.
 #include "lodgs_internal.h"
 #include "lodgs_proj.h"
 
 namespace lodgs {
 
-// Reduce-scatter of 9 per-lane values over a wave (all lanes active): four
+// Reduce-scatter of 10 per-lane values over a wave (all lanes active): four
 // DPP exchange steps inside each 16-lane row pair lane l with l^1, l^2, l^7
 // and l^15; at each step a lane keeps half of its remaining values (chosen by
 // b0^b2, b1^b2, b2^b3 and b3 of l & 15) and adds its partner's copy of that
 // half.  Lane l then holds its row's sum of value
-// slot(l) = (b0^b2) + 2 (b1^b2) + 4 (b2^b3) + 8 b3 (slots 9..15 are zero);
-// in the wave form two cross-row exchanges complete the sums over the wave.
+// slot(l) = (b0^b2) + 2 (b1^b2) + 4 (b2^b3) + 8 b3 (slots 10..15 are zero);
+// two cross-row exchanges complete the sums over the wave.
 #define LODGS_DPP(x, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false))
 #define LODGS_RS_PAIR(out, a, b, k, ctrl)       \
   do {                                          \
@@ -32,7 +29,7 @@ namespace lodgs {
     (out) = keep_ + LODGS_DPP(send_, ctrl);     \
   } while (0)
 
-__device__ __forceinline__ float row_reduce_scatter9(const float* g, int lane, int& slot) {
+__device__ __forceinline__ float wave_reduce_scatter10(const float* g, int lane, int& slot) {
   const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
   const bool k1 = (b0 ^ b2) != 0, k2 = (b1 ^ b2) != 0, k3 = (b2 ^ b3) != 0, k4 = b3 != 0;
   float h0, h1, h2, h3, h4;
@@ -40,7 +37,7 @@ __device__ __forceinline__ float row_reduce_scatter9(const float* g, int lane, i
   LODGS_RS_PAIR(h1, g[2], g[3], k1, 0xB1);
   LODGS_RS_PAIR(h2, g[4], g[5], k1, 0xB1);
   LODGS_RS_PAIR(h3, g[6], g[7], k1, 0xB1);
-  LODGS_RS_PAIR(h4, g[8], 0.0f, k1, 0xB1);
+  LODGS_RS_PAIR(h4, g[8], g[9], k1, 0xB1);
   float q0, q1, q2;
   LODGS_RS_PAIR(q0, h0, h1, k2, 0x4E);  // quad_perm [2,3,0,1]: l^2
   LODGS_RS_PAIR(q1, h2, h3, k2, 0x4E);
@@ -51,11 +48,6 @@ __device__ __forceinline__ float row_reduce_scatter9(const float* g, int lane, i
   float z;
   LODGS_RS_PAIR(z, r0, r1, k4, 0x140);  // row_mirror: l^15
   slot = (int)k1 + 2 * (int)k2 + 4 * (int)k3 + 8 * (int)k4;
-  return z;
-}
-
-__device__ __forceinline__ float wave_reduce_scatter9(const float* g, int lane, int& slot) {
-  float z = row_reduce_scatter9(g, lane, slot);
   z += __shfl_xor(z, 16, 64);
   z += __shfl_xor(z, 32, 64);
   return z;
@@ -71,13 +63,16 @@ __device__ __forceinline__ float wave_reduce_scatter9(const float* g, int lane, 
 // Per pixel, dL/dalpha = T (G . c) - (G . (C - Q)) / (1 - alpha), with G =
 // dL/dC, c the splat colour, C the final colour and Q the colour blended up
 // to and including the splat; G . C is fixed per pixel and G . Q is kept as
-// one running scalar.  The per-pixel sums are taken in the splat's eigenbasis
-// (sum of dpow u1, dpow u2) and without constant factors (dpow dx^2,
-// dpow dx dy, dpow dy^2); the per-splat rotation and factors are applied once
-// per instance when the partial is written.  Per batch, each wave reduces
-// these 9 values of a splat over its lanes (only when some lane contributes)
-// and stores them in its own LDS row; the workgroup then sums the rows in wave
-// order and writes one 9-float partial per (splat, tile) instance at the
+// one running scalar.  With w = dL/dpower = alpha dL/dalpha, the geometric
+// part of a splat's gradient needs sum w d and sum w d d^T over its pixels,
+// d = pixel - mean.  They are gathered as moments about the tile centre c_t
+// (e = pixel - c_t, |e| <= 7.5): sum w, sum w e, sum w e e^T, so the FP32
+// sums stay well conditioned even for a splat whose mean lies far off the
+// screen; the projection backward shifts them by c_t - mean in FP64.  Per
+// batch, each wave reduces these 10 values of a splat (moments, dL/do and the
+// colour gradient) over its lanes (only when some lane contributes) and
+// stores them in its own LDS row; the workgroup then sums the rows in wave
+// order and writes one 10-float partial per (splat, tile) instance at the
 // instance's emission index, with zeros for instances that no pixel reached.
 // No atomics: the result is deterministic.
 template <int PX>
@@ -96,12 +91,13 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   __shared__ uint32_t bid[NT];
   __shared__ uint32_t ev[NT];
   const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
-  __shared__ float acc[NW][9][NT];
+  __shared__ float acc[NW][kPartial][NT];
   const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int px = 0;
   float fy[PX], T[PX], GQ[PX], GC[PX], G0[PX], G1[PX], G2[PX];
+  float ey[PX], exx[PX], exy[PX], eyy[PX];  // offsets from the tile centre
   bool live[PX];
 #pragma unroll
   for (int p = 0; p < PX; ++p) {
@@ -120,10 +116,18 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     }
   }
   const float fx = (float)px + 0.5f;
+  const float ex = fx - (float)(16 * tx + 8);
+#pragma unroll
+  for (int p = 0; p < PX; ++p) {
+    ey[p] = fy[p] - (float)(16 * ty + 8);
+    exx[p] = ex * ex;
+    exy[p] = ex * ey[p];
+    eyy[p] = ey[p] * ey[p];
+  }
   const uint2 rg = ranges[tile];
   const uint32_t nr = (uint32_t)ctr->n_render;
   const float thr = 1.0f / 255.0f;
-  for (int t = threadIdx.x; t < NW * 9 * NT; t += NT) (&acc[0][0][0])[t] = 0.0f;
+  for (int t = threadIdx.x; t < NW * kPartial * NT; t += NT) (&acc[0][0][0])[t] = 0.0f;
   uint32_t b0 = rg.x;
   for (; b0 < rg.y; b0 += NT) {
     bool active = false;
@@ -167,7 +171,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
           act = act | live[p];
         }
         if (__any(any_con)) {  // wave-uniform
-          float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+          float g[kPartial] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
           for (int p = 0; p < PX; ++p) {
             const float alpha = als[p], Tp = T[p];
@@ -183,22 +187,22 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
             const float dpow = unclamped ? dA * alpha : 0.0f;
             const float dop = unclamped ? dA * es[p] : 0.0f;
             const float wc = con ? w : 0.0f;
-            const float tx = dpow * dxs[p], ty = dpow * dys[p];
-            g[0] = __builtin_fmaf(dpow, u1s[p], g[0]);
-            g[1] = __builtin_fmaf(dpow, u2s[p], g[1]);
-            g[2] = __builtin_fmaf(tx, dxs[p], g[2]);
-            g[3] = __builtin_fmaf(tx, dys[p], g[3]);
-            g[4] = __builtin_fmaf(ty, dys[p], g[4]);
-            g[5] += dop;
-            g[6] = __builtin_fmaf(G0[p], wc, g[6]);
-            g[7] = __builtin_fmaf(G1[p], wc, g[7]);
-            g[8] = __builtin_fmaf(G2[p], wc, g[8]);
+            g[0] += dpow;
+            g[1] = __builtin_fmaf(dpow, ex, g[1]);
+            g[2] = __builtin_fmaf(dpow, ey[p], g[2]);
+            g[3] = __builtin_fmaf(dpow, exx[p], g[3]);
+            g[4] = __builtin_fmaf(dpow, exy[p], g[4]);
+            g[5] = __builtin_fmaf(dpow, eyy[p], g[5]);
+            g[6] += dop;
+            g[7] = __builtin_fmaf(G0[p], wc, g[7]);
+            g[8] = __builtin_fmaf(G1[p], wc, g[8]);
+            g[9] = __builtin_fmaf(G2[p], wc, g[9]);
             GQ[p] = con ? gq : GQ[p];
             T[p] = con ? tts[p] : Tp;
           }
           int slot;
-          const float r = wave_reduce_scatter9(g, lane, slot);
-          if (lane < 16 && slot < 9) acc[wv][slot][j] = r;
+          const float r = wave_reduce_scatter10(g, lane, slot);
+          if (lane < 16 && slot < kPartial) acc[wv][slot][j] = r;
         }
         return !__any(act);
       };
@@ -213,36 +217,25 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
-      float r[9];
+      float* dst = partial + kPartial * (int64_t)bid[threadIdx.x];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        r[c] = acc[0][c][threadIdx.x];
+      for (int c = 0; c < kPartial; ++c) {
+        float r = acc[0][c][threadIdx.x];
         acc[0][c][threadIdx.x] = 0.0f;
 #pragma unroll
         for (int w = 1; w < NW; ++w) {
-          r[c] += acc[w][c][threadIdx.x];
+          r += acc[w][c][threadIdx.x];
           acc[w][c][threadIdx.x] = 0.0f;
         }
+        dst[c] = r;
       }
-      // d power / d mean2D = -2 (h1 u1 e1 + h2 u2 e2), e1 = (ce, se),
-      // e2 = (-se, ce); d power / d conic = -(dx^2 / 2, dx dy, dy^2 / 2)
-      const Splat& s = batch[threadIdx.x];
-      const float a1 = -2.0f * s.h1 * r[0], a2 = -2.0f * s.h2 * r[1];
-      float* dst = partial + 9 * (int64_t)bid[threadIdx.x];
-      dst[0] = a1 * s.ce - a2 * s.se;
-      dst[1] = a1 * s.se + a2 * s.ce;
-      dst[2] = -0.5f * r[2];
-      dst[3] = -r[3];
-      dst[4] = -0.5f * r[4];
-#pragma unroll
-      for (int c = 5; c < 9; ++c) dst[c] = r[c];
     }
   }
   // instances that no pixel of the tile reached
   for (uint32_t k = b0 + threadIdx.x; k < rg.y; k += NT) {
-    float* dst = partial + 9 * (int64_t)ival[k];
+    float* dst = partial + kPartial * (int64_t)ival[k];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) dst[c] = 0.0f;
+    for (int c = 0; c < kPartial; ++c) dst[c] = 0.0f;
   }
 }
 
@@ -259,14 +252,6 @@ __global__ void __launch_bounds__(kBlock) k_zero_sel(const FrameCounters* ctr, i
     if (sel.d_opacity_logits) sel.d_opacity_logits[i] = 0.0f;
     if (sel.d_sh) for (int k = 0; k < nc; ++k) sel.d_sh[(int64_t)nc * i + k] = 0.0f;
   }
-}
-
-// Lane of a row that holds value slot s after row_reduce_scatter9 (inverse of
-// slot(l): b3 = k4, b2 = k3 ^ b3, b1 = k2 ^ b2, b0 = k1 ^ b2).
-__device__ __forceinline__ int rs_lane_of_slot(int s) {
-  const int k1 = s & 1, k2 = (s >> 1) & 1, k3 = (s >> 2) & 1, k4 = (s >> 3) & 1;
-  const int b3 = k4, b2 = k3 ^ b3, b1 = k2 ^ b2, b0 = k1 ^ b2;
-  return b0 | (b1 << 1) | (b2 << 2) | (b3 << 3);
 }
 
 // Sum over a 16-lane row (every lane gets it); all lanes active.
@@ -325,80 +310,121 @@ __device__ __forceinline__ void sh_basis_one(int k, float x, float y, float z, f
   dY[2] = t[0] * __builtin_fmaf(t[3], Q, L * qz);
 }
 
-// Splats with more than kLongSegment instances: one workgroup per splat sums
-// its instance partials (independent unrolled loads, then a fixed-order
-// reduction: deterministic) into grad2d at the splat's drawn rank.
+// One instance's partial (moments about its tile's centre, dL/do, colour
+// gradient) as the splat's 2D sums in FP64: with D = c_t - mean,
+//   sum w d = m1 + D m0,  sum w d d^T = m2 + D m1^T + m1 D^T + D D^T m0,
+// added into g = [sum w dx, sum w dy, sum w dx^2, sum w dx dy, sum w dy^2,
+// dL/do, dL/dr, dL/dg, dL/db].  l is the instance's index within its splat,
+// whose tiles it enumerates row by row over the rectangle q.
+__device__ __forceinline__ void add_instance(double* g, const float* P, uint32_t l, ushort4 q, double mx,
+                                             double my) {
+  const uint32_t w = (uint32_t)(q.y - q.x);
+  const uint32_t tyy = w ? (uint32_t)q.z + l / w : 0u, txx = w ? (uint32_t)q.x + l % w : 0u;
+  const double Dx = (double)(16u * txx + 8u) - mx, Dy = (double)(16u * tyy + 8u) - my;
+  const double m0 = P[0], m1x = P[1], m1y = P[2];
+  g[0] += m1x + Dx * m0;
+  g[1] += m1y + Dy * m0;
+  g[2] += (double)P[3] + 2.0 * Dx * m1x + Dx * Dx * m0;
+  g[3] += (double)P[4] + Dx * m1y + Dy * m1x + Dx * Dy * m0;
+  g[4] += (double)P[5] + 2.0 * Dy * m1y + Dy * Dy * m0;
+#pragma unroll
+  for (int c = 5; c < 9; ++c) g[c] += (double)P[c + 1];
+}
+
+__device__ __forceinline__ void splat_mean64(const Splat* splats, int64_t i, double& mx, double& my) {
+  const float4 m = *reinterpret_cast<const float4*>(&splats[i].mxh);  // mxh, mxl, myh, myl
+  mx = (double)m.x + (double)m.y;
+  my = (double)m.z + (double)m.w;
+}
+
+// Splats with more than kLongSegment instances: one workgroup per splat turns
+// its instance partials into the splat's 2D sums (add_instance) in grad2d at
+// its drawn rank.  Per-thread FP64 sums over independent unrolled loads, a
+// butterfly over the wave, the waves in order: a fixed order, so
+// deterministic.
 __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, const uint32_t* long_list,
                                                       const uint32_t* order, const uint32_t* drawn_rank,
                                                       const uint32_t* inst_off, const float* __restrict__ partial,
-                                                      float* grad2d) {
-  __shared__ float part[kBlock / 64][9];
+                                                      const Splat* __restrict__ splats, const ushort4* rect,
+                                                      double* grad2d) {
+  __shared__ double part[kBlock / 64][9];
   const int64_t n = ctr->n_drawn, nl = ctr->n_long;
   const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int64_t li = blockIdx.x; li < nl; li += gridDim.x) {  // block-uniform
     const int64_t r = long_list[li];
-    int64_t a = inst_off[r], b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
+    const int64_t i = order[r];
+    const int64_t a0 = inst_off[r];
+    int64_t a = a0, b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
     a = a < n_cl ? a : n_cl;
     b = b < n_cl ? b : n_cl;
-    float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    const ushort4 q = rect[i];
+    double mx, my;
+    splat_mean64(splats, i, mx, my);
+    double g[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t q0 = a + threadIdx.x; q0 < b; q0 += 4 * kBlock) {
-      float t[4][9];
+      float t[4][kPartial];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int64_t q = q0 + (int64_t)u * kBlock;
+        const int64_t k = q0 + (int64_t)u * kBlock;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) t[u][c] = q < b ? partial[9 * q + c] : 0.0f;
+        for (int c = 0; c < kPartial; ++c) t[u][c] = k < b ? partial[kPartial * k + c] : 0.0f;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int c = 0; c < 9; ++c) g[c] += t[u][c];
+      for (int u = 0; u < 4; ++u) {
+        const int64_t k = q0 + (int64_t)u * kBlock;
+        if (k < b) add_instance(g, t[u], (uint32_t)(k - a0), q, mx, my);
+      }
     }
-    int slot;
-    const float z = wave_reduce_scatter9(g, lane, slot);
-    if (lane < 16 && slot < 9) part[wv][slot] = z;
+#pragma unroll
+    for (int c = 0; c < 9; ++c)
+#pragma unroll
+      for (int d = 32; d > 0; d >>= 1) g[c] += __shfl_xor(g[c], d, 64);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) part[wv][c] = g[c];
+    }
     __syncthreads();
     if (threadIdx.x < 9) {
-      float sum = part[0][threadIdx.x];
+      double sum = part[0][threadIdx.x];
 #pragma unroll
       for (int w = 1; w < kBlock / 64; ++w) sum += part[w][threadIdx.x];
-      grad2d[9 * (int64_t)drawn_rank[order[r]] + threadIdx.x] = sum;
+      grad2d[9 * (int64_t)drawn_rank[i] + threadIdx.x] = sum;
     }
     __syncthreads();
   }
 }
 
 // Per drawn splat, 16 lanes, in selection order (ascending node index, so
-// neighbouring groups read neighbouring nodes): (1) the sum of its
-// instance partials, contiguous in emission order (the lanes stride over the
-// range, then the in-row reduce-scatter leaves each of the 9 sums in one
-// lane; fixed order, so deterministic), or, for a splat with more than
-// kLongSegment instances, the sums k_long_sums left in grad2d; (2) the colour
-// backward: dL/dRGB (zero for a channel
-// the forward clamped at 0, a decision the forward recorded) to the SH
-// coefficients, lane k taking basis function k (contiguous reads and writes of
-// the 192-byte coefficient block), and to the view direction, summed over the
-// row.  grad2d at the splat's drawn rank receives the 6 geometric 2D
-// gradients (mean2D, conic, opacity) and dL/dmean through the view direction.
+// neighbouring groups read neighbouring nodes): (1) the splat's 2D sums
+// (add_instance) from its instance partials, contiguous in emission order
+// (each lane takes at most two, then an FP64 butterfly over the row gives
+// every lane the sums; fixed order, so deterministic), or, for a splat with
+// more than kLongSegment instances, the sums k_long_sums left in grad2d;
+// (2) the colour backward: dL/dRGB (zero for a channel the forward clamped
+// at 0, a decision the forward recorded) to the SH coefficients, lane k
+// taking basis function k (contiguous reads and writes of the 192-byte
+// coefficient block), and to the view direction, summed over the row.
+// grad2d at the splat's drawn rank receives the 6 geometric sums and dL/do,
+// then dL/dmean through the view direction in place of the colour sums.
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewConst* __restrict__ vp,
                                                       const int32_t* idx, const FrameCounters* ctr,
                                                       const uint32_t* drawn_list, const uint32_t* depth_rank,
                                                       const uint32_t* inst_off, const float* __restrict__ partial,
-                                                      const Splat* splats, float* grad2d, float* sel_sh,
-                                                      float* node_sh) {
+                                                      const Splat* splats, const ushort4* rect, double* grad2d,
+                                                      float* sel_sh, float* node_sh) {
   constexpr int nb = (DEG + 1) * (DEG + 1), nc = 3 * nb;
   const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
   const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
-  const int lane = threadIdx.x & 63, sub = lane & 15, row = lane & ~15;
+  const int lane = threadIdx.x & 63, sub = lane & 15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t g0 = wave * 4; g0 < n; g0 += waves * 4) {  // wave-uniform
     const int64_t dr = g0 + (lane >> 4);  // drawn rank
     const bool live = dr < n;
-    float g[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    double g[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int64_t i = 0, node = 0;
     // per-splat inputs of the colour part, requested together with the
     // partials (they depend only on the splat)
@@ -419,12 +445,12 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
           if (node_sh) acc3[c] = node_sh[(int64_t)nc * node + 3 * sub + c];
         }
       }
-      int64_t a = 0, b = 0;  // a rank out of range only follows an instance overflow
+      int64_t a0 = 0, b = 0;  // a rank out of range only follows an instance overflow
       if (r < n) {
-        a = inst_off[r];
+        a0 = inst_off[r];
         b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
       }
-      a = a < n_cl ? a : n_cl;
+      const int64_t a = a0 < n_cl ? a0 : n_cl;
       b = b < n_cl ? b : n_cl;
       if (b - a > (int64_t)kLongSegment) {  // summed by k_long_sums
         if (sub == 0) {
@@ -433,29 +459,37 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
         }
       } else {  // at most 2 instances per lane (kLongSegment = 32), loads issued together
         static_assert(kLongSegment <= 32, "two instances per lane of a 16-lane group");
-        float t[2][9];
+        const ushort4 q = rect[i];
+        double mx, my;
+        splat_mean64(splats, i, mx, my);
+        float t[2][kPartial];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const int64_t q = a + sub + 16 * u;
+          const int64_t k = a + sub + 16 * u;
 #pragma unroll
-          for (int c = 0; c < 9; ++c) t[u][c] = q < b ? partial[9 * q + c] : 0.0f;
+          for (int c = 0; c < kPartial; ++c) t[u][c] = k < b ? partial[kPartial * k + c] : 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int c = 0; c < 9; ++c) g[c] += t[u][c];
+        for (int u = 0; u < 2; ++u) {
+          const int64_t k = a + sub + 16 * u;
+          if (k < b) add_instance(g, t[u], (uint32_t)(k - a0), q, mx, my);
+        }
       }
     }
-    int slot;
-    const float z = row_reduce_scatter9(g, lane, slot);  // all lanes active
-    if (live && slot < 6) grad2d[9 * dr + slot] = z;
-    const float gr = __shfl(z, row + rs_lane_of_slot(6), 64);
-    const float gg = __shfl(z, row + rs_lane_of_slot(7), 64);
-    const float gb = __shfl(z, row + rs_lane_of_slot(8), 64);
+    // every lane of the row gets the row's sums (all lanes active)
+#pragma unroll
+    for (int c = 0; c < 9; ++c)
+#pragma unroll
+      for (int d = 1; d < 16; d <<= 1) g[c] += __shfl_xor(g[c], d, 64);
+    if (live && sub == 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) grad2d[9 * dr + c] = g[c];
+    }
     // gradient values only: FP32 throughout
     float ddx = 0.0f, ddy = 0.0f, ddz = 0.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, il = 0.0f;
     if (live) {
-      const float dRGB[3] = {(clamp & 1u) ? 0.0f : gr, (clamp & 2u) ? 0.0f : gg, (clamp & 4u) ? 0.0f : gb};
+      const float dRGB[3] = {(clamp & 1u) ? 0.0f : (float)g[6], (clamp & 2u) ? 0.0f : (float)g[7],
+                             (clamp & 4u) ? 0.0f : (float)g[8]};
       const float dx = m0 - v.pos[0], dy = m1 - v.pos[1], dz = m2 - v.pos[2];
       il = 1.0f / __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
       d0 = dx * il;
@@ -482,9 +516,9 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
     ddz = row_sum(ddz);
     if (live && sub == 0) {  // projection onto the sphere's tangent plane, / |mu - pos|
       const float dot = __builtin_fmaf(ddx, d0, __builtin_fmaf(ddy, d1, ddz * d2));
-      grad2d[9 * dr + 6] = (ddx - d0 * dot) * il;
-      grad2d[9 * dr + 7] = (ddy - d1 * dot) * il;
-      grad2d[9 * dr + 8] = (ddz - d2 * dot) * il;
+      grad2d[9 * dr + 6] = (double)((ddx - d0 * dot) * il);
+      grad2d[9 * dr + 7] = (double)((ddy - d1 * dot) * il);
+      grad2d[9 * dr + 8] = (double)((ddz - d2 * dot) * il);
     }
   }
 }
@@ -498,13 +532,13 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
                                                         const FrameCounters* ctr, const uint32_t* drawn_list,
-                                                        const float* grad2d, lodgs_grads sel, lodgs_grads nodes) {
+                                                        const double* grad2d, lodgs_grads sel, lodgs_grads nodes) {
   const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = drawn_list[r];
     const int64_t node = idx[i];
-    float g2[9];  // 2D gradients of the splat (drawn rank r)
+    double g2[9];  // 2D sums of the splat (drawn rank r), see add_instance
 #pragma unroll
     for (int c = 0; c < 9; ++c) g2[c] = grad2d[9 * r + c];
     const double gdir[3] = {g2[6], g2[7], g2[8]};
@@ -514,10 +548,12 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewCo
     if (visible) {
       // opacity
       const double o = 1.0 / (1.0 + (double)fexp(-S.opacity_logits[node]));
-      go = (double)g2[5] * o * (1.0 - o);
-      // conic -> projected covariance: GS = -Q GQ Q
+      go = g2[5] * o * (1.0 - o);
+      // d power / d mean2D = Q d, d power / d conic = -(dx^2 / 2, dx dy, dy^2 / 2)
       const double ca = P.C / P.det, cb = -P.B / P.det, cc = P.A / P.det;
-      const double gq00 = g2[2], gq01 = 0.5 * (double)g2[3], gq11 = g2[4];
+      const double gmx = ca * g2[0] + cb * g2[1], gmy = cb * g2[0] + cc * g2[1];
+      // conic -> projected covariance: GS = -Q GQ Q
+      const double gq00 = -0.5 * g2[2], gq01 = -0.5 * g2[3], gq11 = -0.5 * g2[4];
       const double qg00 = ca * gq00 + cb * gq01, qg01 = ca * gq01 + cb * gq11;
       const double qg10 = cb * gq00 + cc * gq01, qg11 = cb * gq01 + cc * gq11;
       const double GS00 = -(qg00 * ca + qg01 * cb), GS01 = -(qg00 * cb + qg01 * cc);
@@ -551,11 +587,10 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewCo
       const double cx = P.c[0], cy = P.c[1], cz = P.c[2];
       const double fx = v.fx, fy = v.fy;
       const double iz = 1.0 / cz, iz2 = iz * iz, iz3 = iz2 * iz;
-      const double dcx = dJ02 * (-fx * iz2) + (double)g2[0] * fx * iz;
-      const double dcy = dJ12 * (-fy * iz2) + (double)g2[1] * fy * iz;
+      const double dcx = dJ02 * (-fx * iz2) + gmx * fx * iz;
+      const double dcy = dJ12 * (-fy * iz2) + gmy * fy * iz;
       const double dcz = dJ00 * (-fx * iz2) + dJ02 * (2.0 * fx * cx * iz3) + dJ11 * (-fy * iz2) +
-                         dJ12 * (2.0 * fy * cy * iz3) + (double)g2[0] * (-fx * cx * iz2) +
-                         (double)g2[1] * (-fy * cy * iz2);
+                         dJ12 * (2.0 * fy * cy * iz3) + gmx * (-fx * cx * iz2) + gmy * (-fy * cy * iz2);
       for (int a = 0; a < 3; ++a)
         gm[a] = (double)v.R[a] * dcx + (double)v.R[3 + a] * dcy + (double)v.R[6 + a] * dcz + gdir[a];
       // Sigma = M M^T, M = Rq diag(s)
@@ -599,9 +634,9 @@ static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodg
   // 16 splats per block: one pass covers 256k drawn splats, so each 16-lane
   // group runs its latency-bound chain of dependent loads once
   hipLaunchKernelGGL(k_long_sums, dim3(1024), dim3(kBlock), 0, st, f->ctr, f->long_list, f->sorted_order,
-                     f->drawn_rank, f->inst_off, f->inst_grad, f->grad2d);
+                     f->drawn_rank, f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
   hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->drawn_list, f->depth_rank, f->inst_off, f->inst_grad, f->splats, f->grad2d, sel.d_sh,
+                     f->drawn_list, f->depth_rank, f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d, sel.d_sh,
                      nodes.d_sh);
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
                      f->drawn_list, f->grad2d, sel, nodes);

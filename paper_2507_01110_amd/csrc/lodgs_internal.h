@@ -98,10 +98,10 @@ struct lodgs_frame {
   uint32_t* ikey2;
   uint32_t* ival2;
   uint32_t* inst_splat;   // [max_instances] selection position of each instance (emission order)
-  float* inst_grad;       // [max_instances][9] per-instance 2D gradient partials (emission order)
+  float* inst_grad;       // [max_instances][kPartial] per-instance partials (emission order)
   uint8_t* inst_event;    // [max_instances] forward event bits per tile quarter (tile order)
   uint8_t* inst_quarters; // [max_instances] quarters the splat's alpha >= 1/255 ellipse reaches (emission order)
-  float* grad2d;          // [max_selected][9] per-drawn-splat 2D gradients (drawn rank)
+  double* grad2d;         // [max_selected][9] per-drawn-splat 2D sums (drawn rank)
   uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances
   uint2* ranges;          // [max tiles]
   uint32_t* tile_order;   // [max tiles] tiles, heaviest first
@@ -136,6 +136,9 @@ namespace lodgs {
 // A drawn splat with more instances than this has its instance partials
 // summed by a whole workgroup in the backward (listed by the duplication).
 constexpr uint32_t kLongSegment = 32;
+// Per-instance partial of the blend backward: sum w, sum w e (2), sum w e e^T
+// (3) about the tile centre, dL/do, dL/dRGB (3).
+constexpr int kPartial = 10;
 
 // Writes the per-view constants to the frame's device slot (one thread): the
 // kernels of a stage read them from there, so a captured graph is replayed

@@ -80,17 +80,17 @@ class Scene:
         self.n_nodes, self.n_upper, self.n_spt = h.n_nodes, h.n_upper, h.n_spt
         self.sh_degree = int(tree.sh_degree)
         self.perm = h.perm
-        perm_d = torch.from_numpy(h.perm.astype(np.int64)).to(self.device)
 
         def up(a):
-            t = torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
-            return t.index_select(0, perm_d).contiguous()
+            # Rows are put in layout order on the host, one array at a time.
+            # torch's device index_select (2.10, ROCm) left the last 2^26 rows
+            # of a 100M x 4 float32 gather unwritten, so it is not used here.
+            return torch.from_numpy(np.take(np.ascontiguousarray(a), h.perm, axis=0)).to(self.device)
 
         self.params = {
             "means": up(tree.means), "log_scales": up(tree.log_scales), "quats": up(tree.quats),
             "opacity_logits": up(tree.opacity_logits), "sh": up(tree.sh.reshape(tree.n_nodes, -1, 3)),
         }
-        del perm_d
         dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
         self.lod = {"r_min": dev(h.r_min), "r_max": dev(h.r_max), "rho": dev(h.rho),
                     "upper_parent": dev(h.upper_parent if h.n_upper else np.zeros(1, np.int32)),

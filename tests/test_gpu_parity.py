@@ -201,6 +201,86 @@ def test_render_tiny_pixels_and_key_order(torch_cuda):
         _say("  max abs err", err, "decisions within 1 ulp:", info["skip_1ulp"], info["stop_1ulp"])
 
 
+def test_render_and_backward_beyond_one_tile_order_chunk(torch_cuda):
+    # 107 x 82 = 8774 tiles: the blends' workgroup order is built by two
+    # workgroups (8192 tiles each at most); every tile must still be drawn once
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    cam = scenegen.camera_look_at((14, -9, 4), (0, 0, 0), (0, 0, 1), 1700, 1300)
+    _say("render + backward", cam.width, cam.height)
+    frame, sel, got, g_o = _backward_pair(tree, O, S, cam, 1.0, 202)
+    F = oracle.OracleFrame(tree, O.select(cam, 1.0)[0], cam)
+    assert F.info()["TX"] * F.info()["TY"] > 8192
+    _check_instances(frame, F)
+    _check_image(frame.render(cam), F)
+
+
+def test_empty_selection_and_nothing_drawn(torch_cuda):
+    # a camera facing away from the scene: with culling nothing is selected;
+    # without it a few upper nodes are selected, all behind the camera, so
+    # nothing is drawn.  The image is the background, gradients are zero.
+    import torch
+    from paper_2507_01110_amd.lodgs import grads_like
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    cam = scenegen.camera_look_at((0, 0, 500), (0, 0, 1000), (0, 1, 0), 96, 64)
+    bg = (0.1, 0.2, 0.3)
+    for cull in (True, False):
+        _say("empty view, cull", cull)
+        frame = _frame(S, cam)
+        ids = _check_select(O, frame, cam, 1.0, cull)
+        assert (len(ids) == 0) == cull
+        img = frame.render(cam, bg=bg)
+        st = frame.stats()
+        assert st["status"] == 0 and st["n_drawn"] == 0 and st["n_instances"] == 0
+        _check_image(img, oracle.OracleFrame(tree, ids, cam, bg=bg))
+        nodes = grads_like(S)
+        sel = grads_like(S, max(len(ids), 1), zero=False)
+        frame.backward(torch.ones_like(img), sel=sel if len(ids) else None, nodes=nodes)
+        for k in nodes:
+            assert int(torch.count_nonzero(nodes[k])) == 0, k
+            if len(ids):
+                assert int(torch.count_nonzero(sel[k][:len(ids)])) == 0, k
+
+
+def test_instance_overflow_is_reported_and_the_frame_recovers(torch_cuda):
+    # 40160 instances into a frame that holds 8192: the render and the backward
+    # stay within the frame's buffers and the overflow is reported; after
+    # clearing it, a view that fits renders as the oracle does
+    import torch
+    from paper_2507_01110_amd.lodgs import Frame, grads_like
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    cam = configs.tiny_camera()
+    ids, _ = O.select(cam, 1.0)
+    need = oracle.OracleFrame(tree, ids, cam).info()["n_inst"]
+    assert need > 8192
+    f = Frame(S, S.n_nodes, 8192, cam.width, cam.height)
+    _say("instance overflow", need, "into 8192")
+    f.lod_select(cam, 1.0)
+    img = f.render(cam)
+    st = f.stats()
+    assert st["status"] == -2 and st["n_instances"] == need, st
+    assert bool(torch.isfinite(img).all())
+    nodes = grads_like(S)
+    f.backward(torch.ones_like(img), nodes=nodes)
+    torch.cuda.synchronize()
+    for k in nodes:
+        assert bool(torch.isfinite(nodes[k]).all()), k
+    f.clear_status()
+    assert f.stats()["status"] == 0
+    small = configs.tiny_camera(48, 40)
+    ids2 = _check_select(O, f, small, 1.0, True)
+    img2 = f.render(small)
+    F2 = oracle.OracleFrame(tree, ids2, small)
+    assert F2.info()["n_inst"] <= 8192 and f.stats()["status"] == 0
+    _check_instances(f, F2)
+    _check_image(img2, F2)
+
+
 def test_render_is_deterministic(torch_cuda):
     import torch
     tree = scenegen.build_tree(configs.tiny_spec())
