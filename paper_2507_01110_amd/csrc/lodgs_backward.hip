@@ -90,6 +90,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   __shared__ Splat batch[NT];
   __shared__ uint32_t bid[NT];
   __shared__ uint32_t ev[NT];
+  __shared__ uint8_t hits[NW][NT];  // per wave: the batch slots it replays, in order
   const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
   __shared__ float acc[NW][kPartial][NT];
   const int tile = (int)tile_order[blockIdx.x];
@@ -148,11 +149,12 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     }
     __syncthreads();
     const int m = (int)min((uint32_t)NT, rg.y - b0);
-    if (__any(active)) {  // wave-uniform
+    const int nh = wave_hit_list<NT, false>(m, qmask, ev, hits[wv]);
+    __syncthreads();
+    if (__any(active) && nh > 0) {  // wave-uniform
       // one splat (batch slot j) against the wave's pixels; true when every
       // pixel has stopped
       auto step = [&](const Splat& s, int j) -> bool {
-        if ((ev[j] & qmask) == 0u) return false;  // wave-uniform
         float dxs[PX], dys[PX], u1s[PX], u2s[PX], es[PX], oes[PX], als[PX], tts[PX];
         bool cons[PX];
         bool any_con = false, act = false;
@@ -206,13 +208,16 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
         }
         return !__any(act);
       };
-      // two register sets, each loaded one splat ahead of its use
-      Splat sa = batch[0], sb;
-      for (int j = 0;;) {
-        sb = batch[j + 1 < m ? j + 1 : j];
-        if (step(sa, j) || ++j >= m) break;
-        sa = batch[j + 1 < m ? j + 1 : j];
-        if (step(sb, j) || ++j >= m) break;
+      // two register sets, each loaded one listed splat ahead of its use
+      const uint8_t* hl = hits[wv];
+      Splat sa = batch[hl[0]], sb;
+      for (int t = 0;;) {
+        const int ja = hl[t];
+        sb = batch[hl[t + 1 < nh ? t + 1 : t]];
+        if (step(sa, ja) || ++t >= nh) break;
+        const int jb = hl[t];
+        sa = batch[hl[t + 1 < nh ? t + 1 : t]];
+        if (step(sb, jb) || ++t >= nh) break;
       }
     }
     __syncthreads();

@@ -136,6 +136,27 @@ namespace lodgs {
 // A drawn splat with more instances than this has its instance partials
 // summed by a whole workgroup in the backward (listed by the duplication).
 constexpr uint32_t kLongSegment = 32;
+// The wave's list of batch slots j < m whose mask bits meet `want` (every
+// slot j < m if ALL), in slot order, written to list; returns its length
+// (wave-uniform).  A blend wave replays only these: for the others its result
+// is known.
+template <int NT, bool ALL>
+__device__ __forceinline__ int wave_hit_list(int m, uint32_t want, const uint32_t* mask, uint8_t* list) {
+  static_assert(NT % 64 == 0 && NT <= 256, "whole waves, byte slot indices");
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lanemask_lt();
+  int nh = 0;
+#pragma unroll
+  for (int c = 0; c < NT / 64; ++c) {
+    const int j = c * 64 + lane;
+    const bool h = j < m && (ALL || (mask[j] & want) != 0u);
+    const uint64_t hb = __ballot(h);
+    if (h) list[nh + __popcll(hb & lt)] = (uint8_t)j;
+    nh += __popcll(hb);
+  }
+  return nh;
+}
+
 // Per-instance partial of the blend backward: sum w, sum w e (2), sum w e e^T
 // (3) about the tile centre, dL/do, dL/dRGB (3).
 constexpr int kPartial = 10;

@@ -334,6 +334,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
   __shared__ Splat batch[NT];
   __shared__ uint32_t ev[NT];
   __shared__ uint32_t qm[NT];
+  __shared__ uint8_t hits[NT / 64][NT];  // per wave: the batch slots it replays, in order
   const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
   const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
@@ -374,10 +375,11 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     }
     __syncthreads();
     const int m = (int)min((uint32_t)NT, rg.y - b0);
+    const int nh = wave_hit_list<NT, COUNT>(m, qmask, qm, hits[wv]);
+    __syncthreads();
     // one splat (batch slot j) against the wave's pixels; true when every
     // pixel has stopped
     auto step = [&](const Splat& s, int j) -> bool {
-      if (!COUNT && (qm[j] & qmask) == 0u) return false;  // wave-uniform
       bool act = false, changed = false;
 #pragma unroll
       for (int p = 0; p < PX; ++p) {
@@ -404,14 +406,17 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
       if (!COUNT && __any(changed) && lane == 0) atomicOr(&ev[j], qmask);
       return !__any(act);
     };
-    if (__any(active)) {  // wave-uniform
-      // two register sets, each loaded one splat ahead of its use
-      Splat sa = batch[0], sb;
-      for (int j = 0;;) {
-        sb = batch[j + 1 < m ? j + 1 : j];
-        if (step(sa, j) || ++j >= m) break;
-        sa = batch[j + 1 < m ? j + 1 : j];
-        if (step(sb, j) || ++j >= m) break;
+    if (__any(active) && nh > 0) {  // wave-uniform
+      // two register sets, each loaded one listed splat ahead of its use
+      const uint8_t* hl = hits[wv];
+      Splat sa = batch[hl[0]], sb;
+      for (int t = 0;;) {
+        const int ja = hl[t];
+        sb = batch[hl[t + 1 < nh ? t + 1 : t]];
+        if (step(sa, ja) || ++t >= nh) break;
+        const int jb = hl[t];
+        sa = batch[hl[t + 1 < nh ? t + 1 : t]];
+        if (step(sb, jb) || ++t >= nh) break;
       }
     }
     if (!COUNT) {
