@@ -14,13 +14,12 @@
 
 namespace lodgs {
 
-// Reduce-scatter of 10 per-lane values over a wave (all lanes active): four
-// DPP exchange steps inside each 16-lane row pair lane l with l^1, l^2, l^7
-// and l^15; at each step a lane keeps half of its remaining values (chosen by
-// b0^b2, b1^b2, b2^b3 and b3 of l & 15) and adds its partner's copy of that
-// half.  Lane l then holds its row's sum of value
-// slot(l) = (b0^b2) + 2 (b1^b2) + 4 (b2^b3) + 8 b3 (slots 10..15 are zero);
-// two cross-row exchanges complete the sums over the wave.
+// Reduce-scatter of 10 per-lane values inside each 16-lane row (all lanes
+// active): four DPP exchange steps pair lane l with l^1, l^2, l^7 and l^15;
+// at each step a lane keeps half of its remaining values (chosen by b0^b2,
+// b1^b2, b2^b3 and b3 of l & 15) and adds its partner's copy of that half.
+// Lane l then holds its row's sum of value
+// slot(l) = (b0^b2) + 2 (b1^b2) + 4 (b2^b3) + 8 b3 (slots 10..15 are zero).
 #define LODGS_DPP(x, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false))
 #define LODGS_RS_PAIR(out, a, b, k, ctrl)       \
   do {                                          \
@@ -29,7 +28,7 @@ namespace lodgs {
     (out) = keep_ + LODGS_DPP(send_, ctrl);     \
   } while (0)
 
-__device__ __forceinline__ float wave_reduce_scatter10(const float* g, int lane, int& slot) {
+__device__ __forceinline__ float row_reduce_scatter10(const float* g, int lane, int& slot) {
   const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
   const bool k1 = (b0 ^ b2) != 0, k2 = (b1 ^ b2) != 0, k3 = (b2 ^ b3) != 0, k4 = b3 != 0;
   float h0, h1, h2, h3, h4;
@@ -48,17 +47,16 @@ __device__ __forceinline__ float wave_reduce_scatter10(const float* g, int lane,
   float z;
   LODGS_RS_PAIR(z, r0, r1, k4, 0x140);  // row_mirror: l^15
   slot = (int)k1 + 2 * (int)k2 + 4 * (int)k3 + 8 * (int)k4;
-  z += __shfl_xor(z, 16, 64);
-  z += __shfl_xor(z, 32, 64);
   return z;
 }
 #undef LODGS_RS_PAIR
 #undef LODGS_DPP
 
 // Backward of the blend: the forward's decisions, pixel layout blend_pixel<PX>.
-// A wave replays only the splats whose forward event bits cover one of its
-// quarters: elsewhere no pixel of the wave blended the splat or stopped on it
-// in the forward, so the replay would leave every value unchanged.
+// Each 16-lane row replays only the splats whose forward event bits cover one
+// of its blocks: elsewhere no pixel of the row blended the splat or stopped on
+// it in the forward, so the replay would leave every value unchanged.  The
+// rows of a wave step through their lists together, each on its own splat.
 //
 // Per pixel, dL/dalpha = T (G . c) - (G . (C - Q)) / (1 - alpha), with G =
 // dL/dC, c the splat colour, C the final colour and Q the colour blended up
@@ -69,12 +67,13 @@ __device__ __forceinline__ float wave_reduce_scatter10(const float* g, int lane,
 // (e = pixel - c_t, |e| <= 7.5): sum w, sum w e, sum w e e^T, so the FP32
 // sums stay well conditioned even for a splat whose mean lies far off the
 // screen; the projection backward shifts them by c_t - mean in FP64.  Per
-// batch, each wave reduces these 10 values of a splat (moments, dL/do and the
-// colour gradient) over its lanes (only when some lane contributes) and
-// stores them in its own LDS row; the workgroup then sums the rows in wave
-// order and writes one 10-float partial per (splat, tile) instance at the
-// instance's emission index, with zeros for instances that no pixel reached.
-// No atomics: the result is deterministic.
+// step, each row reduces these 10 values of its splat (moments, dL/do and the
+// colour gradient) over its lanes (only when some lane of the wave
+// contributes) and adds them to its wave's LDS row of that splat, the rows in
+// order; the workgroup then sums the waves' rows in order and writes one
+// 10-float partial per (splat, tile) instance at the instance's emission
+// index, with zeros for instances that no pixel reached.  No atomics: the
+// result is deterministic.
 template <int PX>
 __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restrict__ vp,
                                                         const uint2* __restrict__ ranges,
@@ -82,7 +81,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
                                                         const uint32_t* __restrict__ inst_splat,
                                                         const Splat* __restrict__ splats, const FrameCounters* ctr,
                                                         const float* __restrict__ rgb, const float* __restrict__ dL,
-                                                        const uint8_t* __restrict__ event,
+                                                        const uint16_t* __restrict__ event,
                                                         const uint32_t* __restrict__ tile_order,
                                                         float* __restrict__ partial) {
   constexpr int NT = 256 / PX, NW = 4 / PX;
@@ -90,12 +89,11 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   __shared__ Splat batch[NT];
   __shared__ uint32_t bid[NT];
   __shared__ uint32_t ev[NT];
-  __shared__ uint8_t hits[NW][NT];  // per wave: the batch slots it replays, in order
-  const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
+  __shared__ uint8_t hits[NW][4][NT];  // per row of each wave: the batch slots it replays, in order
   __shared__ float acc[NW][kPartial][NT];
   const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, row = lane >> 4;
   int px = 0;
   float fy[PX], T[PX], GQ[PX], GC[PX], G0[PX], G1[PX], G2[PX];
   float ey[PX], exx[PX], exy[PX], eyy[PX];  // offsets from the tile centre
@@ -149,12 +147,17 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     }
     __syncthreads();
     const int m = (int)min((uint32_t)NT, rg.y - b0);
-    const int nh = wave_hit_list<NT, false>(m, qmask, ev, hits[wv]);
+    int nh[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) nh[r] = wave_hit_list<NT, false>(m, blend_row_blocks<PX>(wv, r), ev, hits[wv][r]);
     __syncthreads();
-    if (__any(active) && nh > 0) {  // wave-uniform
-      // one splat (batch slot j) against the wave's pixels; true when every
-      // pixel has stopped
-      auto step = [&](const Splat& s, int j) -> bool {
+    const int n = row == 0 ? nh[0] : (row == 1 ? nh[1] : (row == 2 ? nh[2] : nh[3]));  // this row's list
+    const int nmax = max(max(nh[0], nh[1]), max(nh[2], nh[3]));
+    if (__any(active) && nmax > 0) {  // wave-uniform
+      // one splat (batch slot j of this row's list; has = false past its end)
+      // against the row's pixels; true when every pixel of the wave has
+      // stopped
+      auto step = [&](const Splat& s, int j, bool has) -> bool {
         float dxs[PX], dys[PX], u1s[PX], u2s[PX], es[PX], oes[PX], als[PX], tts[PX];
         bool cons[PX];
         bool any_con = false, act = false;
@@ -165,7 +168,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
           oes[p] = s.o * es[p];
           als[p] = fminf(0.99f, oes[p]);
           tts[p] = T[p] * (1.0f - als[p]);
-          const bool hit = live[p] & (als[p] >= thr);
+          const bool hit = live[p] & has & (als[p] >= thr);
           const bool stop = hit & (tts[p] < 0.0001f);
           cons[p] = hit & !stop;
           live[p] = live[p] & !stop;
@@ -203,21 +206,29 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
             T[p] = con ? tts[p] : Tp;
           }
           int slot;
-          const float r = wave_reduce_scatter10(g, lane, slot);
-          if (lane < 16 && slot < kPartial) acc[wv][slot][j] = r;
+          const float r = row_reduce_scatter10(g, lane, slot);
+          // the rows add into the wave's row of their splats in order (two
+          // rows may be on the same splat)
+          const uint64_t cm = __ballot(any_con);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (row == q && slot < kPartial && ((cm >> (16 * q)) & 0xFFFFull) != 0ull) acc[wv][slot][j] += r;
         }
         return !__any(act);
       };
-      // two register sets, each loaded one listed splat ahead of its use
-      const uint8_t* hl = hits[wv];
-      Splat sa = batch[hl[0]], sb;
+      // two register sets, each loaded one list entry ahead of its use
+      const uint8_t* hl = hits[wv][row];
+      auto slot_at = [&](int t) -> int { return t < n ? (int)hl[t] : 0; };
+      Splat sa = batch[slot_at(0)], sb;
       for (int t = 0;;) {
-        const int ja = hl[t];
-        sb = batch[hl[t + 1 < nh ? t + 1 : t]];
-        if (step(sa, ja) || ++t >= nh) break;
-        const int jb = hl[t];
-        sa = batch[hl[t + 1 < nh ? t + 1 : t]];
-        if (step(sb, jb) || ++t >= nh) break;
+        const int ja = slot_at(t);
+        const bool ha = t < n;
+        sb = batch[slot_at(t + 1)];
+        if (step(sa, ja, ha) || ++t >= nmax) break;
+        const int jb = slot_at(t);
+        const bool hb = t < n;
+        sa = batch[slot_at(t + 1)];
+        if (step(sb, jb, hb) || ++t >= nmax) break;
       }
     }
     __syncthreads();

@@ -211,44 +211,77 @@ __device__ __forceinline__ float splat_rect_min(const Splat& s, float x0, float 
   return best;
 }
 
-// Bit q (quarter (q & 1, q >> 1) of the 16x16 tile at (tx, ty)) is set unless
-// alpha < 1/255 is certain at every pixel centre of that 8x8 quarter:
-// alpha >= 1/255 needs -power <= ln(255 o), and the quarter's minimum of
-// -power exceeds that bound by a margin (1% + 0.02) far above the FP32
-// evaluation error of the power, so a cleared bit only skips known results.
-__device__ __forceinline__ uint32_t splat_quarter_mask(const Splat& s, int tx, int ty) {
+// Bit 4 by + bx (the 4x4 block (bx, by) of the 16x16 tile at (tx, ty)) is
+// set unless alpha < 1/255 is certain at every pixel centre of that block:
+// alpha >= 1/255 needs -power <= ln(255 o), and the block's minimum of -power
+// exceeds that bound by a margin (1% + 0.02) far above the FP32 evaluation
+// error of the power, so a cleared bit only skips known results.  The same
+// test on an 8x8 quarter clears its four blocks at once.
+__device__ __forceinline__ uint32_t splat_block_mask(const Splat& s, int tx, int ty) {
   const float lo = 255.0f * s.o;
   if (!(lo >= 1.0f)) return 0u;
   const float qmax = __builtin_fmaf(0.01f, __logf(lo), __logf(lo)) + 0.02f;
   uint32_t m = 0u;
-#pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const float x0 = (float)(tx * kTile + 8 * (q & 1)) + 0.5f, y0 = (float)(ty * kTile + 8 * (q >> 1)) + 0.5f;
-    if (splat_rect_min(s, x0, x0 + 7.0f, y0, y0 + 7.0f) <= qmax) m |= 1u << q;
+    const int qx = q & 1, qy = q >> 1;
+    const float x0 = (float)(tx * kTile + 8 * qx) + 0.5f, y0 = (float)(ty * kTile + 8 * qy) + 0.5f;
+    if (splat_rect_min(s, x0, x0 + 7.0f, y0, y0 + 7.0f) > qmax) continue;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int bx = 2 * qx + (k & 1), by = 2 * qy + (k >> 1);
+      const float bx0 = (float)(tx * kTile + 4 * bx) + 0.5f, by0 = (float)(ty * kTile + 4 * by) + 0.5f;
+      if (splat_rect_min(s, bx0, bx0 + 3.0f, by0, by0 + 3.0f) <= qmax) m |= 1u << (4 * by + bx);
+    }
   }
   return m;
 }
 
 // Pixel layout of the blend kernels: a 16x16 tile is one workgroup of 4/PX
-// waves, PX pixels per lane.  PX = 1: wave w covers the 8x8 quarter
-// (w & 1, w >> 1) of the tile, lane l its pixel (l & 7, l >> 3).  PX = 2, 4:
-// wave w covers the rows [4 PX w, 4 PX (w + 1)), lane l the column l & 15 and
-// the rows 4 PX w + (l >> 4) + 4p, p < PX.
+// waves, PX pixels per lane, and each 16-lane row g of a wave covers 4x4
+// pixel blocks (lane l its pixel (l & 3, (l >> 2) & 3) of the block): block
+// column bx and, for pixel p, block row by, with
+//   PX = 1: wave w on the 8x8 quarter (w & 1, w >> 1): bx = 2 (w & 1) + (g & 1),
+//           by = 2 (w >> 1) + (g >> 1);
+//   PX = 2: wave w on rows [8 w, 8 w + 8): bx = g, by = 2 w + p;
+//   PX = 4: one wave: bx = g, by = p.
+// Block bits are 4 by + bx, as in splat_block_mask.
 template <int PX>
-__device__ __forceinline__ void blend_pixel(int tx, int ty, int wv, int lane, int p, int& x, int& y) {
+__device__ __forceinline__ void blend_block(int wv, int g, int p, int& bx, int& by) {
   if (PX == 1) {
-    x = tx * kTile + 8 * (wv & 1) + (lane & 7);
-    y = ty * kTile + 8 * (wv >> 1) + (lane >> 3);
+    bx = 2 * (wv & 1) + (g & 1);
+    by = 2 * (wv >> 1) + (g >> 1);
+  } else if (PX == 2) {
+    bx = g;
+    by = 2 * wv + p;
   } else {
-    x = tx * kTile + (lane & 15);
-    y = ty * kTile + 4 * PX * wv + (lane >> 4) + 4 * p;
+    bx = g;
+    by = p;
   }
 }
 
-// The 8x8 quarters of the tile (bit qx + 2 qy) that wave w covers.
 template <int PX>
-__device__ __forceinline__ uint32_t blend_wave_quarters(int wv) {
-  return PX == 1 ? (1u << wv) : (PX == 2 ? (3u << (2 * wv)) : 0xFu);
+__device__ __forceinline__ void blend_pixel(int tx, int ty, int wv, int lane, int p, int& x, int& y) {
+  int bx, by;
+  blend_block<PX>(wv, lane >> 4, p, bx, by);
+  x = tx * kTile + 4 * bx + (lane & 3);
+  y = ty * kTile + 4 * by + ((lane >> 2) & 3);
+}
+
+// Block bit of pixel p of row g of wave w.
+template <int PX>
+__device__ __forceinline__ uint32_t blend_pixel_block(int wv, int g, int p) {
+  int bx, by;
+  blend_block<PX>(wv, g, p, bx, by);
+  return 1u << (4 * by + bx);
+}
+
+// The blocks that row g of wave w covers.
+template <int PX>
+__device__ __forceinline__ uint32_t blend_row_blocks(int wv, int g) {
+  uint32_t m = 0u;
+#pragma unroll
+  for (int p = 0; p < PX; ++p) m |= blend_pixel_block<PX>(wv, g, p);
+  return m;
 }
 
 // Sum over the 64 lanes of a wave with DPP lane moves, result in lane 63:

@@ -99,8 +99,8 @@ struct lodgs_frame {
   uint32_t* ival2;
   uint32_t* inst_splat;   // [max_instances] selection position of each instance (emission order)
   float* inst_grad;       // [max_instances][kPartial] per-instance partials (emission order)
-  uint8_t* inst_event;    // [max_instances] forward event bits per tile quarter (tile order)
-  uint8_t* inst_quarters; // [max_instances] quarters the splat's alpha >= 1/255 ellipse reaches (emission order)
+  uint16_t* inst_event;   // [max_instances] forward event bits per 4x4 block of the tile (tile order)
+  uint16_t* inst_blocks;  // [max_instances] blocks the splat's alpha >= 1/255 ellipse reaches (emission order)
   double* grad2d;         // [max_selected][9] per-drawn-splat 2D sums (drawn rank)
   uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances
   uint2* ranges;          // [max tiles]

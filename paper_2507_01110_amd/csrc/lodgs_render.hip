@@ -14,9 +14,9 @@
 //             far less key traffic.
 //  k_ranges   first/last instance of every tile.
 //  k_blend    one workgroup per tile, PX pixels per lane; splat records are
-//             staged in LDS one batch per workgroup size; a wave skips a splat
-//             whose alpha >= 1/255 ellipse reaches none of its 8x8 quarters of
-//             the tile (known result).
+//             staged in LDS one batch per workgroup size; each 16-lane row
+//             (4x4 pixel blocks) replays only the splats whose alpha >= 1/255
+//             ellipse reaches one of its blocks (elsewhere the result is known).
 #include "lodgs_internal.h"
 #include "lodgs_proj.h"
 
@@ -181,14 +181,14 @@ struct LoadTilesInOrder {
 // instance of a splat records the splat's depth rank at its drawn rank (for
 // the backward, which walks the drawn splats in selection order), and lists
 // it when it has more than kLongSegment instances.  Each instance also gets
-// the quarters of its tile that the splat's alpha >= 1/255 ellipse can reach
-// (splat_quarter_mask); the forward skips the others.
+// the 4x4 blocks of its tile that the splat's alpha >= 1/255 ellipse can
+// reach (splat_block_mask); the forward skips the others.
 __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order,
                                                 const uint32_t* inst_off, const ushort4* rect, int32_t tiles_x,
                                                 int64_t cap, uint32_t* ikey, uint32_t* ival, uint32_t* inst_splat,
                                                 uint32_t* long_list, const uint32_t* drawn_rank,
                                                 uint32_t* depth_rank, const Splat* __restrict__ splats,
-                                                uint8_t* inst_quarters) {
+                                                uint16_t* inst_blocks) {
   const uint32_t total = (uint32_t)ctr->n_instances;  // the scan's 32-bit sum
   const int64_t n = (int64_t)total > cap ? cap : (int64_t)total;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -215,12 +215,12 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
     inst_splat[k] = i;
     if (w == 0) {  // only reachable if the instance count overflowed
       ikey[k] = 0xFFFFFFFFu;
-      inst_quarters[k] = 0;
+      inst_blocks[k] = 0;
       continue;
     }
     const uint32_t ty = q.z + l / w, tx = q.x + l % w;
     ikey[k] = ty * (uint32_t)tiles_x + tx;
-    inst_quarters[k] = (uint8_t)splat_quarter_mask(splats[i], (int)tx, (int)ty);
+    inst_blocks[k] = (uint16_t)splat_block_mask(splats[i], (int)tx, (int)ty);
   }
 }
 
@@ -309,42 +309,45 @@ __global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* range
   }
 }
 
-// One workgroup per tile with 4/PX waves, PX pixels per lane (the layout of
-// blend_pixel / blend_wave_box).  A wave skips an instance whose quarter mask
-// (k_dup) covers none of its quarters: there alpha < 1/255 at every pixel.
-// For every instance of the tile that it
-// reaches, the forward records in event[k] the 8x8 quarters of the tile
-// (blend_wave_quarters) where some pixel blended the splat or stopped on it;
+// One workgroup per tile with 4/PX waves, PX pixels per lane; each 16-lane
+// row of a wave covers 4x4 pixel blocks (blend_pixel).  Per batch of
+// instances, every row lists the instances whose block mask (k_dup) meets
+// its blocks and replays only those, in order: elsewhere alpha < 1/255 at
+// every pixel.  The rows of a wave step through their lists together, each on
+// its own splat.  For every instance that it replays, the forward records in
+// event[k] the blocks where some pixel blended the splat or stopped on it;
 // elsewhere the splat changed nothing, which lets the backward skip it there.
-// alpha = min(0.99, o e^power),
-// skipped below 1/255; a pixel stops before its transmittance would drop
-// below 1e-4.  Splat records are staged in LDS one batch per workgroup size
-// and read into registers one splat ahead; the per-pixel steps are written
-// with selects, so the only branches are wave-uniform.
+// alpha = min(0.99, o e^power), skipped below 1/255; a pixel stops before its
+// transmittance would drop below 1e-4.  Splat records are staged in LDS one
+// batch per workgroup size and read into registers one list entry ahead; the
+// per-pixel steps are written with selects, so the only branches are
+// wave-uniform.  The counting variant lists every instance in every row (the
+// algorithmic evaluation count: every splat of the tile up to termination).
 template <bool COUNT, int PX>
 __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict__ vp, const uint2* __restrict__ ranges,
                                                     const uint32_t* __restrict__ ival,
                                                     const uint32_t* __restrict__ inst_splat,
                                                     const Splat* __restrict__ splats,
-                                                    const uint8_t* __restrict__ quarters, const FrameCounters* ctr,
+                                                    const uint16_t* __restrict__ blocks, const FrameCounters* ctr,
                                                     const uint32_t* __restrict__ tile_order, float bg0, float bg1,
-                                                    float bg2, float* rgb, uint8_t* event, unsigned long long* work) {
-  constexpr int NT = 256 / PX;
+                                                    float bg2, float* rgb, uint16_t* event, unsigned long long* work) {
+  constexpr int NT = 256 / PX, NW = 4 / PX;
   const ViewConst v = *vp;
   __shared__ Splat batch[NT];
   __shared__ uint32_t ev[NT];
-  __shared__ uint32_t qm[NT];
-  __shared__ uint8_t hits[NT / 64][NT];  // per wave: the batch slots it replays, in order
-  const uint32_t qmask = blend_wave_quarters<PX>(threadIdx.x >> 6);
+  __shared__ uint32_t bm[NT];
+  __shared__ uint8_t hits[NW][4][NT];  // per row of each wave: the batch slots it replays, in order
   const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4;
   int px, pys[PX];
   float fy[PX], T[PX], cr[PX], cg[PX], cb[PX];
+  uint32_t pbit[PX];
   bool inside[PX], live[PX];
 #pragma unroll
   for (int p = 0; p < PX; ++p) {
     blend_pixel<PX>(tx, ty, wv, lane, p, px, pys[p]);
+    pbit[p] = blend_pixel_block<PX>(wv, g, p);
     fy[p] = (float)pys[p] + 0.5f;
     inside[p] = px < v.width && pys[p] < v.height;
     live[p] = inside[p];
@@ -366,32 +369,38 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     if (k < rg.y) {
       const uint32_t e = ival[k];
       const uint32_t i = inst_splat[e];
-      qm[threadIdx.x] = quarters[e];
+      bm[threadIdx.x] = blocks[e];
       if (i < nr) {
         batch[threadIdx.x] = splats[i];
-      } else {  // only reachable if the instance count overflowed (its quarter mask is 0)
+      } else {  // only reachable if the instance count overflowed (its block mask is 0)
         batch[threadIdx.x].o = 0.0f;
       }
     }
     __syncthreads();
     const int m = (int)min((uint32_t)NT, rg.y - b0);
-    const int nh = wave_hit_list<NT, COUNT>(m, qmask, qm, hits[wv]);
+    int nh[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) nh[r] = wave_hit_list<NT, COUNT>(m, blend_row_blocks<PX>(wv, r), bm, hits[wv][r]);
     __syncthreads();
-    // one splat (batch slot j) against the wave's pixels; true when every
-    // pixel has stopped
-    auto step = [&](const Splat& s, int j) -> bool {
-      bool act = false, changed = false;
+    const int n = g == 0 ? nh[0] : (g == 1 ? nh[1] : (g == 2 ? nh[2] : nh[3]));  // this row's list
+    const int nmax = max(max(nh[0], nh[1]), max(nh[2], nh[3]));
+    // one splat (batch slot j of this row's list; has = false past its end)
+    // against the row's pixels; true when every pixel of the wave has stopped
+    auto step = [&](const Splat& s, int j, bool has) -> bool {
+      bool act = false;
+      uint32_t eb = 0u;
 #pragma unroll
       for (int p = 0; p < PX; ++p) {
         float dx, dy, u1, u2;
         const float power = splat_power(s, fx, fy[p], dx, dy, u1, u2);
         const float alpha = fminf(0.99f, s.o * fexp(power));
         const float tt = T[p] * (1.0f - alpha);
-        const bool hit = live[p] & (alpha >= thr);
+        const bool in = live[p] & has;
+        const bool hit = in & (alpha >= thr);
         const bool stop = hit & (tt < 0.0001f);
         const bool con = hit & !stop;
         if (COUNT) {
-          n_eval += live[p] ? 1 : 0;
+          n_eval += in ? 1 : 0;
           n_contrib += con ? 1 : 0;
         }
         live[p] = live[p] & !stop;
@@ -401,27 +410,30 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
         cb[p] = con ? __builtin_fmaf(s.b, w, cb[p]) : cb[p];
         T[p] = con ? tt : T[p];
         act = act | live[p];
-        changed = changed | hit;
+        if (!COUNT && ((__ballot(hit) >> (lane & 48)) & 0xFFFFull) != 0ull) eb |= pbit[p];
       }
-      if (!COUNT && __any(changed) && lane == 0) atomicOr(&ev[j], qmask);
+      if (!COUNT && (lane & 15) == 0 && eb != 0u) atomicOr(&ev[j], eb);
       return !__any(act);
     };
-    if (__any(active) && nh > 0) {  // wave-uniform
-      // two register sets, each loaded one listed splat ahead of its use
-      const uint8_t* hl = hits[wv];
-      Splat sa = batch[hl[0]], sb;
+    if (__any(active) && nmax > 0) {  // wave-uniform
+      // two register sets, each loaded one list entry ahead of its use
+      const uint8_t* hl = hits[wv][g];
+      auto slot = [&](int t) -> int { return t < n ? (int)hl[t] : 0; };
+      Splat sa = batch[slot(0)], sb;
       for (int t = 0;;) {
-        const int ja = hl[t];
-        sb = batch[hl[t + 1 < nh ? t + 1 : t]];
-        if (step(sa, ja) || ++t >= nh) break;
-        const int jb = hl[t];
-        sa = batch[hl[t + 1 < nh ? t + 1 : t]];
-        if (step(sb, jb) || ++t >= nh) break;
+        const int ja = slot(t);
+        const bool ha = t < n;
+        sb = batch[slot(t + 1)];
+        if (step(sa, ja, ha) || ++t >= nmax) break;
+        const int jb = slot(t);
+        const bool hb = t < n;
+        sa = batch[slot(t + 1)];
+        if (step(sb, jb, hb) || ++t >= nmax) break;
       }
     }
     if (!COUNT) {
       __syncthreads();
-      if ((int)threadIdx.x < m) event[b0 + threadIdx.x] = (uint8_t)ev[threadIdx.x];
+      if ((int)threadIdx.x < m) event[b0 + threadIdx.x] = (uint16_t)ev[threadIdx.x];
     }
   }
   if (COUNT) {
@@ -449,21 +461,21 @@ template <bool COUNT>
 static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], float* d_rgb, hipStream_t st) {
   const int ntiles = v.tiles_x * v.tiles_y;
   unsigned long long* work = COUNT ? f->work : nullptr;
-  uint8_t* event = COUNT ? nullptr : f->inst_event;
+  uint16_t* event = COUNT ? nullptr : f->inst_event;
   switch (f->blend_px_fwd) {
     case 1:
       hipLaunchKernelGGL((k_blend<COUNT, 1>), dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         f->sorted_ival, f->inst_splat, f->splats, f->inst_blocks, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
                          d_rgb, event, work);
       break;
     case 4:
       hipLaunchKernelGGL((k_blend<COUNT, 4>), dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         f->sorted_ival, f->inst_splat, f->splats, f->inst_blocks, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
                          d_rgb, event, work);
       break;
     default:
       hipLaunchKernelGGL((k_blend<COUNT, 2>), dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->inst_quarters, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         f->sorted_ival, f->inst_splat, f->splats, f->inst_blocks, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
                          d_rgb, event, work);
       break;
   }
@@ -503,7 +515,7 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
                  &f->ctr->n_instances, st);
   hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x, icap,
                      f->ikey, f->ival, f->inst_splat, f->long_list, f->drawn_rank, f->depth_rank, f->splats,
-                     f->inst_quarters);
+                     f->inst_blocks);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
