@@ -411,45 +411,73 @@ __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, 
   }
 }
 
+// Every drawn splat that the duplication kernel did not put on the long list
+// (those with more than kLongSegment tiles whose first instance was emitted):
+// one thread per splat, in depth order, so neighbouring threads read
+// neighbouring partials; FP64 sums in instance order (add_instance) into
+// grad2d at the splat's drawn rank (zero for a splat that an instance
+// overflow left without instances).
+__global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr, const uint32_t* order,
+                                                       const uint32_t* drawn_rank, const uint32_t* inst_off,
+                                                       const float* __restrict__ partial,
+                                                       const Splat* __restrict__ splats, const ushort4* rect,
+                                                       double* grad2d) {
+  const int64_t n = ctr->n_drawn;
+  const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = order[r];
+    const ushort4 q = rect[i];
+    const int64_t a0 = inst_off[r];
+    if ((uint32_t)(q.y - q.x) * (uint32_t)(q.w - q.z) > kLongSegment && a0 < n_cl) continue;  // k_long_sums
+    int64_t b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
+    const int64_t a = a0 < n_cl ? a0 : n_cl;
+    b = b < n_cl ? b : n_cl;
+    double mx, my;
+    splat_mean64(splats, i, mx, my);
+    double g[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t k = a; k < b; ++k) {
+      float t[kPartial];
+#pragma unroll
+      for (int c = 0; c < kPartial; ++c) t[c] = partial[kPartial * k + c];
+      add_instance(g, t, (uint32_t)(k - a0), q, mx, my);
+    }
+    double* dst = grad2d + 9 * (int64_t)drawn_rank[i];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dst[c] = g[c];
+  }
+}
+
 // Per drawn splat, 16 lanes, in selection order (ascending node index, so
-// neighbouring groups read neighbouring nodes): (1) the splat's 2D sums
-// (add_instance) from its instance partials, contiguous in emission order
-// (each lane takes at most two, then an FP64 butterfly over the row gives
-// every lane the sums; fixed order, so deterministic), or, for a splat with
-// more than kLongSegment instances, the sums k_long_sums left in grad2d;
-// (2) the colour backward: dL/dRGB (zero for a channel the forward clamped
-// at 0, a decision the forward recorded) to the SH coefficients, lane k
+// neighbouring groups read neighbouring nodes): the colour backward.  dL/dRGB
+// (the splat's colour sums in grad2d; zero for a channel the forward clamped
+// at 0, a decision the forward recorded) goes to the SH coefficients, lane k
 // taking basis function k (contiguous reads and writes of the 192-byte
-// coefficient block), and to the view direction, summed over the row.
-// grad2d at the splat's drawn rank receives the 6 geometric sums and dL/do,
-// then dL/dmean through the view direction in place of the colour sums.
+// coefficient block), and to the view direction, summed over the row;
+// dL/dmean through the view direction then replaces the colour sums in
+// grad2d.
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewConst* __restrict__ vp,
                                                       const int32_t* idx, const FrameCounters* ctr,
-                                                      const uint32_t* drawn_list, const uint32_t* depth_rank,
-                                                      const uint32_t* inst_off, const float* __restrict__ partial,
-                                                      const Splat* splats, const ushort4* rect, double* grad2d,
-                                                      float* sel_sh, float* node_sh) {
+                                                      const uint32_t* drawn_list, const Splat* splats,
+                                                      double* grad2d, float* sel_sh, float* node_sh) {
   constexpr int nb = (DEG + 1) * (DEG + 1), nc = 3 * nb;
   const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
-  const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
   const int lane = threadIdx.x & 63, sub = lane & 15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t g0 = wave * 4; g0 < n; g0 += waves * 4) {  // wave-uniform
     const int64_t dr = g0 + (lane >> 4);  // drawn rank
     const bool live = dr < n;
-    double g[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int64_t i = 0, node = 0;
-    // per-splat inputs of the colour part, requested together with the
-    // partials (they depend only on the splat)
     uint32_t clamp = 0;
     float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, sh3[3] = {0.0f, 0.0f, 0.0f}, acc3[3] = {0.0f, 0.0f, 0.0f};
+    float gc[3] = {0.0f, 0.0f, 0.0f};
     if (live) {
       i = drawn_list[dr];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) gc[c] = (float)grad2d[9 * dr + 6 + c];
       node = idx[i];
-      const int64_t r = depth_rank[dr];  // every drawn splat has an instance, so a rank
       clamp = splats[i].clamp;
       m0 = S.means[3 * node];
       m1 = S.means[3 * node + 1];
@@ -461,51 +489,11 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
           if (node_sh) acc3[c] = node_sh[(int64_t)nc * node + 3 * sub + c];
         }
       }
-      int64_t a0 = 0, b = 0;  // a rank out of range only follows an instance overflow
-      if (r < n) {
-        a0 = inst_off[r];
-        b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
-      }
-      const int64_t a = a0 < n_cl ? a0 : n_cl;
-      b = b < n_cl ? b : n_cl;
-      if (b - a > (int64_t)kLongSegment) {  // summed by k_long_sums
-        if (sub == 0) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) g[c] = grad2d[9 * dr + c];
-        }
-      } else {  // at most 2 instances per lane (kLongSegment = 32), loads issued together
-        static_assert(kLongSegment <= 32, "two instances per lane of a 16-lane group");
-        const ushort4 q = rect[i];
-        double mx, my;
-        splat_mean64(splats, i, mx, my);
-        float t[2][kPartial];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int64_t k = a + sub + 16 * u;
-#pragma unroll
-          for (int c = 0; c < kPartial; ++c) t[u][c] = k < b ? partial[kPartial * k + c] : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int64_t k = a + sub + 16 * u;
-          if (k < b) add_instance(g, t[u], (uint32_t)(k - a0), q, mx, my);
-        }
-      }
-    }
-    // every lane of the row gets the row's sums (all lanes active)
-#pragma unroll
-    for (int c = 0; c < 9; ++c)
-#pragma unroll
-      for (int d = 1; d < 16; d <<= 1) g[c] += __shfl_xor(g[c], d, 64);
-    if (live && sub == 0) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) grad2d[9 * dr + c] = g[c];
     }
     // gradient values only: FP32 throughout
     float ddx = 0.0f, ddy = 0.0f, ddz = 0.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, il = 0.0f;
     if (live) {
-      const float dRGB[3] = {(clamp & 1u) ? 0.0f : (float)g[6], (clamp & 2u) ? 0.0f : (float)g[7],
-                             (clamp & 4u) ? 0.0f : (float)g[8]};
+      const float dRGB[3] = {(clamp & 1u) ? 0.0f : gc[0], (clamp & 2u) ? 0.0f : gc[1], (clamp & 4u) ? 0.0f : gc[2]};
       const float dx = m0 - v.pos[0], dy = m1 - v.pos[1], dz = m2 - v.pos[2];
       il = 1.0f / __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
       d0 = dx * il;
@@ -527,7 +515,7 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
         ddz = a * dYk[2];
       }
     }
-    ddx = row_sum(ddx);  // all lanes active
+    ddx = row_sum(ddx);  // all lanes active; every lane has read its colour sums
     ddy = row_sum(ddy);
     ddz = row_sum(ddz);
     if (live && sub == 0) {  // projection onto the sphere's tangent plane, / |mu - pos|
@@ -651,9 +639,10 @@ static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodg
   // group runs its latency-bound chain of dependent loads once
   hipLaunchKernelGGL(k_long_sums, dim3(1024), dim3(kBlock), 0, st, f->ctr, f->long_list, f->sorted_order,
                      f->drawn_rank, f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
+  hipLaunchKernelGGL(k_splat_sums, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_order, f->drawn_rank,
+                     f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
   hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->drawn_list, f->depth_rank, f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d, sel.d_sh,
-                     nodes.d_sh);
+                     f->drawn_list, f->splats, f->grad2d, sel.d_sh, nodes.d_sh);
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
                      f->drawn_list, f->grad2d, sel, nodes);
 }
