@@ -212,26 +212,46 @@ __device__ __forceinline__ float splat_rect_min(const Splat& s, float x0, float 
 }
 
 // Bit 4 by + bx (the 4x4 block (bx, by) of the 16x16 tile at (tx, ty)) is
-// set unless alpha < 1/255 is certain at every pixel centre of that block:
-// alpha >= 1/255 needs -power <= ln(255 o), and the block's minimum of -power
-// exceeds that bound by a margin (1% + 0.02) far above the FP32 evaluation
-// error of the power, so a cleared bit only skips known results.  The same
-// test on an 8x8 quarter clears its four blocks at once.
+// set unless alpha < 1/255 is certain at every pixel centre of that block.
+// alpha >= 1/255 needs -power = a1 u1^2 + a2 u2^2 <= ln(255 o) (a = -h), an
+// ellipse; the mask keeps the blocks that both of two supersets of it reach:
+// the 8x8 quarters whose minimum of -power does not exceed the bound, and the
+// blocks that meet the ellipse's axis-aligned bounding box (half-widths
+// sqrt(K (ce^2 / a1 + se^2 / a2)) and sqrt(K (se^2 / a1 + ce^2 / a2)), sums of
+// positive terms).  The bound K carries a margin (1% + 0.02) far above the
+// FP32 evaluation error of the power, and the box a further 1e-4 relative +
+// 1e-3 px, so a cleared bit only skips known results.
 __device__ __forceinline__ uint32_t splat_block_mask(const Splat& s, int tx, int ty) {
   const float lo = 255.0f * s.o;
   if (!(lo >= 1.0f)) return 0u;
-  const float qmax = __builtin_fmaf(0.01f, __logf(lo), __logf(lo)) + 0.02f;
-  uint32_t m = 0u;
-  for (int q = 0; q < 4; ++q) {
-    const int qx = q & 1, qy = q >> 1;
-    const float x0 = (float)(tx * kTile + 8 * qx) + 0.5f, y0 = (float)(ty * kTile + 8 * qy) + 0.5f;
-    if (splat_rect_min(s, x0, x0 + 7.0f, y0, y0 + 7.0f) > qmax) continue;
+  const float K = __builtin_fmaf(0.01f, __logf(lo), __logf(lo)) + 0.02f;
+  uint32_t quarters = 0u;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int bx = 2 * qx + (k & 1), by = 2 * qy + (k >> 1);
-      const float bx0 = (float)(tx * kTile + 4 * bx) + 0.5f, by0 = (float)(ty * kTile + 4 * by) + 0.5f;
-      if (splat_rect_min(s, bx0, bx0 + 3.0f, by0, by0 + 3.0f) <= qmax) m |= 1u << (4 * by + bx);
-    }
+  for (int q = 0; q < 4; ++q) {
+    const float x0 = (float)(tx * kTile + 8 * (q & 1)) + 0.5f, y0 = (float)(ty * kTile + 8 * (q >> 1)) + 0.5f;
+    if (splat_rect_min(s, x0, x0 + 7.0f, y0, y0 + 7.0f) <= K) quarters |= 1u << q;
+  }
+  if (quarters == 0u) return 0u;
+  const float i1 = -1.0f / s.h1, i2 = -1.0f / s.h2;  // 1 / a1, 1 / a2
+  const float cc = s.ce * s.ce, ss = s.se * s.se;
+  float hx = 1.0001f * __builtin_sqrtf(K * __builtin_fmaf(cc, i1, ss * i2)) + 1e-3f;
+  float hy = 1.0001f * __builtin_sqrtf(K * __builtin_fmaf(ss, i1, cc * i2)) + 1e-3f;
+  hx = hx == hx ? hx : __builtin_inff();  // no box from a NaN: every block
+  hy = hy == hy ? hy : __builtin_inff();
+  const float mx = s.mxh + s.mxl, my = s.myh + s.myl;
+  uint32_t cols = 0u, rows = 0u;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float x0 = (float)(tx * kTile + 4 * k) + 0.5f, y0 = (float)(ty * kTile + 4 * k) + 0.5f;
+    if (x0 <= mx + hx && x0 + 3.0f >= mx - hx) cols |= 1u << k;
+    if (y0 <= my + hy && y0 + 3.0f >= my - hy) rows |= 1u << k;
+  }
+  uint32_t m = 0u;
+#pragma unroll
+  for (int by = 0; by < 4; ++by) {
+    const uint32_t qrow = (quarters >> (2 * (by >> 1))) & 3u;        // quarters of this block row
+    const uint32_t qcols = (qrow & 1u ? 3u : 0u) | (qrow & 2u ? 12u : 0u);  // their block columns
+    if ((rows >> by) & 1u) m |= (cols & qcols) << (4 * by);
   }
   return m;
 }
