@@ -69,13 +69,17 @@ def stage_bytes(c, H, W, n_coef):
     b["project"] = c["n_rendered"] * (4 + 12 + 12 + 16 + 4) + c["n_drawn"] * (4 + 4 * n_coef + 64 + 4 + 8)
     # compaction of the drawn splats (two reads of the tile counts), then 4 radix passes
     b["depth_sort"] = c["n_rendered"] * 8 + c["n_drawn"] * 16 + 4 * c["n_drawn"] * 16
-    b["duplicate"] = c["n_drawn"] * 16 + c["n_instances"] * 12
+    # instances: tile key, emission index, owning splat, 16-bit block mask
+    b["duplicate"] = c["n_drawn"] * 16 + c["n_instances"] * 14
     b["tile_sort"] = 2 * c["n_instances"] * 16
-    b["ranges"] = c["n_instances"] * 4 + (H * W // 256) * 8
-    b["blend"] = c["n_instances"] * (8 + 64) + H * W * 12
+    # tile ranges (written, then read by the tile order), the tile order
+    b["ranges"] = c["n_instances"] * 4 + (H * W // 256) * (8 + 8 + 4)
+    # per instance: index, splat, 64-byte record, block mask, 16-bit events
+    b["blend"] = c["n_instances"] * (8 + 64 + 2 + 2) + H * W * 12
     b["loss"] = H * W * 36
-    b["blend_bwd"] = c["n_instances"] * (8 + 64 + 36) + H * W * 24
-    b["project_bwd"] = c["n_drawn"] * (16 + 3 * par) + c["n_instances"] * 36
+    # per instance: index, splat, record, events, 10-float partial
+    b["blend_bwd"] = c["n_instances"] * (8 + 64 + 2 + 40) + H * W * 24
+    b["project_bwd"] = c["n_drawn"] * (16 + 3 * par) + c["n_instances"] * 40
     return b
 
 
