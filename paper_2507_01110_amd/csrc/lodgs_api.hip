@@ -28,7 +28,7 @@ int hip_fail(hipError_t e, const char* what) {
 int blend_pixels_per_lane(bool backward) {
   const char* e = std::getenv(backward ? "LODGS_BLEND_PX_BWD" : "LODGS_BLEND_PX_FWD");
   if (e && (e[0] == '1' || e[0] == '2' || e[0] == '4') && e[1] == 0) return e[0] - '0';
-  return backward ? 2 : 1;
+  return 1;
 }
 
 // Per-view constants, FP32 on the host (IEEE single, correctly rounded / and

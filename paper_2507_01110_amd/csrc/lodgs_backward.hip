@@ -84,13 +84,15 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
                                                         const uint16_t* __restrict__ event,
                                                         const uint32_t* __restrict__ tile_order,
                                                         float* __restrict__ partial) {
-  constexpr int NT = 256 / PX, NW = 4 / PX;
+  // NB instances per batch: at most one per thread, and at most 128, which
+  // keeps the per-wave LDS rows small enough for several workgroups per CU
+  constexpr int NT = 256 / PX, NW = 4 / PX, NB = NT < 128 ? NT : 128;
   const ViewConst v = *vp;
-  __shared__ Splat batch[NT];
-  __shared__ uint32_t bid[NT];
-  __shared__ uint32_t ev[NT];
-  __shared__ uint8_t hits[NW][4][NT];  // per row of each wave: the batch slots it replays, in order
-  __shared__ float acc[NW][kPartial][NT];
+  __shared__ Splat batch[NB];
+  __shared__ uint32_t bid[NB];
+  __shared__ uint32_t ev[NB];
+  __shared__ uint8_t hits[NW][4][NB];  // per row of each wave: the batch slots it replays, in order
+  __shared__ float acc[NW][kPartial][NB];
   const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, row = lane >> 4;
@@ -126,15 +128,15 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   const uint2 rg = ranges[tile];
   const uint32_t nr = (uint32_t)ctr->n_render;
   const float thr = 1.0f / 255.0f;
-  for (int t = threadIdx.x; t < NW * kPartial * NT; t += NT) (&acc[0][0][0])[t] = 0.0f;
+  for (int t = threadIdx.x; t < NW * kPartial * NB; t += NT) (&acc[0][0][0])[t] = 0.0f;
   uint32_t b0 = rg.x;
-  for (; b0 < rg.y; b0 += NT) {
+  for (; b0 < rg.y; b0 += NB) {
     bool active = false;
 #pragma unroll
     for (int p = 0; p < PX; ++p) active = active || live[p];
     if (__syncthreads_count(active) == 0) break;
     const uint32_t k = b0 + threadIdx.x;
-    if (k < rg.y) {
+    if ((int)threadIdx.x < NB && k < rg.y) {
       const uint32_t e = ival[k];
       const uint32_t i = inst_splat[e];
       bid[threadIdx.x] = e;
@@ -146,10 +148,10 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
       }
     }
     __syncthreads();
-    const int m = (int)min((uint32_t)NT, rg.y - b0);
+    const int m = (int)min((uint32_t)NB, rg.y - b0);
     int nh[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) nh[r] = wave_hit_list<NT, false>(m, blend_row_blocks<PX>(wv, r), ev, hits[wv][r]);
+    for (int r = 0; r < 4; ++r) nh[r] = wave_hit_list<NB, false>(m, blend_row_blocks<PX>(wv, r), ev, hits[wv][r]);
     __syncthreads();
     const int n = row == 0 ? nh[0] : (row == 1 ? nh[1] : (row == 2 ? nh[2] : nh[3]));  // this row's list
     const int nmax = max(max(nh[0], nh[1]), max(nh[2], nh[3]));

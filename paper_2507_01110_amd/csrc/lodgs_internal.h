@@ -172,7 +172,7 @@ void launch_set_view(const ViewConst& v, ViewConst* dst, FrameCounters* ctr, int
 
 int hip_fail(hipError_t e, const char* what);
 
-// Pixels per lane of the forward blend (1) and the blend backward (2), or
+// Pixels per lane of the forward blend and the blend backward (1), or
 // LODGS_BLEND_PX_FWD / LODGS_BLEND_PX_BWD (1, 2 or 4) when set in the
 // environment (a tuning knob: images are identical, gradients equal up to the
 // order of their sums).
