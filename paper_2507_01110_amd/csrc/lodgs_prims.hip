@@ -45,11 +45,25 @@ __global__ void __launch_bounds__(kBlock) k_radix_offsets(uint32_t* table, const
   }
 }
 
+// Stable scatter of one radix pass.  The block's segment is taken in tiles of
+// up to kScatterTile keys.  For each tile: (1) keys are ranked in order within
+// their digit, 256 per round (one ballot per digit bit finds the lanes of a
+// wave with the same digit, per-wave counts give the order across waves, a
+// running count per digit the order across rounds); (2) the tile is staged in
+// LDS in digit order; (3) consecutive threads write consecutive staged keys,
+// so a digit's keys go to consecutive global positions.
+constexpr int kScatterRounds = 16;
+constexpr int kScatterTile = kScatterRounds * kBlock;
+
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, const uint32_t* vin,
                                                           uint32_t* kout, uint32_t* vout, const int32_t* d_n,
                                                           int64_t cap, int shift, const uint32_t* table) {
-  __shared__ uint32_t base[256];
+  __shared__ uint32_t base[256];   // global position of the digit's next key
+  __shared__ uint32_t lcnt[256];   // keys of the digit in the tile (so far)
+  __shared__ uint32_t lstart[256]; // first staged position of the digit
   __shared__ uint32_t wcnt[kBlock / 64][256];
+  __shared__ uint32_t wt[kBlock / 64];
+  __shared__ uint32_t sk[kScatterTile], sv[kScatterTile];
   int64_t n = *d_n;
   n = n < 0 ? 0 : (n > cap ? cap : n);
   const Segment s = block_segment(n, kSortGrid);
@@ -58,37 +72,68 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, c
   base[t] = table[(int64_t)t * kSortGrid + blockIdx.x];
 #pragma unroll
   for (int w = 0; w < kBlock / 64; ++w) wcnt[w][t] = 0;
-  __syncthreads();
   const uint64_t lt = lanemask_lt();
-  for (int64_t r0 = s.begin; r0 < s.end; r0 += kBlock) {
-    const int64_t i = r0 + t;
-    const bool valid = i < s.end;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const uint32_t d = (key >> shift) & 255u;
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bm = __ballot(bit);
-      m &= bit ? bm : ~bm;
-    }
-    const uint32_t rank = (uint32_t)__popcll(m & lt);
-    if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(m);
+  for (int64_t t0 = s.begin; t0 < s.end; t0 += kScatterTile) {  // block-uniform
+    const int64_t tn = s.end - t0 < kScatterTile ? s.end - t0 : kScatterTile;
+    lcnt[t] = 0;
     __syncthreads();
-    if (valid) {
-      uint32_t pos = base[d] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-      kout[pos] = key;
-      vout[pos] = vin[i];
+    uint32_t kr[kScatterRounds], vr[kScatterRounds], lr[kScatterRounds];
+#pragma unroll
+    for (int u = 0; u < kScatterRounds; ++u) {
+      const int64_t j = (int64_t)u * kBlock + t;
+      const bool valid = j < tn;
+      kr[u] = valid ? kin[t0 + j] : 0u;
+      vr[u] = valid ? vin[t0 + j] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kScatterRounds; ++u) {
+      if ((int64_t)u * kBlock >= tn) break;  // block-uniform
+      const bool valid = (int64_t)u * kBlock + t < tn;
+      const uint32_t d = (kr[u] >> shift) & 255u;
+      uint64_t m = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bm = __ballot(bit);
+        m &= bit ? bm : ~bm;
+      }
+      const uint32_t rank = (uint32_t)__popcll(m & lt);
+      if (valid && rank == 0) wcnt[wave][d] = (uint32_t)__popcll(m);
+      __syncthreads();
+      uint32_t r = lcnt[d] + rank;
+      for (int w = 0; w < wave; ++w) r += wcnt[w][d];
+      lr[u] = r;
+      __syncthreads();
+      uint32_t sum = 0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) {
+        sum += wcnt[w][t];
+        wcnt[w][t] = 0;
+      }
+      lcnt[t] += sum;
+      __syncthreads();
+    }
+    uint32_t tot;
+    lstart[t] = block_exclusive_scan(lcnt[t], wt, &tot);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kScatterRounds; ++u) {
+      if ((int64_t)u * kBlock + t < tn) {
+        const uint32_t pos = lstart[(kr[u] >> shift) & 255u] + lr[u];
+        sk[pos] = kr[u];
+        sv[pos] = vr[u];
+      }
     }
     __syncthreads();
-    uint32_t sum = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-      sum += wcnt[w][t];
-      wcnt[w][t] = 0;
+    for (int j = t; j < (int)tn; j += kBlock) {
+      const uint32_t key = sk[j];
+      const uint32_t d = (key >> shift) & 255u;
+      const uint32_t g = base[d] + ((uint32_t)j - lstart[d]);
+      kout[g] = key;
+      vout[g] = sv[j];
     }
-    base[t] += sum;
+    __syncthreads();
+    base[t] += lcnt[t];
     __syncthreads();
   }
 }
