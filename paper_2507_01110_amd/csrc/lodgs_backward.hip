@@ -454,14 +454,15 @@ __global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr,
 // (the splat's colour sums in grad2d; zero for a channel the forward clamped
 // at 0, a decision the forward recorded) goes to the SH coefficients, lane k
 // taking basis function k (contiguous reads and writes of the 192-byte
-// coefficient block), and to the view direction, summed over the row;
-// dL/dmean through the view direction then replaces the colour sums in
-// grad2d.
+// coefficient block), and, through the forward's d colour / d direction, to
+// the view direction; dL/dmean through the view direction then replaces the
+// colour sums in grad2d.
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewConst* __restrict__ vp,
                                                       const int32_t* idx, const FrameCounters* ctr,
                                                       const uint32_t* drawn_list, const Splat* splats,
-                                                      double* grad2d, float* sel_sh, float* node_sh) {
+                                                      const float* dcol, double* grad2d, float* sel_sh,
+                                                      float* node_sh) {
   constexpr int nb = (DEG + 1) * (DEG + 1), nc = 3 * nb;
   const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
@@ -470,61 +471,44 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
   const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t g0 = wave * 4; g0 < n; g0 += waves * 4) {  // wave-uniform
     const int64_t dr = g0 + (lane >> 4);  // drawn rank
-    const bool live = dr < n;
-    int64_t i = 0, node = 0;
-    uint32_t clamp = 0;
-    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, sh3[3] = {0.0f, 0.0f, 0.0f}, acc3[3] = {0.0f, 0.0f, 0.0f};
-    float gc[3] = {0.0f, 0.0f, 0.0f};
-    if (live) {
-      i = drawn_list[dr];
+    if (dr >= n) continue;
+    const int64_t i = drawn_list[dr];
+    float gc[3], J[9], acc3[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int c = 0; c < 3; ++c) gc[c] = (float)grad2d[9 * dr + 6 + c];
-      node = idx[i];
-      clamp = splats[i].clamp;
-      m0 = S.means[3 * node];
-      m1 = S.means[3 * node + 1];
-      m2 = S.means[3 * node + 2];
-      if (sub < nb) {
+    for (int c = 0; c < 3; ++c) gc[c] = (float)grad2d[9 * dr + 6 + c];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          sh3[c] = S.sh[(int64_t)nc * node + 3 * sub + c];
-          if (node_sh) acc3[c] = node_sh[(int64_t)nc * node + 3 * sub + c];
-        }
-      }
+    for (int q = 0; q < 9; ++q) J[q] = dcol[9 * i + q];
+    const int64_t node = idx[i];
+    const uint32_t clamp = splats[i].clamp;
+    const float m0 = S.means[3 * node], m1 = S.means[3 * node + 1], m2 = S.means[3 * node + 2];
+    if (node_sh && sub < nb) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc3[c] = node_sh[(int64_t)nc * node + 3 * sub + c];
     }
     // gradient values only: FP32 throughout
-    float ddx = 0.0f, ddy = 0.0f, ddz = 0.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, il = 0.0f;
-    if (live) {
-      const float dRGB[3] = {(clamp & 1u) ? 0.0f : gc[0], (clamp & 2u) ? 0.0f : gc[1], (clamp & 4u) ? 0.0f : gc[2]};
-      const float dx = m0 - v.pos[0], dy = m1 - v.pos[1], dz = m2 - v.pos[2];
-      il = 1.0f / __builtin_sqrtf(__builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz)));
-      d0 = dx * il;
-      d1 = dy * il;
-      d2 = dz * il;
-      if (sub < nb) {
-        float Yk, dYk[3];
-        sh_basis_one(sub, d0, d1, d2, Yk, dYk);
-        float a = 0.0f;
+    const float dRGB[3] = {(clamp & 1u) ? 0.0f : gc[0], (clamp & 2u) ? 0.0f : gc[1], (clamp & 4u) ? 0.0f : gc[2]};
+    const float dx = m0 - v.pos[0], dy = m1 - v.pos[1], dz = m2 - v.pos[2];
+    const float il = 1.0f / __builtin_sqrtf(dx * dx + dy * dy + dz * dz);
+    const float d0 = dx * il, d1 = dy * il, d2 = dz * il;
+    if (sub < nb) {
+      float Yk, dYk[3];
+      sh_basis_one(sub, d0, d1, d2, Yk, dYk);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float gk = dRGB[c] * Yk;
-          if (sel_sh) sel_sh[(int64_t)nc * i + 3 * sub + c] = gk;
-          if (node_sh) node_sh[(int64_t)nc * node + 3 * sub + c] = acc3[c] + gk;
-          a = __builtin_fmaf(dRGB[c], sh3[c], a);
-        }
-        ddx = a * dYk[0];
-        ddy = a * dYk[1];
-        ddz = a * dYk[2];
+      for (int c = 0; c < 3; ++c) {
+        const float gk = dRGB[c] * Yk;
+        if (sel_sh) sel_sh[(int64_t)nc * i + 3 * sub + c] = gk;
+        if (node_sh) node_sh[(int64_t)nc * node + 3 * sub + c] = acc3[c] + gk;
       }
     }
-    ddx = row_sum(ddx);  // all lanes active; every lane has read its colour sums
-    ddy = row_sum(ddy);
-    ddz = row_sum(ddz);
-    if (live && sub == 0) {  // projection onto the sphere's tangent plane, / |mu - pos|
-      const float dot = __builtin_fmaf(ddx, d0, __builtin_fmaf(ddy, d1, ddz * d2));
-      grad2d[9 * dr + 6] = (double)((ddx - d0 * dot) * il);
-      grad2d[9 * dr + 7] = (double)((ddy - d1 * dot) * il);
-      grad2d[9 * dr + 8] = (double)((ddz - d2 * dot) * il);
+    if (sub == 0) {  // dL/ddir, projected onto the sphere's tangent plane, / |mu - pos|
+      float dd[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        dd[a] = __builtin_fmaf(dRGB[2], J[6 + a], __builtin_fmaf(dRGB[1], J[3 + a], dRGB[0] * J[a]));
+      const float dot = __builtin_fmaf(dd[0], d0, __builtin_fmaf(dd[1], d1, dd[2] * d2));
+      grad2d[9 * dr + 6] = (double)((dd[0] - d0 * dot) * il);
+      grad2d[9 * dr + 7] = (double)((dd[1] - d1 * dot) * il);
+      grad2d[9 * dr + 8] = (double)((dd[2] - d2 * dot) * il);
     }
   }
 }
@@ -644,7 +628,7 @@ static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodg
   hipLaunchKernelGGL(k_splat_sums, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_order, f->drawn_rank,
                      f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
   hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->drawn_list, f->splats, f->grad2d, sel.d_sh, nodes.d_sh);
+                     f->drawn_list, f->splats, f->dcol, f->grad2d, sel.d_sh, nodes.d_sh);
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
                      f->drawn_list, f->grad2d, sel, nodes);
 }

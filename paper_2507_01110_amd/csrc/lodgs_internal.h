@@ -102,6 +102,7 @@ struct lodgs_frame {
   uint16_t* inst_event;   // [max_instances] forward event bits per 4x4 block of the tile (tile order)
   uint16_t* inst_blocks;  // [max_instances] blocks the splat's alpha >= 1/255 ellipse reaches (emission order)
   double* grad2d;         // [max_selected][9] per-drawn-splat 2D sums (drawn rank)
+  float* dcol;            // [max_selected][9] d colour / d view direction of each drawn splat (selection position)
   uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances
   uint2* ranges;          // [max tiles]
   uint32_t* tile_order;   // [max tiles] tiles, heaviest first

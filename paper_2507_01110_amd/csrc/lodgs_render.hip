@@ -96,21 +96,34 @@ __device__ __forceinline__ Proj project_node(const SceneDev& S, const ViewConst&
 }
 
 // SH colour for the view direction (mu - pos) / |mu - pos|; returns the
-// unclamped value in raw[3].
+// unclamped value in raw[3] and, in J[3 c + a], the derivative of channel c
+// with respect to component a of the unit direction (sum over the basis of
+// coefficient times basis gradient), which the colour backward takes in place
+// of the coefficients.
 template <int DEG>
-__device__ __forceinline__ void sh_color(const SceneDev& S, const ViewConst& v, int64_t n, float* raw) {
+__device__ __forceinline__ void sh_color(const SceneDev& S, const ViewConst& v, int64_t n, float* raw, float* J) {
   const float dx = S.means[3 * n] - v.pos[0], dy = S.means[3 * n + 1] - v.pos[1], dz = S.means[3 * n + 2] - v.pos[2];
   const float il = 1.0f / __builtin_sqrtf(dx * dx + dy * dy + dz * dz);
-  float Y[16];
+  float Y[16], dY[16][3];
   sh_basis(DEG, dx * il, dy * il, dz * il, Y);
+  sh_basis_grad(DEG, dx * il, dy * il, dz * il, dY);
   constexpr int nb = (DEG + 1) * (DEG + 1);
   const float* c = S.sh + (int64_t)(3 * nb) * n;
   float r = 0.5f, g = 0.5f, b = 0.5f;
 #pragma unroll
+  for (int q = 0; q < 9; ++q) J[q] = 0.0f;
+#pragma unroll
   for (int k = 0; k < nb; ++k) {
-    r = __builtin_fmaf(c[3 * k], Y[k], r);
-    g = __builtin_fmaf(c[3 * k + 1], Y[k], g);
-    b = __builtin_fmaf(c[3 * k + 2], Y[k], b);
+    const float c0 = c[3 * k], c1 = c[3 * k + 1], c2 = c[3 * k + 2];
+    r = __builtin_fmaf(c0, Y[k], r);
+    g = __builtin_fmaf(c1, Y[k], g);
+    b = __builtin_fmaf(c2, Y[k], b);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      J[a] = __builtin_fmaf(c0, dY[k][a], J[a]);
+      J[3 + a] = __builtin_fmaf(c1, dY[k][a], J[3 + a]);
+      J[6 + a] = __builtin_fmaf(c2, dY[k][a], J[6 + a]);
+    }
   }
   raw[0] = r;
   raw[1] = g;
@@ -120,7 +133,8 @@ __device__ __forceinline__ void sh_color(const SceneDev& S, const ViewConst& v, 
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_project(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
                                                     const int32_t* d_count, int64_t cap, Splat* splats,
-                                                    uint32_t* depth_key, uint32_t* tiles, ushort4* rect) {
+                                                    uint32_t* depth_key, uint32_t* tiles, ushort4* rect,
+                                                    float* dcol) {
   const ViewConst v = *vp;
   const int64_t n = clamp_count(d_count, cap);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -128,8 +142,10 @@ __global__ void __launch_bounds__(kBlock) k_project(SceneDev S, const ViewConst*
     Proj P = project_node(S, v, node);
     uint32_t t = 0;
     if (P.visible) {
-      float raw[3];
-      sh_color<DEG>(S, v, node, raw);
+      float raw[3], J[9];
+      sh_color<DEG>(S, v, node, raw, J);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) dcol[9 * i + q] = J[q];
       P.sp.r = fmaxf(raw[0], 0.0f);
       P.sp.g = fmaxf(raw[1], 0.0f);
       P.sp.b = fmaxf(raw[2], 0.0f);
@@ -491,7 +507,7 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   switch (S.sh_degree) {
 #define LODGS_PROJECT(D)                                                                                         \
   hipLaunchKernelGGL(k_project<D>, dim3(pgrid), dim3(kBlock), 0, st, S, f->d_view_ren, d_idx, d_count, cap,   \
-                     f->splats, f->depth_key, f->tiles, f->rect)
+                     f->splats, f->depth_key, f->tiles, f->rect, f->dcol)
     case 0: LODGS_PROJECT(0); break;
     case 1: LODGS_PROJECT(1); break;
     case 2: LODGS_PROJECT(2); break;
