@@ -52,7 +52,8 @@ __device__ __forceinline__ float row_reduce_scatter10(const float* g, int lane, 
 #undef LODGS_RS_PAIR
 #undef LODGS_DPP
 
-// Backward of the blend: the forward's decisions, pixel layout blend_pixel<PX>.
+// Backward of the blend: the forward's decisions, pixel layout blend_pixel<PX, true>
+// (each wave's rows spread over the block rows and columns).
 // Each 16-lane row replays only the splats whose forward event bits cover one
 // of its blocks: elsewhere no pixel of the row blended the splat or stopped on
 // it in the forward, so the replay would leave every value unchanged.  The
@@ -103,7 +104,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
 #pragma unroll
   for (int p = 0; p < PX; ++p) {
     int py;
-    blend_pixel<PX>(tx, ty, wv, lane, p, px, py);
+    blend_pixel<PX, true>(tx, ty, wv, lane, p, px, py);
     fy[p] = (float)py + 0.5f;
     live[p] = px < v.width && py < v.height;
     T[p] = 1.0f;
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     const int m = (int)min((uint32_t)NB, rg.y - b0);
     int nh[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) nh[r] = wave_hit_list<NB, false>(m, blend_row_blocks<PX>(wv, r), ev, hits[wv][r]);
+    for (int r = 0; r < 4; ++r) nh[r] = wave_hit_list<NB, false>(m, blend_row_blocks<PX, true>(wv, r), ev, hits[wv][r]);
     __syncthreads();
     const int n = row == 0 ? nh[0] : (row == 1 ? nh[1] : (row == 2 ? nh[2] : nh[3]));  // this row's list
     const int nmax = max(max(nh[0], nh[1]), max(nh[2], nh[3]));

@@ -261,13 +261,19 @@ __device__ __forceinline__ uint32_t splat_block_mask(const Splat& s, int tx, int
 // pixel blocks (lane l its pixel (l & 3, (l >> 2) & 3) of the block): block
 // column bx and, for pixel p, block row by, with
 //   PX = 1: wave w on the 8x8 quarter (w & 1, w >> 1): bx = 2 (w & 1) + (g & 1),
-//           by = 2 (w >> 1) + (g >> 1);
+//           by = 2 (w >> 1) + (g >> 1); or, SPREAD, bx = g, by = (w + g) & 3,
+//           so that every wave has one block in each block row and column (a
+//           band of heavy blocks, such as a horizon, spreads over the waves,
+//           which meet at every batch);
 //   PX = 2: wave w on rows [8 w, 8 w + 8): bx = g, by = 2 w + p;
 //   PX = 4: one wave: bx = g, by = p.
-// Block bits are 4 by + bx, as in splat_block_mask.
-template <int PX>
+// Block bits are 4 by + bx, as in splat_block_mask, whatever the layout.
+template <int PX, bool SPREAD = false>
 __device__ __forceinline__ void blend_block(int wv, int g, int p, int& bx, int& by) {
-  if (PX == 1) {
+  if (PX == 1 && SPREAD) {
+    bx = g;
+    by = (wv + g) & 3;
+  } else if (PX == 1) {
     bx = 2 * (wv & 1) + (g & 1);
     by = 2 * (wv >> 1) + (g >> 1);
   } else if (PX == 2) {
@@ -279,28 +285,28 @@ __device__ __forceinline__ void blend_block(int wv, int g, int p, int& bx, int& 
   }
 }
 
-template <int PX>
+template <int PX, bool SPREAD = false>
 __device__ __forceinline__ void blend_pixel(int tx, int ty, int wv, int lane, int p, int& x, int& y) {
   int bx, by;
-  blend_block<PX>(wv, lane >> 4, p, bx, by);
+  blend_block<PX, SPREAD>(wv, lane >> 4, p, bx, by);
   x = tx * kTile + 4 * bx + (lane & 3);
   y = ty * kTile + 4 * by + ((lane >> 2) & 3);
 }
 
 // Block bit of pixel p of row g of wave w.
-template <int PX>
+template <int PX, bool SPREAD = false>
 __device__ __forceinline__ uint32_t blend_pixel_block(int wv, int g, int p) {
   int bx, by;
-  blend_block<PX>(wv, g, p, bx, by);
+  blend_block<PX, SPREAD>(wv, g, p, bx, by);
   return 1u << (4 * by + bx);
 }
 
 // The blocks that row g of wave w covers.
-template <int PX>
+template <int PX, bool SPREAD = false>
 __device__ __forceinline__ uint32_t blend_row_blocks(int wv, int g) {
   uint32_t m = 0u;
 #pragma unroll
-  for (int p = 0; p < PX; ++p) m |= blend_pixel_block<PX>(wv, g, p);
+  for (int p = 0; p < PX; ++p) m |= blend_pixel_block<PX, SPREAD>(wv, g, p);
   return m;
 }
 
