@@ -151,7 +151,7 @@ void free_frame(lodgs_frame* f) {
   if (f->open_event) (void)hipEventDestroy(f->open_event);
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->upper_test, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->depth_rank, f->rect,
-                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_splat, f->inst_grad, f->inst_event, f->inst_blocks, f->grad2d, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
+                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->grad2d, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
                   f->d_view_ren};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -159,9 +159,9 @@ void free_frame(lodgs_frame* f) {
 }
 
 // Selection position of each instance in tile order.
-__global__ void k_instance_positions(const uint32_t* sorted_e, const uint32_t* inst_splat, int64_t m, int32_t* pos) {
+__global__ void k_instance_positions(const uint2* info_k, int64_t m, int32_t* pos) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
-    pos[k] = (int32_t)inst_splat[sorted_e[k]];
+    pos[k] = (int32_t)info_k[k].x;
 }
 
 }  // namespace
@@ -264,10 +264,10 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(ival, ni);
   A(ikey2, ni);
   A(ival2, ni);
-  A(inst_splat, ni);
+  A(inst_info, ni);
   A(inst_grad, (size_t)lodgs::kPartial * ni);
   A(inst_event, ni);
-  A(inst_blocks, ni);
+  A(info_k, ni);
   A(grad2d, 9 * ns);
   A(dcol, 9 * ns);
   A(long_list, ns);
@@ -378,7 +378,7 @@ int lodgs_frame_read_instances(lodgs_frame* f, int32_t* d_tile, int32_t* d_pos, 
     if (e == hipSuccess) {
       const int64_t g = (m + lodgs::kBlock - 1) / lodgs::kBlock;
       hipLaunchKernelGGL(k_instance_positions, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(lodgs::kBlock), 0, st,
-                         f->sorted_ival, f->inst_splat, m, d_pos);
+                         f->info_k, m, d_pos);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);

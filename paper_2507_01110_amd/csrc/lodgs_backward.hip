@@ -79,10 +79,10 @@ template <int PX>
 __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restrict__ vp,
                                                         const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ ival,
-                                                        const uint32_t* __restrict__ inst_splat,
+                                                        const uint2* __restrict__ info_k,
                                                         const Splat* __restrict__ splats, const FrameCounters* ctr,
                                                         const float* __restrict__ rgb, const float* __restrict__ dL,
-                                                        const uint16_t* __restrict__ event,
+                                                        const uint32_t* __restrict__ event,
                                                         const uint32_t* __restrict__ tile_order,
                                                         float* __restrict__ partial) {
   // NB instances per batch: at most one per thread, and at most 128, which
@@ -139,9 +139,9 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     const uint32_t k = b0 + threadIdx.x;
     if ((int)threadIdx.x < NB && k < rg.y) {
       const uint32_t e = ival[k];
-      const uint32_t i = inst_splat[e];
+      const uint32_t i = info_k[k].x;
       bid[threadIdx.x] = e;
-      ev[threadIdx.x] = event[k];
+      ev[threadIdx.x] = event_blocks(event[k]);
       if (i < nr) {
         batch[threadIdx.x] = splats[i];
       } else {  // only reachable if the instance count overflowed
@@ -643,15 +643,15 @@ void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, 
   switch (f->blend_px_bwd) {
     case 1:
       hipLaunchKernelGGL(k_blend_bwd<1>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
+                         f->info_k, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
       break;
     case 4:
       hipLaunchKernelGGL(k_blend_bwd<4>, dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
+                         f->info_k, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
       break;
     default:
       hipLaunchKernelGGL(k_blend_bwd<2>, dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->inst_splat, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
+                         f->info_k, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
       break;
   }
   stage_end(f, st);

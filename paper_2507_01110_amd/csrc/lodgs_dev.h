@@ -211,8 +211,16 @@ __device__ __forceinline__ float splat_rect_min(const Splat& s, float x0, float 
   return best;
 }
 
-// Bit 4 by + bx (the 4x4 block (bx, by) of the 16x16 tile at (tx, ty)) is
-// set unless alpha < 1/255 is certain at every pixel centre of that block.
+// Bit of the 4x4 block (bx, by) of a 16x16 tile in block masks and events:
+// quarter-major, 4 q + b with q = (bx >> 1) + 2 (by >> 1) the 8x8 quarter and
+// b = (bx & 1) + 2 (by & 1) the block inside it, so the bits of quarter q are
+// nibble q.
+__device__ __forceinline__ uint32_t block_bit(int bx, int by) {
+  return 1u << (4 * ((bx >> 1) + 2 * (by >> 1)) + ((bx & 1) + 2 * (by & 1)));
+}
+
+// Bit block_bit(bx, by) (the 4x4 block (bx, by) of the 16x16 tile at (tx, ty))
+// is set unless alpha < 1/255 is certain at every pixel centre of that block.
 // alpha >= 1/255 needs -power = a1 u1^2 + a2 u2^2 <= ln(255 o) (a = -h), an
 // ellipse; the mask keeps the blocks that both of two supersets of it reach:
 // the 8x8 quarters whose minimum of -power does not exceed the bound, and the
@@ -248,10 +256,13 @@ __device__ __forceinline__ uint32_t splat_block_mask(const Splat& s, int tx, int
   }
   uint32_t m = 0u;
 #pragma unroll
-  for (int by = 0; by < 4; ++by) {
-    const uint32_t qrow = (quarters >> (2 * (by >> 1))) & 3u;        // quarters of this block row
-    const uint32_t qcols = (qrow & 1u ? 3u : 0u) | (qrow & 2u ? 12u : 0u);  // their block columns
-    if ((rows >> by) & 1u) m |= (cols & qcols) << (4 * by);
+  for (int q = 0; q < 4; ++q) {
+    if (!((quarters >> q) & 1u)) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int bx = 2 * (q & 1) + (b & 1), by = 2 * (q >> 1) + (b >> 1);
+      if (((cols >> bx) & 1u) && ((rows >> by) & 1u)) m |= 1u << (4 * q + b);
+    }
   }
   return m;
 }
@@ -267,7 +278,8 @@ __device__ __forceinline__ uint32_t splat_block_mask(const Splat& s, int tx, int
 //           which meet at every batch);
 //   PX = 2: wave w on rows [8 w, 8 w + 8): bx = g, by = 2 w + p;
 //   PX = 4: one wave: bx = g, by = p.
-// Block bits are 4 by + bx, as in splat_block_mask, whatever the layout.
+// Block bits are block_bit(bx, by), as in splat_block_mask, whatever the
+// layout.
 template <int PX, bool SPREAD = false>
 __device__ __forceinline__ void blend_block(int wv, int g, int p, int& bx, int& by) {
   if (PX == 1 && SPREAD) {
@@ -298,7 +310,16 @@ template <int PX, bool SPREAD = false>
 __device__ __forceinline__ uint32_t blend_pixel_block(int wv, int g, int p) {
   int bx, by;
   blend_block<PX, SPREAD>(wv, g, p, bx, by);
-  return 1u << (4 * by + bx);
+  return block_bit(bx, by);
+}
+
+// Forward events of one instance: byte q holds the (4-bit) events of quarter
+// q, written by that quarter's wave; as a 16-bit block mask and back.
+__device__ __forceinline__ uint32_t event_blocks(uint32_t w) {
+  return (w & 0xFu) | ((w >> 4) & 0xF0u) | ((w >> 8) & 0xF00u) | ((w >> 12) & 0xF000u);
+}
+__device__ __forceinline__ uint32_t event_word(uint32_t m) {
+  return (m & 0xFu) | ((m & 0xF0u) << 4) | ((m & 0xF00u) << 8) | ((m & 0xF000u) << 12);
 }
 
 // The blocks that row g of wave w covers.

@@ -97,10 +97,10 @@ struct lodgs_frame {
   uint32_t* ival;
   uint32_t* ikey2;
   uint32_t* ival2;
-  uint32_t* inst_splat;   // [max_instances] selection position of each instance (emission order)
+  uint2* inst_info;       // [max_instances] (selection position of the splat, block mask) (emission order)
   float* inst_grad;       // [max_instances][kPartial] per-instance partials (emission order)
-  uint16_t* inst_event;   // [max_instances] forward event bits per 4x4 block of the tile (tile order)
-  uint16_t* inst_blocks;  // [max_instances] blocks the splat's alpha >= 1/255 ellipse reaches (emission order)
+  uint32_t* inst_event;   // [max_instances] forward events, byte q for quarter q's 4x4 blocks (tile order)
+  uint2* info_k;          // [max_instances] inst_info in tile order
   double* grad2d;         // [max_selected][9] per-drawn-splat 2D sums (drawn rank)
   float* dcol;            // [max_selected][9] d colour / d view direction of each drawn splat (selection position)
   uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances

@@ -201,10 +201,9 @@ struct LoadTilesInOrder {
 // reach (splat_block_mask); the forward skips the others.
 __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order,
                                                 const uint32_t* inst_off, const ushort4* rect, int32_t tiles_x,
-                                                int64_t cap, uint32_t* ikey, uint32_t* ival, uint32_t* inst_splat,
+                                                int64_t cap, uint32_t* ikey, uint32_t* ival, uint2* inst_info,
                                                 uint32_t* long_list, const uint32_t* drawn_rank,
-                                                uint32_t* depth_rank, const Splat* __restrict__ splats,
-                                                uint16_t* inst_blocks) {
+                                                uint32_t* depth_rank, const Splat* __restrict__ splats) {
   const uint32_t total = (uint32_t)ctr->n_instances;  // the scan's 32-bit sum
   const int64_t n = (int64_t)total > cap ? cap : (int64_t)total;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -228,15 +227,14 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
       if (w * (uint32_t)(q.w - q.z) > kLongSegment) long_list[atomicAdd(&ctr->n_long, 1)] = (uint32_t)lo;
     }
     ival[k] = (uint32_t)k;  // the tile sort carries the emission index
-    inst_splat[k] = i;
     if (w == 0) {  // only reachable if the instance count overflowed
       ikey[k] = 0xFFFFFFFFu;
-      inst_blocks[k] = 0;
+      inst_info[k] = make_uint2(i, 0u);
       continue;
     }
     const uint32_t ty = q.z + l / w, tx = q.x + l % w;
     ikey[k] = ty * (uint32_t)tiles_x + tx;
-    inst_blocks[k] = (uint16_t)splat_block_mask(splats[i], (int)tx, (int)ty);
+    inst_info[k] = make_uint2(i, splat_block_mask(splats[i], (int)tx, (int)ty));
   }
 }
 
@@ -244,11 +242,15 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
 // [0, n]: between the keys t0 = key[k - 1] and t1 = key[k] (-1 before the
 // first, ntiles after the last; keys >= ntiles, which only an instance
 // overflow produces, count as ntiles) tile t0 ends at k, tile t1 starts at k,
-// and every tile strictly between them is empty (k, k).
+// and every tile strictly between them is empty (k, k).  Instance k's
+// (owning splat, block mask) word is also gathered into tile order (info_k),
+// which saves the blends a dependent load.
 __global__ void __launch_bounds__(kBlock) k_ranges(const FrameCounters* ctr, const uint32_t* key, uint2* ranges,
-                                                   uint32_t ntiles) {
+                                                   uint32_t ntiles, const uint32_t* ival, const uint2* inst_info,
+                                                   uint2* info_k) {
   const int64_t n = ctr->n_inst_clamped;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= n; k += (int64_t)gridDim.x * blockDim.x) {
+    if (k < n) info_k[k] = inst_info[ival[k]];
     const int64_t t0 = k > 0 ? (int64_t)min(key[k - 1], ntiles) : -1;
     const int64_t t1 = k < n ? (int64_t)min(key[k], ntiles) : (int64_t)ntiles;
     if (t0 == t1) continue;
@@ -341,12 +343,10 @@ __global__ void __launch_bounds__(kOrderThreads) k_tile_order(const uint2* range
 // algorithmic evaluation count: every splat of the tile up to termination).
 template <bool COUNT, int PX>
 __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict__ vp, const uint2* __restrict__ ranges,
-                                                    const uint32_t* __restrict__ ival,
-                                                    const uint32_t* __restrict__ inst_splat,
-                                                    const Splat* __restrict__ splats,
-                                                    const uint16_t* __restrict__ blocks, const FrameCounters* ctr,
+                                                    const uint2* __restrict__ info_k,
+                                                    const Splat* __restrict__ splats, const FrameCounters* ctr,
                                                     const uint32_t* __restrict__ tile_order, float bg0, float bg1,
-                                                    float bg2, float* rgb, uint16_t* event, unsigned long long* work) {
+                                                    float bg2, float* rgb, uint32_t* event, unsigned long long* work) {
   constexpr int NT = 256 / PX, NW = 4 / PX;
   const ViewConst v = *vp;
   __shared__ Splat batch[NT];
@@ -383,9 +383,9 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     const uint32_t k = b0 + threadIdx.x;
     ev[threadIdx.x] = 0u;
     if (k < rg.y) {
-      const uint32_t e = ival[k];
-      const uint32_t i = inst_splat[e];
-      bm[threadIdx.x] = blocks[e];
+      const uint2 w = info_k[k];
+      const uint32_t i = w.x;
+      bm[threadIdx.x] = w.y;
       if (i < nr) {
         batch[threadIdx.x] = splats[i];
       } else {  // only reachable if the instance count overflowed (its block mask is 0)
@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     }
     if (!COUNT) {
       __syncthreads();
-      if ((int)threadIdx.x < m) event[b0 + threadIdx.x] = (uint16_t)ev[threadIdx.x];
+      if ((int)threadIdx.x < m) event[b0 + threadIdx.x] = event_word(ev[threadIdx.x]);
     }
   }
   if (COUNT) {
@@ -473,25 +473,181 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
   }
 }
 
+// Forward blend with one wave per 8x8 quarter of a tile (four single-wave
+// workgroups per tile, tiles in the blend order): the wave's rows are the
+// quarter's four 4x4 blocks (blend_pixel<1>), lane l its pixel.  The wave
+// streams the tile's instances in batches of 64 and replays, row by row, the
+// ones whose block mask meets the row's block, as k_blend does.  Instance
+// words (owning splat, block mask, gathered in tile order) are loaded two
+// batches ahead and the splat records of the instances that reach the quarter
+// one batch ahead, into registers, so the loads overlap the blending; the
+// waves of a tile never wait for each other, and each stops when its own
+// pixels have.  Events: byte q of each instance's event word holds quarter q's
+// (4-bit) events, written by quarter q's wave, zero for instances it never
+// reached.
+__global__ void __launch_bounds__(64) k_blend_q(const ViewConst* __restrict__ vp, const uint2* __restrict__ ranges,
+                                                const uint2* __restrict__ info_k,
+                                                const Splat* __restrict__ splats, const FrameCounters* ctr,
+                                                const uint32_t* __restrict__ tile_order, float bg0, float bg1,
+                                                float bg2, float* rgb, uint8_t* event8) {
+  const ViewConst v = *vp;
+  __shared__ float4 rec[3][64];     // the batch's records: (mx hi, lo, my hi, lo), (ce, se, h1, h2), (o, r, g, b)
+  __shared__ uint8_t hits[4][64];   // per row: the batch slots it replays, in order
+  __shared__ uint32_t evr[64];      // per slot: this quarter's event bits
+  const int tile = (int)tile_order[blockIdx.x >> 2], q = (int)(blockIdx.x & 3u);
+  const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
+  const int lane = threadIdx.x, g = lane >> 4;
+  const uint64_t lt = lanemask_lt();
+  int px, py;
+  blend_pixel<1>(tx, ty, q, lane, 0, px, py);
+  const uint32_t pbit = blend_pixel_block<1>(q, g, 0);
+  const uint32_t qbits = 0xFu << (4 * q);
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const bool inside = px < v.width && py < v.height;
+  bool live = inside;
+  float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+  const uint2 rg = ranges[tile];
+  const uint32_t nr = (uint32_t)ctr->n_render;
+  const float thr = 1.0f / 255.0f;
+  // pipeline: words of batches b and b + 64, the record of batch b (this lane's slot)
+  uint32_t sk0 = 0u, bk0 = 0u, sk1 = 0u, bk1 = 0u;
+  if (rg.x + lane < rg.y) {
+    const uint2 w = info_k[rg.x + lane];
+    sk0 = w.x;
+    bk0 = w.y;
+  }
+  if (rg.x + 64 + lane < rg.y) {
+    const uint2 w = info_k[rg.x + 64 + lane];
+    sk1 = w.x;
+    bk1 = w.y;
+  }
+  float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra;
+  if (rg.x + lane < rg.y && sk0 < nr && (bk0 & qbits) != 0u) {
+    const float4* r = reinterpret_cast<const float4*>(splats + sk0);
+    ra = r[0];
+    rb = r[1];
+    rc = r[2];
+  }
+  uint32_t b0 = rg.x;
+  for (; b0 < rg.y; b0 += 64) {
+    if (!__any(live)) break;  // wave-uniform
+    const int m = (int)min(64u, rg.y - b0);
+    const bool mine = lane < m && sk0 < nr;
+    rec[0][lane] = ra;
+    rec[1][lane] = rb;
+    rec[2][lane] = rc;
+    evr[lane] = 0u;
+    int nh[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool h = mine && (bk0 & blend_row_blocks<1>(q, r)) != 0u;
+      const uint64_t hb = __ballot(h);
+      if (h) hits[r][__popcll(hb & lt)] = (uint8_t)lane;
+      nh[r] = __popcll(hb);
+    }
+    __syncthreads();
+    // prefetch: the records of the next batch, the words of the one after
+    ra = rb = rc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (b0 + 64 + lane < rg.y && sk1 < nr && (bk1 & qbits) != 0u) {
+      const float4* r = reinterpret_cast<const float4*>(splats + sk1);
+      ra = r[0];
+      rb = r[1];
+      rc = r[2];
+    }
+    uint32_t sk2 = 0u, bk2 = 0u;
+    if (b0 + 128 + lane < rg.y) {
+      const uint2 w = info_k[b0 + 128 + lane];
+      sk2 = w.x;
+      bk2 = w.y;
+    }
+    const int n = g == 0 ? nh[0] : (g == 1 ? nh[1] : (g == 2 ? nh[2] : nh[3]));  // this row's list
+    const int nmax = max(max(nh[0], nh[1]), max(nh[2], nh[3]));
+    auto load = [&](int j) -> Splat {
+      Splat s;
+      const float4 a = rec[0][j], b = rec[1][j], c = rec[2][j];
+      s.mxh = a.x; s.mxl = a.y; s.myh = a.z; s.myl = a.w;
+      s.ce = b.x; s.se = b.y; s.h1 = b.z; s.h2 = b.w;
+      s.o = c.x; s.r = c.y; s.g = c.z; s.b = c.w;
+      return s;
+    };
+    // one splat (slot j of this row's list; has = false past its end) against
+    // the lane's pixel; true when every pixel of the wave has stopped
+    auto step = [&](const Splat& s, int j, bool has) -> bool {
+      float dx, dy, u1, u2;
+      const float power = splat_power(s, fx, fy, dx, dy, u1, u2);
+      const float alpha = fminf(0.99f, s.o * fexp(power));
+      const float tt = T * (1.0f - alpha);
+      const bool hit = live & has & (alpha >= thr);
+      const bool stop = hit & (tt < 0.0001f);
+      const bool con = hit & !stop;
+      live = live & !stop;
+      const float w = alpha * T;
+      cr = con ? __builtin_fmaf(s.r, w, cr) : cr;
+      cg = con ? __builtin_fmaf(s.g, w, cg) : cg;
+      cb = con ? __builtin_fmaf(s.b, w, cb) : cb;
+      T = con ? tt : T;
+      const uint64_t hb = __ballot(hit);  // all lanes
+      if ((lane & 15) == 0 && ((hb >> lane) & 0xFFFFull) != 0ull) atomicOr(&evr[j], pbit);
+      return !__any(live);
+    };
+    if (nmax > 0) {
+      const uint8_t* hl = hits[g];
+      auto slot = [&](int t) -> int { return t < n ? (int)hl[t] : 0; };
+      Splat sa = load(slot(0)), sb;
+      for (int t = 0;;) {
+        const int ja = slot(t);
+        const bool ha = t < n;
+        sb = load(slot(t + 1));
+        if (step(sa, ja, ha) || ++t >= nmax) break;
+        const int jb = slot(t);
+        const bool hb = t < n;
+        sa = load(slot(t + 1));
+        if (step(sb, jb, hb) || ++t >= nmax) break;
+      }
+    }
+    __syncthreads();
+    if (lane < m) event8[4 * (int64_t)(b0 + lane) + q] = (uint8_t)((evr[lane] >> (4 * q)) & 0xFu);
+    __syncthreads();
+    sk0 = sk1;
+    bk0 = bk1;
+    sk1 = sk2;
+    bk1 = bk2;
+  }
+  // instances of the tile that this quarter never reached
+  for (uint32_t k = b0 + lane; k < rg.y; k += 64) event8[4 * (int64_t)k + q] = 0;
+  if (inside) {
+    float* o = rgb + 3 * ((int64_t)py * v.width + px);
+    o[0] = __builtin_fmaf(T, bg0, cr);
+    o[1] = __builtin_fmaf(T, bg1, cg);
+    o[2] = __builtin_fmaf(T, bg2, cb);
+  }
+}
+
 template <bool COUNT>
 static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], float* d_rgb, hipStream_t st) {
   const int ntiles = v.tiles_x * v.tiles_y;
   unsigned long long* work = COUNT ? f->work : nullptr;
-  uint16_t* event = COUNT ? nullptr : f->inst_event;
+  uint32_t* event = COUNT ? nullptr : f->inst_event;
+  if (!COUNT && f->blend_px_fwd == 1) {
+    hipLaunchKernelGGL(k_blend_q, dim3(4 * ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges, f->info_k,
+                       f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2], d_rgb,
+                       reinterpret_cast<uint8_t*>(event));
+    return;
+  }
   switch (f->blend_px_fwd) {
     case 1:
       hipLaunchKernelGGL((k_blend<COUNT, 1>), dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->inst_blocks, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         f->info_k, f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
                          d_rgb, event, work);
       break;
     case 4:
       hipLaunchKernelGGL((k_blend<COUNT, 4>), dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->inst_blocks, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         f->info_k, f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
                          d_rgb, event, work);
       break;
     default:
       hipLaunchKernelGGL((k_blend<COUNT, 2>), dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges,
-                         f->sorted_ival, f->inst_splat, f->splats, f->inst_blocks, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         f->info_k, f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
                          d_rgb, event, work);
       break;
   }
@@ -530,8 +686,7 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_drawn, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
   hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x, icap,
-                     f->ikey, f->ival, f->inst_splat, f->long_list, f->drawn_rank, f->depth_rank, f->splats,
-                     f->inst_blocks);
+                     f->ikey, f->ival, f->inst_info, f->long_list, f->drawn_rank, f->depth_rank, f->splats);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
@@ -542,7 +697,8 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   f->sorted_ival = sw2 ? f->ival2 : f->ival;
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_RANGES, st);
-  hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_ikey, f->ranges, (uint32_t)ntiles);
+  hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_ikey, f->ranges, (uint32_t)ntiles,
+                     f->sorted_ival, f->inst_info, f->info_k);
   if (ntiles > 0)
     hipLaunchKernelGGL(k_tile_order, dim3((ntiles + kOrderChunk - 1) / kOrderChunk), dim3(kOrderThreads), 0, st,
                        f->ranges, ntiles, f->tile_order);
