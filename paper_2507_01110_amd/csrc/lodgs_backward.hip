@@ -130,25 +130,52 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   const uint32_t nr = (uint32_t)ctr->n_render;
   const float thr = 1.0f / 255.0f;
   for (int t = threadIdx.x; t < NW * kPartial * NB; t += NT) (&acc[0][0][0])[t] = 0.0f;
+  // Thread j < NB holds batch slot j: the words (emission index, splat, event
+  // word) of this batch and the next, and the splat record of this batch
+  // (only for an instance with events: the others are never replayed), so the
+  // loads overlap the replay of the batch before.
+  const bool loader = (int)threadIdx.x < NB;
+  auto words = [&](uint32_t b, uint32_t& e, uint32_t& i, uint32_t& w) {
+    const uint32_t k = b + threadIdx.x;
+    e = i = w = 0u;
+    if (loader && k < rg.y) {
+      e = ival[k];
+      i = info_k[k].x;
+      w = event[k];
+    }
+  };
+  auto record = [&](uint32_t i, uint32_t w, float4& a, float4& b, float4& c) {
+    a = b = c = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (w != 0u && i < nr) {  // i >= nr only follows an instance overflow (no events)
+      const float4* r = reinterpret_cast<const float4*>(splats + i);
+      a = r[0];
+      b = r[1];
+      c = r[2];
+    }
+  };
+  uint32_t e0, i0, w0, e1, i1, w1;
+  words(rg.x, e0, i0, w0);
+  words(rg.x + NB, e1, i1, w1);
+  float4 ra, rb, rc;
+  record(i0, w0, ra, rb, rc);
   uint32_t b0 = rg.x;
   for (; b0 < rg.y; b0 += NB) {
     bool active = false;
 #pragma unroll
     for (int p = 0; p < PX; ++p) active = active || live[p];
     if (__syncthreads_count(active) == 0) break;
-    const uint32_t k = b0 + threadIdx.x;
-    if ((int)threadIdx.x < NB && k < rg.y) {
-      const uint32_t e = ival[k];
-      const uint32_t i = info_k[k].x;
-      bid[threadIdx.x] = e;
-      ev[threadIdx.x] = event_blocks(event[k]);
-      if (i < nr) {
-        batch[threadIdx.x] = splats[i];
-      } else {  // only reachable if the instance count overflowed
-        batch[threadIdx.x] = Splat{};  // no event bits: never replayed
-      }
+    if (loader) {
+      bid[threadIdx.x] = e0;
+      ev[threadIdx.x] = event_blocks(w0);
+      float4* dst = reinterpret_cast<float4*>(&batch[threadIdx.x]);  // mean, axis, power, opacity, colour
+      dst[0] = ra;
+      dst[1] = rb;
+      dst[2] = rc;
     }
     __syncthreads();
+    record(i1, w1, ra, rb, rc);
+    uint32_t e2, i2, w2;
+    words(b0 + 2 * NB, e2, i2, w2);
     const int m = (int)min((uint32_t)NB, rg.y - b0);
     int nh[4];
 #pragma unroll
@@ -249,6 +276,12 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
         dst[c] = r;
       }
     }
+    e0 = e1;
+    i0 = i1;
+    w0 = w1;
+    e1 = e2;
+    i1 = i2;
+    w1 = w2;
   }
   // instances that no pixel of the tile reached
   for (uint32_t k = b0 + threadIdx.x; k < rg.y; k += NT) {
