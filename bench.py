@@ -162,8 +162,8 @@ def summarize_profiles(trace_csv, fetch_csv, write_csv, commands):
                                                      "-" if scaled is None else "%.2f" % (scaled / 1e6)))
     out.append("")
     h = kernel_source_hash()
-    for stage, pat in (("blend_bwd", "k_blend_bwd"), ("blend", "k_blend<false")):
-        ks = [k for k in hbm if k.replace("void ", "").startswith(pat)]
+    for stage, pats in (("blend_bwd", ("k_blend_bwd",)), ("blend", ("k_blend_q", "k_blend<false"))):
+        ks = [k for k in hbm if k.replace("void ", "").startswith(pats)]
         if ks:
             out.append("TRAFFIC %s %s %d %s" % (stage, ks[0].replace("void ", "").replace(" ", ""), round(hbm[ks[0]]), h))
     return "\n".join(out)
