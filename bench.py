@@ -313,6 +313,8 @@ def main():
     ap.add_argument("--steps", type=int, default=768)
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--workload", choices=["city", "medium", "tiny", "ultra"], default="city")
+    ap.add_argument("--conservative", action="store_true",
+                    help="cut each SPT at max(0, d - R) tau / fx (the CONSERVATIVE variant) instead of d tau / fx")
     ap.add_argument("--leaves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--targets", type=int, default=8, help="distinct seeded targets resident in HBM")
@@ -375,7 +377,7 @@ def main():
     for v in seq:
         cam, tau = views[v]
         while True:
-            frame.lod_select(cam, tau)
+            frame.lod_select(cam, tau, conservative=args.conservative)
             frame.render(cam)
             st = frame.stats()
             if st["status"] == 0:
@@ -407,7 +409,7 @@ def main():
 
     def step(i):
         cam, tau = cstructs[seq[i % K]], views[seq[i % K]][1]
-        frame.lod_select(cam, tau)
+        frame.lod_select(cam, tau, conservative=args.conservative)
         frame.render(cam, out=img)
         frame.l1_loss(img, targets[seq[i % K] % len(targets)], grad=dL)
         frame.backward(dL, nodes=grads)
@@ -491,7 +493,7 @@ def main():
                         "max": round(float(per_view.max()), 4)}, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded scene, cameras and targets)",
         "config": dict(desc, nodes=int(scene.n_nodes), upper_nodes=int(scene.n_upper), spts=int(scene.n_spt),
-                       views_timed=K, parallelism="none"),
+                       views_timed=K, parallelism="none", cut="conservative" if args.conservative else "default"),
         "hbm_fraction_whole_path": round(hbm_frac, 4),
         "algorithmic_GB_per_view": round(all_bytes / K / 1e9, 4),
         "stages": stages,

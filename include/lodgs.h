@@ -41,6 +41,10 @@ extern "C" {
 
 /* lod_select flags */
 #define LODGS_CULL 1u         /* frustum-cull upper nodes and SPT roots (Sec. 4.3) */
+#define LODGS_CONSERVATIVE 2u /* cut each SPT at X = max(0, d - R) tau / fx, R the SPT's
+                                 radius about its root (the conservative distance of
+                                 Sec. 4.1): no member is cut coarser than its own
+                                 distance allows.  Default: X = d tau / fx (Alg. 2). */
 
 typedef void* lodgs_stream; /* a hipStream_t */
 

@@ -18,6 +18,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 CULL = 1
+CONSERVATIVE = 2
 
 
 def build(verbose: bool = False) -> str:
@@ -161,7 +162,7 @@ class OracleScene:
         self.n_upper, self.n_spt = nu.value, ns.value
         self.spt_begin = self.spt_begin[: self.n_spt + 1].copy()
 
-    def select(self, cam, tau: float, cull: bool = True, mode: int = 0):
+    def select(self, cam, tau: float, cull: bool = True, mode: int = 0, conservative: bool = False):
         """Tree ids of the cut, in layout order, and the decision statistics."""
         t = self.tree
         n = t.n_nodes
@@ -171,7 +172,8 @@ class OracleScene:
         c = camera(cam)
         rc = lib().orc_select(n, _p(t.left), _p(t.right), t.root, _p(t.means), _p(self.g), _p(self.rho),
                               _p(self.role), _p(self.spt_of), _p(self.r_min), _p(self.r_max), _p(self.pos_of),
-                              ctypes.byref(c), float(np.float32(tau)), CULL if cull else 0, mode, _p(out), n,
+                              ctypes.byref(c), float(np.float32(tau)),
+                              (CULL if cull else 0) | (CONSERVATIVE if conservative else 0), mode, _p(out), n,
                               ctypes.byref(cnt), ctypes.byref(st))
         if rc != 0:
             raise RuntimeError(f"orc_select failed ({rc})")

@@ -28,6 +28,7 @@
 #endif
 
 #define ORC_CULL 1u
+#define ORC_CONSERVATIVE 2u
 #define ORC_TILE 16
 
 typedef struct orc_camera {
@@ -303,6 +304,34 @@ static int cmp_by_pos(const void* a, const void* b) {
  * mode 0: SPT cut by descent; mode 1: SPT cut by the linear scan of Alg. 2
  * (every member tested with r_min <= X_j < r_max).  Output: tree ids sorted
  * by layout position pos_of.                                                */
+/* Radius of the SPT rooted at u about the root's mean: the largest
+ * |mu_v - mu_u| over the nodes v of u's subtree (the SPT's members), in FP64
+ * from the FP32 means (((dx dx + dy dy) + dz dz), correctly rounded square
+ * root), rounded once to FP32.  READING (Sec. 4.1, the conservative M_d, as
+ * printed camera-dependent): the CONSERVATIVE variant cuts SPT u at
+ * X = max(0, d_u - R_u) tau / fx, a distance no member can be closer than
+ * (triangle inequality), so no member is cut coarser than its own distance
+ * allows; X stays one per SPT, so Eq. 4's sorted intervals still apply. */
+static float spt_radius(const int32_t* left, const int32_t* right, const float* means, int32_t u,
+                        int32_t* stack) {
+  const double rx = means[3 * (int64_t)u], ry = means[3 * (int64_t)u + 1], rz = means[3 * (int64_t)u + 2];
+  double r = 0.0;
+  int64_t sp = 0;
+  stack[sp++] = u;
+  while (sp > 0) {
+    const int32_t v = stack[--sp];
+    const double dx = (double)means[3 * (int64_t)v] - rx, dy = (double)means[3 * (int64_t)v + 1] - ry,
+                 dz = (double)means[3 * (int64_t)v + 2] - rz;
+    const double d = sqrt((dx * dx + dy * dy) + dz * dz);
+    if (d > r) r = d;
+    if (left[v] >= 0) {
+      stack[sp++] = left[v];
+      stack[sp++] = right[v];
+    }
+  }
+  return (float)r;
+}
+
 int orc_select(int64_t n, const int32_t* left, const int32_t* right, int32_t root, const float* means,
                const float* g, const float* rho, const int8_t* role, const int32_t* spt_of,
                const float* r_min, const float* r_max, const int32_t* pos_of, const orc_camera* C,
@@ -341,6 +370,7 @@ int orc_select(int64_t n, const int32_t* left, const int32_t* right, int32_t roo
     if (cull && culled32(C, &F, mu, rho[u])) { st.spt_culled++; continue; }
     st.spt_visible++;
     float X = dist32(mu, C->pos) * k;
+    if (flags & ORC_CONSERVATIVE) X = fmaxf(0.0f, dist32(mu, C->pos) - spt_radius(left, right, means, u, stk2)) * k;
     int64_t tp = 0;
     stk2[tp++] = u;
     while (tp > 0) {

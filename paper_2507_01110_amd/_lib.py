@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(_PKG, "liblodgs.so")
 
 OK, E_INVALID, E_CAPACITY, E_HIP, E_OOM, E_STATE = 0, -1, -2, -3, -4, -5
 CULL = 1
+CONSERVATIVE = 2
 
 c_p = ctypes.c_void_p
 i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float

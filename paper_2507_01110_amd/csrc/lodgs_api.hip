@@ -204,9 +204,14 @@ int lodgs_scene_create(const lodgs_scene_desc* d, lodgs_scene** out) {
   v.spt_parent = d->d_spt_parent;
   v.anc = nullptr;
   v.anc_depth = 0;
+  v.spt_radius = nullptr;
   s->anc_owned = nullptr;
-  const int rc = lodgs::build_ancestor_table(s);
+  s->radius_owned = nullptr;
+  int rc = lodgs::build_ancestor_table(s);
+  if (rc == LODGS_OK) rc = lodgs::build_spt_radius(s);
   if (rc != LODGS_OK) {
+    if (s->anc_owned) (void)hipFree(s->anc_owned);
+    if (s->radius_owned) (void)hipFree(s->radius_owned);
     delete s;
     return rc;
   }
@@ -217,6 +222,7 @@ int lodgs_scene_create(const lodgs_scene_desc* d, lodgs_scene** out) {
 void lodgs_scene_destroy(lodgs_scene* s) {
   if (!s) return;
   if (s->anc_owned) (void)hipFree(s->anc_owned);
+  if (s->radius_owned) (void)hipFree(s->radius_owned);
   delete s;
 }
 
@@ -302,7 +308,7 @@ int lodgs_lod_select(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_
   if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_lod_select: bad camera");
   if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_lod_select: tau must be finite, >= 0");
   if (capacity < 0 || capacity > (int64_t)INT32_MAX) return set_error(LODGS_E_INVALID, "lodgs_lod_select: capacity");
-  if (flags & ~LODGS_CULL) return set_error(LODGS_E_INVALID, "lodgs_lod_select: unknown flag");
+  if (flags & ~(LODGS_CULL | LODGS_CONSERVATIVE)) return set_error(LODGS_E_INVALID, "lodgs_lod_select: unknown flag");
   const lodgs::ViewConst v = lodgs::make_view(*cam, tau);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   lodgs::launch_select(f, v, flags, d_idx, capacity, d_count, st);
@@ -489,7 +495,7 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
   *out = nullptr;
   if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: bad camera");
   if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: bad tau");
-  if (capacity < 0 || capacity > (int64_t)INT32_MAX || (flags & ~LODGS_CULL))
+  if (capacity < 0 || capacity > (int64_t)INT32_MAX || (flags & ~(LODGS_CULL | LODGS_CONSERVATIVE)))
     return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: bad capacity or flags");
   if (cam->width > f->caps.max_width || cam->height > f->caps.max_height)
     return set_error(LODGS_E_CAPACITY, "lodgs_graph_capture_view: image larger than the frame's capacity");

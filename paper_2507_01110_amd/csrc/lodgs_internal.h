@@ -31,11 +31,15 @@ struct SceneDev {
   // root; nullptr when the hierarchy is deeper than kMaxAncDepth.
   const int32_t* anc;
   int32_t anc_depth;
+  // Radius of each SPT about its root's mean (library-owned, built at scene
+  // creation; the CONSERVATIVE cut).
+  const float* spt_radius;
 };
 
 struct lodgs_scene {
   SceneDev dev;
   int32_t* anc_owned;
+  float* radius_owned;
 };
 
 namespace lodgs {
@@ -43,6 +47,7 @@ constexpr int32_t kMaxAncDepth = 64;
 constexpr int kTileClasses = 128;  // blend tile-order classes (quarter octaves of the instance count)
 // Builds the ancestor table (synchronous; scene creation only).
 int build_ancestor_table(lodgs_scene* s);
+int build_spt_radius(lodgs_scene* s);
 }  // namespace lodgs
 
 // Device counters of a frame (one struct in device memory).

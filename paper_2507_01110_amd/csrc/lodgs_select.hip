@@ -146,6 +146,7 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewCons
                                                       float* spt_X, FrameCounters* ctr) {
   const ViewConst v = *vp;
   const bool cull = (flags & LODGS_CULL) != 0;
+  const bool conservative = (flags & LODGS_CONSERVATIVE) != 0 && S.spt_radius != nullptr;
   const int64_t total = (int64_t)S.n_upper + S.n_spt;
   int vis = 0, hsum = 0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -161,7 +162,8 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewCons
       if (reached(S, utest, e, total, S.spt_parent[j])) {
         const float mx = S.means[3 * (int64_t)b], my = S.means[3 * (int64_t)b + 1], mz = S.means[3 * (int64_t)b + 2];
         if (!(cull && sphere_culled(v, mx, my, mz, S.rho[b]))) {
-          X = view_distance(v, mx, my, mz) * v.k;
+          X = conservative ? fmaxf(0.0f, view_distance(v, mx, my, mz) - S.spt_radius[j]) * v.k
+                           : view_distance(v, mx, my, mz) * v.k;
           high = count_above(S.r_max + b, m, X);
           hsum += high;
           ++vis;
@@ -329,6 +331,52 @@ int build_ancestor_table(lodgs_scene* s) {
   s->anc_owned = anc;
   S.anc = anc;
   S.anc_depth = D;
+  return LODGS_OK;
+}
+
+// Radius of each SPT about its root's mean, for the CONSERVATIVE cut: the
+// largest |mu_i - mu_root| over the SPT's members (its layout segment), in
+// FP64 from the FP32 means (((dx dx + dy dy) + dz dz), correctly rounded
+// square root), rounded once to FP32.  One wave per SPT; the maximum is exact,
+// so the order does not matter.
+__global__ void __launch_bounds__(kBlock) k_spt_radius(SceneDev S, float* radius) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t j = wave; j < S.n_spt; j += waves) {  // wave-uniform
+    const int64_t b = S.spt_begin[j], e = S.spt_begin[j + 1];
+    const double rx = S.means[3 * b], ry = S.means[3 * b + 1], rz = S.means[3 * b + 2];
+    double r = 0.0;
+    for (int64_t i = b + lane; i < e; i += 64) {
+      const double dx = (double)S.means[3 * i] - rx, dy = (double)S.means[3 * i + 1] - ry,
+                   dz = (double)S.means[3 * i + 2] - rz;
+      r = fmax(r, __builtin_sqrt((dx * dx + dy * dy) + dz * dz));
+    }
+    for (int d = 32; d > 0; d >>= 1) r = fmax(r, __shfl_xor(r, d, 64));
+    if (lane == 0) radius[j] = (float)r;
+  }
+}
+
+int build_spt_radius(lodgs_scene* s) {
+  SceneDev& S = s->dev;
+  if (S.n_spt <= 0) return LODGS_OK;
+  float* r = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&r), sizeof(float) * (size_t)S.n_spt);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(LODGS_E_OOM, "lodgs_scene_create: SPT radii");
+  }
+  int grid = (int)(((int64_t)S.n_spt * 64 + kBlock - 1) / kBlock);
+  grid = grid > 4096 ? 4096 : grid;
+  hipLaunchKernelGGL(k_spt_radius, dim3(grid), dim3(kBlock), 0, 0, S, r);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(r);
+    return hip_fail(e, "lodgs_scene_create: SPT radii");
+  }
+  s->radius_owned = r;
+  S.spt_radius = r;
   return LODGS_OK;
 }
 

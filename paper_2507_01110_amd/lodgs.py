@@ -137,10 +137,12 @@ class Frame:
             _lib._lib.lodgs_frame_destroy(h)
             self._h = None
 
-    def lod_select(self, cam, tau: float, cull: bool = True, stream=None):
-        """Runs the cut into self.idx / self.count (device); returns them."""
+    def lod_select(self, cam, tau: float, cull: bool = True, conservative: bool = False, stream=None):
+        """Runs the cut into self.idx / self.count (device); returns them.
+        conservative: cut each SPT at max(0, d - R) tau / fx (LODGS_CONSERVATIVE)."""
         c = camera_struct(cam)
-        check(_lib.load().lodgs_lod_select(self._h, ctypes.byref(c), float(tau), _lib.CULL if cull else 0,
+        flags = (_lib.CULL if cull else 0) | (_lib.CONSERVATIVE if conservative else 0)
+        check(_lib.load().lodgs_lod_select(self._h, ctypes.byref(c), float(tau), flags,
                                            _ptr(self.idx), self.idx.numel(), _ptr(self.count), _stream(stream)),
               "lodgs_lod_select")
         return self.idx, self.count

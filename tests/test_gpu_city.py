@@ -105,3 +105,10 @@ def test_city_views_select_render_backward(city):
         for key, v in nodes.items():
             v[rows] = 0
             assert int(torch.count_nonzero(v)) == 0, key
+        # the CONSERVATIVE cut of the same view
+        idx, cnt = f.lod_select(cam, tau, conservative=True)
+        nc = int(cnt.item())
+        assert f.stats()["status"] == 0
+        ids_c, _ = O.select(cam, tau, conservative=True)
+        assert np.array_equal(idx[:nc].cpu().numpy(), O.pos_of[ids_c]), (nc, len(ids_c))
+        _say(f"  conservative cut: {nc} selected (default {n})")

@@ -45,17 +45,17 @@ def _frame(scene, cam, max_sel=None, max_inst=None):
     return Frame(scene, max_sel or n, max_inst or max(1 << 16, 64 * n), cam.width, cam.height)
 
 
-def _gpu_select(frame, cam, tau, cull=True):
-    idx, cnt = frame.lod_select(cam, tau, cull=cull)
+def _gpu_select(frame, cam, tau, cull=True, conservative=False):
+    idx, cnt = frame.lod_select(cam, tau, cull=cull, conservative=conservative)
     st = frame.stats()
     n = int(cnt.item())
     assert st["status"] == 0 and st["n_selected"] == n
     return idx[:n].cpu().numpy(), st
 
 
-def _check_select(O, frame, cam, tau, cull):
-    ids, ost = O.select(cam, tau, cull=cull)
-    got, st = _gpu_select(frame, cam, tau, cull)
+def _check_select(O, frame, cam, tau, cull, conservative=False):
+    ids, ost = O.select(cam, tau, cull=cull, conservative=conservative)
+    got, st = _gpu_select(frame, cam, tau, cull, conservative)
     expect = O.pos_of[ids]
     assert np.array_equal(got, expect), (len(got), len(expect))
     assert st["n_spt_visible"] == ost["spt_visible"]
@@ -130,6 +130,31 @@ def test_select_random_trees_bitexact(torch_cuda):
         _say("select random tree", it, tree.n_nodes)
         for tau in (0.1, 1.0, 10.0, 100.0):
             _check_select(O, _frame(S, cam), cam, tau, cull=bool(it % 2))
+
+
+def test_select_conservative_bitexact(torch_cuda):
+    # the CONSERVATIVE cut (each SPT at max(0, d - R) tau / fx): the SPT radii
+    # built at scene creation and the cut agree with the oracle bit for bit
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    for cull in (True, False):
+        for tau in (0.25, 1.0, 4.0, 16.0):
+            for cam in (configs.tiny_camera(), scenegen.camera_look_at((3, -2, 1), (0, 0, 0), (0, 0, 1), 320, 200)):
+                _say("select conservative tiny", cull, tau, cam.width)
+                ids = _check_select(O, _frame(S, cam), cam, tau, cull, conservative=True)
+                assert len(ids) >= len(O.select(cam, tau, cull=cull)[0])
+    rng = np.random.default_rng(27)
+    for it in range(20):
+        tree = random_tree(rng, int(rng.integers(1, 65)))
+        O = oracle.OracleScene(tree)
+        S = _scene(tree)
+        pos = rng.uniform(-30, 30, 3)
+        cam = scenegen.camera_look_at(pos, rng.uniform(-10, 10, 3), (0, 0, 1) if abs(pos[2]) < 25 else (0, 1, 0),
+                                      64, 48)
+        _say("select conservative random tree", it, tree.n_nodes)
+        for tau in (0.1, 1.0, 10.0, 100.0):
+            _check_select(O, _frame(S, cam), cam, tau, cull=bool(it % 2), conservative=True)
 
 
 def test_select_deep_upper_hierarchy_bitexact(torch_cuda):

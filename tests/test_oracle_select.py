@@ -209,3 +209,81 @@ def test_exact_ties_follow_eq4_inequalities():
         below = np.nextafter(below, np.float32(0))
     ids, _ = S.select(cam, float(below), cull=False)
     assert sorted(ids.tolist()) == [1, 2]
+
+
+# ---------------------------------------------------------------------------
+# CONSERVATIVE variant (Sec. 4.1, the conservative M_d): each SPT is cut at
+# X = max(0, d_root - R) tau / fx with R the SPT's radius about its root.
+
+def _own_x(t, v, cam, tau):
+    return np.linalg.norm(t.means[v].astype(np.float64) - cam.pos.astype(np.float64)) * tau / cam.fx
+
+
+def test_conservative_cut_is_never_coarser_than_each_nodes_own_distance():
+    # the triangle inequality: no member is closer than d_root - R, so a
+    # selected interior node passes the size test at its own distance
+    rng = np.random.default_rng(31)
+    checked = 0
+    for _ in range(120):
+        t = random_tree(rng, int(rng.integers(2, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 2)))
+        ids, _ = S.select(cam, tau, cull=False, conservative=True)
+        for v in ids.tolist():
+            if t.left[v] < 0:
+                continue
+            assert S.g[v] <= _own_x(t, v, cam, tau) * (1 + 1e-5), (v, S.g[v], _own_x(t, v, cam, tau))
+            checked += 1
+    assert checked > 50
+
+
+def test_conservative_cut_is_proper_covers_every_path_and_refines_the_default_cut():
+    rng = np.random.default_rng(32)
+    finer = 0
+    for _ in range(100):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 2)))
+        for mode in (0, 1):
+            cons, _ = S.select(cam, tau, cull=False, mode=mode, conservative=True)
+            _check_proper_and_covering(t, cons)
+            base = set(S.select(cam, tau, cull=False, mode=mode)[0].tolist())
+            for c in cons.tolist():  # every conservative node lies at or below a default node
+                assert c in base or any(a in base for a in ancestors(t, c))
+            finer += len(cons) > len(base)
+    assert finer > 0
+
+
+def test_conservative_cut_equals_the_default_cut_when_every_spt_has_zero_radius():
+    rng = np.random.default_rng(33)
+    for _ in range(40):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        t.means[:] = t.means[t.root]  # every SPT radius is 0
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 2)))
+        for cull in (False, True):
+            a = S.select(cam, tau, cull=cull, conservative=True)[0]
+            b = S.select(cam, tau, cull=cull)[0]
+            assert np.array_equal(a, b)
+
+
+def test_conservative_cut_takes_the_leaves_of_an_spt_whose_radius_holds_the_camera():
+    # one SPT (the whole tree); the camera 0.1 R from the root's mean: X = 0,
+    # so only the leaves (r_min = 0) are selected, while the default cut at
+    # the same large tau stays coarse
+    rng = np.random.default_rng(34)
+    for _ in range(40):
+        t = random_tree(rng, int(rng.integers(4, 65)), log_threshold=math.inf)
+        S = oracle.OracleScene(t)
+        assert S.n_upper == 0 and S.n_spt == 1
+        m = t.means.astype(np.float64)
+        R = np.linalg.norm(m - m[t.root], axis=1).max()
+        d = rng.normal(size=3)
+        pos = m[t.root] + 0.1 * R * d / np.linalg.norm(d)
+        cam = scenegen.camera_look_at(pos, pos + [1.0, 0.3, 0.2], (0, 0, 1), 64, 48)
+        ids = S.select(cam, 1e4, cull=False, conservative=True)[0]
+        assert sorted(ids.tolist()) == list(range(t.n_leaves))
+        assert len(S.select(cam, 1e4, cull=False)[0]) < t.n_leaves
