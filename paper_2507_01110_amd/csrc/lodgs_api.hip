@@ -151,7 +151,7 @@ void free_frame(lodgs_frame* f) {
   if (f->open_event) (void)hipEventDestroy(f->open_event);
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->upper_test, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->depth_rank, f->rect,
-                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->grad2d, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
+                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->rank_info, f->grad2d, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
                   f->d_view_ren};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -274,6 +274,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(inst_grad, (size_t)lodgs::kPartial * ni);
   A(inst_event, ni);
   A(info_k, ni);
+  A(rank_info, 2 * ns);
   A(grad2d, 9 * ns);
   A(dcol, 9 * ns);
   A(long_list, ns);

@@ -457,19 +457,32 @@ __global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr,
                                                        const uint32_t* drawn_rank, const uint32_t* inst_off,
                                                        const float* __restrict__ partial,
                                                        const Splat* __restrict__ splats, const ushort4* rect,
-                                                       double* grad2d) {
+                                                       const uint4* rank_info, double* grad2d) {
   const int64_t n = ctr->n_drawn;
   const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = order[r];
-    const ushort4 q = rect[i];
     const int64_t a0 = inst_off[r];
+    int64_t i, dr;
+    ushort4 q;
+    double mx, my;
+    if (a0 < n_cl) {  // the duplication kernel wrote the rank's record with the first instance
+      const uint4 w0 = rank_info[2 * r], w1 = rank_info[2 * r + 1];
+      i = w0.x;
+      dr = w0.y;
+      q = make_ushort4((unsigned short)(w0.z & 0xFFFFu), (unsigned short)(w0.z >> 16),
+                       (unsigned short)(w0.w & 0xFFFFu), (unsigned short)(w0.w >> 16));
+      mx = (double)__uint_as_float(w1.x) + (double)__uint_as_float(w1.y);
+      my = (double)__uint_as_float(w1.z) + (double)__uint_as_float(w1.w);
+    } else {  // left without instances by an overflow: zero sums
+      i = order[r];
+      dr = drawn_rank[i];
+      q = rect[i];
+      mx = my = 0.0;
+    }
     if ((uint32_t)(q.y - q.x) * (uint32_t)(q.w - q.z) > kLongSegment && a0 < n_cl) continue;  // k_long_sums
     int64_t b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
     const int64_t a = a0 < n_cl ? a0 : n_cl;
     b = b < n_cl ? b : n_cl;
-    double mx, my;
-    splat_mean64(splats, i, mx, my);
     double g[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t k = a; k < b; ++k) {
       float t[kPartial];
@@ -477,7 +490,7 @@ __global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr,
       for (int c = 0; c < kPartial; ++c) t[c] = partial[kPartial * k + c];
       add_instance(g, t, (uint32_t)(k - a0), q, mx, my);
     }
-    double* dst = grad2d + 9 * (int64_t)drawn_rank[i];
+    double* dst = grad2d + 9 * dr;
 #pragma unroll
     for (int c = 0; c < 9; ++c) dst[c] = g[c];
   }
@@ -660,7 +673,7 @@ static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodg
   hipLaunchKernelGGL(k_long_sums, dim3(1024), dim3(kBlock), 0, st, f->ctr, f->long_list, f->sorted_order,
                      f->drawn_rank, f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
   hipLaunchKernelGGL(k_splat_sums, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_order, f->drawn_rank,
-                     f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
+                     f->inst_off, f->inst_grad, f->splats, f->rect, f->rank_info, f->grad2d);
   hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
                      f->drawn_list, f->splats, f->dcol, f->grad2d, sel.d_sh, nodes.d_sh);
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,

@@ -106,6 +106,8 @@ struct lodgs_frame {
   float* inst_grad;       // [max_instances][kPartial] per-instance partials (emission order)
   uint32_t* inst_event;   // [max_instances] forward events, byte q for quarter q's 4x4 blocks (tile order)
   uint2* info_k;          // [max_instances] inst_info in tile order
+  uint4* rank_info;       // [max_selected][2] per depth rank: (splat, drawn rank, rect x0|x1<<16, y0|y1<<16),
+                          // (mean x hi, lo, y hi, lo); written with the splat's first instance
   double* grad2d;         // [max_selected][9] per-drawn-splat 2D sums (drawn rank)
   float* dcol;            // [max_selected][9] d colour / d view direction of each drawn splat (selection position)
   uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances

@@ -196,14 +196,16 @@ struct LoadTilesInOrder {
 // clamped count for the later kernels and flags an overflow).  The first
 // instance of a splat records the splat's depth rank at its drawn rank (for
 // the backward, which walks the drawn splats in selection order), and lists
-// it when it has more than kLongSegment instances.  Each instance also gets
+// it when it has more than kLongSegment instances, and writes the splat's
+// per-rank record (rank_info) for the projection backward.  Each instance also gets
 // the 4x4 blocks of its tile that the splat's alpha >= 1/255 ellipse can
 // reach (splat_block_mask); the forward skips the others.
 __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order,
                                                 const uint32_t* inst_off, const ushort4* rect, int32_t tiles_x,
                                                 int64_t cap, uint32_t* ikey, uint32_t* ival, uint2* inst_info,
                                                 uint32_t* long_list, const uint32_t* drawn_rank,
-                                                uint32_t* depth_rank, const Splat* __restrict__ splats) {
+                                                uint32_t* depth_rank, const Splat* __restrict__ splats,
+                                                uint4* rank_info) {
   const uint32_t total = (uint32_t)ctr->n_instances;  // the scan's 32-bit sum
   const int64_t n = (int64_t)total > cap ? cap : (int64_t)total;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -223,7 +225,13 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
     const ushort4 q = rect[i];
     const uint32_t w = (uint32_t)(q.y - q.x);
     if (l == 0) {
-      depth_rank[drawn_rank[i]] = (uint32_t)lo;
+      const uint32_t dr = drawn_rank[i];
+      depth_rank[dr] = (uint32_t)lo;
+      const Splat& sp = splats[i];
+      rank_info[2 * (int64_t)lo] = make_uint4(i, dr, (uint32_t)q.x | ((uint32_t)q.y << 16),
+                                              (uint32_t)q.z | ((uint32_t)q.w << 16));
+      rank_info[2 * (int64_t)lo + 1] = make_uint4(__float_as_uint(sp.mxh), __float_as_uint(sp.mxl),
+                                                  __float_as_uint(sp.myh), __float_as_uint(sp.myl));
       if (w * (uint32_t)(q.w - q.z) > kLongSegment) long_list[atomicAdd(&ctr->n_long, 1)] = (uint32_t)lo;
     }
     ival[k] = (uint32_t)k;  // the tile sort carries the emission index
@@ -686,7 +694,8 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_drawn, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
   hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x, icap,
-                     f->ikey, f->ival, f->inst_info, f->long_list, f->drawn_rank, f->depth_rank, f->splats);
+                     f->ikey, f->ival, f->inst_info, f->long_list, f->drawn_rank, f->depth_rank, f->splats,
+                     f->rank_info);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
