@@ -222,9 +222,10 @@ def serve_bench(scene, n_per_rate, rates=SERVE_RATES, max_slots=8, warmup=100):
     return out
 
 
-def cpu_baseline(tree, views, target):
+def cpu_baseline(tree, views, target, cut="hspt", conservative=False):
     """The oracle on a bounded sample of the same workload: for each (camera,
-    tau) of views, select, render, L1 and backward; mean wall-clock per view."""
+    tau) of views, select (the same cut), render, L1 and backward; mean
+    wall-clock per view."""
     import oracle
     t0 = time.time()
     O = oracle.OracleScene(tree)
@@ -232,7 +233,10 @@ def cpu_baseline(tree, views, target):
     per, nsel = [], []
     for cam, tau in views:
         t0 = time.time()
-        ids, _ = O.select(cam, tau)
+        if cut == "hspt":
+            ids, _ = O.select(cam, tau, conservative=conservative)
+        else:
+            ids = O.select_full(cam, tau, cut)
         F = oracle.OracleFrame(tree, ids, cam)
         _, dL = oracle.l1_loss_grad(F.image, target)
         F.backward(dL)
@@ -315,6 +319,8 @@ def main():
     ap.add_argument("--workload", choices=["city", "medium", "tiny", "ultra"], default="city")
     ap.add_argument("--conservative", action="store_true",
                     help="cut each SPT at max(0, d - R) tau / fx (the CONSERVATIVE variant) instead of d tau / fx")
+    ap.add_argument("--cut", choices=["hspt", "bfs", "parallel"], default="hspt",
+                    help="LoD cut: the HSPT cut, or a whole-hierarchy comparator (BFS, Eq. 5's parallel cut)")
     ap.add_argument("--leaves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--targets", type=int, default=8, help="distinct seeded targets resident in HBM")
@@ -355,6 +361,9 @@ def main():
     torch.cuda.synchronize()
     log(f"HSPT {scene.n_upper} upper nodes, {scene.n_spt} SPTs; upload {scene.param_bytes() / 1e9:.1f} GB "
         f"in {time.time() - t0:.1f} s")
+    if args.cut != "hspt":
+        scene.attach_hierarchy(tree)
+        log(f"whole hierarchy attached for the {args.cut} cut (height {scene.hierarchy['height']})")
     W, H = views[0][0].width, views[0][0].height
     n_coef = 3 * (tree.sh_degree + 1) ** 2
     K = max(1, args.steps)
@@ -377,13 +386,16 @@ def main():
     for v in seq:
         cam, tau = views[v]
         while True:
-            frame.lod_select(cam, tau, conservative=args.conservative)
+            frame.lod_select(cam, tau, conservative=args.conservative, method=args.cut)
             frame.render(cam)
             st = frame.stats()
             if st["status"] == 0:
                 break
+            grown = (cap_sel, cap_inst)
             cap_sel = max(cap_sel, int(st["n_selected"] * 1.25) + 1024)
             cap_inst = max(cap_inst, int(st["n_instances"] * 1.25) + 1024)
+            if (cap_sel, cap_inst) == grown:  # a BFS frontier longer than the selection capacity
+                cap_sel = min(2 * cap_sel, scene.n_nodes)
             log(f"capacity grown to {cap_sel} selected / {cap_inst} instances")
             del frame
             torch.cuda.empty_cache()
@@ -409,7 +421,7 @@ def main():
 
     def step(i):
         cam, tau = cstructs[seq[i % K]], views[seq[i % K]][1]
-        frame.lod_select(cam, tau, conservative=args.conservative)
+        frame.lod_select(cam, tau, conservative=args.conservative, method=args.cut)
         frame.render(cam, out=img)
         frame.l1_loss(img, targets[seq[i % K] % len(targets)], grad=dL)
         frame.backward(dL, nodes=grads)
@@ -480,7 +492,7 @@ def main():
         else:
             sample = [views[0]]
         log(f"cpu baseline: oracle on {len(sample)} view(s) ...")
-        cpu = cpu_baseline(tree, sample, scenegen.target_image(H, W, 202))
+        cpu = cpu_baseline(tree, sample, scenegen.target_image(H, W, 202), args.cut, args.conservative)
         log(f"cpu baseline {cpu['value']} ms per view on {cpu['cores']} threads")
 
     mean = lambda k: float(np.mean([c[k] for c in counts]))
@@ -493,7 +505,7 @@ def main():
                         "max": round(float(per_view.max()), 4)}, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded scene, cameras and targets)",
         "config": dict(desc, nodes=int(scene.n_nodes), upper_nodes=int(scene.n_upper), spts=int(scene.n_spt),
-                       views_timed=K, parallelism="none", cut="conservative" if args.conservative else "default"),
+                       views_timed=K, parallelism="none", cut="conservative" if args.conservative else ("default" if args.cut == "hspt" else args.cut)),
         "hbm_fraction_whole_path": round(hbm_frac, 4),
         "algorithmic_GB_per_view": round(all_bytes / K / 1e9, 4),
         "stages": stages,

@@ -45,6 +45,17 @@ extern "C" {
                                  radius about its root (the conservative distance of
                                  Sec. 4.1): no member is cut coarser than its own
                                  distance allows.  Default: X = d tau / fx (Alg. 2). */
+/* Comparator cuts over the whole hierarchy (Sec. 4.3, the two approaches the
+ * HSPT replaces); both need lodgs_scene_set_hierarchy and exclude each other
+ * and LODGS_CONSERVATIVE.  A node is fine at its own distance when
+ * r_min <= X = d tau / fx (leaves, r_min = 0, always are). */
+#define LODGS_CUT_BFS 4u      /* descent from the root: a reached node is dropped with its
+                                 subtree when culled (if LODGS_CULL), selected when fine,
+                                 else both children are reached */
+#define LODGS_CUT_PARALLEL 8u /* the per-node test of Eq. 5: selected when fine and its
+                                 parent (if any) is not; with LODGS_CULL a node whose own
+                                 sphere is culled is dropped.  A proper cut only when
+                                 fineness passes from parents to children. */
 
 typedef void* lodgs_stream; /* a hipStream_t */
 
@@ -127,6 +138,21 @@ typedef struct lodgs_scene lodgs_scene;
 int lodgs_scene_create(const lodgs_scene_desc* desc, lodgs_scene** out);
 void lodgs_scene_destroy(lodgs_scene* scene);
 
+/* Attaches the whole binary hierarchy for the comparator cuts LODGS_CUT_BFS
+ * and LODGS_CUT_PARALLEL (Sec. 4.3: the BFS cut, and the parallel cut of
+ * Eq. 5).  Borrowed device arrays in layout order (they must outlive the
+ * scene): d_parent [n_nodes] the layout position of each node's parent, -1
+ * for the root, which must be position 0; d_child [n_nodes][2] the layout
+ * positions of the two children, (-1, -1) for a leaf.  height = the number of
+ * levels (1 for a lone root), at most 4096: the BFS runs one pass per level.
+ * Frames created after this call hold the comparators' workspace (a bit per
+ * node and two frontier queues of max_selected entries) and run height BFS
+ * passes, the height at their creation; a BFS that still has a frontier after
+ * them records LODGS_E_INVALID in the frame's status.  Synchronous; checks
+ * that position 0 is the root.  Errors: LODGS_E_INVALID (null array, height
+ * out of range, position 0 has a parent). */
+int lodgs_scene_set_hierarchy(lodgs_scene* scene, const int32_t* d_parent, const int32_t* d_child, int32_t height);
+
 /* ---------------------------------------------------------------- frame
  * A frame owns the device workspace of one view in flight: the LoD-cut
  * scratch, the per-splat projections, the sorted instance lists, the tile
@@ -156,7 +182,10 @@ void lodgs_frame_destroy(lodgs_frame* frame);
  * Writes the selected layout positions in ascending order to d_idx[0 ..
  * min(count, capacity)) and the full count to *d_count (device int32).  If
  * count > capacity the frame records LODGS_E_CAPACITY (see lodgs_frame_stats).
- * tau must be finite and >= 0. */
+ * tau must be finite and >= 0.  With LODGS_CUT_BFS or LODGS_CUT_PARALLEL the
+ * comparator cut replaces the HSPT cut (same output contract; the frame must
+ * have been created after lodgs_scene_set_hierarchy, else LODGS_E_STATE); a
+ * BFS frontier longer than max_selected records LODGS_E_CAPACITY. */
 int lodgs_lod_select(lodgs_frame* frame, const lodgs_camera* cam, float tau, uint32_t flags, int32_t* d_idx,
                      int64_t capacity, int32_t* d_count, lodgs_stream stream);
 

@@ -71,6 +71,10 @@ def lib():
         L.orc_select.argtypes = [i64, P, P, i32, P, P, P, P, P, P, P, P, ctypes.POINTER(OrcCamera), f32,
                                  ctypes.c_uint32, ctypes.c_int, P, i64, P, ctypes.POINTER(SelectStats)]
         L.orc_select.restype = ctypes.c_int
+        for name in ("orc_select_bfs", "orc_select_parallel"):
+            fn = getattr(L, name)
+            fn.argtypes = [i64, P, P, i32, P, P, P, P, ctypes.POINTER(OrcCamera), f32, ctypes.c_uint32, P, i64, P]
+            fn.restype = ctypes.c_int
         L.orc_sh_basis.argtypes = [P, P, P]
         L.orc_render.argtypes = [i64, P, P, P, P, P, P, ctypes.c_int, ctypes.POINTER(OrcCamera), P, P]
         L.orc_render.restype = ctypes.c_void_p
@@ -178,6 +182,21 @@ class OracleScene:
         if rc != 0:
             raise RuntimeError(f"orc_select failed ({rc})")
         return out[: cnt.value].copy(), st.as_dict()
+
+
+    def select_full(self, cam, tau: float, method: str, cull: bool = True):
+        """Tree ids of a whole-hierarchy comparator cut ("bfs" or "parallel"), in layout order."""
+        fn = {"bfs": lib().orc_select_bfs, "parallel": lib().orc_select_parallel}[method]
+        t = self.tree
+        n = t.n_nodes
+        out = np.zeros(n, np.int32)
+        cnt = ctypes.c_int64(0)
+        c = camera(cam)
+        rc = fn(n, _p(t.left), _p(t.right), t.root, _p(t.means), _p(self.g), _p(self.rho), _p(self.pos_of),
+                ctypes.byref(c), float(np.float32(tau)), CULL if cull else 0, _p(out), n, ctypes.byref(cnt))
+        if rc != 0:
+            raise RuntimeError(f"orc_select_{method} failed ({rc})")
+        return out[: cnt.value].copy()
 
 
 class OracleFrame:

@@ -412,6 +412,81 @@ int orc_select(int64_t n, const int32_t* left, const int32_t* right, int32_t roo
   return 0;
 }
 
+/* The two whole-hierarchy cuts that the HSPT replaces (Sec. 4.3, "BFS" and
+ * "Parallel Cut"), for comparison.  Every node is tested at its own distance,
+ * X_i = d_i tau / fx, with the size test read as for the HSPT cut: fine(i)
+ * when i is a leaf or g_i <= X_i.
+ *  - BFS cut: the descent of Alg. 1 over the whole hierarchy, in breadth-first
+ *    order from the root: a reached node is dropped with its subtree when
+ *    culled, selected when fine, else its two children are reached.
+ *  - Parallel cut (Eq. 5, with the same reading of its size test): node i is
+ *    selected when fine(i) and, unless it is the root, its parent is not
+ *    fine; with culling, a node whose own sphere is culled is dropped.
+ * Output: tree ids sorted by layout position pos_of; -2 when more than cap. */
+static int finish_cut(int32_t* out, int64_t cnt, int64_t cap, const int32_t* pos_of, int64_t* n_out) {
+  *n_out = cnt;
+  if (cnt > cap) return -2;
+  g_sort_pos = pos_of;
+  qsort(out, (size_t)cnt, sizeof(int32_t), cmp_by_pos);
+  return 0;
+}
+
+static int fine32(const int32_t* left, const float* means, const float* g, int32_t v, const float* pos, float k) {
+  return left[v] < 0 || g[v] <= dist32(means + 3 * (int64_t)v, pos) * k;
+}
+
+int orc_select_bfs(int64_t n, const int32_t* left, const int32_t* right, int32_t root, const float* means,
+                   const float* g, const float* rho, const int32_t* pos_of, const orc_camera* C, float tau,
+                   uint32_t flags, int32_t* out, int64_t cap, int64_t* n_out) {
+  const float k = tau / C->fx;
+  const orc_frustum F = frustum32(C);
+  const int cull = (flags & ORC_CULL) != 0;
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  if (!queue) return -1;
+  int64_t head = 0, tail = 0, cnt = 0;
+  queue[tail++] = root;
+  while (head < tail) {
+    const int32_t u = queue[head++];
+    if (cull && culled32(C, &F, means + 3 * (int64_t)u, rho[u])) continue;
+    if (fine32(left, means, g, u, C->pos, k)) {
+      if (cnt < cap) out[cnt] = u;
+      cnt++;
+    } else {
+      queue[tail++] = left[u];
+      queue[tail++] = right[u];
+    }
+  }
+  free(queue);
+  return finish_cut(out, cnt, cap, pos_of, n_out);
+}
+
+int orc_select_parallel(int64_t n, const int32_t* left, const int32_t* right, int32_t root, const float* means,
+                        const float* g, const float* rho, const int32_t* pos_of, const orc_camera* C, float tau,
+                        uint32_t flags, int32_t* out, int64_t cap, int64_t* n_out) {
+  const float k = tau / C->fx;
+  const orc_frustum F = frustum32(C);
+  const int cull = (flags & ORC_CULL) != 0;
+  int32_t* parent = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  if (!parent) return -1;
+  for (int64_t v = 0; v < n; ++v) parent[v] = -1;
+  for (int64_t v = 0; v < n; ++v)
+    if (left[v] >= 0) {
+      parent[left[v]] = (int32_t)v;
+      parent[right[v]] = (int32_t)v;
+    }
+  int64_t cnt = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t i = (int32_t)v;
+    if (!fine32(left, means, g, i, C->pos, k)) continue;
+    if (i != root && parent[i] >= 0 && fine32(left, means, g, parent[i], C->pos, k)) continue;
+    if (cull && culled32(C, &F, means + 3 * v, rho[i])) continue;
+    if (cnt < cap) out[cnt] = i;
+    cnt++;
+  }
+  free(parent);
+  return finish_cut(out, cnt, cap, pos_of, n_out);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Real spherical harmonics up to degree 3 (Sec. 3: view-dependent colour from
  * SH coefficients), index k = l^2 + l + m, Condon-Shortley signs folded in

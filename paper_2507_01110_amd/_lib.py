@@ -12,6 +12,8 @@ LIB_PATH = os.path.join(_PKG, "liblodgs.so")
 OK, E_INVALID, E_CAPACITY, E_HIP, E_OOM, E_STATE = 0, -1, -2, -3, -4, -5
 CULL = 1
 CONSERVATIVE = 2
+CUT_BFS = 4
+CUT_PARALLEL = 8
 
 c_p = ctypes.c_void_p
 i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
@@ -62,6 +64,7 @@ EXPORTS = {
                          ctypes.c_int),
     "lodgs_scene_create": ([ctypes.POINTER(SceneDesc), ctypes.POINTER(c_p)], ctypes.c_int),
     "lodgs_scene_destroy": ([c_p], None),
+    "lodgs_scene_set_hierarchy": ([c_p, c_p, c_p, ctypes.c_int32], ctypes.c_int),
     "lodgs_frame_create": ([c_p, ctypes.POINTER(FrameCaps), ctypes.POINTER(c_p)], ctypes.c_int),
     "lodgs_frame_destroy": ([c_p], None),
     "lodgs_lod_select": ([c_p, ctypes.POINTER(Camera), f32, ctypes.c_uint32, c_p, i64, c_p, c_p], ctypes.c_int),

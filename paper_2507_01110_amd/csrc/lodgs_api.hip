@@ -152,7 +152,7 @@ void free_frame(lodgs_frame* f) {
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->upper_test, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->depth_rank, f->rect,
                   f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->rank_info, f->grad2d, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
-                  f->d_view_ren};
+                  f->d_view_ren, f->cut_bits, f->frontier[0], f->frontier[1], f->level_count};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete f;
@@ -205,6 +205,9 @@ int lodgs_scene_create(const lodgs_scene_desc* d, lodgs_scene** out) {
   v.anc = nullptr;
   v.anc_depth = 0;
   v.spt_radius = nullptr;
+  v.parent = nullptr;
+  v.child = nullptr;
+  v.height = 0;
   s->anc_owned = nullptr;
   s->radius_owned = nullptr;
   int rc = lodgs::build_ancestor_table(s);
@@ -216,6 +219,21 @@ int lodgs_scene_create(const lodgs_scene_desc* d, lodgs_scene** out) {
     return rc;
   }
   *out = s;
+  return LODGS_OK;
+}
+
+int lodgs_scene_set_hierarchy(lodgs_scene* s, const int32_t* d_parent, const int32_t* d_child, int32_t height) {
+  if (!s || !d_parent || !d_child) return set_error(LODGS_E_INVALID, "lodgs_scene_set_hierarchy: null argument");
+  if (height < 1 || height > 4096) return set_error(LODGS_E_INVALID, "lodgs_scene_set_hierarchy: height 1..4096");
+  if ((reinterpret_cast<uintptr_t>(d_child) & 7u) != 0)
+    return set_error(LODGS_E_INVALID, "lodgs_scene_set_hierarchy: d_child must be 8-byte aligned");
+  int32_t p0 = 0;
+  hipError_t e = hipMemcpy(&p0, d_parent, sizeof p0, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "lodgs_scene_set_hierarchy");
+  if (p0 != -1) return set_error(LODGS_E_INVALID, "lodgs_scene_set_hierarchy: position 0 must be the root");
+  s->dev.parent = d_parent;
+  s->dev.child = reinterpret_cast<const int2*>(d_child);
+  s->dev.height = height;
   return LODGS_OK;
 }
 
@@ -283,6 +301,13 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(work, 2);
   A(d_view_sel, 1);
   A(d_view_ren, 1);
+  if (S.parent) {
+    A(cut_bits, (size_t)lodgs::cut_bit_words(S.n_nodes));
+    A(frontier[0], ns);
+    A(frontier[1], ns);
+    A(level_count, (size_t)S.height + 1);
+    f->cut_height = S.height;
+  }
 #undef A
   if (e != hipSuccess) {
     free_frame(f);
@@ -292,6 +317,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   FrameCounters c;
   std::memset(&c, 0, sizeof c);
   c.spt_count = S.n_spt;
+  c.n_bit_words = (int32_t)lodgs::cut_bit_words(S.n_nodes);
   e = hipMemcpy(f->ctr, &c, sizeof c, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_frame(f);
@@ -309,10 +335,17 @@ int lodgs_lod_select(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_
   if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_lod_select: bad camera");
   if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_lod_select: tau must be finite, >= 0");
   if (capacity < 0 || capacity > (int64_t)INT32_MAX) return set_error(LODGS_E_INVALID, "lodgs_lod_select: capacity");
-  if (flags & ~(LODGS_CULL | LODGS_CONSERVATIVE)) return set_error(LODGS_E_INVALID, "lodgs_lod_select: unknown flag");
+  if (flags & ~(LODGS_CULL | LODGS_CONSERVATIVE | LODGS_CUT_BFS | LODGS_CUT_PARALLEL))
+    return set_error(LODGS_E_INVALID, "lodgs_lod_select: unknown flag");
+  const uint32_t full = flags & (LODGS_CUT_BFS | LODGS_CUT_PARALLEL);
+  if (full && (full == (LODGS_CUT_BFS | LODGS_CUT_PARALLEL) || (flags & LODGS_CONSERVATIVE)))
+    return set_error(LODGS_E_INVALID, "lodgs_lod_select: LODGS_CUT_BFS, LODGS_CUT_PARALLEL and LODGS_CONSERVATIVE exclude each other");
+  if (full && !f->cut_bits)
+    return set_error(LODGS_E_STATE, "lodgs_lod_select: the frame was created before lodgs_scene_set_hierarchy");
   const lodgs::ViewConst v = lodgs::make_view(*cam, tau);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  lodgs::launch_select(f, v, flags, d_idx, capacity, d_count, st);
+  if (full) lodgs::launch_select_full(f, v, flags, d_idx, capacity, d_count, st);
+  else lodgs::launch_select(f, v, flags, d_idx, capacity, d_count, st);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_lod_select");
 }

@@ -34,6 +34,12 @@ struct SceneDev {
   // Radius of each SPT about its root's mean (library-owned, built at scene
   // creation; the CONSERVATIVE cut).
   const float* spt_radius;
+  // Whole hierarchy for the comparator cuts (borrowed; nullptr when not
+  // attached): parent and two children per layout position, and the number of
+  // levels.
+  const int32_t* parent;
+  const int2* child;
+  int32_t height;
 };
 
 struct lodgs_scene {
@@ -61,7 +67,7 @@ struct FrameCounters {
   int32_t n_drawn;
   int32_t n_instances;   // full count
   int32_t n_inst_clamped;
-  int32_t pad0;
+  int32_t n_bit_words;   // constant: words of the comparator cuts' node bitmask
   int32_t upper_plus_high;
   int32_t spt_count;     // constant n_spt
   int32_t n_chunks;      // SPT candidate chunks of the last select
@@ -86,6 +92,11 @@ struct lodgs_frame {
   uint32_t* spt_off;      // [n_spt]
   uint32_t* seg;          // [ceil(n_upper/64) + n_spt + n_nodes/512 + 1]
   uint32_t* chunk_owner;  // [n_spt + n_nodes/512 + 1] SPT of each candidate chunk
+  // comparator cuts (allocated when the scene has its hierarchy attached)
+  uint32_t* cut_bits;     // [n_bit_words] one bit per node, selected
+  int32_t* frontier[2];   // [max_selected] BFS frontiers (ping-pong)
+  int32_t* level_count;   // [cut_height + 1] BFS frontier lengths
+  int32_t cut_height;     // the scene's height when the frame was created
   // render
   lodgs::Splat* splats;   // [max_selected]
   uint32_t* depth_key;    // [max_selected]
@@ -193,6 +204,11 @@ void stage_end(lodgs_frame* f, hipStream_t st);
 // Stage launchers (all stream-ordered, no host synchronisation).
 void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
                    int32_t* d_count, hipStream_t st);
+// The comparator cuts (LODGS_CUT_BFS / LODGS_CUT_PARALLEL in flags).
+void launch_select_full(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
+                        int32_t* d_count, hipStream_t st);
+// Words of the node bitmask: whole 64-node waves.
+inline int64_t cut_bit_words(int64_t n_nodes) { return 2 * ((n_nodes + 63) / 64); }
 void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, const ViewConst& v,
                    const float bg[3], float* d_rgb, hipStream_t st);
 void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,

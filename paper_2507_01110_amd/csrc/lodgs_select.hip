@@ -407,4 +407,169 @@ void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* 
   stage_end(f, st);
 }
 
+// ---------------------------------------------------------------- comparator cuts
+// The two whole-hierarchy cuts the HSPT replaces (Sec. 4.3): the BFS cut and
+// the parallel cut of Eq. 5.  Both mark the selected nodes in a bitmask (bit
+// i % 32 of word i / 32); an exclusive scan of the words' popcounts then
+// writes the ascending list, so the order of the marking does not matter.
+namespace {
+
+__device__ __forceinline__ bool node_fine(const SceneDev& S, const ViewConst& v, int64_t i, float mx, float my,
+                                          float mz) {
+  return S.r_min[i] <= view_distance(v, mx, my, mz) * v.k;
+}
+
+// Clears the bitmask and the BFS level counts (level 0 holds the root alone).
+__global__ void __launch_bounds__(kBlock) k_cut_clear(uint32_t* bits, int64_t n_words, int32_t* level_count,
+                                                      int32_t n_levels) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t w = t0; w < n_words; w += stride) bits[w] = 0u;
+  if (level_count)
+    for (int64_t l = t0; l < n_levels; l += stride) level_count[l] = l == 0 ? 1 : 0;
+}
+
+// Eq. 5 per node: fine at its own distance while its parent is not (the root
+// has none); with culling, a node whose own sphere is outside the frustum is
+// dropped.  One wave per 64 nodes writes their two bitmask words.
+__global__ void __launch_bounds__(kBlock) k_parallel_cut(SceneDev S, const ViewConst* __restrict__ vp, uint32_t flags,
+                                                         uint32_t* bits) {
+  const ViewConst v = *vp;
+  const bool cull = (flags & LODGS_CULL) != 0;
+  const int lane = threadIdx.x & 63;
+  const int64_t n_waves = (S.n_nodes + 63) / 64;
+  for (int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < n_waves;
+       w += ((int64_t)gridDim.x * blockDim.x) >> 6) {  // wave-uniform
+    const int64_t i = w * 64 + lane;
+    bool sel = false;
+    if (i < S.n_nodes) {
+      const float mx = S.means[3 * i], my = S.means[3 * i + 1], mz = S.means[3 * i + 2];
+      sel = node_fine(S, v, i, mx, my, mz);
+      if (sel) {
+        const int64_t p = S.parent[i];
+        if (p >= 0 && p < S.n_nodes)
+          sel = !node_fine(S, v, p, S.means[3 * p], S.means[3 * p + 1], S.means[3 * p + 2]);
+      }
+      if (sel && cull) sel = !sphere_culled(v, mx, my, mz, S.rho[i]);
+    }
+    const uint64_t b = __ballot(sel);
+    if (lane == 0) reinterpret_cast<uint2*>(bits)[w] = make_uint2((uint32_t)b, (uint32_t)(b >> 32));
+  }
+}
+
+// One BFS level: every frontier node is dropped when culled, marked when fine
+// at its own distance, else its two children join the next frontier (one
+// atomic per wave for their slots).  Level 0 is the root, position 0.  Counts stay even past the root's level,
+// and fcap is even, so a pair of children is written whole or not at all; a
+// full queue records LODGS_E_CAPACITY and the next level reads only what was
+// written.
+__global__ void __launch_bounds__(kBlock) k_bfs_level(SceneDev S, const ViewConst* __restrict__ vp, uint32_t flags,
+                                                      int32_t level, const int32_t* fin, int32_t* fout,
+                                                      int32_t* level_count, int64_t fcap, uint32_t* bits,
+                                                      FrameCounters* ctr) {
+  const ViewConst v = *vp;
+  const bool cull = (flags & LODGS_CULL) != 0;
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lanemask_lt();
+  int64_t n_in = level_count[level];
+  n_in = level == 0 ? 1 : (n_in < fcap ? n_in : fcap);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < n_in; t0 += stride) {
+    const int64_t t = t0 + lane;  // t0 is wave-aligned: the loop is wave-uniform
+    bool push = false;
+    int2 ch = make_int2(-1, -1);
+    if (t < n_in) {
+      const int64_t u = level == 0 ? 0 : fin[t];
+      if (u >= 0 && u < S.n_nodes) {
+        const float mx = S.means[3 * u], my = S.means[3 * u + 1], mz = S.means[3 * u + 2];
+        if (!(cull && sphere_culled(v, mx, my, mz, S.rho[u]))) {
+          if (node_fine(S, v, u, mx, my, mz)) {
+            atomicOr(&bits[u >> 5], 1u << (u & 31));
+          } else {
+            ch = S.child[u];
+            push = ch.x >= 0 && ch.x < S.n_nodes && ch.y >= 0 && ch.y < S.n_nodes;
+          }
+        }
+      }
+    }
+    const uint64_t pb = __ballot(push);
+    if (pb) {
+      uint32_t base = 0;
+      if (lane == 0) base = (uint32_t)atomicAdd(&level_count[level + 1], 2 * __popcll(pb));
+      base = __shfl(base, 0, 64);
+      if (push) {
+        const int64_t pos = (int64_t)base + 2 * __popcll(pb & lt);
+        if (pos < fcap) {
+          fout[pos] = ch.x;
+          fout[pos + 1] = ch.y;
+        } else {
+          ctr->status = LODGS_E_CAPACITY;
+        }
+      }
+    }
+  }
+}
+
+struct LoadPopc {
+  const uint32_t* bits;
+  __device__ uint32_t operator()(int64_t w) const { return (uint32_t)__popc(bits[w]); }
+};
+
+// Word w's set bits, lowest first, at idx[prefix ...].
+struct StoreBits {
+  const uint32_t* bits;
+  int32_t* idx;
+  int64_t cap;
+  __device__ void operator()(int64_t w, uint32_t prefix, uint32_t) const {
+    uint32_t b = bits[w];
+    int64_t p = prefix;
+    while (b) {
+      const int k = __ffs(b) - 1;
+      b &= b - 1u;
+      if (p < cap) idx[p] = (int32_t)(w * 32 + k);
+      ++p;
+    }
+  }
+};
+
+// The count, the capacity check and, for the BFS, the depth check: a
+// frontier left after the last level means the hierarchy is deeper than its
+// stated height.
+__global__ void k_cut_finish(FrameCounters* ctr, int32_t* d_count, int64_t capacity, const int32_t* level_count,
+                             int32_t height) {
+  const int32_t n = ctr->n_selected;
+  *d_count = n;
+  if ((int64_t)n > capacity) ctr->status = LODGS_E_CAPACITY;
+  if (level_count && level_count[height] > 0) ctr->status = LODGS_E_INVALID;
+}
+
+}  // namespace
+
+void launch_select_full(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
+                        int32_t* d_count, hipStream_t st) {
+  const SceneDev& S = f->scene->dev;
+  const bool bfs = (flags & LODGS_CUT_BFS) != 0;
+  const int64_t n_words = cut_bit_words(S.n_nodes);
+  stage_begin(f, LODGS_STAGE_SELECT, st);
+  launch_set_view(v, f->d_view_sel, f->ctr, kViewSelect, nullptr, 0, st);
+  int cgrid = (int)((n_words + kBlock - 1) / kBlock);
+  cgrid = cgrid < 1 ? 1 : (cgrid > 2048 ? 2048 : cgrid);
+  hipLaunchKernelGGL(k_cut_clear, dim3(cgrid), dim3(kBlock), 0, st, f->cut_bits, n_words,
+                     bfs ? f->level_count : (int32_t*)nullptr, f->cut_height + 1);
+  if (bfs) {
+    const int64_t fcap = f->caps.max_selected & ~(int64_t)1;
+    for (int32_t l = 0; l < f->cut_height; ++l)
+      hipLaunchKernelGGL(k_bfs_level, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_sel, flags, l,
+                         f->frontier[l & 1], f->frontier[(l + 1) & 1], f->level_count, fcap, f->cut_bits, f->ctr);
+  } else {
+    int pgrid = (int)((S.n_nodes + kBlock - 1) / kBlock);
+    pgrid = pgrid < 1 ? 1 : (pgrid > 8192 ? 8192 : pgrid);
+    hipLaunchKernelGGL(k_parallel_cut, dim3(pgrid), dim3(kBlock), 0, st, S, f->d_view_sel, flags, f->cut_bits);
+  }
+  scan_exclusive(LoadPopc{f->cut_bits}, &f->ctr->n_bit_words, n_words, f->block_sums,
+                 StoreBits{f->cut_bits, d_idx, capacity}, &f->ctr->n_selected, st);
+  hipLaunchKernelGGL(k_cut_finish, dim3(1), dim3(1), 0, st, f->ctr, d_count, capacity,
+                     bfs ? (const int32_t*)f->level_count : (const int32_t*)nullptr, f->cut_height);
+  stage_end(f, st);
+}
+
 }  // namespace lodgs

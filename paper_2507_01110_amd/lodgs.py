@@ -116,6 +116,33 @@ class Scene:
     def param_bytes(self) -> int:
         return sum(t.numel() * t.element_size() for t in self.params.values())
 
+    def attach_hierarchy(self, tree):
+        """Uploads the whole hierarchy (parent and two children per layout
+        position) for the comparator cuts, BFS and Eq. 5's parallel cut
+        (lodgs_scene_set_hierarchy); frames created afterwards can run them."""
+        n = self.n_nodes
+        perm = self.perm.astype(np.int64)
+        pos = np.empty(n, np.int32)
+        pos[perm] = np.arange(n, dtype=np.int32)
+
+        def at(a):  # tree ids -> layout positions, -1 kept, rows in layout order
+            a = np.take(np.asarray(a), perm)
+            return np.where(a >= 0, pos[np.maximum(a, 0)], -1).astype(np.int32)
+
+        parent = at(tree.parent)
+        parent[pos[tree.root]] = -1
+        child = np.stack([at(tree.left), at(tree.right)], axis=1)
+        height, front = 0, np.array([tree.root], np.int64)
+        while front.size:
+            height += 1
+            front = front[tree.left[front] >= 0]
+            front = np.concatenate([tree.left[front], tree.right[front]]).astype(np.int64)
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(self.device)
+        self.hierarchy = {"parent": dev(parent), "child": dev(child), "height": height}
+        check(_lib.load().lodgs_scene_set_hierarchy(self._h, _ptr(self.hierarchy["parent"]),
+                                                    _ptr(self.hierarchy["child"]), height),
+              "lodgs_scene_set_hierarchy")
+
 
 class Frame:
     """Device workspace of one view in flight (lodgs_frame)."""
@@ -137,11 +164,16 @@ class Frame:
             _lib._lib.lodgs_frame_destroy(h)
             self._h = None
 
-    def lod_select(self, cam, tau: float, cull: bool = True, conservative: bool = False, stream=None):
+    def lod_select(self, cam, tau: float, cull: bool = True, conservative: bool = False, method: str = "hspt",
+                   stream=None):
         """Runs the cut into self.idx / self.count (device); returns them.
-        conservative: cut each SPT at max(0, d - R) tau / fx (LODGS_CONSERVATIVE)."""
+        conservative: cut each SPT at max(0, d - R) tau / fx (LODGS_CONSERVATIVE).
+        method: "hspt" (the HSPT cut), or the whole-hierarchy comparators "bfs"
+        and "parallel" (Eq. 5), which need Scene.attach_hierarchy before the
+        frame was created."""
         c = camera_struct(cam)
         flags = (_lib.CULL if cull else 0) | (_lib.CONSERVATIVE if conservative else 0)
+        flags |= {"hspt": 0, "bfs": _lib.CUT_BFS, "parallel": _lib.CUT_PARALLEL}[method]
         check(_lib.load().lodgs_lod_select(self._h, ctypes.byref(c), float(tau), flags,
                                            _ptr(self.idx), self.idx.numel(), _ptr(self.count), _stream(stream)),
               "lodgs_lod_select")

@@ -1,7 +1,9 @@
 """GPU parity at the full city size: 50M leaves (100M nodes, 23.6 GB of
 parameters), 1920x1080 views of the aerial-to-street path, in the frame
 configuration the benchmark times (selection capacity 2^24, instance capacity
-2^27, the default blend layouts, node-gradient accumulation).  Whole views
+2^27, the default blend layouts, node-gradient accumulation).  The
+CONSERVATIVE cut and the whole-hierarchy comparator cuts (BFS, Eq. 5) of the
+same views are compared bit for bit too.  Whole views
 are compared with the oracle: the selected index set and the instance order
 bit-exact, pixels within 1e-4 max-abs, accumulated node gradients within 1e-3
 relative L2 per parameter group, every node outside the selection untouched.
@@ -51,6 +53,9 @@ def city():
             e = min(S.n_nodes, c + (1 << 23))
             assert np.array_equal(d[c:e].cpu().numpy(), np.take(a, perm[c:e], axis=0)), (k, c)
     _say("city: device parameters checked")
+    t0 = time.time()
+    S.attach_hierarchy(tree)
+    _say(f"city: hierarchy attached (height {S.hierarchy['height']}) in {time.time() - t0:.1f} s")
     t0 = time.time()
     O = oracle.OracleScene(tree)
     _say(f"city: oracle set up in {time.time() - t0:.1f} s")
@@ -112,3 +117,11 @@ def test_city_views_select_render_backward(city):
         ids_c, _ = O.select(cam, tau, conservative=True)
         assert np.array_equal(idx[:nc].cpu().numpy(), O.pos_of[ids_c]), (nc, len(ids_c))
         _say(f"  conservative cut: {nc} selected (default {n})")
+        # the whole-hierarchy comparator cuts of the same view
+        for method in ("bfs", "parallel"):
+            idx, cnt = f.lod_select(cam, tau, method=method)
+            nm = int(cnt.item())
+            assert f.stats()["status"] == 0
+            want = O.pos_of[O.select_full(cam, tau, method)]
+            assert np.array_equal(idx[:nm].cpu().numpy(), want), (method, nm, len(want))
+            _say(f"  {method} cut: {nm} selected")

@@ -187,6 +187,80 @@ def test_select_capacity_overflow_is_reported(torch_cuda):
     assert f.stats()["status"] == 0
 
 
+# The whole-hierarchy comparator cuts (Sec. 4.3: BFS, and the parallel cut of
+# Eq. 5), every node at its own distance.
+
+def _check_full_cut(O, frame, cam, tau, method, cull):
+    want = O.pos_of[O.select_full(cam, tau, method, cull=cull)]
+    idx, cnt = frame.lod_select(cam, tau, cull=cull, method=method)
+    st = frame.stats()
+    n = int(cnt.item())
+    assert st["status"] == 0 and st["n_selected"] == n
+    assert np.array_equal(idx[:n].cpu().numpy(), want), (method, len(want), n)
+    return n
+
+
+def test_comparator_cuts_bitexact(torch_cuda):
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    S.attach_hierarchy(tree)
+    for cam in (configs.tiny_camera(), scenegen.camera_look_at((25, -8, 6), (3, 2, 0), (0, 0, 1), 320, 200)):
+        f = _frame(S, cam)
+        for cull in (True, False):
+            for tau in (0.25, 1.0, 4.0, 16.0, 64.0):
+                _say("comparator cuts tiny", cull, tau, cam.width)
+                nb = _check_full_cut(O, f, cam, tau, "bfs", cull)
+                npar = _check_full_cut(O, f, cam, tau, "parallel", cull)
+                assert npar >= nb
+    # random trees break the heap condition; caterpillars are 300 levels deep
+    rng = np.random.default_rng(28)
+    trees = [random_tree(rng, int(rng.integers(1, 65))) for _ in range(20)] + [caterpillar_tree(rng, 300)]
+    for it, tree in enumerate(trees):
+        O = oracle.OracleScene(tree)
+        S = _scene(tree)
+        S.attach_hierarchy(tree)
+        pos = rng.uniform(-30, 30, 3)
+        cam = scenegen.camera_look_at(pos, rng.uniform(-10, 10, 3), (0, 0, 1) if abs(pos[2]) < 25 else (0, 1, 0),
+                                      64, 48)
+        f = _frame(S, cam)
+        _say("comparator cuts random tree", it, tree.n_nodes, S.hierarchy["height"])
+        for tau in (0.1, 1.0, 10.0, 100.0):
+            for method in ("bfs", "parallel"):
+                _check_full_cut(O, f, cam, tau, method, cull=bool(it % 2))
+
+
+def test_comparator_cuts_need_the_hierarchy_and_report_overflow(torch_cuda):
+    from paper_2507_01110_amd import _lib
+    from paper_2507_01110_amd.lodgs import Frame
+    tree = scenegen.build_tree(configs.tiny_spec())
+    S = _scene(tree)
+    cam = configs.tiny_camera()
+    before = _frame(S, cam)
+    with pytest.raises(_lib.LodgsError) as e:
+        before.lod_select(cam, 1.0, method="bfs")
+    assert e.value.code == -5
+    S.attach_hierarchy(tree)
+    with pytest.raises(_lib.LodgsError) as e:
+        _frame(S, cam).lod_select(cam, 1.0, conservative=True, method="parallel")
+    assert e.value.code == -1
+    # a frontier or an output longer than max_selected
+    for method in ("bfs", "parallel"):
+        f = Frame(S, 100, 1 << 16, cam.width, cam.height)
+        idx, cnt = f.lod_select(cam, 1.0, method=method)
+        assert f.stats()["status"] == -2, method
+        f.clear_status()
+        assert f.stats()["status"] == 0
+    # a stated height below the hierarchy's: a frontier is left after the last pass
+    H = S.hierarchy
+    _lib.check(_lib.load().lodgs_scene_set_hierarchy(S._h, H["parent"].data_ptr(), H["child"].data_ptr(), 3), "set")
+    f = _frame(S, cam)
+    f.lod_select(cam, 1.0, method="bfs")
+    assert f.stats()["status"] == -1
+    with pytest.raises(_lib.LodgsError):
+        _lib.check(_lib.load().lodgs_scene_set_hierarchy(S._h, H["child"].data_ptr(), H["child"].data_ptr(), 30), "x")
+
+
 def _render_pair(tree, O, S, cam, tau, bg=(0.0, 0.0, 0.0)):
     import torch
     frame = _frame(S, cam)
@@ -432,3 +506,14 @@ def test_medium_view_select_render_backward(medium):
     img = frame.render(cam)
     err = _check_image(img, F)
     _say("  medium max abs err", err, frame.stats())
+
+
+def test_medium_view_comparator_cuts(medium):
+    tree, O, S = medium
+    S.attach_hierarchy(tree)
+    cam = configs.medium_camera()
+    f = _frame(S, cam, max_inst=1 << 20)
+    for tau in (0.5, 1.0, 4.0):
+        for method in ("bfs", "parallel"):
+            n = _check_full_cut(O, f, cam, tau, method, cull=True)
+            _say("  medium", method, tau, n)

@@ -287,3 +287,113 @@ def test_conservative_cut_takes_the_leaves_of_an_spt_whose_radius_holds_the_came
         ids = S.select(cam, 1e4, cull=False, conservative=True)[0]
         assert sorted(ids.tolist()) == list(range(t.n_leaves))
         assert len(S.select(cam, 1e4, cull=False)[0]) < t.n_leaves
+
+
+# The whole-hierarchy comparator cuts the HSPT replaces (Sec. 4.3): the BFS
+# cut and the parallel cut of Eq. 5, every node at its own distance.
+
+def _depths(t):
+    d = np.zeros(t.n_nodes, np.int64)
+    st = [t.root]
+    while st:
+        u = st.pop()
+        if t.left[u] >= 0:
+            for c in (t.left[u], t.right[u]):
+                d[c] = d[u] + 1
+                st.append(c)
+    return d
+
+
+def _heap_tree(rng, n_leaves):
+    """Every node at one point, and each child smaller than its parent along
+    every axis: fineness at any camera passes from a parent to its children,
+    and the cull spheres are nested."""
+    t = random_tree(rng, n_leaves)
+    t.means[:] = t.means[t.root]
+    d = _depths(t)
+    t.log_scales[:] = (0.5 - 0.3 * d[:, None] + rng.uniform(0.0, 0.1, (t.n_nodes, 3))).astype(np.float32)
+    return t
+
+
+@pytest.mark.parametrize("cull", [False, True])
+def test_bfs_cut_equals_the_hspt_cut_when_every_interior_node_is_upper(cull):
+    # with the SPTs reduced to single leaves the HSPT cut is Alg. 1 over the
+    # whole hierarchy, culling included
+    rng = np.random.default_rng(41)
+    for _ in range(60):
+        t = random_tree(rng, int(rng.integers(1, 65)), log_threshold=-math.inf)
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 2)))
+        assert np.array_equal(S.select_full(cam, tau, "bfs", cull=cull), S.select(cam, tau, cull=cull)[0])
+
+
+def test_bfs_cut_matches_the_python_queue_reference_and_is_proper():
+    rng = np.random.default_rng(42)
+    for _ in range(80):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 2)))
+        g = g64(t)
+        k = tau / cam.fx
+        pos = cam.pos.astype(np.float64)
+        cond = lambda u: t.left[u] < 0 or g[u] <= np.linalg.norm(t.means[u].astype(np.float64) - pos) * k
+        ids = S.select_full(cam, tau, "bfs", cull=False)
+        assert sorted(ids.tolist()) == sorted(bfs_cut(t, cond))
+        _check_proper_and_covering(t, ids)
+        assert np.all(np.diff(S.pos_of[ids]) > 0)
+
+
+@pytest.mark.parametrize("cull", [False, True])
+def test_every_bfs_node_passes_eq5_so_the_parallel_cut_contains_the_bfs_cut(cull):
+    # a BFS-selected node is fine and was reached through a parent that was not
+    rng = np.random.default_rng(43)
+    larger = 0
+    for _ in range(80):
+        t = random_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 2)))
+        b = set(S.select_full(cam, tau, "bfs", cull=cull).tolist())
+        p = S.select_full(cam, tau, "parallel", cull=cull)
+        assert b <= set(p.tolist())
+        assert np.all(np.diff(S.pos_of[p]) > 0)
+        larger += len(p) > len(b)
+    assert larger > 0  # random trees break the heap condition
+
+
+@pytest.mark.parametrize("cull", [False, True])
+def test_parallel_cut_equals_the_bfs_cut_under_the_heap_condition(cull):
+    rng = np.random.default_rng(44)
+    for _ in range(60):
+        t = _heap_tree(rng, int(rng.integers(1, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 3)))
+        p = S.select_full(cam, tau, "parallel", cull=cull)
+        assert np.array_equal(p, S.select_full(cam, tau, "bfs", cull=cull))
+        if not cull:
+            _check_proper_and_covering(t, p)
+
+
+def test_parallel_cut_selects_an_ancestor_and_its_descendants_when_a_child_outgrows_its_parent():
+    # root R (g 1) with children A (g 3, above the threshold) and leaf B; A's
+    # children are the leaves L1, L2; all at one point, X = 2: R is fine as the
+    # root, A is not, so L1 and L2 pass Eq. 5 too: R and its grandchildren
+    # are both selected, while the BFS stops at R
+    import scenegen
+    left = np.array([-1, -1, -1, 0, 3], np.int32)   # 0 L1, 1 L2, 2 B, 3 A, 4 R
+    right = np.array([-1, -1, -1, 1, 2], np.int32)
+    parent = np.array([3, 3, 4, 4, -1], np.int32)
+    g_want = {3: 3.0, 4: 1.0}
+    ls = np.full((5, 3), -3.0)
+    for v, gv in g_want.items():  # isotropic: g = sqrt(3) s
+        ls[v] = math.log(gv / math.sqrt(3.0))
+    t = scenegen.tree_from_arrays(np.zeros((5, 3)), ls, np.tile([1.0, 0, 0, 0], (5, 1)), np.zeros(5),
+                                  np.zeros((5, 4, 3)), left, right, parent, 4, -math.inf, 1)
+    S = oracle.OracleScene(t)
+    cam = scenegen.camera_look_at((0.0, 0.0, -10.0), (0.0, 0.0, 0.0), (0, 1, 0), 64, 48)
+    tau = float(np.float32(2.0 / 10.0 * cam.fx))  # X = 2 at distance 10
+    assert sorted(S.select_full(cam, tau, "parallel", cull=False).tolist()) == [0, 1, 4]
+    assert S.select_full(cam, tau, "bfs", cull=False).tolist() == [4]
