@@ -321,6 +321,9 @@ def main():
                     help="cut each SPT at max(0, d - R) tau / fx (the CONSERVATIVE variant) instead of d tau / fx")
     ap.add_argument("--cut", choices=["hspt", "bfs", "parallel"], default="hspt",
                     help="LoD cut: the HSPT cut, or a whole-hierarchy comparator (BFS, Eq. 5's parallel cut)")
+    ap.add_argument("--adam", action="store_true",
+                    help="training iteration: backward into selection-indexed gradients, then the cut-set Adam "
+                         "step (instead of accumulating node gradients)")
     ap.add_argument("--leaves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--targets", type=int, default=8, help="distinct seeded targets resident in HBM")
@@ -346,7 +349,7 @@ def main():
     import numpy as np
     import torch
     import scenegen
-    from paper_2507_01110_amd.lodgs import Frame, Scene, camera_struct
+    from paper_2507_01110_amd.lodgs import AdamCut, Frame, Scene, camera_struct
 
     torch.cuda.set_device(0)
     if args.workload == "ultra":
@@ -413,7 +416,12 @@ def main():
         f"mean instances {np.mean([c['n_instances'] for c in counts]):.0f}")
 
     targets = [torch.from_numpy(scenegen.target_image(H, W, 202 + k)).cuda() for k in range(args.targets)]
-    grads = {k: torch.zeros_like(v) for k, v in scene.params.items()}
+    if args.adam:
+        opt = AdamCut(scene.params, tree.sh_degree)
+        sel = {k: torch.zeros((cap_sel,) + tuple(v.shape[1:]), dtype=torch.float32, device="cuda")
+               for k, v in scene.params.items()}
+    else:
+        grads = {k: torch.zeros_like(v) for k, v in scene.params.items()}
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     dL = torch.empty_like(img)
 
@@ -424,7 +432,11 @@ def main():
         frame.lod_select(cam, tau, conservative=args.conservative, method=args.cut)
         frame.render(cam, out=img)
         frame.l1_loss(img, targets[seq[i % K] % len(targets)], grad=dL)
-        frame.backward(dL, nodes=grads)
+        if args.adam:
+            frame.backward(dL, sel=sel)
+            opt.step(sel, frame.idx, frame.count)
+        else:
+            frame.backward(dL, nodes=grads)
 
     for i in range(args.warmup):
         step(i)
@@ -505,7 +517,8 @@ def main():
                         "max": round(float(per_view.max()), 4)}, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic (seeded scene, cameras and targets)",
         "config": dict(desc, nodes=int(scene.n_nodes), upper_nodes=int(scene.n_upper), spts=int(scene.n_spt),
-                       views_timed=K, parallelism="none", cut="conservative" if args.conservative else ("default" if args.cut == "hspt" else args.cut)),
+                       views_timed=K, parallelism="none", cut="conservative" if args.conservative else ("default" if args.cut == "hspt" else args.cut),
+                       update="cut-set Adam" if args.adam else "node-gradient accumulation"),
         "hbm_fraction_whole_path": round(hbm_frac, 4),
         "algorithmic_GB_per_view": round(all_bytes / K / 1e9, 4),
         "stages": stages,

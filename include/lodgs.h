@@ -317,6 +317,34 @@ int lodgs_selftest_arith(const float* d_in32, const double* d_in64, int64_t n, f
 int lodgs_l1_loss(lodgs_frame* frame, const float* d_img, const float* d_target, int64_t n, float* d_grad,
                   float* d_loss, lodgs_stream stream);
 
+/* ---------------------------------------------------------------- optimiser
+ * Adam step on the cut set (init/training appendix: each view updates only
+ * the parameters of its cut set; the optimiser is the 3DGS one, Adam).  For
+ * every selected position i < min(*d_count, capacity) with node = d_idx[i] in
+ * [0, n_nodes), and every parameter group whose member of params is not NULL
+ * (widths 3, 3, 4, 1 and 3 (sh_degree + 1)^2), element by element with
+ * g = grads.<group>[i][c] (selection-indexed: the sel output of
+ * lodgs_render_backward) and p, m, v the node's elements in params, exp_avg
+ * and exp_avg_sq (node-indexed, the parameters' layouts):
+ *   m = beta1 m + (1 - beta1) g,   v = beta2 v + (1 - beta2) g^2,
+ *   p = p - lr / (1 - beta1^step) * m / (sqrt(v) / sqrt(1 - beta2^step) + eps).
+ * step >= 1 counts the optimiser's steps (one count for all nodes).  d_idx must
+ * not repeat a node (lodgs_lod_select's output does not); nodes outside
+ * [0, n_nodes) are skipped.  All arrays are device arrays; FP32 throughout.
+ * Errors: LODGS_E_INVALID (a NULL grads / exp_avg / exp_avg_sq member where
+ * the params member is set, step < 1, a beta outside [0, 1), eps < 0,
+ * sh_degree outside 0..3). */
+typedef struct lodgs_adam {
+  float lr[5]; /* per group: means, log_scales, quats, opacity_logits, sh */
+  float beta1, beta2, eps;
+  int32_t step;
+  int32_t sh_degree;
+} lodgs_adam;
+
+int lodgs_adam_cut(const lodgs_grads* params, const lodgs_grads* grads, const lodgs_grads* exp_avg,
+                   const lodgs_grads* exp_avg_sq, const lodgs_adam* hp, const int32_t* d_idx, const int32_t* d_count,
+                   int64_t capacity, int64_t n_nodes, lodgs_stream stream);
+
 const char* lodgs_last_error(void);
 
 #ifdef __cplusplus

@@ -292,3 +292,21 @@ def l1_loss_grad(image: np.ndarray, target: np.ndarray):
     """L = mean |C - target| over H*W*3; dL/dC = sign(C - target) / (3 H W), sign(0) = 0."""
     d = image.astype(np.float64) - target.astype(np.float64)
     return float(np.abs(d).mean()), np.sign(d) / d.size
+
+
+def adam_cut(p, m, v, grads, idx, lr, beta1, beta2, eps, step):
+    """Adam (Kingma and Ba, Algorithm 1) applied to the rows idx of node-indexed
+    arrays p, m, v: the cut-set update of the init/training appendix (only the
+    nodes of the view's cut are touched).  grads[i] is the gradient of node
+    idx[i]; step t >= 1 is the optimiser's step count, used for the bias
+    corrections m / (1 - beta1^t) and v / (1 - beta2^t).  FP64; returns the
+    new (p, m, v)."""
+    p, m, v = (np.array(a, np.float64) for a in (p, m, v))
+    g = np.asarray(grads, np.float64)
+    for i, node in enumerate(np.asarray(idx).tolist()):
+        m[node] = beta1 * m[node] + (1.0 - beta1) * g[i]
+        v[node] = beta2 * v[node] + (1.0 - beta2) * g[i] * g[i]
+        m_hat = m[node] / (1.0 - beta1 ** step)
+        v_hat = v[node] / (1.0 - beta2 ** step)
+        p[node] = p[node] - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return p, m, v

@@ -40,6 +40,10 @@ class Grads(ctypes.Structure):
                 ("d_sh", c_p)]
 
 
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", f32 * 5), ("beta1", f32), ("beta2", f32), ("eps", f32), ("step", i32), ("sh_degree", i32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("status", i32), ("n_selected", i32), ("n_upper_selected", i32), ("n_spt_visible", i32),
                 ("n_spt_candidates", i64), ("n_rendered", i32), ("n_drawn", i32), ("n_instances", i64)]
@@ -82,6 +86,7 @@ EXPORTS = {
                                   ctypes.POINTER(c_p)], ctypes.c_int),
     "lodgs_graph_launch": ([c_p, ctypes.POINTER(Camera), f32, c_p], ctypes.c_int),
     "lodgs_graph_destroy": ([c_p], None),
+    "lodgs_adam_cut": ([ctypes.POINTER(Grads)] * 4 + [ctypes.POINTER(Adam), c_p, c_p, i64, i64, c_p], ctypes.c_int),
     "lodgs_last_error": ([], ctypes.c_char_p),
 }
 

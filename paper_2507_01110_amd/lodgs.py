@@ -144,6 +144,39 @@ class Scene:
               "lodgs_scene_set_hierarchy")
 
 
+GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+class AdamCut:
+    """Adam on the cut set (lodgs_adam_cut): node-indexed first and second
+    moments beside each parameter group; step() updates the rows of the
+    selected nodes from selection-indexed gradients (the sel output of
+    Frame.backward).  lr: per-group learning rates (3DGS's defaults, one rate
+    for all SH coefficients)."""
+
+    DEFAULT_LR = {"means": 1.6e-4, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+
+    def __init__(self, params: dict, sh_degree: int, lr: dict | None = None, betas=(0.9, 0.999), eps=1e-15):
+        self.params = params
+        self.sh_degree = int(sh_degree)
+        self.lr = dict(self.DEFAULT_LR, **(lr or {}))
+        self.betas, self.eps = betas, eps
+        self.exp_avg = {k: torch.zeros_like(v) for k, v in params.items()}
+        self.exp_avg_sq = {k: torch.zeros_like(v) for k, v in params.items()}
+        self.step_count = 0
+
+    def step(self, grads: dict, idx, count, stream=None):
+        self.step_count += 1
+        g = lambda d: _lib.Grads(*[_ptr(d.get(k)) if k in self.params else None for k in GROUPS])
+        hp = _lib.Adam((ctypes.c_float * 5)(*[float(self.lr[k]) for k in GROUPS]), float(self.betas[0]),
+                       float(self.betas[1]), float(self.eps), self.step_count, self.sh_degree)
+        n_nodes = next(iter(self.params.values())).shape[0]
+        check(_lib.load().lodgs_adam_cut(ctypes.byref(g(self.params)), ctypes.byref(g(grads)),
+                                         ctypes.byref(g(self.exp_avg)), ctypes.byref(g(self.exp_avg_sq)),
+                                         ctypes.byref(hp), _ptr(idx), _ptr(count), int(idx.numel()), int(n_nodes),
+                                         _stream(stream)), "lodgs_adam_cut")
+
+
 class Frame:
     """Device workspace of one view in flight (lodgs_frame)."""
 
