@@ -218,7 +218,9 @@ typedef struct lodgs_grads {
  *   sel (optional):   written for positions i < count: gradient of node
  *                     d_idx[i] (zero for nodes that were not drawn);
  *   nodes (optional): accumulated (+=) into node-indexed arrays at d_idx[i].
- * Returns LODGS_E_STATE if the frame has not rendered. */
+ * The d_sh members must be 16-byte aligned (rows move as float4s).
+ * Returns LODGS_E_STATE if the frame has not rendered, LODGS_E_INVALID for a
+ * misaligned d_sh. */
 int lodgs_render_backward(lodgs_frame* frame, const float* d_dL_drgb, const lodgs_grads* sel,
                           const lodgs_grads* nodes, lodgs_stream stream);
 
@@ -331,8 +333,10 @@ int lodgs_l1_loss(lodgs_frame* frame, const float* d_img, const float* d_target,
  * step >= 1 counts the optimiser's steps (one count for all nodes).  d_idx must
  * not repeat a node (lodgs_lod_select's output does not); nodes outside
  * [0, n_nodes) are skipped.  All arrays are device arrays; FP32 throughout.
- * Errors: LODGS_E_INVALID (a NULL grads / exp_avg / exp_avg_sq member where
- * the params member is set, step < 1, a beta outside [0, 1), eps < 0,
+ * The quaternion and SH arrays (rows of 4 and 12 or 48 floats, which move as
+ * float4s) must be 16-byte aligned.  Errors: LODGS_E_INVALID (a NULL grads /
+ * exp_avg / exp_avg_sq member where the params member is set, a misaligned
+ * quaternion or SH array, step < 1, a beta outside [0, 1), eps < 0,
  * sh_degree outside 0..3). */
 typedef struct lodgs_adam {
   float lr[5]; /* per group: means, log_scales, quats, opacity_logits, sh */

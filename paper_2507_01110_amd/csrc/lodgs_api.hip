@@ -377,6 +377,8 @@ int lodgs_render_backward(lodgs_frame* f, const float* d_dL_drgb, const lodgs_gr
                           lodgs_stream stream) {
   if (!f || !d_dL_drgb) return set_error(LODGS_E_INVALID, "lodgs_render_backward: null argument");
   if (!f->rendered) return set_error(LODGS_E_STATE, "lodgs_render_backward: no render on this frame");
+  if ((sel && (reinterpret_cast<uintptr_t>(sel->d_sh) & 15u)) || (nodes && (reinterpret_cast<uintptr_t>(nodes->d_sh) & 15u)))
+    return set_error(LODGS_E_INVALID, "lodgs_render_backward: SH gradient arrays must be 16-byte aligned");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   lodgs::launch_backward(f, d_dL_drgb, sel, nodes, st);
   hipError_t e = hipGetLastError();

@@ -294,15 +294,18 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
 // Projection backward, FP64 (per splat): the forward chain is replayed and the
 // 2D gradients (mean2D, conic, opacity, colour) are carried to the raw
 // parameters.
-// Zeroes the per-selection gradient rows (splats that were not drawn keep 0).
+// Zeroes the per-selection gradient rows (splats that were not drawn keep 0):
+// each group's rows [0, n_render) are one contiguous span, cleared with
+// consecutive lanes on consecutive words.
 __global__ void __launch_bounds__(kBlock) k_zero_sel(const FrameCounters* ctr, int nc, lodgs_grads sel) {
   const int64_t n = ctr->n_render;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    if (sel.d_means) for (int k = 0; k < 3; ++k) sel.d_means[3 * i + k] = 0.0f;
-    if (sel.d_log_scales) for (int k = 0; k < 3; ++k) sel.d_log_scales[3 * i + k] = 0.0f;
-    if (sel.d_quats) for (int k = 0; k < 4; ++k) sel.d_quats[4 * i + k] = 0.0f;
-    if (sel.d_opacity_logits) sel.d_opacity_logits[i] = 0.0f;
-    if (sel.d_sh) for (int k = 0; k < nc; ++k) sel.d_sh[(int64_t)nc * i + k] = 0.0f;
+  float* const arr[5] = {sel.d_means, sel.d_log_scales, sel.d_quats, sel.d_opacity_logits, sel.d_sh};
+  const int w[5] = {3, 3, 4, 1, nc};
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int g = 0; g < 5; ++g) {
+    float* a = arr[g];
+    if (!a) continue;
+    for (int64_t e = t0; e < n * w[g]; e += stride) a[e] = 0.0f;
   }
 }
 
@@ -528,7 +531,15 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
     const int64_t node = idx[i];
     const uint32_t clamp = splats[i].clamp;
     const float m0 = S.means[3 * node], m1 = S.means[3 * node + 1], m2 = S.means[3 * node + 2];
-    if (node_sh && sub < nb) {
+    // rows of 12 or 48 floats (degree 1 or 3) move as float4s: lane q takes
+    // floats 4q .. 4q + 3 of the row, coefficient f / 3 and channel f % 3 of
+    // float f; other degrees move one coefficient (3 floats) per lane
+    constexpr bool kVec = nc % 4 == 0;
+    constexpr int nq = nc / 4;
+    float4 acc4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (kVec) {
+      if (node_sh && sub < nq) acc4 = *reinterpret_cast<const float4*>(node_sh + (int64_t)nc * node + 4 * sub);
+    } else if (node_sh && sub < nb) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) acc3[c] = node_sh[(int64_t)nc * node + 3 * sub + c];
     }
@@ -537,9 +548,25 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
     const float dx = m0 - v.pos[0], dy = m1 - v.pos[1], dz = m2 - v.pos[2];
     const float il = 1.0f / __builtin_sqrtf(dx * dx + dy * dy + dz * dz);
     const float d0 = dx * il, d1 = dy * il, d2 = dz * il;
-    if (sub < nb) {
-      float Yk, dYk[3];
-      sh_basis_one(sub, d0, d1, d2, Yk, dYk);
+    float Yk = 0.0f, dYk[3];
+    if (sub < nb) sh_basis_one(sub, d0, d1, d2, Yk, dYk);
+    if (kVec) {
+      float gk[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {  // every lane of the row takes part in the shuffles
+        const int f = 4 * sub + t;
+        const int k = f / 3 < nb ? f / 3 : nb - 1, c = f - 3 * (f / 3);
+        const float Yf = __shfl(Yk, (lane & ~15) + k, 64);
+        gk[t] = (c == 0 ? dRGB[0] : (c == 1 ? dRGB[1] : dRGB[2])) * Yf;
+      }
+      if (sub < nq) {
+        if (sel_sh)
+          *reinterpret_cast<float4*>(sel_sh + (int64_t)nc * i + 4 * sub) = make_float4(gk[0], gk[1], gk[2], gk[3]);
+        if (node_sh)
+          *reinterpret_cast<float4*>(node_sh + (int64_t)nc * node + 4 * sub) =
+              make_float4(acc4.x + gk[0], acc4.y + gk[1], acc4.z + gk[2], acc4.w + gk[3]);
+      }
+    } else if (sub < nb) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float gk = dRGB[c] * Yk;
