@@ -324,6 +324,8 @@ def main():
     ap.add_argument("--adam", action="store_true",
                     help="training iteration: backward into selection-indexed gradients, then the cut-set Adam "
                          "step (instead of accumulating node gradients)")
+    ap.add_argument("--cache", type=str, default="",
+                    help="select through the SPT-cut cache: max_nodes,d_min,d_max,flush_every (e.g. 15000000,0.8,1.25,1000)")
     ap.add_argument("--leaves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--targets", type=int, default=8, help="distinct seeded targets resident in HBM")
@@ -349,7 +351,7 @@ def main():
     import numpy as np
     import torch
     import scenegen
-    from paper_2507_01110_amd.lodgs import AdamCut, Frame, Scene, camera_struct
+    from paper_2507_01110_amd.lodgs import AdamCut, CutCache, Frame, Scene, camera_struct
 
     torch.cuda.set_device(0)
     if args.workload == "ultra":
@@ -427,9 +429,17 @@ def main():
 
     cstructs = [camera_struct(c) for c, _ in views]
 
+    cache = None
+    if args.cache:
+        mx, dmin, dmax, fl = args.cache.split(",")
+        cache = CutCache(scene, int(mx), float(dmin), float(dmax), int(fl))
+
     def step(i):
         cam, tau = cstructs[seq[i % K]], views[seq[i % K]][1]
-        frame.lod_select(cam, tau, conservative=args.conservative, method=args.cut)
+        if cache is not None:
+            frame.lod_select(cam, tau, cache=cache)
+        else:
+            frame.lod_select(cam, tau, conservative=args.conservative, method=args.cut)
         frame.render(cam, out=img)
         frame.l1_loss(img, targets[seq[i % K] % len(targets)], grad=dL)
         if args.adam:
@@ -528,6 +538,9 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
     }
+    if cache is not None:
+        out["config"]["cut"] = "default through the SPT-cut cache " + args.cache
+        out["cut_cache"] = cache.stats()
     print(json.dumps(out), flush=True)
 
 

@@ -189,6 +189,45 @@ void lodgs_frame_destroy(lodgs_frame* frame);
 int lodgs_lod_select(lodgs_frame* frame, const lodgs_camera* cam, float tau, uint32_t flags, int32_t* d_idx,
                      int64_t capacity, int32_t* d_count, lodgs_stream stream);
 
+/* ---------------------------------------------------------------- SPT-cut cache
+ * The GPU cache of SPT cuts (Sec. 4.4 "Caching on the GPU", Eq. 7, and the
+ * training loop of Alg. 3).  Here the scene is resident, so a cache entry
+ * holds what decides the cut, the root distance d_c and the X_c an SPT was
+ * cut at, and its node count; a hit reuses the cached cut, which makes the
+ * level of detail depend on the cache state as the paper describes.
+ * Iteration t = 1, 2, ... of lodgs_lod_select_cached on a cache: when
+ * flush_every > 0 and t is a multiple of it, every entry is dropped first.  A
+ * visible SPT (reached and not culled) at root distance d (FP32, as the cut
+ * computes it) with an entry is a hit when d_min <= r * r <= d_max, r = d / d_c
+ * in FP32 (Alg. 3 compares squared ratios), and is cut at X_c; otherwise it
+ * is loaded: cut at X = d tau / fx like lodgs_lod_select, then entered with
+ * (d, X) and its number of selected nodes.  Every visible SPT's last use
+ * becomes t.  Then, oldest last use first (ties by SPT index), entries are
+ * dropped while the node counts of those left exceed max_nodes (the LRU
+ * write-back).  Flags: LODGS_CULL only.  One cache per scene; calls on one
+ * cache must be stream-ordered. */
+typedef struct lodgs_cut_cache_params {
+  int64_t max_nodes;   /* budget of cached SPT-cut nodes, >= 0 */
+  float d_min, d_max;  /* the window of squared distance ratios, 0 <= d_min <= d_max */
+  int32_t flush_every; /* drop everything at multiples of this iteration count (0: never) */
+} lodgs_cut_cache_params;
+
+typedef struct lodgs_cut_cache lodgs_cut_cache;
+
+typedef struct lodgs_cut_cache_stats {
+  int64_t iterations, hits, loads, evictions; /* totals since creation */
+  int64_t cached_spts, cached_nodes;          /* entries now */
+} lodgs_cut_cache_stats;
+
+int lodgs_cut_cache_create(const lodgs_scene* scene, const lodgs_cut_cache_params* params, lodgs_cut_cache** out);
+void lodgs_cut_cache_destroy(lodgs_cut_cache* cache);
+/* lodgs_lod_select through the cache (same output contract).  The frame must
+ * belong to the cache's scene. */
+int lodgs_lod_select_cached(lodgs_frame* frame, lodgs_cut_cache* cache, const lodgs_camera* cam, float tau,
+                            uint32_t flags, int32_t* d_idx, int64_t capacity, int32_t* d_count, lodgs_stream stream);
+/* Blocks on the stream. */
+int lodgs_cut_cache_stats_read(lodgs_cut_cache* cache, lodgs_cut_cache_stats* out, lodgs_stream stream);
+
 /* render (Sec. 3, Eq. 1 front-to-back compositing with Eq. 2 alpha over the
  * EWA projection; the rasterizer conventions the paper reuses): projects the
  * d_idx[0 .. *d_count) nodes (count clamped to the frame's max_selected),

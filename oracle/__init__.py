@@ -69,7 +69,7 @@ def lib():
         L.orc_layout.argtypes = [i64, P, P, i32, P, P, P, P, P, P, P, P, P]
         L.orc_layout.restype = ctypes.c_int
         L.orc_select.argtypes = [i64, P, P, i32, P, P, P, P, P, P, P, P, ctypes.POINTER(OrcCamera), f32,
-                                 ctypes.c_uint32, ctypes.c_int, P, i64, P, ctypes.POINTER(SelectStats)]
+                                 ctypes.c_uint32, ctypes.c_int, P, i64, P, ctypes.POINTER(SelectStats), P, P]
         L.orc_select.restype = ctypes.c_int
         for name in ("orc_select_bfs", "orc_select_parallel"):
             fn = getattr(L, name)
@@ -166,8 +166,11 @@ class OracleScene:
         self.n_upper, self.n_spt = nu.value, ns.value
         self.spt_begin = self.spt_begin[: self.n_spt + 1].copy()
 
-    def select(self, cam, tau: float, cull: bool = True, mode: int = 0, conservative: bool = False):
-        """Tree ids of the cut, in layout order, and the decision statistics."""
+    def select(self, cam, tau: float, cull: bool = True, mode: int = 0, conservative: bool = False,
+               spt_X: np.ndarray | None = None, spt_visible: np.ndarray | None = None):
+        """Tree ids of the cut, in layout order, and the decision statistics.
+        spt_X (float32 [n_nodes], NaN = own): X of the SPT rooted at each tree id;
+        spt_visible (uint8 [n_nodes]): receives 1 at the visible SPT roots."""
         t = self.tree
         n = t.n_nodes
         out = np.zeros(n, np.int32)
@@ -178,7 +181,8 @@ class OracleScene:
                               _p(self.role), _p(self.spt_of), _p(self.r_min), _p(self.r_max), _p(self.pos_of),
                               ctypes.byref(c), float(np.float32(tau)),
                               (CULL if cull else 0) | (CONSERVATIVE if conservative else 0), mode, _p(out), n,
-                              ctypes.byref(cnt), ctypes.byref(st))
+                              ctypes.byref(cnt), ctypes.byref(st),
+                              None if spt_X is None else _p(spt_X), None if spt_visible is None else _p(spt_visible))
         if rc != 0:
             raise RuntimeError(f"orc_select failed ({rc})")
         return out[: cnt.value].copy(), st.as_dict()
@@ -310,3 +314,82 @@ def adam_cut(p, m, v, grads, idx, lr, beta1, beta2, eps, step):
         v_hat = v[node] / (1.0 - beta2 ** step)
         p[node] = p[node] - lr * m_hat / (np.sqrt(v_hat) + eps)
     return p, m, v
+
+
+def dist32(mu, pos) -> np.float32:
+    """|mu - pos| in FP32 with the cut's operation order (((dx dx + dy dy) + dz dz), then sqrt)."""
+    mu, pos = np.asarray(mu, np.float32), np.asarray(pos, np.float32)
+    dx, dy, dz = mu[0] - pos[0], mu[1] - pos[1], mu[2] - pos[2]
+    s = dx * dx
+    s = np.float32(s + dy * dy)
+    s = np.float32(s + dz * dz)
+    return np.float32(np.sqrt(s))
+
+
+class OracleCutCache:
+    """The GPU cache of SPT cuts (Sec. 4.4 "Caching on the GPU", Eq. 7, and the
+    training loop of Alg. 3) as a plain state machine over the SPTs.
+
+    Iteration t (1, 2, ...) of select: when flush_every > 0 and t is a multiple
+    of it, every entry is dropped first.  A visible SPT j at root distance d
+    (FP32, as the cut computes it) that has an entry (d_c, X_c) is a hit when
+    d_min <= r * r <= d_max with r = d / d_c in FP32 (Alg. 3 compares squared
+    ratios) and is cut at X_c; otherwise it is loaded: cut at its own
+    X = d tau / fx, then entered with (d, X) and size = the number of its
+    nodes the cut selected.  Every visible SPT's last use becomes t.  Then,
+    oldest last use first (ties by SPT index), entries are dropped while the
+    sizes of those left exceed max_nodes."""
+
+    def __init__(self, scene: "OracleScene", max_nodes: int, d_min: float, d_max: float, flush_every: int = 0):
+        self.S = scene
+        self.max_nodes, self.flush_every = int(max_nodes), int(flush_every)
+        self.d_min, self.d_max = np.float32(d_min), np.float32(d_max)
+        self.entries = {}  # SPT root tree id -> [d_c, X_c, size, last_use]
+        self.t = 0
+        self.hits = self.loads = self.evictions = 0
+        roots = scene.perm[scene.spt_begin[:-1]]
+        self.spt_index = {int(r): j for j, r in enumerate(roots)}
+
+    def select(self, cam, tau: float, cull: bool = True):
+        S = self.S
+        tree = S.tree
+        self.t += 1
+        if self.flush_every > 0 and self.t % self.flush_every == 0:
+            self.entries.clear()
+        n = tree.n_nodes
+        vis = np.zeros(n, np.uint8)
+        S.select(cam, tau, cull=cull, spt_visible=vis)
+        k = np.float32(np.float32(tau) / np.float32(cam.fx))
+        override = np.full(n, np.nan, np.float32)
+        loaded = []
+        for r in np.flatnonzero(vis).tolist():
+            d = dist32(tree.means[r], cam.pos)
+            e = self.entries.get(r)
+            hit = False
+            if e is not None:
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    q = np.float32(d / e[0])
+                    q2 = np.float32(q * q)
+                hit = bool(self.d_min <= q2) and bool(q2 <= self.d_max)
+            if hit:
+                override[r] = e[1]
+                e[3] = self.t
+                self.hits += 1
+            else:
+                loaded.append((r, d, np.float32(d * k)))
+                self.loads += 1
+        ids, st = S.select(cam, tau, cull=cull, spt_X=override)
+        counts = {}
+        for sp in S.spt_of[ids].tolist():
+            if sp >= 0:
+                counts[sp] = counts.get(sp, 0) + 1
+        for r, d, X in loaded:
+            self.entries[r] = [d, X, counts.get(r, 0), self.t]
+        remaining = sum(e[2] for e in self.entries.values())
+        for r in sorted(self.entries, key=lambda r: (self.entries[r][3], self.spt_index[r])):
+            if remaining <= self.max_nodes:
+                break
+            remaining -= self.entries[r][2]
+            del self.entries[r]
+            self.evictions += 1
+        return ids, st

@@ -44,6 +44,18 @@ class Adam(ctypes.Structure):
     _fields_ = [("lr", f32 * 5), ("beta1", f32), ("beta2", f32), ("eps", f32), ("step", i32), ("sh_degree", i32)]
 
 
+class CutCacheParams(ctypes.Structure):
+    _fields_ = [("max_nodes", i64), ("d_min", f32), ("d_max", f32), ("flush_every", i32)]
+
+
+class CutCacheStats(ctypes.Structure):
+    _fields_ = [("iterations", i64), ("hits", i64), ("loads", i64), ("evictions", i64), ("cached_spts", i64),
+                ("cached_nodes", i64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("status", i32), ("n_selected", i32), ("n_upper_selected", i32), ("n_spt_visible", i32),
                 ("n_spt_candidates", i64), ("n_rendered", i32), ("n_drawn", i32), ("n_instances", i64)]
@@ -87,6 +99,11 @@ EXPORTS = {
     "lodgs_graph_launch": ([c_p, ctypes.POINTER(Camera), f32, c_p], ctypes.c_int),
     "lodgs_graph_destroy": ([c_p], None),
     "lodgs_adam_cut": ([ctypes.POINTER(Grads)] * 4 + [ctypes.POINTER(Adam), c_p, c_p, i64, i64, c_p], ctypes.c_int),
+    "lodgs_cut_cache_create": ([c_p, ctypes.POINTER(CutCacheParams), ctypes.POINTER(c_p)], ctypes.c_int),
+    "lodgs_cut_cache_destroy": ([c_p], None),
+    "lodgs_lod_select_cached": ([c_p, c_p, ctypes.POINTER(Camera), f32, ctypes.c_uint32, c_p, i64, c_p, c_p],
+                                ctypes.c_int),
+    "lodgs_cut_cache_stats_read": ([c_p, ctypes.POINTER(CutCacheStats), c_p], ctypes.c_int),
     "lodgs_last_error": ([], ctypes.c_char_p),
 }
 

@@ -350,6 +350,19 @@ int lodgs_lod_select(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_
   return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_lod_select");
 }
 
+int lodgs_lod_select_cached(lodgs_frame* f, lodgs_cut_cache* c, const lodgs_camera* cam, float tau, uint32_t flags,
+                            int32_t* d_idx, int64_t capacity, int32_t* d_count, lodgs_stream stream) {
+  if (!f || !c || !d_idx || !d_count) return set_error(LODGS_E_INVALID, "lodgs_lod_select_cached: null argument");
+  if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_lod_select_cached: bad camera");
+  if (!std::isfinite(tau) || tau < 0.0f)
+    return set_error(LODGS_E_INVALID, "lodgs_lod_select_cached: tau must be finite, >= 0");
+  if (capacity < 0 || capacity > (int64_t)INT32_MAX)
+    return set_error(LODGS_E_INVALID, "lodgs_lod_select_cached: capacity");
+  if (flags & ~LODGS_CULL) return set_error(LODGS_E_INVALID, "lodgs_lod_select_cached: only LODGS_CULL is allowed");
+  return lodgs::cache_select(f, c, lodgs::make_view(*cam, tau), flags, d_idx, capacity, d_count,
+                             reinterpret_cast<hipStream_t>(stream));
+}
+
 int lodgs_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, const lodgs_camera* cam,
                  const float bg[3], float* d_rgb, lodgs_stream stream) {
   if (!f || !d_idx || !d_count || !d_rgb) return set_error(LODGS_E_INVALID, "lodgs_render: null argument");

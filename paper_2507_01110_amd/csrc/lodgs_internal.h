@@ -42,6 +42,17 @@ struct SceneDev {
   int32_t height;
 };
 
+// SPT-cut cache state handed to the cut kernels (cached == nullptr: no cache).
+struct CacheDev {
+  const uint8_t* cached;  // [n_spt] entry present
+  const float* dc;        // [n_spt] cached root distance
+  const float* Xc;        // [n_spt] cached X
+  float d_min, d_max;
+  uint8_t* vstate;        // [n_spt] this view: 0 not visible, 1 hit, 2 loaded
+  float* dcur;            // [n_spt] this view's root distance
+  uint32_t* spt_sel;      // [n_spt] this view's selected nodes per SPT
+};
+
 struct lodgs_scene {
   SceneDev dev;
   int32_t* anc_owned;
@@ -203,7 +214,10 @@ void stage_end(lodgs_frame* f, hipStream_t st);
 
 // Stage launchers (all stream-ordered, no host synchronisation).
 void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
-                   int32_t* d_count, hipStream_t st);
+                   int32_t* d_count, hipStream_t st, const CacheDev* cache = nullptr);
+// lod_select through an SPT-cut cache (arguments validated by the caller).
+int cache_select(lodgs_frame* f, lodgs_cut_cache* c, const ViewConst& v, uint32_t flags, int32_t* d_idx,
+                 int64_t capacity, int32_t* d_count, hipStream_t st);
 // The comparator cuts (LODGS_CUT_BFS / LODGS_CUT_PARALLEL in flags).
 void launch_select_full(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
                         int32_t* d_count, hipStream_t st);

@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) k_anc_fill(SceneDev S, int32_t D, int3
 
 __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewConst* __restrict__ vp, uint32_t flags,
                                                       const uint8_t* utest, uint8_t* upper_sel, int32_t* spt_high,
-                                                      float* spt_X, FrameCounters* ctr) {
+                                                      float* spt_X, FrameCounters* ctr, CacheDev C) {
   const ViewConst v = *vp;
   const bool cull = (flags & LODGS_CULL) != 0;
   const bool conservative = (flags & LODGS_CONSERVATIVE) != 0 && S.spt_radius != nullptr;
@@ -159,15 +159,32 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewCons
       const int32_t b = S.spt_begin[j], m = S.spt_begin[j + 1] - b;
       int32_t high = 0;
       float X = 0.0f;
+      uint8_t vst = 0;
       if (reached(S, utest, e, total, S.spt_parent[j])) {
         const float mx = S.means[3 * (int64_t)b], my = S.means[3 * (int64_t)b + 1], mz = S.means[3 * (int64_t)b + 2];
         if (!(cull && sphere_culled(v, mx, my, mz, S.rho[b]))) {
-          X = conservative ? fmaxf(0.0f, view_distance(v, mx, my, mz) - S.spt_radius[j]) * v.k
-                           : view_distance(v, mx, my, mz) * v.k;
+          const float d = view_distance(v, mx, my, mz);
+          X = conservative ? fmaxf(0.0f, d - S.spt_radius[j]) * v.k : d * v.k;
+          if (C.cached) {  // the cache's ratio test (squared, FP32)
+            vst = 2;
+            if (C.cached[j]) {
+              const float r = d / C.dc[j];
+              const float r2 = r * r;
+              if (C.d_min <= r2 && r2 <= C.d_max) {
+                X = C.Xc[j];
+                vst = 1;
+              }
+            }
+            C.dcur[j] = d;
+          }
           high = count_above(S.r_max + b, m, X);
           hsum += high;
           ++vis;
         }
+      }
+      if (C.cached) {
+        C.vstate[j] = vst;
+        C.spt_sel[j] = 0u;
       }
       spt_high[j] = high;
       spt_X[j] = X;
@@ -224,7 +241,7 @@ __global__ void __launch_bounds__(kBlock) k_segments(SceneDev S, const uint8_t* 
                                                      const float* spt_X, const uint32_t* ch_off,
                                                      const uint32_t* owner, int32_t n_up_chunks,
                                                      uint32_t* seg, int32_t* idx, int64_t capacity,
-                                                     FrameCounters* ctr, int32_t* d_count) {
+                                                     FrameCounters* ctr, int32_t* d_count, uint32_t* spt_sel) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt = lanemask_lt();
   const int64_t nseg = (int64_t)n_up_chunks + ctr->n_chunks;
@@ -271,6 +288,7 @@ __global__ void __launch_bounds__(kBlock) k_segments(SceneDev S, const uint8_t* 
         }
         c += (uint32_t)__popcll(b);
       }
+      if (!WRITE && spt_sel && lane == 0 && c) atomicAdd(&spt_sel[j], c);
     }
     if (!WRITE && lane == 0) seg[sg] = c;
   }
@@ -381,7 +399,9 @@ int build_spt_radius(lodgs_scene* s) {
 }
 
 void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
-                   int32_t* d_count, hipStream_t st) {
+                   int32_t* d_count, hipStream_t st, const CacheDev* cache) {
+  CacheDev C{};
+  if (cache) C = *cache;
   const SceneDev& S = f->scene->dev;
   stage_begin(f, LODGS_STAGE_SELECT, st);
   launch_set_view(v, f->d_view_sel, f->ctr, kViewSelect, nullptr, 0, st);
@@ -392,7 +412,7 @@ void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* 
   ugrid = ugrid < 1 ? 1 : (ugrid > 4096 ? 4096 : ugrid);
   hipLaunchKernelGGL(k_upper_tests, dim3(ugrid), dim3(kBlock), 0, st, S, f->d_view_sel, flags, f->upper_test);
   hipLaunchKernelGGL(k_cut_upper, dim3(grid), dim3(kBlock), 0, st, S, f->d_view_sel, flags, f->upper_test,
-                     f->upper_sel, f->spt_high, f->spt_X, f->ctr);
+                     f->upper_sel, f->spt_high, f->spt_X, f->ctr, C);
   const int32_t n_up_chunks = (S.n_upper + 63) / 64;
   // chunks per visible SPT prefix -> offsets, total -> n_chunks
   scan_exclusive(LoadChunks{f->spt_high}, &f->ctr->spt_count, (int64_t)S.n_spt, f->block_sums,
@@ -400,10 +420,12 @@ void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* 
   const int sgrid = 4096;
   const int64_t seg_cap = (int64_t)n_up_chunks + S.n_spt + S.n_nodes / kChunk + 1;
   hipLaunchKernelGGL(k_segments<false>, dim3(sgrid), dim3(kBlock), 0, st, S, f->upper_sel, f->spt_high, f->spt_X,
-                     f->spt_off, f->chunk_owner, n_up_chunks, f->seg, (int32_t*)nullptr, capacity, f->ctr, d_count);
+                     f->spt_off, f->chunk_owner, n_up_chunks, f->seg, (int32_t*)nullptr, capacity, f->ctr, d_count,
+                     C.spt_sel);
   scan_exclusive(LoadArray{f->seg}, &f->ctr->seg_total, seg_cap, f->block_sums, f->seg, &f->ctr->n_selected, st);
   hipLaunchKernelGGL(k_segments<true>, dim3(sgrid), dim3(kBlock), 0, st, S, f->upper_sel, f->spt_high, f->spt_X,
-                     f->spt_off, f->chunk_owner, n_up_chunks, f->seg, d_idx, capacity, f->ctr, d_count);
+                     f->spt_off, f->chunk_owner, n_up_chunks, f->seg, d_idx, capacity, f->ctr, d_count,
+                     (uint32_t*)nullptr);
   stage_end(f, st);
 }
 

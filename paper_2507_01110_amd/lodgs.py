@@ -144,6 +144,33 @@ class Scene:
               "lodgs_scene_set_hierarchy")
 
 
+class CutCache:
+    """The GPU cache of SPT cuts (lodgs_cut_cache): a visible SPT whose squared
+    root-distance ratio to its cached cut lies in [d_min, d_max] reuses that
+    cut; entries beyond max_nodes are dropped least recently used first; every
+    flush_every-th cached select starts from an empty cache."""
+
+    def __init__(self, scene: Scene, max_nodes: int, d_min: float, d_max: float, flush_every: int = 0):
+        self.scene = scene
+        prm = _lib.CutCacheParams(int(max_nodes), float(d_min), float(d_max), int(flush_every))
+        h = ctypes.c_void_p()
+        check(_lib.load().lodgs_cut_cache_create(scene._h, ctypes.byref(prm), ctypes.byref(h)),
+              "lodgs_cut_cache_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.lodgs_cut_cache_destroy(h)
+            self._h = None
+
+    def stats(self, stream=None) -> dict:
+        s = _lib.CutCacheStats()
+        check(_lib.load().lodgs_cut_cache_stats_read(self._h, ctypes.byref(s), _stream(stream)),
+              "lodgs_cut_cache_stats_read")
+        return s.as_dict()
+
+
 GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
@@ -198,13 +225,21 @@ class Frame:
             self._h = None
 
     def lod_select(self, cam, tau: float, cull: bool = True, conservative: bool = False, method: str = "hspt",
-                   stream=None):
+                   cache: CutCache | None = None, stream=None):
         """Runs the cut into self.idx / self.count (device); returns them.
         conservative: cut each SPT at max(0, d - R) tau / fx (LODGS_CONSERVATIVE).
         method: "hspt" (the HSPT cut), or the whole-hierarchy comparators "bfs"
         and "parallel" (Eq. 5), which need Scene.attach_hierarchy before the
-        frame was created."""
+        frame was created.  cache: select through an SPT-cut cache (HSPT cut,
+        culling only)."""
         c = camera_struct(cam)
+        if cache is not None:
+            if conservative or method != "hspt":
+                raise ValueError("the SPT-cut cache takes the default HSPT cut only")
+            check(_lib.load().lodgs_lod_select_cached(self._h, cache._h, ctypes.byref(c), float(tau),
+                                                      _lib.CULL if cull else 0, _ptr(self.idx), self.idx.numel(),
+                                                      _ptr(self.count), _stream(stream)), "lodgs_lod_select_cached")
+            return self.idx, self.count
         flags = (_lib.CULL if cull else 0) | (_lib.CONSERVATIVE if conservative else 0)
         flags |= {"hspt": 0, "bfs": _lib.CUT_BFS, "parallel": _lib.CUT_PARALLEL}[method]
         check(_lib.load().lodgs_lod_select(self._h, ctypes.byref(c), float(tau), flags,

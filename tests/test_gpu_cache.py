@@ -1,0 +1,100 @@
+"""GPU parity of the SPT-cut cache (Sec. 4.4 "Caching on the GPU", Eq. 7,
+Alg. 3's loop; lodgs_lod_select_cached through the C ABI) against the
+oracle's state machine, run side by side over view sequences: after every
+iteration the selected index set is bit-exact and the counters (hits,
+loads, evictions, entries, cached nodes) are equal."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from scenegen import configs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_lockstep(tree, O, S, frame, cams, taus, max_nodes, d_min, d_max, flush_every, cull=True):
+    from paper_2507_01110_amd.lodgs import CutCache
+    G = CutCache(S, max_nodes, d_min, d_max, flush_every)
+    C = oracle.OracleCutCache(O, max_nodes, d_min, d_max, flush_every)
+    for it, (cam, tau) in enumerate(zip(cams, taus)):
+        idx, cnt = frame.lod_select(cam, tau, cull=cull, cache=G)
+        st = frame.stats()
+        n = int(cnt.item())
+        assert st["status"] == 0
+        ids, _ = C.select(cam, tau, cull=cull)
+        assert np.array_equal(idx[:n].cpu().numpy(), O.pos_of[ids]), (it, n, len(ids))
+        g = G.stats()
+        want = {"iterations": C.t, "hits": C.hits, "loads": C.loads, "evictions": C.evictions,
+                "cached_spts": len(C.entries), "cached_nodes": sum(e[2] for e in C.entries.values())}
+        assert g == want, (it, g, want)
+    _say("  cache", max_nodes, d_min, d_max, flush_every, G.stats())
+    return G.stats()
+
+
+def _orbit(n, radius, height, w=256, h=256):
+    return [scenegen.camera_look_at((radius * np.cos(a), radius * np.sin(a), height), (0.0, 0.0, 0.0),
+                                    (0.0, 0.0, 1.0), w, h) for a in np.linspace(0.0, 1.2, n)]
+
+
+def test_cache_tiny_lockstep(torch_cuda):
+    from paper_2507_01110_amd.lodgs import Frame, Scene
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = Scene(tree)
+    f = Frame(S, S.n_nodes, 1 << 20, 256, 256)
+    rng = np.random.default_rng(11)
+    cams = _orbit(6, 28.0, 12.0) + _orbit(6, 16.0, 6.0) + _orbit(4, 24.0, 20.0)
+    taus = [float(np.float32(t)) for t in rng.choice([0.5, 1.0, 2.0], len(cams))]
+    for prm in ((10 ** 9, 0.5, 1.5, 0), (6000, 0.6, 1.6, 5), (0, 0.0, 1e30, 0), (20000, 1.0, 1.0, 3)):
+        s = run_lockstep(tree, O, S, f, cams, taus, *prm)
+        if prm[0] == 10 ** 9:
+            assert s["hits"] > 0 and s["evictions"] == 0
+        if prm[0] == 6000:
+            assert s["evictions"] > 0
+    run_lockstep(tree, O, S, f, cams[:6], taus[:6], 10 ** 9, 0.5, 1.5, 0, cull=False)
+
+
+def test_cache_medium_lockstep(torch_cuda):
+    from paper_2507_01110_amd.lodgs import Frame, Scene
+    tree = scenegen.build_tree(configs.medium_spec())
+    O = oracle.OracleScene(tree)
+    S = Scene(tree)
+    # a 1080p fly-in: forward and down at 45 degrees pitch
+    cams = [scenegen.camera_yaw_pitch((4.0 * k, 1.2 * k, 40.0 - 3.0 * k), 0.3, np.radians(-45.0), 1920, 1080)
+            for k in range(8)]
+    f = Frame(S, S.n_nodes, 1 << 23, 1920, 1080)
+    s = run_lockstep(tree, O, S, f, cams, [1.0] * len(cams), 400000, 0.7, 1.4, 0)
+    assert s["hits"] > 0
+
+
+def test_cache_rejects_other_cuts_and_foreign_frames(torch_cuda):
+    from paper_2507_01110_amd import _lib
+    from paper_2507_01110_amd.lodgs import CutCache, Frame, Scene
+    tree = scenegen.build_tree(configs.tiny_spec(n=1024))
+    S1, S2 = Scene(tree), Scene(tree)
+    cam = configs.tiny_camera(64, 64)
+    G = CutCache(S1, 1000, 0.5, 1.5)
+    f2 = Frame(S2, S2.n_nodes, 1 << 16, 64, 64)
+    with pytest.raises(_lib.LodgsError):
+        f2.lod_select(cam, 1.0, cache=G)
+    f1 = Frame(S1, S1.n_nodes, 1 << 16, 64, 64)
+    with pytest.raises(ValueError):
+        f1.lod_select(cam, 1.0, conservative=True, cache=G)
+    with pytest.raises(_lib.LodgsError):
+        CutCache(S1, 1000, 1.5, 0.5)

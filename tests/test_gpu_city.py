@@ -125,3 +125,25 @@ def test_city_views_select_render_backward(city):
             want = O.pos_of[O.select_full(cam, tau, method)]
             assert np.array_equal(idx[:nm].cpu().numpy(), want), (method, nm, len(want))
             _say(f"  {method} cut: {nm} selected")
+
+
+def test_city_cut_cache_along_the_path(city):
+    # the SPT-cut cache over consecutive path poses, in lockstep with the
+    # oracle's state machine (selection bit-exact, counters equal)
+    from paper_2507_01110_amd.lodgs import CutCache, Frame
+    tree, S, O = city
+    cams = [configs.city_path_camera(k) for k in range(120, 126)]
+    f = Frame(S, min(S.n_nodes, 1 << 24), 1 << 27, cams[0].width, cams[0].height)
+    G = CutCache(S, 1_500_000, 0.8, 1.25, 4)
+    C = oracle.OracleCutCache(O, 1_500_000, 0.8, 1.25, 4)
+    for k, cam in enumerate(cams):
+        idx, cnt = f.lod_select(cam, 1.0, cache=G)
+        n = int(cnt.item())
+        assert f.stats()["status"] == 0
+        ids, _ = C.select(cam, 1.0)
+        assert np.array_equal(idx[:n].cpu().numpy(), O.pos_of[ids]), (k, n, len(ids))
+        g = G.stats()
+        want = {"iterations": C.t, "hits": C.hits, "loads": C.loads, "evictions": C.evictions,
+                "cached_spts": len(C.entries), "cached_nodes": sum(e[2] for e in C.entries.values())}
+        assert g == want, (k, g, want)
+        _say(f"  cached select, pose {120 + k}: {n} selected, {g}")
