@@ -41,7 +41,8 @@ __device__ __forceinline__ void block_add(unsigned long long* dst, unsigned long
 }
 
 // Enters the loaded SPTs, stamps every visible one with iteration t, counts
-// hits and loads, and writes the sort keys (last use; absent entries last).
+// hits and loads, and writes the sort keys (last use <= t; absent entries
+// t + 1, so they sort last and the keys need only the bits of t + 1).
 __global__ void __launch_bounds__(kBlock) k_cache_update(int64_t n, uint32_t t, const uint8_t* vstate,
                                                          const float* dcur, const float* spt_X,
                                                          const uint32_t* spt_sel, uint8_t* cached, float* dc,
@@ -64,7 +65,7 @@ __global__ void __launch_bounds__(kBlock) k_cache_update(int64_t n, uint32_t t, 
         ++hits;
       }
       if (s) last_use[j] = t;
-      keys[j] = cached[j] ? last_use[j] : 0xFFFFFFFFu;
+      keys[j] = cached[j] ? last_use[j] : t + 1u;
       vals[j] = (uint32_t)j;
     }
   }
@@ -155,7 +156,9 @@ int cache_select(lodgs_frame* f, lodgs_cut_cache* c, const ViewConst& v, uint32_
   hipLaunchKernelGGL(k_cache_update, dim3(grid_for(n)), dim3(kBlock), 0, st, n, t, c->vstate, c->dcur, f->spt_X,
                      c->spt_sel, c->cached, c->dc, c->Xc, c->size, c->last_use, c->keys[0], c->vals[0], c->counters);
   const SortScratch ws{f->sort_table, f->sort_below};
-  const bool in2 = sort_pairs(c->keys[0], c->vals[0], c->keys[1], c->vals[1], &f->ctr->spt_count, n, 32, ws, st);
+  int bits = 8;  // whole 8-bit digits covering t + 1
+  while (bits < 32 && ((uint64_t)t + 1u) >> bits) bits += 8;
+  const bool in2 = sort_pairs(c->keys[0], c->vals[0], c->keys[1], c->vals[1], &f->ctr->spt_count, n, bits, ws, st);
   const uint32_t* order = in2 ? c->vals[1] : c->vals[0];
   scan_exclusive(LoadSortedSize{order, c->cached, c->size}, &f->ctr->spt_count, n, f->block_sums, c->prefix, c->total,
                  st);
