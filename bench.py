@@ -326,6 +326,9 @@ def main():
                          "step (instead of accumulating node gradients)")
     ap.add_argument("--cache", type=str, default="",
                     help="select through the SPT-cut cache: max_nodes,d_min,d_max,flush_every (e.g. 15000000,0.8,1.25,1000)")
+    ap.add_argument("--rows", action="store_true",
+                    help="out-of-core parameters: gather each cut's rows from pinned host memory, render from the "
+                         "rows, backward into selection-indexed gradients")
     ap.add_argument("--leaves", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--targets", type=int, default=8, help="distinct seeded targets resident in HBM")
@@ -351,7 +354,7 @@ def main():
     import numpy as np
     import torch
     import scenegen
-    from paper_2507_01110_amd.lodgs import AdamCut, CutCache, Frame, Scene, camera_struct
+    from paper_2507_01110_amd.lodgs import AdamCut, CutCache, Frame, HostParams, Scene, camera_struct, rows_like
 
     torch.cuda.set_device(0)
     if args.workload == "ultra":
@@ -418,10 +421,15 @@ def main():
         f"mean instances {np.mean([c['n_instances'] for c in counts]):.0f}")
 
     targets = [torch.from_numpy(scenegen.target_image(H, W, 202 + k)).cuda() for k in range(args.targets)]
-    if args.adam:
-        opt = AdamCut(scene.params, tree.sh_degree)
+    if args.adam or args.rows:
+        if args.adam:
+            opt = AdamCut(scene.params, tree.sh_degree)
         sel = {k: torch.zeros((cap_sel,) + tuple(v.shape[1:]), dtype=torch.float32, device="cuda")
                for k, v in scene.params.items()}
+        if args.rows:
+            host = HostParams.from_scene(scene)
+            rows = rows_like(tree.sh_degree, cap_sel)
+            log(f"out-of-core store: {sum(v.numel() * 4 for v in host.params.values()) / 1e9:.1f} GB pinned host memory")
     else:
         grads = {k: torch.zeros_like(v) for k, v in scene.params.items()}
     img = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
@@ -440,11 +448,16 @@ def main():
             frame.lod_select(cam, tau, cache=cache)
         else:
             frame.lod_select(cam, tau, conservative=args.conservative, method=args.cut)
-        frame.render(cam, out=img)
+        if args.rows:
+            frame.gather_rows(host, rows)
+            frame.render_rows(cam, rows, out=img)
+        else:
+            frame.render(cam, out=img)
         frame.l1_loss(img, targets[seq[i % K] % len(targets)], grad=dL)
-        if args.adam:
+        if args.adam or args.rows:
             frame.backward(dL, sel=sel)
-            opt.step(sel, frame.idx, frame.count)
+            if args.adam:
+                opt.step(sel, frame.idx, frame.count)
         else:
             frame.backward(dL, nodes=grads)
 
@@ -528,7 +541,9 @@ def main():
         "dtype": "f32", "data": "synthetic (seeded scene, cameras and targets)",
         "config": dict(desc, nodes=int(scene.n_nodes), upper_nodes=int(scene.n_upper), spts=int(scene.n_spt),
                        views_timed=K, parallelism="none", cut="conservative" if args.conservative else ("default" if args.cut == "hspt" else args.cut),
-                       update="cut-set Adam" if args.adam else "node-gradient accumulation"),
+                       update="cut-set Adam" if args.adam else ("selection-indexed gradients" if args.rows
+                                                                else "node-gradient accumulation"),
+                       params="pinned host memory, rows gathered per view" if args.rows else "resident in HBM"),
         "hbm_fraction_whole_path": round(hbm_frac, 4),
         "algorithmic_GB_per_view": round(all_bytes / K / 1e9, 4),
         "stages": stages,

@@ -241,7 +241,8 @@ int lodgs_render(lodgs_frame* frame, const int32_t* d_idx, const int32_t* d_coun
                  const float bg[3], float* d_rgb, lodgs_stream stream);
 
 /* Gradient destinations, one array per parameter group, same layouts as the
- * parameters.  Any member may be NULL to skip that group. */
+ * parameters.  Any member may be NULL to skip that group.  (The same struct
+ * carries parameter arrays where a call says so.) */
 typedef struct lodgs_grads {
   float* d_means;
   float* d_log_scales;
@@ -249,6 +250,29 @@ typedef struct lodgs_grads {
   float* d_opacity_logits;
   float* d_sh;
 } lodgs_grads;
+
+/* ---------------------------------------------------------------- out-of-core parameters
+ * Rendering a cut whose parameters live in host memory (Sec. 4.4: the cut's
+ * Gaussians are loaded from RAM).  lodgs_gather_rows copies, with one kernel
+ * reading host memory over the host link, the parameter rows of the selected
+ * nodes: row k of every group of rows receives node d_idx[k]'s parameters,
+ * k < min(*d_count, capacity).  host: the five parameter groups in layout
+ * order (the scene's layouts; sh of sh_degree), in pinned host memory from
+ * hipHostMalloc (or torch's pin_memory); rows: device arrays of capacity rows
+ * each.  Rows of 4 or 12 / 48 floats move as float4s: all arrays 16-byte
+ * aligned.  Errors: LODGS_E_INVALID (a NULL member, a host array that is not
+ * pinned host memory, a rows array that is not device memory, misalignment,
+ * sh_degree outside 0..3). */
+int lodgs_gather_rows(const lodgs_grads* host, const lodgs_grads* rows, int32_t sh_degree, const int32_t* d_idx,
+                      const int32_t* d_count, int64_t capacity, int64_t n_nodes, lodgs_stream stream);
+
+/* lodgs_render with the parameters of the i-th rendered node taken from row
+ * i of rows (as lodgs_gather_rows writes them) instead of the scene: the
+ * image, the instances and the frame state equal those of lodgs_render on
+ * the same cut.  lodgs_render_backward after it takes sel only (rows-indexed
+ * gradients; nodes must be NULL).  rows must stay unchanged until then. */
+int lodgs_render_rows(lodgs_frame* frame, const lodgs_grads* rows, const int32_t* d_count, const lodgs_camera* cam,
+                      const float bg[3], float* d_rgb, lodgs_stream stream);
 
 /* render_backward: given dL/dimage (d_dL_drgb, [height][width][3]) for the
  * last render of this frame, computes the gradients of the raw parameters of

@@ -104,6 +104,8 @@ EXPORTS = {
     "lodgs_lod_select_cached": ([c_p, c_p, ctypes.POINTER(Camera), f32, ctypes.c_uint32, c_p, i64, c_p, c_p],
                                 ctypes.c_int),
     "lodgs_cut_cache_stats_read": ([c_p, ctypes.POINTER(CutCacheStats), c_p], ctypes.c_int),
+    "lodgs_gather_rows": ([ctypes.POINTER(Grads), ctypes.POINTER(Grads), i32, c_p, c_p, i64, i64, c_p], ctypes.c_int),
+    "lodgs_render_rows": ([c_p, ctypes.POINTER(Grads), c_p, ctypes.POINTER(Camera), c_p, c_p, c_p], ctypes.c_int),
     "lodgs_last_error": ([], ctypes.c_char_p),
 }
 

@@ -152,10 +152,15 @@ void free_frame(lodgs_frame* f) {
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->upper_test, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->depth_rank, f->rect,
                   f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->rank_info, f->grad2d, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
-                  f->d_view_ren, f->cut_bits, f->frontier[0], f->frontier[1], f->level_count};
+                  f->d_view_ren, f->cut_bits, f->frontier[0], f->frontier[1], f->level_count, f->iota};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete f;
+}
+
+__global__ void k_iota(int32_t* a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = (int32_t)i;
 }
 
 // Selection position of each instance in tile order.
@@ -301,6 +306,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   A(work, 2);
   A(d_view_sel, 1);
   A(d_view_ren, 1);
+  A(iota, ns);
   if (S.parent) {
     A(cut_bits, (size_t)lodgs::cut_bit_words(S.n_nodes));
     A(frontier[0], ns);
@@ -319,6 +325,11 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   c.spt_count = S.n_spt;
   c.n_bit_words = (int32_t)lodgs::cut_bit_words(S.n_nodes);
   e = hipMemcpy(f->ctr, &c, sizeof c, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_iota, dim3(1024), dim3(256), 0, 0, f->iota, (int64_t)ns);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
   if (e != hipSuccess) {
     free_frame(f);
     return hip_fail(e, "lodgs_frame_create");
@@ -374,6 +385,7 @@ int lodgs_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, c
   if (bg)
     for (int k = 0; k < 3; ++k) b[k] = bg[k];
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  f->rows_mode = false;
   lodgs::launch_render(f, d_idx, d_count, v, b, d_rgb, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "lodgs_render");
@@ -386,10 +398,46 @@ int lodgs_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, c
   return LODGS_OK;
 }
 
+int lodgs_render_rows(lodgs_frame* f, const lodgs_grads* rows, const int32_t* d_count, const lodgs_camera* cam,
+                      const float bg[3], float* d_rgb, lodgs_stream stream) {
+  if (!f || !rows || !d_count || !d_rgb) return set_error(LODGS_E_INVALID, "lodgs_render_rows: null argument");
+  if (!rows->d_means || !rows->d_log_scales || !rows->d_quats || !rows->d_opacity_logits || !rows->d_sh)
+    return set_error(LODGS_E_INVALID, "lodgs_render_rows: every parameter group is needed");
+  if ((reinterpret_cast<uintptr_t>(rows->d_quats) | reinterpret_cast<uintptr_t>(rows->d_sh)) & 15u)
+    return set_error(LODGS_E_INVALID, "lodgs_render_rows: quaternion and SH rows must be 16-byte aligned");
+  if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_render_rows: bad camera");
+  if (cam->width > f->caps.max_width || cam->height > f->caps.max_height)
+    return set_error(LODGS_E_CAPACITY, "lodgs_render_rows: image larger than the frame's capacity");
+  const lodgs::ViewConst v = lodgs::make_view(*cam, 0.0f);
+  float b[3] = {0.0f, 0.0f, 0.0f};
+  if (bg)
+    for (int k = 0; k < 3; ++k) b[k] = bg[k];
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  f->rows_dev = f->scene->dev;
+  f->rows_dev.means = rows->d_means;
+  f->rows_dev.log_scales = rows->d_log_scales;
+  f->rows_dev.quats = rows->d_quats;
+  f->rows_dev.opacity_logits = rows->d_opacity_logits;
+  f->rows_dev.sh = rows->d_sh;
+  f->rows_mode = true;
+  lodgs::launch_render(f, f->iota, d_count, v, b, d_rgb, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "lodgs_render_rows");
+  f->rendered = true;
+  f->r_idx = f->iota;
+  f->r_count = d_count;
+  f->r_rgb = d_rgb;
+  std::memcpy(f->bg, b, sizeof b);
+  f->view = v;
+  return LODGS_OK;
+}
+
 int lodgs_render_backward(lodgs_frame* f, const float* d_dL_drgb, const lodgs_grads* sel, const lodgs_grads* nodes,
                           lodgs_stream stream) {
   if (!f || !d_dL_drgb) return set_error(LODGS_E_INVALID, "lodgs_render_backward: null argument");
   if (!f->rendered) return set_error(LODGS_E_STATE, "lodgs_render_backward: no render on this frame");
+  if (f->rows_mode && nodes)
+    return set_error(LODGS_E_INVALID, "lodgs_render_backward: after lodgs_render_rows only sel gradients are written");
   if ((sel && (reinterpret_cast<uintptr_t>(sel->d_sh) & 15u)) || (nodes && (reinterpret_cast<uintptr_t>(nodes->d_sh) & 15u)))
     return set_error(LODGS_E_INVALID, "lodgs_render_backward: SH gradient arrays must be 16-byte aligned");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -565,6 +613,7 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
     return hip_fail(e, "lodgs_graph_capture_view: begin capture");
   }
   lodgs::launch_select(f, vs, flags, d_idx, capacity, d_count, st);
+  f->rows_mode = false;
   lodgs::launch_render(f, d_idx, d_count, vr, b, d_rgb, st);
   e = hipStreamEndCapture(st, &g->graph);
   if (e != hipSuccess) {

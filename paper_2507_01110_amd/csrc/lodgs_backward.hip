@@ -709,7 +709,7 @@ static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodg
 
 void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
                      hipStream_t st) {
-  const SceneDev& S = f->scene->dev;
+  const SceneDev& S = render_params(f);
   const ViewConst& v = f->view;
   stage_begin(f, LODGS_STAGE_BLEND_BWD, st);
   const int ntiles = v.tiles_x * v.tiles_y;

@@ -157,6 +157,10 @@ struct lodgs_frame {
   int open_stage;
   hipEvent_t open_event;
   unsigned long long* work;  // [2] evaluation / contribution counters (device)
+  // rendering from gathered parameter rows (lodgs_render_rows)
+  bool rows_mode;            // the last render read rows_dev, with node i at row i
+  SceneDev rows_dev;         // the scene's view with the parameter pointers on the rows
+  int32_t* iota;             // [max_selected] i at i
   int blend_px_fwd;          // pixels per lane of the forward blend (1, 2 or 4)
   int blend_px_bwd;          // pixels per lane of the blend backward (1, 2 or 4)
 };
@@ -215,6 +219,8 @@ void stage_end(lodgs_frame* f, hipStream_t st);
 // Stage launchers (all stream-ordered, no host synchronisation).
 void launch_select(lodgs_frame* f, const ViewConst& v, uint32_t flags, int32_t* d_idx, int64_t capacity,
                    int32_t* d_count, hipStream_t st, const CacheDev* cache = nullptr);
+// The parameters the last render read: the scene's, or the gathered rows.
+inline const SceneDev& render_params(const lodgs_frame* f) { return f->rows_mode ? f->rows_dev : f->scene->dev; }
 // lod_select through an SPT-cut cache (arguments validated by the caller).
 int cache_select(lodgs_frame* f, lodgs_cut_cache* c, const ViewConst& v, uint32_t flags, int32_t* d_idx,
                  int64_t capacity, int32_t* d_count, hipStream_t st);

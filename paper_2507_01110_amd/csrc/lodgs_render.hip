@@ -663,7 +663,7 @@ static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], 
 
 void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, const ViewConst& v,
                    const float bg[3], float* d_rgb, hipStream_t st) {
-  const SceneDev& S = f->scene->dev;
+  const SceneDev& S = render_params(f);
   const int64_t cap = f->caps.max_selected, icap = f->caps.max_instances;
   stage_begin(f, LODGS_STAGE_PROJECT, st);
   launch_set_view(v, f->d_view_ren, f->ctr, kViewRender, d_count, cap, st);

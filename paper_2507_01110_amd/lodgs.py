@@ -144,6 +144,27 @@ class Scene:
               "lodgs_scene_set_hierarchy")
 
 
+class HostParams:
+    """Scene parameters in pinned host memory, rows in layout order: the
+    out-of-core store that Frame.gather_rows reads over the host link."""
+
+    def __init__(self, params: dict, sh_degree: int):
+        self.params = {k: (v if v.is_pinned() else v.cpu().pin_memory()) for k, v in params.items()}
+        self.sh_degree = int(sh_degree)
+        self.n_nodes = int(self.params["means"].shape[0])
+
+    @classmethod
+    def from_scene(cls, scene: "Scene") -> "HostParams":
+        return cls({k: v.detach().cpu() for k, v in scene.params.items()}, scene.sh_degree)
+
+
+def rows_like(sh_degree: int, capacity: int, device="cuda") -> dict:
+    """Device row arrays for capacity gathered nodes (the parameter layouts)."""
+    nb = (int(sh_degree) + 1) ** 2
+    shapes = {"means": (3,), "log_scales": (3,), "quats": (4,), "opacity_logits": (), "sh": (nb, 3)}
+    return {k: torch.zeros((int(capacity),) + s, dtype=torch.float32, device=device) for k, s in shapes.items()}
+
+
 class CutCache:
     """The GPU cache of SPT cuts (lodgs_cut_cache): a visible SPT whose squared
     root-distance ratio to its cached cut lies in [d_min, d_max] reuses that
@@ -257,6 +278,31 @@ class Frame:
         check(_lib.load().lodgs_render(self._h, _ptr(idx), _ptr(count), ctypes.byref(c),
                                        ctypes.cast(b, ctypes.c_void_p), _ptr(out), _stream(stream)), "lodgs_render")
         self._last = (idx, count, out)
+        return out
+
+    def gather_rows(self, host: HostParams, rows: dict, idx=None, count=None, stream=None):
+        """Copies the selected nodes' parameters from the host store into rows
+        (row k = node idx[k]) with one kernel reading host memory."""
+        idx = self.idx if idx is None else idx
+        count = self.count if count is None else count
+        g = lambda d: _lib.Grads(*[_ptr(d[k]) for k in GROUPS])
+        check(_lib.load().lodgs_gather_rows(ctypes.byref(g(host.params)), ctypes.byref(g(rows)), host.sh_degree,
+                                            _ptr(idx), _ptr(count), int(rows["means"].shape[0]), host.n_nodes,
+                                            _stream(stream)), "lodgs_gather_rows")
+        return rows
+
+    def render_rows(self, cam, rows: dict, count=None, bg=(0.0, 0.0, 0.0), out=None, stream=None):
+        """render() with the i-th rendered node's parameters at row i of rows."""
+        count = self.count if count is None else count
+        if out is None:
+            out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=self.scene.device)
+        c = camera_struct(cam)
+        b = (ctypes.c_float * 3)(*[float(x) for x in bg])
+        g = _lib.Grads(*[_ptr(rows[k]) for k in GROUPS])
+        check(_lib.load().lodgs_render_rows(self._h, ctypes.byref(g), _ptr(count), ctypes.byref(c),
+                                            ctypes.cast(b, ctypes.c_void_p), _ptr(out), _stream(stream)),
+              "lodgs_render_rows")
+        self._last = (None, count, out)
         return out
 
     def backward(self, dL_drgb, sel: dict | None = None, nodes: dict | None = None, stream=None):
