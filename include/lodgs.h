@@ -269,8 +269,9 @@ int lodgs_gather_rows(const lodgs_grads* host, const lodgs_grads* rows, int32_t 
 /* lodgs_render with the parameters of the i-th rendered node taken from row
  * i of rows (as lodgs_gather_rows writes them) instead of the scene: the
  * image, the instances and the frame state equal those of lodgs_render on
- * the same cut.  lodgs_render_backward after it takes sel only (rows-indexed
- * gradients; nodes must be NULL).  rows must stay unchanged until then. */
+ * the same cut.  rows must hold at least min(*d_count, max_selected) rows.
+ * lodgs_render_backward after it takes sel only (rows-indexed gradients;
+ * nodes must be NULL).  rows must stay unchanged until then. */
 int lodgs_render_rows(lodgs_frame* frame, const lodgs_grads* rows, const int32_t* d_count, const lodgs_camera* cam,
                       const float bg[3], float* d_rgb, lodgs_stream stream);
 
