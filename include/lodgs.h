@@ -204,8 +204,9 @@ int lodgs_lod_select(lodgs_frame* frame, const lodgs_camera* cam, float tau, uin
  * (d, X) and its number of selected nodes.  Every visible SPT's last use
  * becomes t.  Then, oldest last use first (ties by SPT index), entries are
  * dropped while the node counts of those left exceed max_nodes (the LRU
- * write-back).  Flags: LODGS_CULL only.  One cache per scene; calls on one
- * cache must be stream-ordered. */
+ * write-back).  Flags: LODGS_CULL only.  One cache per scene, which must
+ * outlive it; calls on one cache must be stream-ordered (they use the
+ * frame's scratch and the cache's state in order). */
 typedef struct lodgs_cut_cache_params {
   int64_t max_nodes;   /* budget of cached SPT-cut nodes, >= 0 */
   float d_min, d_max;  /* the window of squared distance ratios, 0 <= d_min <= d_max */
