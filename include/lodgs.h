@@ -314,6 +314,15 @@ int lodgs_frame_read_instances(lodgs_frame* frame, int32_t* d_tile, int32_t* d_p
 /* Clears the recorded device error of the frame. */
 int lodgs_frame_clear_status(lodgs_frame* frame, lodgs_stream stream);
 
+/* The densification criterion (Sec. 4.2: nodes are chosen for densification
+ * by their largest screen-space gradient): with d_max_grad2d [n_nodes]
+ * (device, node-indexed, borrowed) attached, every later
+ * lodgs_render_backward on this frame raises d_max_grad2d[node] to the norm
+ * of dL/d(projected mean) in pixels (FP64, rounded to FP32) of each drawn
+ * node; NULL detaches it.  Not updated after lodgs_render_rows.  Frames that
+ * share one array must not run backwards concurrently. */
+int lodgs_frame_set_densify_stats(lodgs_frame* frame, float* d_max_grad2d);
+
 /* ---------------------------------------------------------------- graphs
  * A forward view (lod_select + render) captured once into a HIP graph and
  * replayed for any camera of the same image size and any tau.  All counts

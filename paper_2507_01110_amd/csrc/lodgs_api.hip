@@ -691,6 +691,12 @@ int lodgs_graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, lodgs
   return LODGS_OK;
 }
 
+int lodgs_frame_set_densify_stats(lodgs_frame* f, float* d_max_grad2d) {
+  if (!f) return set_error(LODGS_E_INVALID, "lodgs_frame_set_densify_stats: null frame");
+  f->max_grad2d = d_max_grad2d;
+  return LODGS_OK;
+}
+
 int lodgs_frame_clear_status(lodgs_frame* f, lodgs_stream stream) {
   if (!f) return set_error(LODGS_E_INVALID, "lodgs_frame_clear_status: null argument");
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, reinterpret_cast<hipStream_t>(stream), f->ctr);

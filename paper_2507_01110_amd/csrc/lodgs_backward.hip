@@ -596,7 +596,8 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
                                                         const FrameCounters* ctr, const uint32_t* drawn_list,
-                                                        const double* grad2d, lodgs_grads sel, lodgs_grads nodes) {
+                                                        const double* grad2d, lodgs_grads sel, lodgs_grads nodes,
+                                                        float* max_grad2d) {
   const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
@@ -616,6 +617,9 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewCo
       // d power / d mean2D = Q d, d power / d conic = -(dx^2 / 2, dx dy, dy^2 / 2)
       const double ca = P.C / P.det, cb = -P.B / P.det, cc = P.A / P.det;
       const double gmx = ca * g2[0] + cb * g2[1], gmy = cb * g2[0] + cc * g2[1];
+      // the densification statistic: the largest screen-space mean gradient
+      // over views (a drawn node is one splat of its view: no races)
+      if (max_grad2d) max_grad2d[node] = fmaxf(max_grad2d[node], (float)__builtin_sqrt(gmx * gmx + gmy * gmy));
       // conic -> projected covariance: GS = -Q GQ Q
       const double gq00 = -0.5 * g2[2], gq01 = -0.5 * g2[3], gq11 = -0.5 * g2[4];
       const double qg00 = ca * gq00 + cb * gq01, qg01 = ca * gq01 + cb * gq11;
@@ -704,7 +708,7 @@ static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodg
   hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
                      f->drawn_list, f->splats, f->dcol, f->grad2d, sel.d_sh, nodes.d_sh);
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->drawn_list, f->grad2d, sel, nodes);
+                     f->drawn_list, f->grad2d, sel, nodes, f->rows_mode ? (float*)nullptr : f->max_grad2d);
 }
 
 void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,

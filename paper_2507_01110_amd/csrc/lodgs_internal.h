@@ -161,6 +161,7 @@ struct lodgs_frame {
   bool rows_mode;            // the last render read rows_dev, with node i at row i
   SceneDev rows_dev;         // the scene's view with the parameter pointers on the rows
   int32_t* iota;             // [max_selected] i at i
+  float* max_grad2d;         // [n_nodes] densification statistic raised by each backward (borrowed; optional)
   int blend_px_fwd;          // pixels per lane of the forward blend (1, 2 or 4)
   int blend_px_bwd;          // pixels per lane of the blend backward (1, 2 or 4)
 };

@@ -318,6 +318,12 @@ class Frame:
         check(_lib.load().lodgs_frame_stats(self._h, ctypes.byref(s), _stream(stream)), "lodgs_frame_stats")
         return s.as_dict()
 
+    def set_densify_stats(self, max_grad2d=None):
+        """Attach a node-indexed float32 array that every later backward raises
+        to each drawn node's screen-space mean-gradient norm (None detaches)."""
+        self._densify = max_grad2d
+        check(_lib.load().lodgs_frame_set_densify_stats(self._h, _ptr(max_grad2d)), "lodgs_frame_set_densify_stats")
+
     def clear_status(self, stream=None):
         check(_lib.load().lodgs_frame_clear_status(self._h, _stream(stream)), "lodgs_frame_clear_status")
 

@@ -517,3 +517,34 @@ def test_medium_view_comparator_cuts(medium):
         for method in ("bfs", "parallel"):
             n = _check_full_cut(O, f, cam, tau, method, cull=True)
             _say("  medium", method, tau, n)
+
+
+def test_densify_statistic_matches_the_oracle(torch_cuda):
+    # the largest screen-space mean gradient of each node over three views
+    # (the densification criterion), against the oracle's FP64 2D gradients;
+    # the same bar as the gradients (1e-3 relative L2), the same nodes touched
+    torch = torch_cuda
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    stat = torch.zeros(S.n_nodes, dtype=torch.float32, device="cuda")
+    want = np.zeros(S.n_nodes)
+    cams = [configs.tiny_camera(256, 256), scenegen.camera_look_at((25, -8, 6), (3, 2, 0), (0, 0, 1), 320, 200),
+            scenegen.camera_look_at((-6, 14, 18), (0, 0, 0), (0, 0, 1), 300, 240)]
+    for k, cam in enumerate(cams):
+        f = _frame(S, cam)
+        f.set_densify_stats(stat)
+        idx, cnt = f.lod_select(cam, 1.0)
+        f.render(cam)
+        ids, _ = O.select(cam, 1.0)
+        F = oracle.OracleFrame(tree, ids, cam)
+        _, dL = oracle.l1_loss_grad(F.image, scenegen.target_image(cam.height, cam.width, 40 + k))
+        f.backward(torch.from_numpy(dL.astype(np.float32)).cuda())
+        g2, _ = F.backward(dL)
+        pos = O.pos_of[ids]
+        want[pos] = np.maximum(want[pos], np.hypot(g2[:, 0], g2[:, 1]))
+    got = stat.cpu().numpy().astype(np.float64)
+    assert np.array_equal(got > 0, want > 0)
+    rel = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+    _say("densify statistic rel L2", rel, int((want > 0).sum()), "nodes")
+    assert rel <= 1e-3
