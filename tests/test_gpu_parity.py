@@ -548,3 +548,32 @@ def test_densify_statistic_matches_the_oracle(torch_cuda):
     rel = float(np.linalg.norm(got - want) / np.linalg.norm(want))
     _say("densify statistic rel L2", rel, int((want > 0).sum()), "nodes")
     assert rel <= 1e-3
+
+
+def test_densify_loop_statistic_edit_rebuild_render(torch_cuda):
+    # the densification loop: the statistic from GPU backwards, the hierarchy
+    # edit on the host, the HSPT rebuilt by a new Scene, and the edited scene
+    # cut and rendered as the oracle does
+    torch = torch_cuda
+    from paper_2507_01110_amd.densify import densify
+    tree = scenegen.build_tree(configs.tiny_spec(n=4096))
+    tree.opacity_logits[::37] = -9.0  # some dead leaves (ids below n_leaves are leaves)
+    S = _scene(tree)
+    stat = torch.zeros(S.n_nodes, dtype=torch.float32, device="cuda")
+    cam = configs.tiny_camera(192, 192)
+    f = _frame(S, cam)
+    f.set_densify_stats(stat)
+    f.lod_select(cam, 1.0)
+    img = f.render(cam)
+    f.backward(torch.sign(img - 0.5))
+    by_id = np.zeros(S.n_nodes)
+    by_id[S.perm] = stat.cpu().numpy()
+    t2, info = densify(tree, by_id, n_spawn=64)
+    _say("densify", info, t2.n_nodes)
+    assert info["respawned"] > 0 and info["spawned"] == 64
+    O2 = oracle.OracleScene(t2)
+    S2 = _scene(t2)
+    f2 = _frame(S2, cam)
+    ids = _check_select(O2, f2, cam, 1.0, True)
+    F = oracle.OracleFrame(t2, ids, cam)
+    _check_image(f2.render(cam), F)
