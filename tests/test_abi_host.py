@@ -83,3 +83,18 @@ def test_hspt_builder_rejects_malformed_trees():
         HSPT(3, np.array([-1, -1, -1]), np.array([-1, -1, -1]), 0, ls, 0.0)
     with pytest.raises(LodgsError):  # cycle: 0 -> (1, 2), 1 -> (0, 2) is rejected (two parents)
         HSPT(3, np.array([1, 0, -1]), np.array([2, 2, -1]), 0, ls, 0.0)
+
+
+def test_public_header_is_plain_c99(tmp_path):
+    # callers of the C ABI need nothing but a C compiler and the header
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("no gcc")
+    src = tmp_path / "t.c"
+    src.write_text('#include "lodgs.h"\nint main(void) { lodgs_adam a; lodgs_cut_cache_params p; (void)a; (void)p;'
+                   ' return 0; }\n')
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), "-c", str(src), "-o", str(tmp_path / "t.o")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
