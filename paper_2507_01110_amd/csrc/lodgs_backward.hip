@@ -93,6 +93,9 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   __shared__ uint32_t bid[NB];
   __shared__ uint32_t ev[NB];
   __shared__ uint8_t hits[NW][4][NB];  // per row of each wave: the batch slots it replays, in order
+  // a row of acc per partial component; slot j's component c sits at column
+  // j ^ c, so the ten lanes of a row adding one slot's components hit ten
+  // banks (the rows are 128 words apart)
   __shared__ float acc[NW][kPartial][NB];
   const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
@@ -242,7 +245,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
           const uint64_t cm = __ballot(any_con);
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            if (row == q && slot < kPartial && ((cm >> (16 * q)) & 0xFFFFull) != 0ull) acc[wv][slot][j] += r;
+            if (row == q && slot < kPartial && ((cm >> (16 * q)) & 0xFFFFull) != 0ull) acc[wv][slot][j ^ slot] += r;
         }
         return !__any(act);
       };
@@ -266,12 +269,13 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
       float* dst = partial + kPartial * (int64_t)bid[threadIdx.x];
 #pragma unroll
       for (int c = 0; c < kPartial; ++c) {
-        float r = acc[0][c][threadIdx.x];
-        acc[0][c][threadIdx.x] = 0.0f;
+        const int col = (int)threadIdx.x ^ c;
+        float r = acc[0][c][col];
+        acc[0][c][col] = 0.0f;
 #pragma unroll
         for (int w = 1; w < NW; ++w) {
-          r += acc[w][c][threadIdx.x];
-          acc[w][c][threadIdx.x] = 0.0f;
+          r += acc[w][c][col];
+          acc[w][c][col] = 0.0f;
         }
         dst[c] = r;
       }
