@@ -89,7 +89,13 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   // keeps the per-wave LDS rows small enough for several workgroups per CU
   constexpr int NT = 256 / PX, NW = 4 / PX, NB = NT < 128 ? NT : 128;
   const ViewConst v = *vp;
-  __shared__ Splat batch[NB];
+  // the first 12 floats of each splat record (mean, axis, power, opacity,
+  // colour): all a replay reads, at a 12-word stride that spreads the rows'
+  // reads of different slots over the banks
+  struct BatchRec {
+    float4 a, b, c;
+  };
+  __shared__ BatchRec batch[NB];
   __shared__ uint32_t bid[NB];
   __shared__ uint32_t ev[NB];
   __shared__ uint8_t hits[NW][4][NB];  // per row of each wave: the batch slots it replays, in order
@@ -252,15 +258,34 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
       // two register sets, each loaded one list entry ahead of its use
       const uint8_t* hl = hits[wv][row];
       auto slot_at = [&](int t) -> int { return t < n ? (int)hl[t] : 0; };
-      Splat sa = batch[slot_at(0)], sb;
+      auto rec = [&](int j) -> Splat {
+        const BatchRec& q = batch[j];
+        Splat sp;
+        sp.mxh = q.a.x;
+        sp.mxl = q.a.y;
+        sp.myh = q.a.z;
+        sp.myl = q.a.w;
+        sp.ce = q.b.x;
+        sp.se = q.b.y;
+        sp.h1 = q.b.z;
+        sp.h2 = q.b.w;
+        sp.o = q.c.x;
+        sp.r = q.c.y;
+        sp.g = q.c.z;
+        sp.b = q.c.w;
+        sp.radius = sp.pad0 = sp.pad1 = 0.0f;
+        sp.clamp = 0u;
+        return sp;
+      };
+      Splat sa = rec(slot_at(0)), sb;
       for (int t = 0;;) {
         const int ja = slot_at(t);
         const bool ha = t < n;
-        sb = batch[slot_at(t + 1)];
+        sb = rec(slot_at(t + 1));
         if (step(sa, ja, ha) || ++t >= nmax) break;
         const int jb = slot_at(t);
         const bool hb = t < n;
-        sa = batch[slot_at(t + 1)];
+        sa = rec(slot_at(t + 1));
         if (step(sb, jb, hb) || ++t >= nmax) break;
       }
     }
