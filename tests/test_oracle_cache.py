@@ -109,3 +109,16 @@ def test_the_budget_holds_and_evicts_the_least_recently_used_first(tiny):
         if kept and dropped:  # nothing older survives a dropped entry
             assert max(dropped) <= min(kept)
     assert C.evictions > 0 and C.hits > 0
+
+
+def test_dist32_is_within_its_rounding_bound_of_the_exact_distance():
+    # five FP32 roundings (three products, two sums) and a correctly rounded
+    # square root: within a few ulp of the exact distance of the FP32 inputs
+    rng = np.random.default_rng(61)
+    for _ in range(2000):
+        mu = rng.uniform(-2000, 2000, 3).astype(np.float32)
+        pos = (mu + rng.normal(0, 10.0 ** rng.uniform(-2, 3), 3)).astype(np.float32)
+        d = oracle.dist32(mu, pos)
+        exact = float(np.sqrt(np.sum((mu.astype(np.float64) - pos.astype(np.float64)) ** 2)))
+        ulp = float(np.spacing(np.float32(exact)))
+        assert abs(float(d) - exact) <= 4 * ulp + 1e-30, (d, exact)
