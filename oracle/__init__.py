@@ -50,7 +50,8 @@ class SelectStats(ctypes.Structure):
 class FrameInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("n_inst", ctypes.c_int64), ("n_visible", ctypes.c_int64),
                 ("n_contrib", ctypes.c_int64), ("TX", ctypes.c_int32), ("TY", ctypes.c_int32),
-                ("skip_1ulp", ctypes.c_int64), ("stop_1ulp", ctypes.c_int64)]
+                ("skip_1ulp", ctypes.c_int64), ("stop_1ulp", ctypes.c_int64), ("skip_flip64", ctypes.c_int64),
+                ("stop_flip64", ctypes.c_int64), ("clamp_flip64", ctypes.c_int64)]
 
 
 def lib():

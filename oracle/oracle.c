@@ -740,8 +740,12 @@ typedef struct orc_frame {
   int64_t* pix_off;   /* [W*H + 1] */
   int32_t* pix_list;
   uint8_t* pix_clamp;
-  /* decision log */
+  /* decision log: FP32 decisions within one ulp of their threshold, and
+   * decisions that the FP64 evaluation of the same test takes the other way
+   * (skip: alpha < 1/255; clamp: o e^power > 0.99; stop: T (1 - alpha) <
+   * 1e-4 with T the FP64 transmittance along the FP32 decisions) */
   int64_t skip_1ulp, stop_1ulp, skip_flip64, stop_flip64, clamp_flip64;
+  double* v64;        /* [n][6] FP64 mx, my, conic a, b, c, opacity (visible splats; the log pass only) */
   /* lazily built for directional finite differences */
   orc_g64* g64;       /* [n] FP64 values of the unperturbed splats */
   int64_t* gpix_off;  /* [n + 1] pixels each splat contributes to (CSR) */
@@ -770,10 +774,11 @@ static uint32_t fbits(float f) {
  *   dx = (px - mxh) - mxl;  dy = (py - myh) - myl;
  *   u1 = fmaf(se, dy, ce*dx);  u2 = fmaf(-se, dx, ce*dy);
  *   power = fmaf(h1*u1, u1, (h2*u2)*u2). */
-static int64_t pixel32(const orc_frame* F, int px, int py, int32_t* list, uint8_t* clampf, int64_t* log4) {
+static int64_t pixel32(const orc_frame* F, int px, int py, int32_t* list, uint8_t* clampf, int64_t* log5) {
   int tile = (py / ORC_TILE) * F->TX + px / ORC_TILE;
   float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   float T = 1.0f;
+  double T64 = 1.0;
   int64_t cnt = 0;
   const float thr = 1.0f / 255.0f;
   for (int64_t k = F->tile_start[tile]; k < F->tile_start[tile + 1]; ++k) {
@@ -789,13 +794,24 @@ static int64_t pixel32(const orc_frame* F, int px, int py, int32_t* list, uint8_
     float power = fmaf(G->h1 * u1, u1, a2);
     float oe = G->o * orc_pexp(power);
     float alpha = fminf(0.99f, oe);
-    if (log4) {
-      if (fabsf(alpha - thr) <= fabsf(nextafterf(thr, 1.0f) - thr)) log4[0]++;
+    /* the FP64 evaluation of the same tests (log pass only) */
+    double oe64 = 0.0, a64 = 0.0;
+    if (log5) {
+      if (fabsf(alpha - thr) <= fabsf(nextafterf(thr, 1.0f) - thr)) log5[0]++;
+      const double* V = F->v64 + 6 * (int64_t)i;
+      const double ddx = ((double)px + 0.5) - V[0], ddy = ((double)py + 0.5) - V[1];
+      oe64 = V[5] * exp(-0.5 * (V[2] * ddx * ddx + V[4] * ddy * ddy) - V[3] * ddx * ddy);
+      a64 = oe64 < 0.99 ? oe64 : 0.99;
+      if ((a64 < 1.0 / 255.0) != (alpha < thr)) log5[2]++;
     }
     if (alpha < thr) continue;
     float tt = T * (1.0f - alpha);
-    if (log4) {
-      if (fabsf(tt - 0.0001f) <= fabsf(nextafterf(0.0001f, 1.0f) - 0.0001f)) log4[1]++;
+    if (log5) {
+      if (fabsf(tt - 0.0001f) <= fabsf(nextafterf(0.0001f, 1.0f) - 0.0001f)) log5[1]++;
+      if ((oe64 > 0.99) != (oe > 0.99f)) log5[4]++;
+      if ((T64 * (1.0 - a64) < 1e-4) != (tt < 0.0001f)) log5[3]++;
+      /* the FP64 transmittance follows the FP32 decisions (the FP64 image's) */
+      T64 *= 1.0 - (oe > 0.99f ? 0.99 : oe64);
     }
     if (tt < 0.0001f) break;
     if (list) {
@@ -812,7 +828,7 @@ void orc_frame_free(orc_frame* F) {
   if (!F) return;
   free(F->P); free(F->g32); free(F->inst_tile); free(F->inst_pos); free(F->tile_start);
   free(F->pix_off); free(F->pix_list); free(F->pix_clamp);
-  free(F->g64); free(F->gpix_off); free(F->gpix);
+  free(F->g64); free(F->gpix_off); free(F->gpix); free(F->v64);
   free(F);
 }
 
@@ -876,20 +892,39 @@ orc_frame* orc_render(int64_t n, const int32_t* ids, const float* means, const f
   }
   free(inst);
   for (int64_t t = 0; t < (int64_t)F->TX * F->TY; ++t) F->tile_start[t + 1] += F->tile_start[t];
+  /* FP64 values of the visible splats for the decision log */
+  F->v64 = (double*)calloc((size_t)(n > 0 ? n : 1) * 6, sizeof(double));
+  if (!F->v64) { orc_frame_free(F); return NULL; }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    if (!F->g32[i].visible) continue;
+    orc_g64 G;
+    orc_project64(F->P + i * np, n_coef, C, &G);
+    double* V = F->v64 + 6 * i;
+    V[0] = G.mx; V[1] = G.my; V[2] = G.ca; V[3] = G.cb; V[4] = G.cc; V[5] = G.o;
+  }
   /* per-pixel contributor lists (CSR) */
   const int64_t npx = (int64_t)F->W * F->H;
   F->pix_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(npx + 1));
   if (!F->pix_off) { orc_frame_free(F); return NULL; }
-  int64_t l1 = 0, l2 = 0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(+ : l1, l2)
+  int64_t l1 = 0, l2 = 0, l3 = 0, l4 = 0, l5 = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : l1, l2, l3, l4, l5)
   for (int64_t p = 0; p < npx; ++p) {
-    int64_t lg[2] = {0, 0};
+    int64_t lg[5] = {0, 0, 0, 0, 0};
     F->pix_off[p + 1] = pixel32(F, (int)(p % F->W), (int)(p / F->W), NULL, NULL, lg);
     l1 += lg[0];
     l2 += lg[1];
+    l3 += lg[2];
+    l4 += lg[3];
+    l5 += lg[4];
   }
   F->skip_1ulp = l1;
   F->stop_1ulp = l2;
+  F->skip_flip64 = l3;
+  F->stop_flip64 = l4;
+  F->clamp_flip64 = l5;
+  free(F->v64);
+  F->v64 = NULL;
   F->pix_off[0] = 0;
   for (int64_t p = 0; p < npx; ++p) F->pix_off[p + 1] += F->pix_off[p];
   int64_t tot = F->pix_off[npx];
@@ -1190,7 +1225,7 @@ int orc_backward(const orc_frame* F, const double* dL_dimg, double* grad2d_out, 
 typedef struct orc_frame_info {
   int64_t n, n_inst, n_visible, n_contrib;
   int32_t TX, TY;
-  int64_t skip_1ulp, stop_1ulp;
+  int64_t skip_1ulp, stop_1ulp, skip_flip64, stop_flip64, clamp_flip64;
 } orc_frame_info;
 
 void orc_frame_get_info(const orc_frame* F, orc_frame_info* I) {
@@ -1204,6 +1239,9 @@ void orc_frame_get_info(const orc_frame* F, orc_frame_info* I) {
   I->TY = F->TY;
   I->skip_1ulp = F->skip_1ulp;
   I->stop_1ulp = F->stop_1ulp;
+  I->skip_flip64 = F->skip_flip64;
+  I->stop_flip64 = F->stop_flip64;
+  I->clamp_flip64 = F->clamp_flip64;
 }
 
 /* Per-splat mirror outputs: depth bits, tiles, rect [x0,x1,y0,y1] and the
