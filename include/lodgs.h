@@ -189,6 +189,24 @@ void lodgs_frame_destroy(lodgs_frame* frame);
 int lodgs_lod_select(lodgs_frame* frame, const lodgs_camera* cam, float tau, uint32_t flags, int32_t* d_idx,
                      int64_t capacity, int32_t* d_count, lodgs_stream stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the HSPT cut of
+ * lodgs_lod_select with no frame.  Its workspace (counters, view constants,
+ * scan sums, 2 bytes per upper node, 12 per SPT and the compaction segments,
+ * about 30 bytes per 512 nodes) lives in one static device array of
+ * LODGS_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; the call
+ * allocates nothing.  Same arguments and output contract as lodgs_lod_select
+ * (selected positions ascending in d_idx, the full count in *d_count, a
+ * count above capacity meaning the list was cut short), with the scene in
+ * place of the frame and flags limited to LODGS_CULL | LODGS_CONSERVATIVE
+ * (else LODGS_E_INVALID).  A scene whose workspace exceeds the array returns
+ * LODGS_E_CAPACITY before any launch.  Every call on one GPU shares the
+ * array, which keeps the last call's contents (each call resets the counters
+ * it reads): calls that overlap on one GPU race, so keep them stream-ordered. */
+#define LODGS_NOALLOC_SCRATCH_BYTES (32u << 20)
+int lodgs_lod_select_noalloc(const lodgs_scene* scene, const lodgs_camera* cam, float tau, uint32_t flags,
+                             int32_t* d_idx, int64_t capacity, int32_t* d_count, lodgs_stream stream);
+
 /* ---------------------------------------------------------------- SPT-cut cache
  * The GPU cache of SPT cuts (Sec. 4.4 "Caching on the GPU", Eq. 7, and the
  * training loop of Alg. 3).  Here the scene is resident, so a cache entry

@@ -84,6 +84,8 @@ EXPORTS = {
     "lodgs_frame_create": ([c_p, ctypes.POINTER(FrameCaps), ctypes.POINTER(c_p)], ctypes.c_int),
     "lodgs_frame_destroy": ([c_p], None),
     "lodgs_lod_select": ([c_p, ctypes.POINTER(Camera), f32, ctypes.c_uint32, c_p, i64, c_p, c_p], ctypes.c_int),
+    "lodgs_lod_select_noalloc": ([c_p, ctypes.POINTER(Camera), f32, ctypes.c_uint32, c_p, i64, c_p, c_p],
+                                 ctypes.c_int),
     "lodgs_render": ([c_p, c_p, c_p, ctypes.POINTER(Camera), c_p, c_p, c_p], ctypes.c_int),
     "lodgs_render_backward": ([c_p, c_p, ctypes.POINTER(Grads), ctypes.POINTER(Grads), c_p], ctypes.c_int),
     "lodgs_frame_stats": ([c_p, ctypes.POINTER(Stats), c_p], ctypes.c_int),

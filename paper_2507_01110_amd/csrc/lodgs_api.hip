@@ -124,6 +124,10 @@ __global__ void k_selftest(const float* in32, const double* in64, int64_t n, flo
   }
 }
 
+}  // namespace
+
+namespace lodgs {
+
 bool camera_ok(const lodgs_camera* c) {
   if (!c) return false;
   if (c->width <= 0 || c->height <= 0 || c->width > 16384 || c->height > 16384) return false;
@@ -136,6 +140,12 @@ bool camera_ok(const lodgs_camera* c) {
     if (!std::isfinite(c->t[k]) || !std::isfinite(c->pos[k])) return false;
   return true;
 }
+
+}  // namespace lodgs
+
+using lodgs::camera_ok;
+
+namespace {
 
 template <class T>
 hipError_t dalloc(T** p, size_t count) {

@@ -207,6 +207,10 @@ void launch_set_view(const ViewConst& v, ViewConst* dst, FrameCounters* ctr, int
 
 int hip_fail(hipError_t e, const char* what);
 
+// A camera the kernels can take: positive sizes up to 16384, finite values,
+// positive focal lengths and near plane.
+bool camera_ok(const lodgs_camera* c);
+
 // Pixels per lane of the forward blend and the blend backward (1), or
 // LODGS_BLEND_PX_FWD / LODGS_BLEND_PX_BWD (1, 2 or 4) when set in the
 // environment (a tuning knob: images are identical, gradients equal up to the

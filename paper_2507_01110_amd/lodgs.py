@@ -113,6 +113,18 @@ class Scene:
             _lib._lib.lodgs_scene_destroy(h)
             self._h = None
 
+    def lod_select_noalloc(self, cam, tau: float, idx, count, cull: bool = True, conservative: bool = False,
+                           stream=None):
+        """The HSPT cut into the caller's idx (int32 [capacity]) / count (int32
+        [1]) device tensors through lodgs_lod_select_noalloc: no frame, no
+        device allocation (the workspace is the library's static array)."""
+        c = camera_struct(cam)
+        flags = (_lib.CULL if cull else 0) | (_lib.CONSERVATIVE if conservative else 0)
+        check(_lib.load().lodgs_lod_select_noalloc(self._h, ctypes.byref(c), float(tau), flags, _ptr(idx),
+                                                   idx.numel(), _ptr(count), _stream(stream)),
+              "lodgs_lod_select_noalloc")
+        return idx, count
+
     def param_bytes(self) -> int:
         return sum(t.numel() * t.element_size() for t in self.params.values())
 
