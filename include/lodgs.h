@@ -360,6 +360,81 @@ int lodgs_graph_capture_view(lodgs_frame* frame, const lodgs_camera* cam, float 
 int lodgs_graph_launch(lodgs_graph* graph, const lodgs_camera* cam, float tau, lodgs_stream stream);
 void lodgs_graph_destroy(lodgs_graph* graph);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous-batching render server, forward only (the renderer of Sec. 5
+ * on the same LoD path: lodgs_lod_select then lodgs_render per request).
+ * Requests of the declared image-size classes, any camera and any tau are
+ * queued by lodgs_server_submit and admitted into slots as slots and memory
+ * free up; each slot owns a frame, a stream and one captured view graph per
+ * size class, so the requests of different slots overlap on the device.  The
+ * scene and every per-request buffer stay on the device; the host only
+ * queues, launches and polls events.
+ * Admission: an idle slot whose capacities cover the request takes it;
+ * otherwise a new slot is made if fewer than max_slots exist and free HBM
+ * (hipMemGetInfo) is at least the slot's bytes plus hbm_reserve; otherwise
+ * the request waits.  A request whose selection or instance list overflows
+ * its slot's capacities runs again, first in the queue, with the counts it
+ * reported as its minimum capacities (a larger slot is made, evicting idle
+ * slots too small for it when memory or the slot limit requires).  A request
+ * that no slot can ever take (no slot busy, none large enough, none can be
+ * made) completes with LODGS_E_CAPACITY: rejected, its image unwritten.
+ * A server is driven by one host thread; it must be destroyed before the
+ * scene.  Making a slot synchronises the null stream. */
+#define LODGS_SERVER_MAX_SIZES 8
+typedef struct lodgs_server_caps {
+  int32_t n_sizes;                         /* image-size classes, 1..LODGS_SERVER_MAX_SIZES  */
+  int32_t sizes[LODGS_SERVER_MAX_SIZES][2]; /* width, height of each class                   */
+  int32_t max_slots;                       /* requests in flight at most, 1..64              */
+  int64_t max_selected;                    /* capacities of a slot as first made             */
+  int64_t max_instances;
+  int64_t hbm_reserve;                     /* free HBM bytes a new slot must leave           */
+  uint32_t flags;                          /* LODGS_CULL | LODGS_CONSERVATIVE                 */
+  float bg[3];                             /* background colour                              */
+} lodgs_server_caps;
+
+typedef struct lodgs_request {
+  lodgs_camera cam;  /* width x height must be one of the size classes       */
+  float tau;         /* pixel threshold of the cut, finite, >= 0              */
+  float* d_rgb;      /* caller's device image [height][width][3] FP32, written
+                        by the time the request completes; owned by the caller,
+                        who keeps it until then                               */
+  uint64_t user;     /* returned in the completion                            */
+} lodgs_request;
+
+typedef struct lodgs_completion {
+  uint64_t ticket;      /* lodgs_server_submit's ticket                        */
+  uint64_t user;
+  int32_t status;       /* LODGS_OK, or LODGS_E_CAPACITY: rejected             */
+  int32_t attempts;     /* launches it took (1 + capacity retries)             */
+  int32_t n_selected;   /* counts of its final launch                          */
+  int32_t n_drawn;
+  int64_t n_instances;
+  double t_submit;      /* host monotonic clock, seconds: queued, first        */
+  double t_admit;       /* launch of the final attempt, seen complete by a poll */
+  double t_done;
+} lodgs_completion;
+
+typedef struct lodgs_server_stats {
+  int32_t slots, busy, queued, unpolled;
+  int64_t slot_bytes;       /* device bytes held by the slots                   */
+  int64_t base_slot_bytes;  /* bytes of one slot at the first capacities        */
+  int64_t retries, rejected, evicted;
+} lodgs_server_stats;
+
+typedef struct lodgs_server lodgs_server;
+
+int lodgs_server_create(const lodgs_scene* scene, const lodgs_server_caps* caps, lodgs_server** out);
+void lodgs_server_destroy(lodgs_server* server);
+/* Queues the request (LODGS_E_INVALID for a size outside the classes or a
+ * bad camera / tau / null image) and admits what can be admitted; *ticket
+ * identifies it in its completion. */
+int lodgs_server_submit(lodgs_server* server, const lodgs_request* request, uint64_t* ticket);
+/* Non-blocking: collects finished requests (re-queueing overflowed ones),
+ * admits queued ones, and copies up to max completions, oldest first, to
+ * out; *n receives their number. */
+int lodgs_server_poll(lodgs_server* server, lodgs_completion* out, int32_t max, int32_t* n);
+int lodgs_server_stats_read(const lodgs_server* server, lodgs_server_stats* out);
+
 /* ---------------------------------------------------------------- timing
  * Timing mode brackets every stage of lod_select / render / render_backward
  * with HIP events on the call's stream.  lodgs_frame_timings blocks until

@@ -75,6 +75,33 @@ class Timings(ctypes.Structure):
         return {name: (float(self.ms[k]), int(self.calls[k])) for k, name in enumerate(STAGES)}
 
 
+SERVER_MAX_SIZES = 8
+
+
+class ServerCaps(ctypes.Structure):
+    _fields_ = [("n_sizes", i32), ("sizes", (i32 * 2) * SERVER_MAX_SIZES), ("max_slots", i32),
+                ("max_selected", i64), ("max_instances", i64), ("hbm_reserve", i64), ("flags", ctypes.c_uint32),
+                ("bg", f32 * 3)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("cam", Camera), ("tau", f32), ("d_rgb", c_p), ("user", ctypes.c_uint64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("user", ctypes.c_uint64), ("status", i32), ("attempts", i32),
+                ("n_selected", i32), ("n_drawn", i32), ("n_instances", i64), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("slots", i32), ("busy", i32), ("queued", i32), ("unpolled", i32), ("slot_bytes", i64),
+                ("base_slot_bytes", i64), ("retries", i64), ("rejected", i64), ("evicted", i64)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
 EXPORTS = {
     "lodgs_hspt_build": ([i64, c_p, c_p, i32, c_p, ctypes.c_double, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p],
                          ctypes.c_int),
@@ -109,6 +136,11 @@ EXPORTS = {
     "lodgs_gather_rows": ([ctypes.POINTER(Grads), ctypes.POINTER(Grads), i32, c_p, c_p, i64, i64, c_p], ctypes.c_int),
     "lodgs_render_rows": ([c_p, ctypes.POINTER(Grads), c_p, ctypes.POINTER(Camera), c_p, c_p, c_p], ctypes.c_int),
     "lodgs_frame_set_densify_stats": ([c_p, c_p], ctypes.c_int),
+    "lodgs_server_create": ([c_p, ctypes.POINTER(ServerCaps), ctypes.POINTER(c_p)], ctypes.c_int),
+    "lodgs_server_destroy": ([c_p], None),
+    "lodgs_server_submit": ([c_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "lodgs_server_poll": ([c_p, ctypes.POINTER(Completion), i32, ctypes.POINTER(i32)], ctypes.c_int),
+    "lodgs_server_stats_read": ([c_p, ctypes.POINTER(ServerStats)], ctypes.c_int),
     "lodgs_last_error": ([], ctypes.c_char_p),
 }
 

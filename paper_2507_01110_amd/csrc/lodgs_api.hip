@@ -173,6 +173,24 @@ __global__ void k_iota(int32_t* a, int64_t n) {
     a[i] = (int32_t)i;
 }
 
+}  // namespace
+
+namespace lodgs {
+
+size_t frame_bytes(const lodgs_scene* scene, const lodgs_frame_caps& caps) {
+  lodgs_frame f{};
+  size_t total = 0;
+  frame_arrays(&f, scene->dev, caps, [&total](auto*& ptr, size_t cnt) {
+    const size_t b = sizeof(*ptr) * (cnt > 0 ? cnt : 1);
+    total += (b + 255) / 256 * 256;  // hipMalloc's granularity at least
+  });
+  return total;
+}
+
+}  // namespace lodgs
+
+namespace {
+
 // Selection position of each instance in tile order.
 __global__ void k_instance_positions(const uint2* info_k, int64_t m, int32_t* pos) {
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < m; k += (int64_t)gridDim.x * blockDim.x)
@@ -272,64 +290,18 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   f->caps = *caps;
   f->blend_px_fwd = lodgs::blend_pixels_per_lane(false);
   f->blend_px_bwd = lodgs::blend_pixels_per_lane(true);
-  const SceneDev& S = scene->dev;
-  const size_t ns = (size_t)caps->max_selected, ni = (size_t)caps->max_instances;
-  const size_t nt = (size_t)((caps->max_width + 15) / 16) * ((caps->max_height + 15) / 16);
   hipError_t e = hipSuccess;
-#define A(ptr, cnt) if (e == hipSuccess) e = dalloc(&f->ptr, cnt)
-  A(ctr, 1);
-  A(block_sums, lodgs::kScanGrid + 1);
-  A(sort_table, (size_t)256 * lodgs::kSortGrid);
-  A(sort_below, (size_t)256 * lodgs::kSortGrid);
-  A(upper_sel, (size_t)S.n_upper);
-  A(upper_test, (size_t)S.n_upper);
-  A(spt_high, (size_t)S.n_spt);
-  A(spt_X, (size_t)S.n_spt);
-  A(spt_off, (size_t)S.n_spt);
-  A(seg, (size_t)(S.n_upper + 63) / 64 + (size_t)S.n_spt + (size_t)S.n_nodes / 512 + 1);
-  A(chunk_owner, (size_t)S.n_spt + (size_t)S.n_nodes / 512 + 1);
-  A(splats, ns);
-  A(depth_key, ns);
-  A(depth_key2, ns);
-  A(order, ns);
-  A(order2, ns);
-  A(tiles, ns);
-  A(inst_off, ns);
-  A(drawn_rank, ns);
-  A(drawn_list, ns);
-  A(depth_rank, ns);
-  A(rect, ns);
-  A(ikey, ni);
-  A(ival, ni);
-  A(ikey2, ni);
-  A(ival2, ni);
-  A(inst_info, ni);
-  A(inst_grad, (size_t)lodgs::kPartial * ni);
-  A(inst_event, ni);
-  A(info_k, ni);
-  A(rank_info, 2 * ns);
-  A(grad2d, 9 * ns);
-  A(dcol, 9 * ns);
-  A(long_list, ns);
-  A(ranges, nt);
-  A(tile_order, nt);
-  A(work, 2);
-  A(d_view_sel, 1);
-  A(d_view_ren, 1);
-  A(iota, ns);
-  if (S.parent) {
-    A(cut_bits, (size_t)lodgs::cut_bit_words(S.n_nodes));
-    A(frontier[0], ns);
-    A(frontier[1], ns);
-    A(level_count, (size_t)S.height + 1);
-    f->cut_height = S.height;
-  }
-#undef A
+  lodgs::frame_arrays(f, scene->dev, *caps, [&e](auto*& ptr, size_t cnt) {
+    if (e == hipSuccess) e = dalloc(&ptr, cnt);
+  });
+  if (scene->dev.parent) f->cut_height = scene->dev.height;
   if (e != hipSuccess) {
     free_frame(f);
     (void)hipGetLastError();
     return set_error(LODGS_E_OOM, "lodgs_frame_create: device allocation failed");
   }
+  const SceneDev& S = scene->dev;
+  const size_t ns = (size_t)caps->max_selected;
   FrameCounters c;
   std::memset(&c, 0, sizeof c);
   c.spt_count = S.n_spt;
@@ -338,7 +310,9 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_iota, dim3(1024), dim3(256), 0, 0, f->iota, (int64_t)ns);
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    // the null stream only: work in flight on other (non-blocking) streams,
+    // such as a server's other slots, is not waited for
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   }
   if (e != hipSuccess) {
     free_frame(f);
@@ -583,7 +557,46 @@ struct lodgs_graph {
   const int32_t* count_ren;
   int64_t cap_sel, cap_ren;
   int32_t width, height;
+  // the forward blend node: its output image argument is replaced when a
+  // replay writes to another image
+  hipGraphNode_t node_blend;
+  hipKernelNodeParams p_blend;
+  int blend_arg, blend_nargs;
 };
+
+namespace lodgs {
+
+int graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, float* d_rgb, hipStream_t st) {
+  if (!g || !camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: bad argument");
+  if (cam->width != g->width || cam->height != g->height)
+    return set_error(LODGS_E_INVALID, "lodgs_graph_launch: image size differs from the captured one");
+  if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: bad tau");
+  ViewConst vs = make_view(*cam, tau), vr = make_view(*cam, 0.0f);
+  void* args_s[6] = {&vs, &g->dst_sel, &g->ctr_sel, &g->mode_sel, &g->count_sel, &g->cap_sel};
+  void* args_r[6] = {&vr, &g->dst_ren, &g->ctr_ren, &g->mode_ren, &g->count_ren, &g->cap_ren};
+  hipKernelNodeParams ps = g->p_sel, pr = g->p_ren;
+  ps.kernelParams = args_s;
+  pr.kernelParams = args_r;
+  hipError_t e = hipGraphExecKernelNodeSetParams(g->exec, g->node_sel, &ps);
+  if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->node_ren, &pr);
+  if (e == hipSuccess && d_rgb) {
+    // the captured arguments of the blend node, with the image replaced
+    void* args_b[16];
+    if (g->blend_nargs > 16) return set_error(LODGS_E_STATE, "lodgs_graph_launch: blend node arguments");
+    for (int k = 0; k < g->blend_nargs; ++k) args_b[k] = g->p_blend.kernelParams[k];
+    args_b[g->blend_arg] = &d_rgb;
+    hipKernelNodeParams pb = g->p_blend;
+    pb.kernelParams = args_b;
+    e = hipGraphExecKernelNodeSetParams(g->exec, g->node_blend, &pb);
+  }
+  if (e == hipSuccess) e = hipGraphLaunch(g->exec, st);
+  if (e != hipSuccess) return hip_fail(e, "lodgs_graph_launch");
+  g->frame->view = vr;
+  if (d_rgb) g->frame->r_rgb = d_rgb;
+  return LODGS_OK;
+}
+
+}  // namespace lodgs
 
 extern "C" {
 
@@ -639,6 +652,15 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
     if (hipGraphNodeGetType(nodes[k], &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
     hipKernelNodeParams p;
     if (hipGraphKernelNodeGetParams(nodes[k], &p) != hipSuccess) continue;
+    int nargs = 0;
+    const int oa = lodgs::blend_output_arg(p.func, &nargs);
+    if (oa >= 0) {
+      g->node_blend = nodes[k];
+      g->p_blend = p;
+      g->blend_arg = oa;
+      g->blend_nargs = nargs;
+      continue;
+    }
     if (p.func != reinterpret_cast<void*>(&lodgs::k_set_view)) continue;
     lodgs::ViewConst* dst = *reinterpret_cast<lodgs::ViewConst**>(p.kernelParams[1]);
     FrameCounters* ctr = *reinterpret_cast<FrameCounters**>(p.kernelParams[2]);
@@ -663,7 +685,7 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
       g->cap_ren = cap;
     }
   }
-  if (e == hipSuccess && (!g->node_sel || !g->node_ren)) {
+  if (e == hipSuccess && (!g->node_sel || !g->node_ren || !g->node_blend)) {
     lodgs_graph_destroy(g);
     return set_error(LODGS_E_STATE, "lodgs_graph_capture_view: view nodes not found in the captured graph");
   }
@@ -683,22 +705,7 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
 }
 
 int lodgs_graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, lodgs_stream stream) {
-  if (!g || !camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: bad argument");
-  if (cam->width != g->width || cam->height != g->height)
-    return set_error(LODGS_E_INVALID, "lodgs_graph_launch: image size differs from the captured one");
-  if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: bad tau");
-  lodgs::ViewConst vs = lodgs::make_view(*cam, tau), vr = lodgs::make_view(*cam, 0.0f);
-  void* args_s[6] = {&vs, &g->dst_sel, &g->ctr_sel, &g->mode_sel, &g->count_sel, &g->cap_sel};
-  void* args_r[6] = {&vr, &g->dst_ren, &g->ctr_ren, &g->mode_ren, &g->count_ren, &g->cap_ren};
-  hipKernelNodeParams ps = g->p_sel, pr = g->p_ren;
-  ps.kernelParams = args_s;
-  pr.kernelParams = args_r;
-  hipError_t e = hipGraphExecKernelNodeSetParams(g->exec, g->node_sel, &ps);
-  if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->node_ren, &pr);
-  if (e == hipSuccess) e = hipGraphLaunch(g->exec, reinterpret_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "lodgs_graph_launch");
-  g->frame->view = vr;
-  return LODGS_OK;
+  return lodgs::graph_launch(g, cam, tau, nullptr, reinterpret_cast<hipStream_t>(stream));
 }
 
 int lodgs_frame_set_densify_stats(lodgs_frame* f, float* d_max_grad2d) {

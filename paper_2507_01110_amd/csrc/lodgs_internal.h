@@ -234,9 +234,79 @@ void launch_select_full(lodgs_frame* f, const ViewConst& v, uint32_t flags, int3
                         int32_t* d_count, hipStream_t st);
 // Words of the node bitmask: whole 64-node waves.
 inline int64_t cut_bit_words(int64_t n_nodes) { return 2 * ((n_nodes + 63) / 64); }
+// Replays a captured view for cam and tau on st, writing the image to d_rgb
+// (the captured image when null).
+int graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, float* d_rgb, hipStream_t st);
+// Position of the output image among the arguments of a forward blend kernel
+// (the function of a captured kernel node) and its argument count in
+// *n_args, or -1 when func is not one: a captured view is pointed at another
+// image by updating that one argument.
+int blend_output_arg(const void* func, int* n_args);
 void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, const ViewConst& v,
                    const float bg[3], float* d_rgb, hipStream_t st);
 void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
                      hipStream_t st);
+
+}  // namespace lodgs
+
+namespace lodgs {
+
+// Every device array of a frame with its element count, in allocation order:
+// fn(pointer member, count).  lodgs_frame_create allocates through it and
+// frame_bytes sums it, so the two cannot disagree.
+template <class Fn>
+void frame_arrays(lodgs_frame* f, const SceneDev& S, const lodgs_frame_caps& caps, Fn&& fn) {
+  const size_t ns = (size_t)caps.max_selected, ni = (size_t)caps.max_instances;
+  const size_t nt = (size_t)((caps.max_width + 15) / 16) * ((caps.max_height + 15) / 16);
+  fn(f->ctr, 1);
+  fn(f->block_sums, kScanGrid + 1);
+  fn(f->sort_table, (size_t)256 * kSortGrid);
+  fn(f->sort_below, (size_t)256 * kSortGrid);
+  fn(f->upper_sel, (size_t)S.n_upper);
+  fn(f->upper_test, (size_t)S.n_upper);
+  fn(f->spt_high, (size_t)S.n_spt);
+  fn(f->spt_X, (size_t)S.n_spt);
+  fn(f->spt_off, (size_t)S.n_spt);
+  fn(f->seg, (size_t)(S.n_upper + 63) / 64 + (size_t)S.n_spt + (size_t)S.n_nodes / 512 + 1);
+  fn(f->chunk_owner, (size_t)S.n_spt + (size_t)S.n_nodes / 512 + 1);
+  fn(f->splats, ns);
+  fn(f->depth_key, ns);
+  fn(f->depth_key2, ns);
+  fn(f->order, ns);
+  fn(f->order2, ns);
+  fn(f->tiles, ns);
+  fn(f->inst_off, ns);
+  fn(f->drawn_rank, ns);
+  fn(f->drawn_list, ns);
+  fn(f->depth_rank, ns);
+  fn(f->rect, ns);
+  fn(f->ikey, ni);
+  fn(f->ival, ni);
+  fn(f->ikey2, ni);
+  fn(f->ival2, ni);
+  fn(f->inst_info, ni);
+  fn(f->inst_grad, (size_t)kPartial * ni);
+  fn(f->inst_event, ni);
+  fn(f->info_k, ni);
+  fn(f->rank_info, 2 * ns);
+  fn(f->grad2d, 9 * ns);
+  fn(f->dcol, 9 * ns);
+  fn(f->long_list, ns);
+  fn(f->ranges, nt);
+  fn(f->tile_order, nt);
+  fn(f->work, 2);
+  fn(f->d_view_sel, 1);
+  fn(f->d_view_ren, 1);
+  fn(f->iota, ns);
+  if (S.parent) {
+    fn(f->cut_bits, (size_t)cut_bit_words(S.n_nodes));
+    fn(f->frontier[0], ns);
+    fn(f->frontier[1], ns);
+    fn(f->level_count, (size_t)S.height + 1);
+  }
+}
+
+// Device bytes lodgs_frame_create allocates for these capacities.
+size_t frame_bytes(const lodgs_scene* scene, const lodgs_frame_caps& caps);
 
 }  // namespace lodgs

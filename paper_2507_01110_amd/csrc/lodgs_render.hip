@@ -661,6 +661,21 @@ static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], 
   }
 }
 
+int blend_output_arg(const void* func, int* n_args) {
+  // k_blend_q (..., bg2, rgb, event8) and k_blend<false, PX> (..., bg2, rgb, event, work)
+  if (func == reinterpret_cast<const void*>(&k_blend_q)) {
+    *n_args = 11;
+    return 9;
+  }
+  if (func == reinterpret_cast<const void*>(&k_blend<false, 1>) ||
+      func == reinterpret_cast<const void*>(&k_blend<false, 2>) ||
+      func == reinterpret_cast<const void*>(&k_blend<false, 4>)) {
+    *n_args = 12;
+    return 9;
+  }
+  return -1;
+}
+
 void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, const ViewConst& v,
                    const float bg[3], float* d_rgb, hipStream_t st) {
   const SceneDev& S = render_params(f);

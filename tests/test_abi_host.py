@@ -98,3 +98,38 @@ def test_public_header_is_plain_c99(tmp_path):
                         os.path.join(ROOT, "include"), "-c", str(src), "-o", str(tmp_path / "t.o")],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    # every struct the binding passes across the ABI has the C compiler's size
+    # and field offsets
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("no gcc")
+    L = _lib()
+    structs = {"lodgs_camera": L.Camera, "lodgs_scene_desc": L.SceneDesc, "lodgs_frame_caps": L.FrameCaps,
+               "lodgs_grads": L.Grads, "lodgs_adam": L.Adam, "lodgs_cut_cache_params": L.CutCacheParams,
+               "lodgs_cut_cache_stats": L.CutCacheStats, "lodgs_stats": L.Stats, "lodgs_timings": L.Timings,
+               "lodgs_server_caps": L.ServerCaps, "lodgs_request": L.Request, "lodgs_completion": L.Completion,
+               "lodgs_server_stats": L.ServerStats}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lodgs.h"', 'int main(void) {']
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        w = line.split()
+        got[tuple(w[:-1])] = int(w[-1])
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
