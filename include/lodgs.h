@@ -359,6 +359,21 @@ int lodgs_graph_capture_view(lodgs_frame* frame, const lodgs_camera* cam, float 
  * stream; LODGS_E_INVALID for another image size. */
 int lodgs_graph_launch(lodgs_graph* graph, const lodgs_camera* cam, float tau, lodgs_stream stream);
 void lodgs_graph_destroy(lodgs_graph* graph);
+/* A training step captured into one graph: lod_select, render into d_rgb,
+ * the L1 loss against d_target (d_dL receives dL/dimage, *d_loss the loss if
+ * d_loss is not NULL) and render_backward into sel or nodes (one of them, or
+ * neither; as lodgs_render_backward), the operations of Alg. 3's
+ * render-and-optimise step without the optimizer.  Same rules as
+ * lodgs_graph_capture_view; every buffer given here is reused by every
+ * replay and must outlive the graph. */
+int lodgs_graph_capture_step(lodgs_frame* frame, const lodgs_camera* cam, float tau, uint32_t flags,
+                             int32_t* d_idx, int64_t capacity, int32_t* d_count, const float bg[3], float* d_rgb,
+                             const float* d_target, float* d_dL, float* d_loss, const lodgs_grads* sel,
+                             const lodgs_grads* nodes, lodgs_stream stream, lodgs_graph** out);
+/* Replays a training-step graph for cam (the captured size), tau and the
+ * target image d_target ([height][width][3], device). */
+int lodgs_graph_launch_step(lodgs_graph* graph, const lodgs_camera* cam, float tau, const float* d_target,
+                            lodgs_stream stream);
 
 /* ---------------------------------------------------------------- serving
  * Continuous-batching render server, forward only (the renderer of Sec. 5

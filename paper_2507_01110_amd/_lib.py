@@ -127,6 +127,10 @@ EXPORTS = {
                                   ctypes.POINTER(c_p)], ctypes.c_int),
     "lodgs_graph_launch": ([c_p, ctypes.POINTER(Camera), f32, c_p], ctypes.c_int),
     "lodgs_graph_destroy": ([c_p], None),
+    "lodgs_graph_capture_step": ([c_p, ctypes.POINTER(Camera), f32, ctypes.c_uint32, c_p, i64, c_p, c_p, c_p, c_p, c_p,
+                                  c_p, ctypes.POINTER(Grads), ctypes.POINTER(Grads), c_p, ctypes.POINTER(c_p)],
+                                 ctypes.c_int),
+    "lodgs_graph_launch_step": ([c_p, ctypes.POINTER(Camera), f32, c_p, c_p], ctypes.c_int),
     "lodgs_adam_cut": ([ctypes.POINTER(Grads)] * 4 + [ctypes.POINTER(Adam), c_p, c_p, i64, i64, c_p], ctypes.c_int),
     "lodgs_cut_cache_create": ([c_p, ctypes.POINTER(CutCacheParams), ctypes.POINTER(c_p)], ctypes.c_int),
     "lodgs_cut_cache_destroy": ([c_p], None),

@@ -562,9 +562,27 @@ struct lodgs_graph {
   hipGraphNode_t node_blend;
   hipKernelNodeParams p_blend;
   int blend_arg, blend_nargs;
+  // a training step's loss node (nullptr in a view graph): its target image
+  // argument is replaced when a replay takes another target
+  hipGraphNode_t node_l1;
+  hipKernelNodeParams p_l1;
+  int l1_arg, l1_nargs;
 };
 
 namespace lodgs {
+
+// Replaces argument `arg` of a captured kernel node (nargs arguments) by the
+// pointer value v.
+static hipError_t set_pointer_arg(hipGraphExec_t exec, hipGraphNode_t node, const hipKernelNodeParams& p, int arg,
+                                  int nargs, const void* v) {
+  void* args[16];
+  if (nargs > 16) return hipErrorInvalidValue;
+  for (int k = 0; k < nargs; ++k) args[k] = p.kernelParams[k];
+  args[arg] = &v;
+  hipKernelNodeParams q = p;
+  q.kernelParams = args;
+  return hipGraphExecKernelNodeSetParams(exec, node, &q);
+}
 
 int graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, float* d_rgb, hipStream_t st) {
   if (!g || !camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: bad argument");
@@ -580,14 +598,8 @@ int graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, float* d_rg
   hipError_t e = hipGraphExecKernelNodeSetParams(g->exec, g->node_sel, &ps);
   if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g->exec, g->node_ren, &pr);
   if (e == hipSuccess && d_rgb) {
-    // the captured arguments of the blend node, with the image replaced
-    void* args_b[16];
-    if (g->blend_nargs > 16) return set_error(LODGS_E_STATE, "lodgs_graph_launch: blend node arguments");
-    for (int k = 0; k < g->blend_nargs; ++k) args_b[k] = g->p_blend.kernelParams[k];
-    args_b[g->blend_arg] = &d_rgb;
-    hipKernelNodeParams pb = g->p_blend;
-    pb.kernelParams = args_b;
-    e = hipGraphExecKernelNodeSetParams(g->exec, g->node_blend, &pb);
+    if (g->node_l1) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: a training step keeps its image");
+    e = set_pointer_arg(g->exec, g->node_blend, g->p_blend, g->blend_arg, g->blend_nargs, d_rgb);
   }
   if (e == hipSuccess) e = hipGraphLaunch(g->exec, st);
   if (e != hipSuccess) return hip_fail(e, "lodgs_graph_launch");
@@ -596,53 +608,17 @@ int graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, float* d_rg
   return LODGS_OK;
 }
 
-}  // namespace lodgs
-
-extern "C" {
-
-void lodgs_graph_destroy(lodgs_graph* g) {
-  if (!g) return;
-  if (g->exec) (void)hipGraphExecDestroy(g->exec);
-  if (g->graph) (void)hipGraphDestroy(g->graph);
-  delete g;
-}
-
-int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_t flags, int32_t* d_idx,
-                             int64_t capacity, int32_t* d_count, const float bg[3], float* d_rgb,
-                             lodgs_stream stream, lodgs_graph** out) {
-  if (!f || !d_idx || !d_count || !d_rgb || !out || !stream)
-    return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: null argument (a non-default stream is required)");
-  *out = nullptr;
-  if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: bad camera");
-  if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: bad tau");
-  if (capacity < 0 || capacity > (int64_t)INT32_MAX || (flags & ~(LODGS_CULL | LODGS_CONSERVATIVE)))
-    return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: bad capacity or flags");
-  if (cam->width > f->caps.max_width || cam->height > f->caps.max_height)
-    return set_error(LODGS_E_CAPACITY, "lodgs_graph_capture_view: image larger than the frame's capacity");
-  if (f->timing) return set_error(LODGS_E_STATE, "lodgs_graph_capture_view: frame is in timing mode");
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  lodgs_graph* g = new (std::nothrow) lodgs_graph();
-  if (!g) return set_error(LODGS_E_OOM, "lodgs_graph_capture_view: out of host memory");
-  g->frame = f;
-  g->width = cam->width;
-  g->height = cam->height;
-  float b[3] = {0.0f, 0.0f, 0.0f};
-  if (bg)
-    for (int k = 0; k < 3; ++k) b[k] = bg[k];
-  const lodgs::ViewConst vs = lodgs::make_view(*cam, tau), vr = lodgs::make_view(*cam, 0.0f);
+// Captures what launch() enqueues on st into g, finds the nodes a replay
+// updates (the two view-constant nodes, the forward blend, the loss if any)
+// and instantiates the graph.
+template <class Launch>
+static int capture(lodgs_graph* g, hipStream_t st, const char* who, Launch launch) {
+  lodgs_frame* f = g->frame;
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) {
-    delete g;
-    return hip_fail(e, "lodgs_graph_capture_view: begin capture");
-  }
-  lodgs::launch_select(f, vs, flags, d_idx, capacity, d_count, st);
-  f->rows_mode = false;
-  lodgs::launch_render(f, d_idx, d_count, vr, b, d_rgb, st);
+  if (e != hipSuccess) return hip_fail(e, who);
+  launch();
   e = hipStreamEndCapture(st, &g->graph);
-  if (e != hipSuccess) {
-    lodgs_graph_destroy(g);
-    return hip_fail(e, "lodgs_graph_capture_view: end capture");
-  }
+  if (e != hipSuccess) return hip_fail(e, who);
   size_t nn = 0;
   e = hipGraphGetNodes(g->graph, nullptr, &nn);
   std::vector<hipGraphNode_t> nodes(nn);
@@ -653,16 +629,24 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
     hipKernelNodeParams p;
     if (hipGraphKernelNodeGetParams(nodes[k], &p) != hipSuccess) continue;
     int nargs = 0;
-    const int oa = lodgs::blend_output_arg(p.func, &nargs);
-    if (oa >= 0) {
+    int a = blend_output_arg(p.func, &nargs);
+    if (a >= 0) {
       g->node_blend = nodes[k];
       g->p_blend = p;
-      g->blend_arg = oa;
+      g->blend_arg = a;
       g->blend_nargs = nargs;
       continue;
     }
-    if (p.func != reinterpret_cast<void*>(&lodgs::k_set_view)) continue;
-    lodgs::ViewConst* dst = *reinterpret_cast<lodgs::ViewConst**>(p.kernelParams[1]);
+    a = l1_target_arg(p.func, &nargs);
+    if (a >= 0) {
+      g->node_l1 = nodes[k];
+      g->p_l1 = p;
+      g->l1_arg = a;
+      g->l1_nargs = nargs;
+      continue;
+    }
+    if (p.func != reinterpret_cast<void*>(&k_set_view)) continue;
+    ViewConst* dst = *reinterpret_cast<ViewConst**>(p.kernelParams[1]);
     FrameCounters* ctr = *reinterpret_cast<FrameCounters**>(p.kernelParams[2]);
     const int mode = *reinterpret_cast<int*>(p.kernelParams[3]);
     const int32_t* cnt = *reinterpret_cast<const int32_t**>(p.kernelParams[4]);
@@ -685,14 +669,118 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
       g->cap_ren = cap;
     }
   }
-  if (e == hipSuccess && (!g->node_sel || !g->node_ren || !g->node_blend)) {
+  if (e != hipSuccess) return hip_fail(e, who);
+  if (!g->node_sel || !g->node_ren || !g->node_blend)
+    return set_error(LODGS_E_STATE, "graph capture: view nodes not found in the captured graph");
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  return e == hipSuccess ? LODGS_OK : hip_fail(e, who);
+}
+
+// Argument checks shared by the two captures.
+static int capture_args_ok(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_t flags, int64_t capacity,
+                           const char* who) {
+  if (!camera_ok(cam)) return set_error(LODGS_E_INVALID, who);
+  if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, who);
+  if (capacity < 0 || capacity > (int64_t)INT32_MAX || (flags & ~(LODGS_CULL | LODGS_CONSERVATIVE)))
+    return set_error(LODGS_E_INVALID, who);
+  if (cam->width > f->caps.max_width || cam->height > f->caps.max_height)
+    return set_error(LODGS_E_CAPACITY, who);
+  if (f->timing) return set_error(LODGS_E_STATE, who);
+  return LODGS_OK;
+}
+
+}  // namespace lodgs
+
+extern "C" {
+
+void lodgs_graph_destroy(lodgs_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_t flags, int32_t* d_idx,
+                             int64_t capacity, int32_t* d_count, const float bg[3], float* d_rgb,
+                             lodgs_stream stream, lodgs_graph** out) {
+  if (!f || !d_idx || !d_count || !d_rgb || !out || !stream)
+    return set_error(LODGS_E_INVALID, "lodgs_graph_capture_view: null argument (a non-default stream is required)");
+  *out = nullptr;
+  int rc = lodgs::capture_args_ok(f, cam, tau, flags, capacity,
+                                  "lodgs_graph_capture_view: bad camera, tau, capacity or flags, an image larger "
+                                  "than the frame's, or a frame in timing mode");
+  if (rc != LODGS_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  lodgs_graph* g = new (std::nothrow) lodgs_graph();
+  if (!g) return set_error(LODGS_E_OOM, "lodgs_graph_capture_view: out of host memory");
+  g->frame = f;
+  g->width = cam->width;
+  g->height = cam->height;
+  float b[3] = {0.0f, 0.0f, 0.0f};
+  if (bg)
+    for (int k = 0; k < 3; ++k) b[k] = bg[k];
+  const lodgs::ViewConst vs = lodgs::make_view(*cam, tau), vr = lodgs::make_view(*cam, 0.0f);
+  rc = lodgs::capture(g, st, "lodgs_graph_capture_view", [&] {
+    lodgs::launch_select(f, vs, flags, d_idx, capacity, d_count, st);
+    f->rows_mode = false;
+    lodgs::launch_render(f, d_idx, d_count, vr, b, d_rgb, st);
+  });
+  if (rc != LODGS_OK) {
     lodgs_graph_destroy(g);
-    return set_error(LODGS_E_STATE, "lodgs_graph_capture_view: view nodes not found in the captured graph");
+    return rc;
   }
-  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
+  f->rendered = true;
+  f->r_idx = d_idx;
+  f->r_count = d_count;
+  f->r_rgb = d_rgb;
+  std::memcpy(f->bg, b, sizeof b);
+  f->view = vr;
+  *out = g;
+  return LODGS_OK;
+}
+
+int lodgs_graph_capture_step(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_t flags, int32_t* d_idx,
+                             int64_t capacity, int32_t* d_count, const float bg[3], float* d_rgb,
+                             const float* d_target, float* d_dL, float* d_loss, const lodgs_grads* sel,
+                             const lodgs_grads* nodes, lodgs_stream stream, lodgs_graph** out) {
+  if (!f || !d_idx || !d_count || !d_rgb || !d_target || !d_dL || !out || !stream)
+    return set_error(LODGS_E_INVALID, "lodgs_graph_capture_step: null argument (a non-default stream is required)");
+  *out = nullptr;
+  int rc = lodgs::capture_args_ok(f, cam, tau, flags, capacity,
+                                  "lodgs_graph_capture_step: bad camera, tau, capacity or flags, an image larger "
+                                  "than the frame's, or a frame in timing mode");
+  if (rc != LODGS_OK) return rc;
+  if (nodes && sel) return set_error(LODGS_E_INVALID, "lodgs_graph_capture_step: give sel or nodes, not both");
+  if ((sel && sel->d_sh && (reinterpret_cast<uintptr_t>(sel->d_sh) & 15u)) ||
+      (nodes && nodes->d_sh && (reinterpret_cast<uintptr_t>(nodes->d_sh) & 15u)))
+    return set_error(LODGS_E_INVALID, "lodgs_graph_capture_step: d_sh must be 16-byte aligned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  lodgs_graph* g = new (std::nothrow) lodgs_graph();
+  if (!g) return set_error(LODGS_E_OOM, "lodgs_graph_capture_step: out of host memory");
+  g->frame = f;
+  g->width = cam->width;
+  g->height = cam->height;
+  float b[3] = {0.0f, 0.0f, 0.0f};
+  if (bg)
+    for (int k = 0; k < 3; ++k) b[k] = bg[k];
+  const lodgs::ViewConst vs = lodgs::make_view(*cam, tau), vr = lodgs::make_view(*cam, 0.0f);
+  const int64_t npx = 3 * (int64_t)cam->width * cam->height;
+  rc = lodgs::capture(g, st, "lodgs_graph_capture_step", [&] {
+    lodgs::launch_select(f, vs, flags, d_idx, capacity, d_count, st);
+    f->rows_mode = false;
+    lodgs::launch_render(f, d_idx, d_count, vr, b, d_rgb, st);
+    // the state the backward's launches read, as lodgs_render leaves it
+    f->r_idx = d_idx;
+    f->r_count = d_count;
+    f->r_rgb = d_rgb;
+    f->view = vr;
+    lodgs::launch_l1_loss(d_rgb, d_target, npx, d_dL, d_loss, st);
+    lodgs::launch_backward(f, d_dL, sel, nodes, st);
+  });
+  if (rc == LODGS_OK && !g->node_l1) rc = set_error(LODGS_E_STATE, "lodgs_graph_capture_step: loss node not found");
+  if (rc != LODGS_OK) {
     lodgs_graph_destroy(g);
-    return hip_fail(e, "lodgs_graph_capture_view: instantiate");
+    return rc;
   }
   f->rendered = true;
   f->r_idx = d_idx;
@@ -705,6 +793,15 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
 }
 
 int lodgs_graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, lodgs_stream stream) {
+  return lodgs::graph_launch(g, cam, tau, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+int lodgs_graph_launch_step(lodgs_graph* g, const lodgs_camera* cam, float tau, const float* d_target,
+                            lodgs_stream stream) {
+  if (!g || !g->node_l1 || !d_target)
+    return set_error(LODGS_E_INVALID, "lodgs_graph_launch_step: not a training-step graph, or no target");
+  const hipError_t e = lodgs::set_pointer_arg(g->exec, g->node_l1, g->p_l1, g->l1_arg, g->l1_nargs, d_target);
+  if (e != hipSuccess) return hip_fail(e, "lodgs_graph_launch_step");
   return lodgs::graph_launch(g, cam, tau, nullptr, reinterpret_cast<hipStream_t>(stream));
 }
 

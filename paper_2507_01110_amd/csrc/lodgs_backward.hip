@@ -797,6 +797,12 @@ __global__ void __launch_bounds__(kBlock) k_l1(const float* img, const float* tg
 
 __global__ void k_zero_one(float* p) { *p = 0.0f; }
 
+int l1_target_arg(const void* func, int* n_args) {
+  if (func != reinterpret_cast<const void*>(&k_l1)) return -1;
+  *n_args = 5;  // (img, tgt, n, grad, loss)
+  return 1;
+}
+
 void launch_l1_loss(const float* img, const float* target, int64_t n, float* grad, float* loss, hipStream_t st) {
   if (loss) hipLaunchKernelGGL(k_zero_one, dim3(1), dim3(1), 0, st, loss);
   int64_t g = (n + kBlock - 1) / kBlock;

@@ -234,6 +234,10 @@ void launch_select_full(lodgs_frame* f, const ViewConst& v, uint32_t flags, int3
                         int32_t* d_count, hipStream_t st);
 // Words of the node bitmask: whole 64-node waves.
 inline int64_t cut_bit_words(int64_t n_nodes) { return 2 * ((n_nodes + 63) / 64); }
+// Position of the target image among the arguments of the L1 loss kernel
+// (the function of a captured kernel node) and its argument count, or -1.
+int l1_target_arg(const void* func, int* n_args);
+void launch_l1_loss(const float* img, const float* target, int64_t n, float* grad, float* loss, hipStream_t st);
 // Replays a captured view for cam and tau on st, writing the image to d_rgb
 // (the captured image when null).
 int graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, float* d_rgb, hipStream_t st);

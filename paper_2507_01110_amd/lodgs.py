@@ -405,6 +405,49 @@ class ViewGraph:
             self._h = None
 
 
+class StepGraph:
+    """A training step (lod_select, render, L1 loss against a target, backward
+    into sel or nodes) captured in one HIP graph (lodgs_graph_capture_step);
+    replayed for any camera of the captured size, any tau and any target.
+    The image goes to ``self.out``, dL/dimage to ``self.dL``, the loss to
+    ``self.loss``."""
+
+    def __init__(self, frame: Frame, cam, tau: float, target, stream, sel: dict | None = None,
+                 nodes: dict | None = None, cull: bool = True, bg=(0.0, 0.0, 0.0)):
+        self.frame = frame
+        self.width, self.height = cam.width, cam.height
+        self.stream = stream
+        dev = frame.scene.device
+        self.out = torch.zeros((cam.height, cam.width, 3), dtype=torch.float32, device=dev)
+        self.dL = torch.zeros_like(self.out)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self._keep = (target, sel, nodes)
+        g = lambda d: _lib.Grads(*[_ptr(d.get(k)) for k in ("means", "log_scales", "quats", "opacity_logits", "sh")])
+        gs = g(sel) if sel else None
+        gn = g(nodes) if nodes else None
+        c = camera_struct(cam)
+        b = (ctypes.c_float * 3)(*[float(x) for x in bg])
+        h = ctypes.c_void_p()
+        check(_lib.load().lodgs_graph_capture_step(
+            frame._h, ctypes.byref(c), float(tau), _lib.CULL if cull else 0, _ptr(frame.idx), frame.idx.numel(),
+            _ptr(frame.count), ctypes.cast(b, ctypes.c_void_p), _ptr(self.out), _ptr(target), _ptr(self.dL),
+            _ptr(self.loss), ctypes.byref(gs) if gs else None, ctypes.byref(gn) if gn else None,
+            stream.cuda_stream, ctypes.byref(h)), "lodgs_graph_capture_step")
+        self._h = h
+
+    def launch(self, cam, tau: float, target, stream=None):
+        s = self.stream if stream is None else stream
+        check(_lib.load().lodgs_graph_launch_step(self._h, ctypes.byref(camera_struct(cam)), float(tau),
+                                                  _ptr(target), s.cuda_stream), "lodgs_graph_launch_step")
+        return self.out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.lodgs_graph_destroy(h)
+            self._h = None
+
+
 def grads_like(scene: Scene, n: int | None = None, zero: bool = True) -> dict:
     """Gradient arrays shaped like the scene parameters ([n, ...], default all nodes)."""
     out = {}
