@@ -246,10 +246,47 @@ def cpu_baseline(tree, views, target, cut="hspt", conservative=False):
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     taus = ", ".join(str(t) for _, t in views)
     return {"value": round(1000.0 * sum(per) / len(per), 1), "unit": "ms per view", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{len(views)} views of the same scene (the middle path pose at tau {taus}): select + render + "
                       f"L1 + backward, mean per view; per-scene oracle setup ({setup:.1f} s) excluded",
-            "per_view_ms": [round(1000.0 * x, 1) for x in per], "n_selected": nsel}
+            "per_view_ms": [round(1000.0 * x, 1) for x in per], "n_selected": nsel,
+            "tiny_forward": tiny_forward_oracle(threads)}
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def tiny_forward_oracle(threads, repeats=5):
+    """The oracle on the tiny plain-forward workload (16,384 leaves, 512 x 512,
+    tau 1: select + render), on 1 thread and on `threads`; mean ms per view."""
+    import ctypes
+    import oracle
+    import scenegen
+    from scenegen import configs
+    tree = scenegen.build_tree(configs.tiny_spec())
+    cam = configs.tiny_camera()
+    O = oracle.OracleScene(tree)
+    set_threads = oracle.lib().omp_set_num_threads
+    set_threads.argtypes = [ctypes.c_int]
+    out = {}
+    for nt in (1, threads):
+        set_threads(nt)
+        t0 = time.time()
+        for _ in range(repeats):
+            ids, _ = O.select(cam, 1.0)
+            oracle.OracleFrame(tree, ids, cam)
+        out[f"ms_{nt}_thread" + ("s" if nt > 1 else "")] = round(1000.0 * (time.time() - t0) / repeats, 2)
+    set_threads(threads)
+    return out
 
 
 def ultra_bench(args):

@@ -115,7 +115,8 @@ int lodgs_hspt_build(int64_t n_nodes, const int32_t* left, const int32_t* right,
  * A scene borrows device arrays in layout order (the outputs of
  * lodgs_hspt_build, uploaded, plus the node parameters permuted by perm).  The
  * arrays must outlive the scene handle.  rho is indexed by layout position.
- * sh_degree is 0..3. */
+ * sh_degree is 0..3.  d_quats and d_sh must be 16-byte aligned (rows are read
+ * as float4s), else LODGS_E_INVALID. */
 typedef struct lodgs_scene_desc {
   int64_t n_nodes;
   int32_t n_upper, n_spt, sh_degree;

@@ -160,7 +160,7 @@ void free_frame(lodgs_frame* f) {
   }
   if (f->open_event) (void)hipEventDestroy(f->open_event);
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->upper_test, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
-                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->depth_rank, f->rect,
+                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->rect,
                   f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->rank_info, f->grad2d, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
                   f->d_view_ren, f->cut_bits, f->frontier[0], f->frontier[1], f->level_count, f->iota};
   for (void* p : ptrs)
@@ -214,8 +214,8 @@ int lodgs_scene_create(const lodgs_scene_desc* d, lodgs_scene** out) {
   if (!d->d_means || !d->d_log_scales || !d->d_quats || !d->d_opacity_logits || !d->d_sh || !d->d_r_min ||
       !d->d_r_max || !d->d_rho || (!d->d_upper_parent && d->n_upper > 0) || !d->d_spt_begin || !d->d_spt_parent)
     return set_error(LODGS_E_INVALID, "lodgs_scene_create: null device array");
-  if ((reinterpret_cast<uintptr_t>(d->d_quats) & 15u) != 0)
-    return set_error(LODGS_E_INVALID, "lodgs_scene_create: quats must be 16-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(d->d_quats) & 15u) != 0 || (reinterpret_cast<uintptr_t>(d->d_sh) & 15u) != 0)
+    return set_error(LODGS_E_INVALID, "lodgs_scene_create: quats and sh must be 16-byte aligned");
   lodgs_scene* s = new (std::nothrow) lodgs_scene;
   if (!s) return set_error(LODGS_E_OOM, "lodgs_scene_create: out of host memory");
   SceneDev& v = s->dev;

@@ -338,23 +338,12 @@ __global__ void __launch_bounds__(kBlock) k_zero_sel(const FrameCounters* ctr, i
   }
 }
 
-// Sum over a 16-lane row (every lane gets it); all lanes active.
-__device__ __forceinline__ float row_sum(float x) {
-#define LODGS_DPP(v, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xf, 0xf, false))
-  x += LODGS_DPP(x, 0xB1);   // l^1
-  x += LODGS_DPP(x, 0x4E);   // l^2
-  x += LODGS_DPP(x, 0x141);  // l^7 inside 8
-  x += LODGS_DPP(x, 0x140);  // l^15 inside 16
-#undef LODGS_DPP
-  return x;
-}
-
 // Every real SH basis function of degree <= 3 is C L Q with a linear
 // monomial L = lx x + ly y + lz z + l1 (one coefficient set) and a quadratic
 // form Q = a xx + b yy + g zz + d xy + e yz + f xz + h; row k holds
 // (C, lx, ly, lz, l1, a, b, g, d, e, f, h) for basis function k (the same
-// functions as sh_basis).  One lane evaluates one function and its gradient
-// without branches.
+// functions as sh_basis), so any basis function is evaluated without
+// branches.
 __constant__ float kShFactors[16][12] = {
     {kSH0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 0, 1},
     {-kSH1, 0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 1},
@@ -374,8 +363,8 @@ __constant__ float kShFactors[16][12] = {
     {kSH3_6, 1, 0, 0, 0, 1, -3, 0, 0, 0, 0, 0},
 };
 
-// Basis function k and its gradient with respect to (x, y, z).
-__device__ __forceinline__ void sh_basis_one(int k, float x, float y, float z, float& Y, float* dY) {
+// Real SH basis function k at the unit direction (x, y, z).
+__device__ __forceinline__ float sh_basis_value(int k, float x, float y, float z) {
   const float* t = kShFactors[k];
   const float L = __builtin_fmaf(t[1], x, __builtin_fmaf(t[2], y, __builtin_fmaf(t[3], z, t[4])));
   float Q = t[11];
@@ -385,13 +374,7 @@ __device__ __forceinline__ void sh_basis_one(int k, float x, float y, float z, f
   Q = __builtin_fmaf(t[8] * x, y, Q);
   Q = __builtin_fmaf(t[9] * y, z, Q);
   Q = __builtin_fmaf(t[10] * x, z, Q);
-  const float qx = __builtin_fmaf(2.0f * t[5], x, __builtin_fmaf(t[8], y, t[10] * z));
-  const float qy = __builtin_fmaf(2.0f * t[6], y, __builtin_fmaf(t[8], x, t[9] * z));
-  const float qz = __builtin_fmaf(2.0f * t[7], z, __builtin_fmaf(t[9], y, t[10] * x));
-  Y = t[0] * L * Q;
-  dY[0] = t[0] * __builtin_fmaf(t[1], Q, L * qx);
-  dY[1] = t[0] * __builtin_fmaf(t[2], Q, L * qy);
-  dY[2] = t[0] * __builtin_fmaf(t[3], Q, L * qz);
+  return t[0] * L * Q;
 }
 
 // One instance's partial (moments about its tile's centre, dL/do, colour
@@ -535,15 +518,14 @@ __global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr,
 // taking basis function k (contiguous reads and writes of the 192-byte
 // coefficient block), and, through the forward's d colour / d direction, to
 // the view direction; dL/dmean through the view direction then replaces the
-// colour sums in grad2d.
+// colour sums in grad2d.  The forward's per-splat record holds the view
+// direction, 1 / distance and the clamp bits, so no node parameter but the
+// coefficients is read.
 template <int DEG>
-__global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewConst* __restrict__ vp,
-                                                      const int32_t* idx, const FrameCounters* ctr,
-                                                      const uint32_t* drawn_list, const Splat* splats,
-                                                      const float* dcol, double* grad2d, float* sel_sh,
-                                                      float* node_sh) {
+__global__ void __launch_bounds__(kBlock) k_color_bwd(const int32_t* idx, const FrameCounters* ctr,
+                                                      const uint32_t* drawn_list, const float* __restrict__ dcol,
+                                                      double* grad2d, float* sel_sh, float* node_sh) {
   constexpr int nb = (DEG + 1) * (DEG + 1), nc = 3 * nb;
-  const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
   const int lane = threadIdx.x & 63, sub = lane & 15;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -552,14 +534,15 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
     const int64_t dr = g0 + (lane >> 4);  // drawn rank
     if (dr >= n) continue;
     const int64_t i = drawn_list[dr];
-    float gc[3], J[9], acc3[3] = {0.0f, 0.0f, 0.0f};
+    float gc[3], acc3[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int c = 0; c < 3; ++c) gc[c] = (float)grad2d[9 * dr + 6 + c];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) J[q] = dcol[9 * i + q];
+    const float4* rec = reinterpret_cast<const float4*>(dcol + kColorRec * i);
+    const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
+    const float J[9] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x};
+    const float d0 = r2.y, d1 = r2.z, d2 = r2.w, il = r3.x;
+    const uint32_t clamp = __float_as_uint(r3.y);
     const int64_t node = idx[i];
-    const uint32_t clamp = splats[i].clamp;
-    const float m0 = S.means[3 * node], m1 = S.means[3 * node + 1], m2 = S.means[3 * node + 2];
     // rows of 12 or 48 floats (degree 1 or 3) move as float4s: lane q takes
     // floats 4q .. 4q + 3 of the row, coefficient f / 3 and channel f % 3 of
     // float f; other degrees move one coefficient (3 floats) per lane
@@ -574,11 +557,7 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(SceneDev S, const ViewCons
     }
     // gradient values only: FP32 throughout
     const float dRGB[3] = {(clamp & 1u) ? 0.0f : gc[0], (clamp & 2u) ? 0.0f : gc[1], (clamp & 4u) ? 0.0f : gc[2]};
-    const float dx = m0 - v.pos[0], dy = m1 - v.pos[1], dz = m2 - v.pos[2];
-    const float il = 1.0f / __builtin_sqrtf(dx * dx + dy * dy + dz * dz);
-    const float d0 = dx * il, d1 = dy * il, d2 = dz * il;
-    float Yk = 0.0f, dYk[3];
-    if (sub < nb) sh_basis_one(sub, d0, d1, d2, Yk, dYk);
+    const float Yk = sub < nb ? sh_basis_value(sub, d0, d1, d2) : 0.0f;
     if (kVec) {
       float gk[4];
 #pragma unroll
@@ -734,8 +713,8 @@ static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodg
                      f->drawn_rank, f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
   hipLaunchKernelGGL(k_splat_sums, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_order, f->drawn_rank,
                      f->inst_off, f->inst_grad, f->splats, f->rect, f->rank_info, f->grad2d);
-  hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->drawn_list, f->splats, f->dcol, f->grad2d, sel.d_sh, nodes.d_sh);
+  hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, f->r_idx, f->ctr, f->drawn_list, f->dcol,
+                     f->grad2d, sel.d_sh, nodes.d_sh);
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
                      f->drawn_list, f->grad2d, sel, nodes, f->rows_mode ? (float*)nullptr : f->max_grad2d);
 }

@@ -219,6 +219,30 @@ __device__ __forceinline__ uint32_t block_bit(int bx, int by) {
   return 1u << (4 * ((bx >> 1) + 2 * (by >> 1)) + ((bx & 1) + 2 * (by & 1)));
 }
 
+// The per-splat part of splat_block_mask: the bound K, the bounding box's
+// half-widths and the mean (ok = false: alpha < 1/255 everywhere).
+struct MaskSetup {
+  float K, hx, hy, mx, my;
+  bool ok;
+};
+
+__device__ __forceinline__ MaskSetup block_mask_setup(const Splat& s) {
+  MaskSetup m;
+  const float lo = 255.0f * s.o;
+  m.ok = lo >= 1.0f;
+  const float L = __logf(m.ok ? lo : 1.0f);
+  m.K = __builtin_fmaf(0.01f, L, L) + 0.02f;
+  const float i1 = -1.0f / s.h1, i2 = -1.0f / s.h2;  // 1 / a1, 1 / a2
+  const float cc = s.ce * s.ce, ss = s.se * s.se;
+  float hx = 1.0001f * __builtin_sqrtf(m.K * __builtin_fmaf(cc, i1, ss * i2)) + 1e-3f;
+  float hy = 1.0001f * __builtin_sqrtf(m.K * __builtin_fmaf(ss, i1, cc * i2)) + 1e-3f;
+  m.hx = hx == hx ? hx : __builtin_inff();  // no box from a NaN: every block
+  m.hy = hy == hy ? hy : __builtin_inff();
+  m.mx = s.mxh + s.mxl;
+  m.my = s.myh + s.myl;
+  return m;
+}
+
 // Bit block_bit(bx, by) (the 4x4 block (bx, by) of the 16x16 tile at (tx, ty))
 // is set unless alpha < 1/255 is certain at every pixel centre of that block.
 // alpha >= 1/255 needs -power = a1 u1^2 + a2 u2^2 <= ln(255 o) (a = -h), an
@@ -229,30 +253,21 @@ __device__ __forceinline__ uint32_t block_bit(int bx, int by) {
 // positive terms).  The bound K carries a margin (1% + 0.02) far above the
 // FP32 evaluation error of the power, and the box a further 1e-4 relative +
 // 1e-3 px, so a cleared bit only skips known results.
-__device__ __forceinline__ uint32_t splat_block_mask(const Splat& s, int tx, int ty) {
-  const float lo = 255.0f * s.o;
-  if (!(lo >= 1.0f)) return 0u;
-  const float K = __builtin_fmaf(0.01f, __logf(lo), __logf(lo)) + 0.02f;
+__device__ __forceinline__ uint32_t splat_block_mask(const Splat& s, const MaskSetup& ms, int tx, int ty) {
+  if (!ms.ok) return 0u;
   uint32_t quarters = 0u;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const float x0 = (float)(tx * kTile + 8 * (q & 1)) + 0.5f, y0 = (float)(ty * kTile + 8 * (q >> 1)) + 0.5f;
-    if (splat_rect_min(s, x0, x0 + 7.0f, y0, y0 + 7.0f) <= K) quarters |= 1u << q;
+    if (splat_rect_min(s, x0, x0 + 7.0f, y0, y0 + 7.0f) <= ms.K) quarters |= 1u << q;
   }
   if (quarters == 0u) return 0u;
-  const float i1 = -1.0f / s.h1, i2 = -1.0f / s.h2;  // 1 / a1, 1 / a2
-  const float cc = s.ce * s.ce, ss = s.se * s.se;
-  float hx = 1.0001f * __builtin_sqrtf(K * __builtin_fmaf(cc, i1, ss * i2)) + 1e-3f;
-  float hy = 1.0001f * __builtin_sqrtf(K * __builtin_fmaf(ss, i1, cc * i2)) + 1e-3f;
-  hx = hx == hx ? hx : __builtin_inff();  // no box from a NaN: every block
-  hy = hy == hy ? hy : __builtin_inff();
-  const float mx = s.mxh + s.mxl, my = s.myh + s.myl;
   uint32_t cols = 0u, rows = 0u;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const float x0 = (float)(tx * kTile + 4 * k) + 0.5f, y0 = (float)(ty * kTile + 4 * k) + 0.5f;
-    if (x0 <= mx + hx && x0 + 3.0f >= mx - hx) cols |= 1u << k;
-    if (y0 <= my + hy && y0 + 3.0f >= my - hy) rows |= 1u << k;
+    if (x0 <= ms.mx + ms.hx && x0 + 3.0f >= ms.mx - ms.hx) cols |= 1u << k;
+    if (y0 <= ms.my + ms.hy && y0 + 3.0f >= ms.my - ms.hy) rows |= 1u << k;
   }
   uint32_t m = 0u;
 #pragma unroll

@@ -118,7 +118,6 @@ struct lodgs_frame {
   uint32_t* inst_off;     // [max_selected] instance offsets of the drawn splats in depth order
   uint32_t* drawn_rank;   // [max_selected] rank of a drawn splat among the drawn ones (selection order)
   uint32_t* drawn_list;   // [max_selected] selection positions of the drawn splats (selection order)
-  uint32_t* depth_rank;   // [max_selected] depth rank of each drawn splat, by drawn rank
   ushort4* rect;          // [max_selected]
   uint32_t* ikey;         // [max_instances]
   uint32_t* ival;
@@ -131,7 +130,9 @@ struct lodgs_frame {
   uint4* rank_info;       // [max_selected][2] per depth rank: (splat, drawn rank, rect x0|x1<<16, y0|y1<<16),
                           // (mean x hi, lo, y hi, lo); written with the splat's first instance
   double* grad2d;         // [max_selected][9] per-drawn-splat 2D sums (drawn rank)
-  float* dcol;            // [max_selected][9] d colour / d view direction of each drawn splat (selection position)
+  float* dcol;            // [max_selected][kColorRec] colour backward record of each drawn splat (selection
+                          // position): d colour / d view direction (9), unit view direction (3), 1 / distance,
+                          // clamp bits, 2 unused
   uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances
   uint2* ranges;          // [max tiles]
   uint32_t* tile_order;   // [max tiles] tiles, heaviest first
@@ -195,6 +196,9 @@ __device__ __forceinline__ int wave_hit_list(int m, uint32_t want, const uint32_
 // Per-instance partial of the blend backward: sum w, sum w e (2), sum w e e^T
 // (3) about the tile centre, dL/do, dL/dRGB (3).
 constexpr int kPartial = 10;
+
+// Floats of the colour backward's per-splat record (written by the forward).
+constexpr int kColorRec = 16;
 
 // Writes the per-view constants to the frame's device slot (one thread): the
 // kernels of a stage read them from there, so a captured graph is replayed
@@ -282,7 +286,6 @@ void frame_arrays(lodgs_frame* f, const SceneDev& S, const lodgs_frame_caps& cap
   fn(f->inst_off, ns);
   fn(f->drawn_rank, ns);
   fn(f->drawn_list, ns);
-  fn(f->depth_rank, ns);
   fn(f->rect, ns);
   fn(f->ikey, ni);
   fn(f->ival, ni);
@@ -294,7 +297,7 @@ void frame_arrays(lodgs_frame* f, const SceneDev& S, const lodgs_frame_caps& cap
   fn(f->info_k, ni);
   fn(f->rank_info, 2 * ns);
   fn(f->grad2d, 9 * ns);
-  fn(f->dcol, 9 * ns);
+  fn(f->dcol, (size_t)kColorRec * ns);
   fn(f->long_list, ns);
   fn(f->ranges, nt);
   fn(f->tile_order, nt);

@@ -99,16 +99,37 @@ __device__ __forceinline__ Proj project_node(const SceneDev& S, const ViewConst&
 // unclamped value in raw[3] and, in J[3 c + a], the derivative of channel c
 // with respect to component a of the unit direction (sum over the basis of
 // coefficient times basis gradient), which the colour backward takes in place
-// of the coefficients.
+// of the coefficients, and the unit direction and 1 / |mu - pos| it used.
 template <int DEG>
-__device__ __forceinline__ void sh_color(const SceneDev& S, const ViewConst& v, int64_t n, float* raw, float* J) {
+__device__ __forceinline__ void sh_color(const SceneDev& S, const ViewConst& v, int64_t n, float* raw, float* J,
+                                         float* dir, float& inv_len) {
   const float dx = S.means[3 * n] - v.pos[0], dy = S.means[3 * n + 1] - v.pos[1], dz = S.means[3 * n + 2] - v.pos[2];
   const float il = 1.0f / __builtin_sqrtf(dx * dx + dy * dy + dz * dz);
+  dir[0] = dx * il;
+  dir[1] = dy * il;
+  dir[2] = dz * il;
+  inv_len = il;
   float Y[16], dY[16][3];
-  sh_basis(DEG, dx * il, dy * il, dz * il, Y);
-  sh_basis_grad(DEG, dx * il, dy * il, dz * il, dY);
-  constexpr int nb = (DEG + 1) * (DEG + 1);
-  const float* c = S.sh + (int64_t)(3 * nb) * n;
+  sh_basis(DEG, dir[0], dir[1], dir[2], Y);
+  sh_basis_grad(DEG, dir[0], dir[1], dir[2], dY);
+  constexpr int nb = (DEG + 1) * (DEG + 1), nc = 3 * nb;
+  // the coefficient row, as float4s when its length allows (rows are 16-byte
+  // aligned: the scene's array is, and a row is a multiple of 16 bytes)
+  float c[nc];
+  if (nc % 4 == 0) {
+    const float4* c4 = reinterpret_cast<const float4*>(S.sh + (int64_t)nc * n);
+#pragma unroll
+    for (int q = 0; q < nc / 4; ++q) {
+      const float4 x = c4[q];
+      c[4 * q] = x.x;
+      c[4 * q + 1] = x.y;
+      c[4 * q + 2] = x.z;
+      c[4 * q + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < nc; ++f) c[f] = S.sh[(int64_t)nc * n + f];
+  }
   float r = 0.5f, g = 0.5f, b = 0.5f;
 #pragma unroll
   for (int q = 0; q < 9; ++q) J[q] = 0.0f;
@@ -142,14 +163,18 @@ __global__ void __launch_bounds__(kBlock) k_project(SceneDev S, const ViewConst*
     Proj P = project_node(S, v, node);
     uint32_t t = 0;
     if (P.visible) {
-      float raw[3], J[9];
-      sh_color<DEG>(S, v, node, raw, J);
-#pragma unroll
-      for (int q = 0; q < 9; ++q) dcol[9 * i + q] = J[q];
+      float raw[3], J[9], dir[3], il;
+      sh_color<DEG>(S, v, node, raw, J, dir, il);
       P.sp.r = fmaxf(raw[0], 0.0f);
       P.sp.g = fmaxf(raw[1], 0.0f);
       P.sp.b = fmaxf(raw[2], 0.0f);
       P.sp.clamp = (raw[0] < 0.0f ? 1u : 0u) | (raw[1] < 0.0f ? 2u : 0u) | (raw[2] < 0.0f ? 4u : 0u);
+      // the colour backward's record: everything it needs but the gradients
+      float4* rec = reinterpret_cast<float4*>(dcol + kColorRec * i);
+      rec[0] = make_float4(J[0], J[1], J[2], J[3]);
+      rec[1] = make_float4(J[4], J[5], J[6], J[7]);
+      rec[2] = make_float4(J[8], dir[0], dir[1], dir[2]);
+      rec[3] = make_float4(il, __uint_as_float(P.sp.clamp), 0.0f, 0.0f);
       t = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
       splats[i] = P.sp;
       depth_key[i] = __float_as_uint(P.depth);
@@ -189,60 +214,106 @@ struct LoadTilesInOrder {
   __device__ uint32_t operator()(int64_t r) const { return tiles[order[r]]; }
 };
 
-// One thread per (splat, tile) instance: the owning splat is found by binary
-// search over the instance offsets of the drawn splats in depth order, so
-// splats covering thousands of tiles cost no more than small ones.  The
-// instance count is clamped to the capacity here (thread 0 publishes the
-// clamped count for the later kernels and flags an overflow).  The first
-// instance of a splat records the splat's depth rank at its drawn rank (for
-// the backward, which walks the drawn splats in selection order), and lists
-// it when it has more than kLongSegment instances, and writes the splat's
-// per-rank record (rank_info) for the projection backward.  Each instance also gets
-// the 4x4 blocks of its tile that the splat's alpha >= 1/255 ellipse can
-// reach (splat_block_mask); the forward skips the others.
-__global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order,
-                                                const uint32_t* inst_off, const ushort4* rect, int32_t tiles_x,
-                                                int64_t cap, uint32_t* ikey, uint32_t* ival, uint2* inst_info,
-                                                uint32_t* long_list, const uint32_t* drawn_rank,
-                                                uint32_t* depth_rank, const Splat* __restrict__ splats,
+// Instance emission, load-balanced over the instances: the instances (splat,
+// tile) in depth order of their splats are cut into chunks of 64 and each
+// wave takes a contiguous run of chunks.  The drawn splats whose instances
+// meet a chunk (at most 64, as every drawn splat has one) are found from the
+// instance offsets (the scan of the tile counts in depth order): a 64-ary
+// search for the wave's first chunk, then one comparison per chunk.  Lane l
+// loads the l-th of them (splat, rectangle, 64-byte record and the per-splat
+// part of the block mask) into LDS; lane l then emits instance k0 + l, whose
+// splat is the last one starting at or before it (a binary search over the
+// chunk's splats in LDS).  An instance is its tile key (tile row-major in the
+// rectangle), its emission index (the tile sort carries it) and the (splat,
+// block mask) word: the 4x4 blocks of the tile that the splat's alpha >=
+// 1/255 ellipse can reach (splat_block_mask).  The chunk holding a splat's
+// first instance also writes the splat's record for the projection backward
+// (rank_info) and lists it when it has more than kLongSegment instances.  The
+// instance count is clamped to the capacity here (block 0 publishes the
+// clamped count and flags an overflow); only instances below it are emitted,
+// so only splats whose first instance is emitted get a record or a place on
+// the list.
+constexpr int kDupWaves = kBlock / 64;
+
+__global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order, const uint32_t* inst_off,
+                                                const ushort4* rect, int32_t tiles_x, int64_t cap, uint32_t* ikey,
+                                                uint32_t* ival, uint2* inst_info, uint32_t* long_list,
+                                                const uint32_t* drawn_rank, const Splat* __restrict__ splats,
                                                 uint4* rank_info) {
+  __shared__ Splat rec[kDupWaves][64];
+  __shared__ MaskSetup msk[kDupWaves][64];
+  __shared__ uint4 own[kDupWaves][64];  // (splat, instance offset, rectangle width, x0 | y0 << 16)
   const uint32_t total = (uint32_t)ctr->n_instances;  // the scan's 32-bit sum
   const int64_t n = (int64_t)total > cap ? cap : (int64_t)total;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctr->n_inst_clamped = (int32_t)n;
     if ((int64_t)total > cap) ctr->status = LODGS_E_CAPACITY;
   }
-  const int32_t nd = ctr->n_drawn;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-    int32_t lo = 0, hi = nd;  // largest r < nd with inst_off[r] <= k
-    while (hi - lo > 1) {
-      const int32_t mid = (lo + hi) >> 1;
-      if (inst_off[mid] <= (uint32_t)k) lo = mid;
-      else hi = mid;
+  const int64_t nd = ctr->n_drawn;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t nchunks = (n + 63) / 64, nw = (int64_t)gridDim.x * kDupWaves;
+  const int64_t per = (nchunks + nw - 1) / nw;
+  const int64_t c0 = ((int64_t)blockIdx.x * kDupWaves + wv) * per;
+  const int64_t c1 = c0 + per < nchunks ? c0 + per : nchunks;
+  if (c0 >= c1) return;  // wave-uniform; no block barrier below
+  // rf = the last drawn splat with inst_off[rf] <= 64 c0 (inst_off[0] = 0,
+  // offsets strictly increase): 64 samples of [lo, hi) per step, the answer
+  // stays in [lo, hi)
+  int64_t lo = 0, hi = nd;
+  {
+    const uint32_t k0 = (uint32_t)(64 * c0);
+    while (hi - lo > 1) {  // wave-uniform
+      const int64_t span = hi - lo;
+      const bool le = inst_off[lo + span * lane / 64] <= k0;  // a prefix of the lanes (lane 0 always)
+      const int m = 63 - __builtin_clzll(__ballot(le));
+      const int64_t nlo = lo + span * m / 64;
+      hi = m == 63 ? hi : lo + span * (m + 1) / 64;
+      lo = nlo;
     }
-    const uint32_t i = order[lo];
-    const uint32_t l = (uint32_t)k - inst_off[lo];
-    const ushort4 q = rect[i];
-    const uint32_t w = (uint32_t)(q.y - q.x);
-    if (l == 0) {
-      const uint32_t dr = drawn_rank[i];
-      depth_rank[dr] = (uint32_t)lo;
-      const Splat& sp = splats[i];
-      rank_info[2 * (int64_t)lo] = make_uint4(i, dr, (uint32_t)q.x | ((uint32_t)q.y << 16),
-                                              (uint32_t)q.z | ((uint32_t)q.w << 16));
-      rank_info[2 * (int64_t)lo + 1] = make_uint4(__float_as_uint(sp.mxh), __float_as_uint(sp.mxl),
-                                                  __float_as_uint(sp.myh), __float_as_uint(sp.myl));
-      if (w * (uint32_t)(q.w - q.z) > kLongSegment) long_list[atomicAdd(&ctr->n_long, 1)] = (uint32_t)lo;
+  }
+  int64_t rf = lo;
+  for (int64_t c = c0; c < c1; ++c) {  // wave-uniform
+    const int64_t k0 = 64 * c, k1 = k0 + 64 < n ? k0 + 64 : n;
+    // the splats rf .. rf + cnt - 1 start before k1
+    const int64_t r = rf + lane;
+    const uint32_t off = r < nd ? inst_off[r] : 0xFFFFFFFFu;
+    const bool in = r < nd && (int64_t)off < k1;  // a prefix of the lanes (lane 0 always)
+    const int cnt = __popcll(__ballot(in));
+    if (in) {
+      const uint32_t i = order[r];
+      const ushort4 q = rect[i];
+      const uint32_t w = (uint32_t)(q.y - q.x);
+      const Splat sp = splats[i];
+      rec[wv][lane] = sp;
+      msk[wv][lane] = block_mask_setup(sp);
+      own[wv][lane] = make_uint4(i, off, w, (uint32_t)q.x | ((uint32_t)q.z << 16));
+      if ((int64_t)off >= k0) {  // the splat's first instance is in this chunk
+        const uint32_t dr = drawn_rank[i];
+        rank_info[2 * r] = make_uint4(i, dr, (uint32_t)q.x | ((uint32_t)q.y << 16), (uint32_t)q.z | ((uint32_t)q.w << 16));
+        rank_info[2 * r + 1] = make_uint4(__float_as_uint(sp.mxh), __float_as_uint(sp.mxl), __float_as_uint(sp.myh),
+                                          __float_as_uint(sp.myl));
+        if (w * (uint32_t)(q.w - q.z) > kLongSegment) long_list[atomicAdd(&ctr->n_long, 1)] = (uint32_t)r;
+      }
     }
-    ival[k] = (uint32_t)k;  // the tile sort carries the emission index
-    if (w == 0) {  // only reachable if the instance count overflowed
-      ikey[k] = 0xFFFFFFFFu;
-      inst_info[k] = make_uint2(i, 0u);
-      continue;
+    __builtin_amdgcn_wave_barrier();
+    const int64_t k = k0 + lane;
+    if (k < k1) {
+      int o = 0;  // the last of the chunk's splats starting at or before k
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1)
+        if (o + step < cnt && (int64_t)own[wv][o + step].y <= k) o += step;
+      const uint4 ow = own[wv][o];
+      const uint32_t l = (uint32_t)(k - ow.y);
+      const uint32_t ty = (ow.w >> 16) + l / ow.z, tx = (ow.w & 0xFFFFu) + l % ow.z;
+      ikey[k] = ty * (uint32_t)tiles_x + tx;
+      ival[k] = (uint32_t)k;  // the tile sort carries the emission index
+      inst_info[k] = make_uint2(ow.x, splat_block_mask(rec[wv][o], msk[wv][o], (int)tx, (int)ty));
     }
-    const uint32_t ty = q.z + l / w, tx = q.x + l % w;
-    ikey[k] = ty * (uint32_t)tiles_x + tx;
-    inst_info[k] = make_uint2(i, splat_block_mask(splats[i], (int)tx, (int)ty));
+    __builtin_amdgcn_wave_barrier();  // rec, msk and own are rewritten by the next chunk
+    // the next chunk's first splat: the last one starting at or before k1
+    const int64_t rn = rf + cnt;
+    const uint32_t offn = rn < nd ? inst_off[rn] : 0xFFFFFFFFu;
+    rf = (int64_t)offn == k1 ? rn : rn - 1;
   }
 }
 
@@ -709,8 +780,7 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_drawn, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
   hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x, icap,
-                     f->ikey, f->ival, f->inst_info, f->long_list, f->drawn_rank, f->depth_rank, f->splats,
-                     f->rank_info);
+                     f->ikey, f->ival, f->inst_info, f->long_list, f->drawn_rank, f->splats, f->rank_info);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
