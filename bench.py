@@ -169,6 +169,60 @@ def summarize_profiles(trace_csv, fetch_csv, write_csv, commands):
     return "\n".join(out)
 
 
+def summarize_counters(csvs, commands, trace_stats=None, kernels=("k_blend_q", "k_blend_bwd")):
+    """Text summary of rocprofv3 --pmc runs (SQ counters): per kernel whose
+    name starts with one of `kernels`, the sum of each counter over its
+    dispatches, and the derived shares (active / wait / VALU / LDS per wave
+    cycle, executed VALU instructions per busy cycle and SIMD, LDS bank
+    conflicts per LDS-active cycle)."""
+    import collections
+    import csv
+    import re
+    short = lambda n: re.sub(r"\(.*", "", n.replace("(anonymous namespace)::", "")).replace("lodgs::", "").strip()
+    sums = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    avg_us = {}
+    if trace_stats:
+        for r in csv.DictReader(open(trace_stats)):
+            avg_us[short(r["Name"]).replace("void ", "")] = float(r["AverageNs"]) / 1e3
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            k = short(r["Kernel_Name"]).replace("void ", "")
+            if not k.startswith(tuple(kernels)):
+                continue
+            sums[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[k].add((path, r["Dispatch_Id"]))
+    out = ["rocprofv3 SQ counter summary, kernel sources at hash %s" % kernel_source_hash(), "", "commands:"]
+    out += ["  " + c for c in commands] + ["", "counter sums over the kernel's dispatches:", ""]
+    for k in sorted(sums):
+        c = sums[k]
+        out.append("%s  (%d dispatches per counter pass)" % (k, len(disp[k]) // max(1, len(csvs))))
+        for name in sorted(c):
+            out.append("  %-24s %.4g" % (name, c[name]))
+        g = lambda n: c.get(n, float("nan"))
+        d = []
+        wc = g("SQ_WAVE_CYCLES")
+        for n, label in (("SQ_ACTIVE_INST_ANY", "active-any"), ("SQ_WAIT_ANY", "wait-any"),
+                         ("SQ_WAIT_INST_ANY", "wait-inst-any"), ("SQ_ACTIVE_INST_VALU", "VALU active"),
+                         ("SQ_ACTIVE_INST_LDS", "LDS active")):
+            if n in c and wc == wc:
+                d.append("%s / wave-cycles %.2f" % (label, c[n] / wc))
+        if "SQ_LDS_BANK_CONFLICT" in c and "SQ_LDS_IDX_ACTIVE" in c:
+            d.append("LDS bank-conflict / LDS-active cycles %.2f" % (c["SQ_LDS_BANK_CONFLICT"] / c["SQ_LDS_IDX_ACTIVE"]))
+        nd = max(1, len(disp[k]) // max(1, len(csvs)))
+        if "SQ_INSTS_VALU" in c:
+            per = c["SQ_INSTS_VALU"] / nd
+            d.append("VALU wave-instructions per dispatch %.4g" % per)
+            if k in avg_us:
+                # 1024 SIMDs at 2.4 GHz issue at most one wave64 FP32 instruction per 4 cycles each
+                # (the 78.6 TFLOP/s non-packed FMA peak)
+                d.append("issue utilisation at the traced %.1f us per dispatch %.2f"
+                         % (avg_us[k], per / (avg_us[k] * 1e-6 * 1024 * 2.4e9 / 4.0)))
+        out.append("  derived: " + "; ".join(d))
+        out.append("")
+    return "\n".join(out)
+
+
 def configs_taus(workload):
     from scenegen import configs
     return configs.CITY_TAUS if workload == "city" else (1.0,)
@@ -378,6 +432,10 @@ def main():
                     help="measured requests per arrival rate 50,200,800,1600 req/s (0 disables serving)")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_STATS_CSV", "FETCH_CSV", "WRITE_CSV"),
                     help="print a text summary of rocprofv3 outputs (no GPU work)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="COUNTER_CSV",
+                    help="print a text summary of rocprofv3 --pmc SQ counter runs of the blend kernels (no GPU work)")
+    ap.add_argument("--trace-stats", default=None,
+                    help="with --summarize-counters: a rocprofv3 kernel-trace stats CSV for per-dispatch durations")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line that produced the profiles (repeatable; recorded in the summary)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -385,6 +443,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_profiles:
         print(summarize_profiles(*args.summarize_profiles, args.profile_command))
+        return
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.profile_command, args.trace_stats))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

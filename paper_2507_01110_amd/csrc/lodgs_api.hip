@@ -160,7 +160,7 @@ void free_frame(lodgs_frame* f) {
   }
   if (f->open_event) (void)hipEventDestroy(f->open_event);
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->upper_test, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
-                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_rank, f->drawn_list, f->rect,
+                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_list, f->rect,
                   f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->rank_info, f->grad2d, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
                   f->d_view_ren, f->cut_bits, f->frontier[0], f->frontier[1], f->level_count, f->iota};
   for (void* p : ptrs)
@@ -465,7 +465,7 @@ int lodgs_frame_read_instances(lodgs_frame* f, int32_t* d_tile, int32_t* d_pos, 
     if (e == hipSuccess) {
       const int64_t g = (m + lodgs::kBlock - 1) / lodgs::kBlock;
       hipLaunchKernelGGL(k_instance_positions, dim3((unsigned)(g < 4096 ? g : 4096)), dim3(lodgs::kBlock), 0, st,
-                         f->info_k, m, d_pos);
+                         f->sorted_info, m, d_pos);
       e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -273,8 +273,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
         sp.r = q.c.y;
         sp.g = q.c.z;
         sp.b = q.c.w;
-        sp.radius = sp.pad0 = sp.pad1 = 0.0f;
-        sp.clamp = 0u;
+        sp.rect_x = sp.rect_y = sp.pad0 = sp.pad1 = 0u;
         return sp;
       };
       Splat sa = rec(slot_at(0)), sb;
@@ -406,11 +405,11 @@ __device__ __forceinline__ void splat_mean64(const Splat* splats, int64_t i, dou
 
 // Splats with more than kLongSegment instances: one workgroup per splat turns
 // its instance partials into the splat's 2D sums (add_instance) in grad2d at
-// its drawn rank.  Per-thread FP64 sums over independent unrolled loads, a
+// its selection position.  Per-thread FP64 sums over independent unrolled loads, a
 // butterfly over the wave, the waves in order: a fixed order, so
 // deterministic.
 __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, const uint32_t* long_list,
-                                                      const uint32_t* order, const uint32_t* drawn_rank,
+                                                      const uint32_t* order,
                                                       const uint32_t* inst_off, const float* __restrict__ partial,
                                                       const Splat* __restrict__ splats, const ushort4* rect,
                                                       double* grad2d) {
@@ -456,7 +455,7 @@ __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, 
       double sum = part[0][threadIdx.x];
 #pragma unroll
       for (int w = 1; w < kBlock / 64; ++w) sum += part[w][threadIdx.x];
-      grad2d[9 * (int64_t)drawn_rank[i] + threadIdx.x] = sum;
+      grad2d[9 * i + threadIdx.x] = sum;
     }
     __syncthreads();
   }
@@ -466,10 +465,10 @@ __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, 
 // (those with more than kLongSegment tiles whose first instance was emitted):
 // one thread per splat, in depth order, so neighbouring threads read
 // neighbouring partials; FP64 sums in instance order (add_instance) into
-// grad2d at the splat's drawn rank (zero for a splat that an instance
-// overflow left without instances).
+// grad2d at the splat's selection position (zero for a splat that an
+// instance overflow left without instances).
 __global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr, const uint32_t* order,
-                                                       const uint32_t* drawn_rank, const uint32_t* inst_off,
+                                                       const uint32_t* inst_off,
                                                        const float* __restrict__ partial,
                                                        const Splat* __restrict__ splats, const ushort4* rect,
                                                        const uint4* rank_info, double* grad2d) {
@@ -477,20 +476,18 @@ __global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr,
   const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t a0 = inst_off[r];
-    int64_t i, dr;
+    int64_t i;
     ushort4 q;
     double mx, my;
     if (a0 < n_cl) {  // the duplication kernel wrote the rank's record with the first instance
       const uint4 w0 = rank_info[2 * r], w1 = rank_info[2 * r + 1];
       i = w0.x;
-      dr = w0.y;
       q = make_ushort4((unsigned short)(w0.z & 0xFFFFu), (unsigned short)(w0.z >> 16),
                        (unsigned short)(w0.w & 0xFFFFu), (unsigned short)(w0.w >> 16));
       mx = (double)__uint_as_float(w1.x) + (double)__uint_as_float(w1.y);
       my = (double)__uint_as_float(w1.z) + (double)__uint_as_float(w1.w);
     } else {  // left without instances by an overflow: zero sums
       i = order[r];
-      dr = drawn_rank[i];
       q = rect[i];
       mx = my = 0.0;
     }
@@ -505,7 +502,7 @@ __global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr,
       for (int c = 0; c < kPartial; ++c) t[c] = partial[kPartial * k + c];
       add_instance(g, t, (uint32_t)(k - a0), q, mx, my);
     }
-    double* dst = grad2d + 9 * dr;
+    double* dst = grad2d + 9 * i;
 #pragma unroll
     for (int c = 0; c < 9; ++c) dst[c] = g[c];
   }
@@ -536,7 +533,7 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(const int32_t* idx, const 
     const int64_t i = drawn_list[dr];
     float gc[3], acc3[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) gc[c] = (float)grad2d[9 * dr + 6 + c];
+    for (int c = 0; c < 3; ++c) gc[c] = (float)grad2d[9 * i + 6 + c];
     const float4* rec = reinterpret_cast<const float4*>(dcol + kColorRec * i);
     const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
     const float J[9] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w, r2.x};
@@ -588,9 +585,9 @@ __global__ void __launch_bounds__(kBlock) k_color_bwd(const int32_t* idx, const 
       for (int a = 0; a < 3; ++a)
         dd[a] = __builtin_fmaf(dRGB[2], J[6 + a], __builtin_fmaf(dRGB[1], J[3 + a], dRGB[0] * J[a]));
       const float dot = __builtin_fmaf(dd[0], d0, __builtin_fmaf(dd[1], d1, dd[2] * d2));
-      grad2d[9 * dr + 6] = (double)((dd[0] - d0 * dot) * il);
-      grad2d[9 * dr + 7] = (double)((dd[1] - d1 * dot) * il);
-      grad2d[9 * dr + 8] = (double)((dd[2] - d2 * dot) * il);
+      grad2d[9 * i + 6] = (double)((dd[0] - d0 * dot) * il);
+      grad2d[9 * i + 7] = (double)((dd[1] - d1 * dot) * il);
+      grad2d[9 * i + 8] = (double)((dd[2] - d2 * dot) * il);
     }
   }
 }
@@ -611,9 +608,9 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewCo
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = drawn_list[r];
     const int64_t node = idx[i];
-    double g2[9];  // 2D sums of the splat (drawn rank r), see add_instance
+    double g2[9];  // 2D sums of the splat (selection position i), see add_instance
 #pragma unroll
-    for (int c = 0; c < 9; ++c) g2[c] = grad2d[9 * r + c];
+    for (int c = 0; c < 9; ++c) g2[c] = grad2d[9 * i + c];
     const double gdir[3] = {g2[6], g2[7], g2[8]};
     double gm[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, go = 0.0;
     Proj64 P;
@@ -710,9 +707,9 @@ static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodg
   // 16 splats per block: one pass covers 256k drawn splats, so each 16-lane
   // group runs its latency-bound chain of dependent loads once
   hipLaunchKernelGGL(k_long_sums, dim3(1024), dim3(kBlock), 0, st, f->ctr, f->long_list, f->sorted_order,
-                     f->drawn_rank, f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
-  hipLaunchKernelGGL(k_splat_sums, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_order, f->drawn_rank,
-                     f->inst_off, f->inst_grad, f->splats, f->rect, f->rank_info, f->grad2d);
+                     f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
+  hipLaunchKernelGGL(k_splat_sums, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_order, f->inst_off,
+                     f->inst_grad, f->splats, f->rect, f->rank_info, f->grad2d);
   hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, f->r_idx, f->ctr, f->drawn_list, f->dcol,
                      f->grad2d, sel.d_sh, nodes.d_sh);
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
@@ -728,15 +725,15 @@ void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, 
   switch (f->blend_px_bwd) {
     case 1:
       hipLaunchKernelGGL(k_blend_bwd<1>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->info_k, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
+                         f->sorted_info, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
       break;
     case 4:
       hipLaunchKernelGGL(k_blend_bwd<4>, dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->info_k, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
+                         f->sorted_info, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
       break;
     default:
       hipLaunchKernelGGL(k_blend_bwd<2>, dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->info_k, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
+                         f->sorted_info, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
       break;
   }
   stage_end(f, st);

@@ -104,9 +104,9 @@ struct alignas(16) Splat {
   float mxh, mxl, myh, myl;
   float ce, se, h1, h2;
   float o, r, g, b;
-  float radius;
-  uint32_t clamp;  // bit c: colour channel c was clamped at 0 (read by the backward)
-  float pad0, pad1;
+  uint32_t rect_x;  // tile rectangle: x0 | x1 << 16 (columns [x0, x1))
+  uint32_t rect_y;  // y0 | y1 << 16 (rows [y0, y1))
+  uint32_t pad0, pad1;
 };
 
 // Power of a splat at the pixel centre (px, py), FP32, fixed operation order.

@@ -116,20 +116,20 @@ struct lodgs_frame {
   uint32_t* order2;
   uint32_t* tiles;        // [max_selected]
   uint32_t* inst_off;     // [max_selected] instance offsets of the drawn splats in depth order
-  uint32_t* drawn_rank;   // [max_selected] rank of a drawn splat among the drawn ones (selection order)
   uint32_t* drawn_list;   // [max_selected] selection positions of the drawn splats (selection order)
   ushort4* rect;          // [max_selected]
   uint32_t* ikey;         // [max_instances]
   uint32_t* ival;
   uint32_t* ikey2;
   uint32_t* ival2;
-  uint2* inst_info;       // [max_instances] (selection position of the splat, block mask) (emission order)
+  uint2* inst_info;       // [max_instances] (selection position of the splat, block mask) (emission order),
+                          // then a ping-pong buffer of the tile sort's payload
   float* inst_grad;       // [max_instances][kPartial] per-instance partials (emission order)
   uint32_t* inst_event;   // [max_instances] forward events, byte q for quarter q's 4x4 blocks (tile order)
-  uint2* info_k;          // [max_instances] inst_info in tile order
-  uint4* rank_info;       // [max_selected][2] per depth rank: (splat, drawn rank, rect x0|x1<<16, y0|y1<<16),
+  uint2* info_k;          // [max_instances] the other ping-pong buffer of that payload
+  uint4* rank_info;       // [max_selected][2] per depth rank: (splat, 0, rect x0|x1<<16, y0|y1<<16),
                           // (mean x hi, lo, y hi, lo); written with the splat's first instance
-  double* grad2d;         // [max_selected][9] per-drawn-splat 2D sums (drawn rank)
+  double* grad2d;         // [max_selected][9] per-drawn-splat 2D sums (selection position)
   float* dcol;            // [max_selected][kColorRec] colour backward record of each drawn splat (selection
                           // position): d colour / d view direction (9), unit view direction (3), 1 / distance,
                           // clamp bits, 2 unused
@@ -147,6 +147,7 @@ struct lodgs_frame {
   lodgs::ViewConst view;
   const uint32_t* sorted_ival;  // the buffer holding the final instance order
   const uint32_t* sorted_ikey;
+  const uint2* sorted_info;     // the (splat, block mask) words in tile order (inst_info or info_k)
   const uint32_t* sorted_order;  // selection positions of the drawn splats in depth order
   // timing mode: one (stage, start, end) event pair per stage and call
   bool timing;
@@ -284,7 +285,6 @@ void frame_arrays(lodgs_frame* f, const SceneDev& S, const lodgs_frame_caps& cap
   fn(f->order2, ns);
   fn(f->tiles, ns);
   fn(f->inst_off, ns);
-  fn(f->drawn_rank, ns);
   fn(f->drawn_list, ns);
   fn(f->rect, ns);
   fn(f->ikey, ni);

@@ -153,9 +153,11 @@ inline void scan_exclusive(Load load, const int32_t* d_n, int64_t cap, uint32_t*
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* keys, const int32_t* d_n, int64_t cap,
                                                        int shift, uint32_t* table, uint32_t* below);
 __global__ void __launch_bounds__(kBlock) k_radix_offsets(uint32_t* table, const uint32_t* below);
+template <bool XTRA>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, const uint32_t* vin,
-                                                          uint32_t* kout, uint32_t* vout, const int32_t* d_n,
-                                                          int64_t cap, int shift, const uint32_t* table);
+                                                          uint32_t* kout, uint32_t* vout, const uint2* xin,
+                                                          uint2* xout, const int32_t* d_n, int64_t cap, int shift,
+                                                          const uint32_t* table);
 
 // Workspace for sort_pairs: two tables of 256 * kSortGrid words.
 struct SortScratch {
@@ -165,8 +167,9 @@ struct SortScratch {
 
 // Sorts (keys, vals) of length min(*d_n, cap) by the key bits [0, bits), stable.
 // Uses (k2, v2) as ping-pong buffers; returns true if the result ended in
-// (k2, v2), false if in (keys, vals).
+// (k2, v2), false if in (keys, vals).  With xtra non-null, an 8-byte payload
+// per element moves with it (xtra / x2 ping-pong like keys / k2).
 bool sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* k2, uint32_t* v2, const int32_t* d_n, int64_t cap,
-                int bits, const SortScratch& ws, hipStream_t st);
+                int bits, const SortScratch& ws, hipStream_t st, uint2* xtra = nullptr, uint2* x2 = nullptr);
 
 }  // namespace lodgs

@@ -51,19 +51,24 @@ __global__ void __launch_bounds__(kBlock) k_radix_offsets(uint32_t* table, const
 // wave with the same digit, per-wave counts give the order across waves, a
 // running count per digit the order across rounds); (2) the tile is staged in
 // LDS in digit order; (3) consecutive threads write consecutive staged keys,
-// so a digit's keys go to consecutive global positions.
+// so a digit's keys go to consecutive global positions.  With XTRA an 8-byte
+// payload per key is read when the tile is staged (coalesced: input order)
+// and written beside it.
 constexpr int kScatterRounds = 16;
 constexpr int kScatterTile = kScatterRounds * kBlock;
 
+template <bool XTRA>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, const uint32_t* vin,
-                                                          uint32_t* kout, uint32_t* vout, const int32_t* d_n,
-                                                          int64_t cap, int shift, const uint32_t* table) {
+                                                          uint32_t* kout, uint32_t* vout, const uint2* xin,
+                                                          uint2* xout, const int32_t* d_n, int64_t cap, int shift,
+                                                          const uint32_t* table) {
   __shared__ uint32_t base[256];   // global position of the digit's next key
   __shared__ uint32_t lcnt[256];   // keys of the digit in the tile (so far)
   __shared__ uint32_t lstart[256]; // first staged position of the digit
   __shared__ uint32_t wcnt[kBlock / 64][256];
   __shared__ uint32_t wt[kBlock / 64];
   __shared__ uint32_t sk[kScatterTile], sv[kScatterTile];
+  __shared__ uint2 sx[XTRA ? kScatterTile : 1];
   int64_t n = *d_n;
   n = n < 0 ? 0 : (n > cap ? cap : n);
   const Segment s = block_segment(n, kSortGrid);
@@ -122,6 +127,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, c
         const uint32_t pos = lstart[(kr[u] >> shift) & 255u] + lr[u];
         sk[pos] = kr[u];
         sv[pos] = vr[u];
+        if (XTRA) sx[pos] = xin[t0 + (int64_t)u * kBlock + t];
       }
     }
     __syncthreads();
@@ -131,6 +137,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, c
       const uint32_t g = base[d] + ((uint32_t)j - lstart[d]);
       kout[g] = key;
       vout[g] = sv[j];
+      if (XTRA) xout[g] = sx[j];
     }
     __syncthreads();
     base[t] += lcnt[t];
@@ -139,17 +146,23 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, c
 }
 
 bool sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* k2, uint32_t* v2, const int32_t* d_n, int64_t cap,
-                int bits, const SortScratch& ws, hipStream_t st) {
+                int bits, const SortScratch& ws, hipStream_t st, uint2* xtra, uint2* x2) {
   uint32_t *ka = keys, *va = vals, *kb = k2, *vb = v2;
+  uint2 *xa = xtra, *xb = x2;
   bool swapped = false;
   for (int shift = 0; shift < bits; shift += 8) {
     hipLaunchKernelGGL(k_radix_hist, dim3(kSortGrid), dim3(kBlock), 0, st, ka, d_n, cap, shift, ws.table,
                        ws.below);
     hipLaunchKernelGGL(k_radix_offsets, dim3(256), dim3(kBlock), 0, st, ws.table, ws.below);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(kSortGrid), dim3(kBlock), 0, st, ka, va, kb, vb, d_n, cap, shift,
-                       ws.table);
+    if (xtra)
+      hipLaunchKernelGGL(k_radix_scatter<true>, dim3(kSortGrid), dim3(kBlock), 0, st, ka, va, kb, vb, xa, xb, d_n,
+                         cap, shift, ws.table);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, dim3(kSortGrid), dim3(kBlock), 0, st, ka, va, kb, vb,
+                         (const uint2*)nullptr, (uint2*)nullptr, d_n, cap, shift, ws.table);
     uint32_t* tk = ka; ka = kb; kb = tk;
     uint32_t* tv = va; va = vb; vb = tv;
+    uint2* tx = xa; xa = xb; xb = tx;
     swapped = !swapped;
   }
   return swapped;

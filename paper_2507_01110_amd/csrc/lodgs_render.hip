@@ -89,9 +89,9 @@ __device__ __forceinline__ Proj project_node(const SceneDev& S, const ViewConst&
   P.sp.h1 = (float)(-0.5 / l1);
   P.sp.h2 = (float)(-0.5 / l2);
   P.sp.o = 1.0f / (1.0f + fexp(-theta));
-  P.sp.radius = (float)r;
-  P.sp.clamp = 0u;
-  P.sp.pad0 = P.sp.pad1 = 0.0f;
+  P.sp.rect_x = (uint32_t)P.x0 | ((uint32_t)P.x1 << 16);
+  P.sp.rect_y = (uint32_t)P.y0 | ((uint32_t)P.y1 << 16);
+  P.sp.pad0 = P.sp.pad1 = 0u;
   return P;
 }
 
@@ -168,13 +168,13 @@ __global__ void __launch_bounds__(kBlock) k_project(SceneDev S, const ViewConst*
       P.sp.r = fmaxf(raw[0], 0.0f);
       P.sp.g = fmaxf(raw[1], 0.0f);
       P.sp.b = fmaxf(raw[2], 0.0f);
-      P.sp.clamp = (raw[0] < 0.0f ? 1u : 0u) | (raw[1] < 0.0f ? 2u : 0u) | (raw[2] < 0.0f ? 4u : 0u);
+      const uint32_t clamp = (raw[0] < 0.0f ? 1u : 0u) | (raw[1] < 0.0f ? 2u : 0u) | (raw[2] < 0.0f ? 4u : 0u);
       // the colour backward's record: everything it needs but the gradients
       float4* rec = reinterpret_cast<float4*>(dcol + kColorRec * i);
       rec[0] = make_float4(J[0], J[1], J[2], J[3]);
       rec[1] = make_float4(J[4], J[5], J[6], J[7]);
       rec[2] = make_float4(J[8], dir[0], dir[1], dir[2]);
-      rec[3] = make_float4(il, __uint_as_float(P.sp.clamp), 0.0f, 0.0f);
+      rec[3] = make_float4(il, __uint_as_float(clamp), 0.0f, 0.0f);
       t = (uint32_t)((P.x1 - P.x0) * (P.y1 - P.y0));
       splats[i] = P.sp;
       depth_key[i] = __float_as_uint(P.depth);
@@ -190,17 +190,15 @@ struct LoadDrawn {
 };
 
 // Order-preserving compaction of the drawn splats, done by the scan of their
-// flags: the drawn splat at selection position i gets rank = its prefix among
+// flags: the drawn splat at selection position i has rank = its prefix among
 // the drawn ones; (depth key, i) go to that rank (the sort's input), and so
 // does i in the list of drawn selection positions (kept for the backward).
 struct StoreDrawn {
-  uint32_t* rank;
   const uint32_t* depth_key;
   uint32_t* key_out;
   uint32_t* val_out;
   uint32_t* list;
   __device__ void operator()(int64_t i, uint32_t prefix, uint32_t drawn) const {
-    rank[i] = prefix;
     if (!drawn) return;
     key_out[prefix] = depth_key[i];
     val_out[prefix] = (uint32_t)i;
@@ -236,10 +234,9 @@ struct LoadTilesInOrder {
 constexpr int kDupWaves = kBlock / 64;
 
 __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32_t* order, const uint32_t* inst_off,
-                                                const ushort4* rect, int32_t tiles_x, int64_t cap, uint32_t* ikey,
-                                                uint32_t* ival, uint2* inst_info, uint32_t* long_list,
-                                                const uint32_t* drawn_rank, const Splat* __restrict__ splats,
-                                                uint4* rank_info) {
+                                                int32_t tiles_x, int64_t cap, uint32_t* ikey, uint32_t* ival,
+                                                uint2* inst_info, uint32_t* long_list,
+                                                const Splat* __restrict__ splats, uint4* rank_info) {
   __shared__ Splat rec[kDupWaves][64];
   __shared__ MaskSetup msk[kDupWaves][64];
   __shared__ uint4 own[kDupWaves][64];  // (splat, instance offset, rectangle width, x0 | y0 << 16)
@@ -281,18 +278,17 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
     const int cnt = __popcll(__ballot(in));
     if (in) {
       const uint32_t i = order[r];
-      const ushort4 q = rect[i];
-      const uint32_t w = (uint32_t)(q.y - q.x);
-      const Splat sp = splats[i];
+      const Splat sp = splats[i];  // the one random read per splat (the record holds the rectangle)
+      const uint32_t x0 = sp.rect_x & 0xFFFFu, y0 = sp.rect_y & 0xFFFFu;
+      const uint32_t w = (sp.rect_x >> 16) - x0, h = (sp.rect_y >> 16) - y0;
       rec[wv][lane] = sp;
       msk[wv][lane] = block_mask_setup(sp);
-      own[wv][lane] = make_uint4(i, off, w, (uint32_t)q.x | ((uint32_t)q.z << 16));
+      own[wv][lane] = make_uint4(i, off, w, x0 | (y0 << 16));
       if ((int64_t)off >= k0) {  // the splat's first instance is in this chunk
-        const uint32_t dr = drawn_rank[i];
-        rank_info[2 * r] = make_uint4(i, dr, (uint32_t)q.x | ((uint32_t)q.y << 16), (uint32_t)q.z | ((uint32_t)q.w << 16));
+        rank_info[2 * r] = make_uint4(i, 0u, sp.rect_x, sp.rect_y);
         rank_info[2 * r + 1] = make_uint4(__float_as_uint(sp.mxh), __float_as_uint(sp.mxl), __float_as_uint(sp.myh),
                                           __float_as_uint(sp.myl));
-        if (w * (uint32_t)(q.w - q.z) > kLongSegment) long_list[atomicAdd(&ctr->n_long, 1)] = (uint32_t)r;
+        if (w * h > kLongSegment) long_list[atomicAdd(&ctr->n_long, 1)] = (uint32_t)r;
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -321,15 +317,11 @@ __global__ void __launch_bounds__(kBlock) k_dup(FrameCounters* ctr, const uint32
 // [0, n]: between the keys t0 = key[k - 1] and t1 = key[k] (-1 before the
 // first, ntiles after the last; keys >= ntiles, which only an instance
 // overflow produces, count as ntiles) tile t0 ends at k, tile t1 starts at k,
-// and every tile strictly between them is empty (k, k).  Instance k's
-// (owning splat, block mask) word is also gathered into tile order (info_k),
-// which saves the blends a dependent load.
+// and every tile strictly between them is empty (k, k).
 __global__ void __launch_bounds__(kBlock) k_ranges(const FrameCounters* ctr, const uint32_t* key, uint2* ranges,
-                                                   uint32_t ntiles, const uint32_t* ival, const uint2* inst_info,
-                                                   uint2* info_k) {
+                                                   uint32_t ntiles) {
   const int64_t n = ctr->n_inst_clamped;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k <= n; k += (int64_t)gridDim.x * blockDim.x) {
-    if (k < n) info_k[k] = inst_info[ival[k]];
     const int64_t t0 = k > 0 ? (int64_t)min(key[k - 1], ntiles) : -1;
     const int64_t t1 = k < n ? (int64_t)min(key[k], ntiles) : (int64_t)ntiles;
     if (t0 == t1) continue;
@@ -708,7 +700,7 @@ static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], 
   unsigned long long* work = COUNT ? f->work : nullptr;
   uint32_t* event = COUNT ? nullptr : f->inst_event;
   if (!COUNT && f->blend_px_fwd == 1) {
-    hipLaunchKernelGGL(k_blend_q, dim3(4 * ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges, f->info_k,
+    hipLaunchKernelGGL(k_blend_q, dim3(4 * ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges, f->sorted_info,
                        f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2], d_rgb,
                        reinterpret_cast<uint8_t*>(event));
     return;
@@ -716,17 +708,17 @@ static void launch_blend(lodgs_frame* f, const ViewConst& v, const float bg[3], 
   switch (f->blend_px_fwd) {
     case 1:
       hipLaunchKernelGGL((k_blend<COUNT, 1>), dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges,
-                         f->info_k, f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         f->sorted_info, f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
                          d_rgb, event, work);
       break;
     case 4:
       hipLaunchKernelGGL((k_blend<COUNT, 4>), dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges,
-                         f->info_k, f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         f->sorted_info, f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
                          d_rgb, event, work);
       break;
     default:
       hipLaunchKernelGGL((k_blend<COUNT, 2>), dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges,
-                         f->info_k, f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
+                         f->sorted_info, f->splats, f->ctr, f->tile_order, bg[0], bg[1], bg[2],
                          d_rgb, event, work);
       break;
   }
@@ -769,7 +761,7 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   // drawn splats only: ranks among them in selection order, then a stable
   // sort of their depth keys, ties in selection order
   scan_exclusive(LoadDrawn{f->tiles}, &f->ctr->n_render, cap, f->block_sums,
-                 StoreDrawn{f->drawn_rank, f->depth_key, f->depth_key2, f->order, f->drawn_list}, &f->ctr->n_drawn,
+                 StoreDrawn{f->depth_key, f->depth_key2, f->order, f->drawn_list}, &f->ctr->n_drawn,
                  st);
   SortScratch ws{f->sort_table, f->sort_below};
   const bool sw = sort_pairs(f->depth_key2, f->order, f->depth_key, f->order2, &f->ctr->n_drawn, cap, 32, ws, st);
@@ -779,20 +771,23 @@ void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count,
   stage_begin(f, LODGS_STAGE_DUPLICATE, st);
   scan_exclusive(LoadTilesInOrder{f->tiles, order}, &f->ctr->n_drawn, cap, f->block_sums, f->inst_off,
                  &f->ctr->n_instances, st);
-  hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, f->rect, v.tiles_x, icap,
-                     f->ikey, f->ival, f->inst_info, f->long_list, f->drawn_rank, f->splats, f->rank_info);
+  hipLaunchKernelGGL(k_dup, dim3(pgrid), dim3(kBlock), 0, st, f->ctr, order, f->inst_off, v.tiles_x, icap, f->ikey,
+                     f->ival, f->inst_info, f->long_list, f->splats, f->rank_info);
   stage_end(f, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   int tbits = 8;
   while ((1 << tbits) < ntiles) tbits += 8;
   stage_begin(f, LODGS_STAGE_TILE_SORT, st);
-  const bool sw2 = sort_pairs(f->ikey, f->ival, f->ikey2, f->ival2, &f->ctr->n_inst_clamped, icap, tbits, ws, st);
+  // the (splat, block mask) word of each instance moves with it (read in
+  // emission order, so coalesced)
+  const bool sw2 = sort_pairs(f->ikey, f->ival, f->ikey2, f->ival2, &f->ctr->n_inst_clamped, icap, tbits, ws, st,
+                              f->inst_info, f->info_k);
   f->sorted_ikey = sw2 ? f->ikey2 : f->ikey;
   f->sorted_ival = sw2 ? f->ival2 : f->ival;
+  f->sorted_info = sw2 ? f->info_k : f->inst_info;
   stage_end(f, st);
   stage_begin(f, LODGS_STAGE_RANGES, st);
-  hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_ikey, f->ranges, (uint32_t)ntiles,
-                     f->sorted_ival, f->inst_info, f->info_k);
+  hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_ikey, f->ranges, (uint32_t)ntiles);
   if (ntiles > 0)
     hipLaunchKernelGGL(k_tile_order, dim3((ntiles + kOrderChunk - 1) / kOrderChunk), dim3(kOrderThreads), 0, st,
                        f->ranges, ntiles, f->tile_order);
