@@ -342,6 +342,20 @@ int lodgs_frame_clear_status(lodgs_frame* frame, lodgs_stream stream);
  * share one array must not run backwards concurrently. */
 int lodgs_frame_set_densify_stats(lodgs_frame* frame, float* d_max_grad2d);
 
+/* The pruning statistic (appendix on densification details: the opacity of a
+ * Gaussian that has not contributed for a number of iterations equal to
+ * twice the training-set size is zeroed): with d_last attached, every later
+ * lodgs_render_backward on this frame writes *d_iteration (a device int32 the
+ * caller advances) into d_last[node] for each rendered node that contributed
+ * to at least one pixel (composited with alpha >= 1/255 before its pixel
+ * stopped, the forward's FP32 decisions), and, if d_count is not NULL, adds
+ * that node's number of contributing pixels to d_count[node].  d_last and
+ * d_count: node-indexed int32 device arrays (borrowed).  NULL d_last
+ * detaches; d_iteration is required with it (else LODGS_E_INVALID).  Not
+ * updated after lodgs_render_rows.  Frames that share the arrays must not
+ * run backwards concurrently. */
+int lodgs_frame_set_contrib_stats(lodgs_frame* frame, int32_t* d_last, int32_t* d_count, const int32_t* d_iteration);
+
 /* ---------------------------------------------------------------- graphs
  * A forward view (lod_select + render) captured once into a HIP graph and
  * replayed for any camera of the same image size and any tau.  All counts

@@ -87,6 +87,7 @@ def lib():
         L.orc_frame_get_splats.argtypes = [P, P, P, P, P]
         L.orc_frame_get_instances.argtypes = [P, P, P]
         L.orc_frame_get_pixel_counts.argtypes = [P, P]
+        L.orc_frame_get_splat_contrib.argtypes = [P, P]
         L.orc_frame_get_values64.argtypes = [P, P]
         L.orc_project64_one.argtypes = [P, ctypes.c_int, ctypes.POINTER(OrcCamera), P]
         L.orc_fd_directional.argtypes = [P, P, i64, P, ctypes.c_double, P]
@@ -252,6 +253,12 @@ class OracleFrame:
     def pixel_counts(self) -> np.ndarray:
         c = np.zeros((self.cam.height, self.cam.width), np.int32)
         lib().orc_frame_get_pixel_counts(self._h, _p(c))
+        return c
+
+    def splat_contrib(self) -> np.ndarray:
+        """Pixels each selected splat is composited into (selection order)."""
+        c = np.zeros(len(self.ids), np.int32)
+        lib().orc_frame_get_splat_contrib(self._h, _p(c))
         return c
 
     def values64(self) -> np.ndarray:

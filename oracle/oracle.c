@@ -1274,6 +1274,16 @@ void orc_frame_get_pixel_counts(const orc_frame* F, int32_t* counts) {
   for (int64_t p = 0; p < npx; ++p) counts[p] = (int32_t)(F->pix_off[p + 1] - F->pix_off[p]);
 }
 
+/* Pixels each splat is composited into (the pruning statistic of the
+ * appendix on densification details: a Gaussian that has not contributed for
+ * long has its opacity zeroed): counts[i] = the number of pixels whose
+ * contributor list holds selection position i. */
+void orc_frame_get_splat_contrib(const orc_frame* F, int32_t* counts) {
+  for (int64_t i = 0; i < F->n; ++i) counts[i] = 0;
+  const int64_t m = F->pix_off[(int64_t)F->W * F->H];
+  for (int64_t k = 0; k < m; ++k) counts[F->pix_list[k]]++;
+}
+
 /* FP64 per-splat values: mean2D, conic (a, b, c), opacity, rgb, depth. */
 void orc_frame_get_values64(const orc_frame* F, double* out9) {
   const int np = 11 + F->n_coef;

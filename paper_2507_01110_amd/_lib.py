@@ -140,6 +140,7 @@ EXPORTS = {
     "lodgs_gather_rows": ([ctypes.POINTER(Grads), ctypes.POINTER(Grads), i32, c_p, c_p, i64, i64, c_p], ctypes.c_int),
     "lodgs_render_rows": ([c_p, ctypes.POINTER(Grads), c_p, ctypes.POINTER(Camera), c_p, c_p, c_p], ctypes.c_int),
     "lodgs_frame_set_densify_stats": ([c_p, c_p], ctypes.c_int),
+    "lodgs_frame_set_contrib_stats": ([c_p, c_p, c_p, c_p], ctypes.c_int),
     "lodgs_server_create": ([c_p, ctypes.POINTER(ServerCaps), ctypes.POINTER(c_p)], ctypes.c_int),
     "lodgs_server_destroy": ([c_p], None),
     "lodgs_server_submit": ([c_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),

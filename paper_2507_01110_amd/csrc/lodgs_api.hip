@@ -161,7 +161,7 @@ void free_frame(lodgs_frame* f) {
   if (f->open_event) (void)hipEventDestroy(f->open_event);
   void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->upper_test, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
                   f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_list, f->rect,
-                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->rank_info, f->grad2d, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
+                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->rank_info, f->grad2d, f->contrib, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
                   f->d_view_ren, f->cut_bits, f->frontier[0], f->frontier[1], f->level_count, f->iota};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -803,6 +803,16 @@ int lodgs_graph_launch_step(lodgs_graph* g, const lodgs_camera* cam, float tau, 
   const hipError_t e = lodgs::set_pointer_arg(g->exec, g->node_l1, g->p_l1, g->l1_arg, g->l1_nargs, d_target);
   if (e != hipSuccess) return hip_fail(e, "lodgs_graph_launch_step");
   return lodgs::graph_launch(g, cam, tau, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+int lodgs_frame_set_contrib_stats(lodgs_frame* f, int32_t* d_last, int32_t* d_count, const int32_t* d_iteration) {
+  if (!f) return set_error(LODGS_E_INVALID, "lodgs_frame_set_contrib_stats: null frame");
+  if (d_last && !d_iteration)
+    return set_error(LODGS_E_INVALID, "lodgs_frame_set_contrib_stats: d_iteration is required with d_last");
+  f->last_contrib = d_last;
+  f->contrib_count = d_last ? d_count : nullptr;
+  f->contrib_iteration = d_last ? d_iteration : nullptr;
+  return LODGS_OK;
 }
 
 int lodgs_frame_set_densify_stats(lodgs_frame* f, float* d_max_grad2d) {

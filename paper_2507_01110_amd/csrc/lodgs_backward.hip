@@ -14,12 +14,12 @@
 
 namespace lodgs {
 
-// Reduce-scatter of 10 per-lane values inside each 16-lane row (all lanes
+// Reduce-scatter of NP (10 or 11) per-lane values inside each 16-lane row (all lanes
 // active): four DPP exchange steps pair lane l with l^1, l^2, l^7 and l^15;
 // at each step a lane keeps half of its remaining values (chosen by b0^b2,
 // b1^b2, b2^b3 and b3 of l & 15) and adds its partner's copy of that half.
 // Lane l then holds its row's sum of value
-// slot(l) = (b0^b2) + 2 (b1^b2) + 4 (b2^b3) + 8 b3 (slots 10..15 are zero).
+// slot(l) = (b0^b2) + 2 (b1^b2) + 4 (b2^b3) + 8 b3 (slots NP..15 are zero).
 #define LODGS_DPP(x, ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xf, 0xf, false))
 #define LODGS_RS_PAIR(out, a, b, k, ctrl)       \
   do {                                          \
@@ -28,19 +28,23 @@ namespace lodgs {
     (out) = keep_ + LODGS_DPP(send_, ctrl);     \
   } while (0)
 
-__device__ __forceinline__ float row_reduce_scatter10(const float* g, int lane, int& slot) {
+template <int NP>
+__device__ __forceinline__ float row_reduce_scatter(const float* g, int lane, int& slot) {
+  static_assert(NP == 10 || NP == 11, "10 or 11 values");
   const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
   const bool k1 = (b0 ^ b2) != 0, k2 = (b1 ^ b2) != 0, k3 = (b2 ^ b3) != 0, k4 = b3 != 0;
-  float h0, h1, h2, h3, h4;
+  float h0, h1, h2, h3, h4, h5;
   LODGS_RS_PAIR(h0, g[0], g[1], k1, 0xB1);  // quad_perm [1,0,3,2]: l^1
   LODGS_RS_PAIR(h1, g[2], g[3], k1, 0xB1);
   LODGS_RS_PAIR(h2, g[4], g[5], k1, 0xB1);
   LODGS_RS_PAIR(h3, g[6], g[7], k1, 0xB1);
   LODGS_RS_PAIR(h4, g[8], g[9], k1, 0xB1);
+  if (NP == 11) LODGS_RS_PAIR(h5, g[10], 0.0f, k1, 0xB1);
+  else h5 = 0.0f;
   float q0, q1, q2;
   LODGS_RS_PAIR(q0, h0, h1, k2, 0x4E);  // quad_perm [2,3,0,1]: l^2
   LODGS_RS_PAIR(q1, h2, h3, k2, 0x4E);
-  LODGS_RS_PAIR(q2, h4, 0.0f, k2, 0x4E);
+  LODGS_RS_PAIR(q2, h4, h5, k2, 0x4E);
   float r0, r1;
   LODGS_RS_PAIR(r0, q0, q1, k3, 0x141);  // row_half_mirror: l^7
   LODGS_RS_PAIR(r1, q2, 0.0f, k3, 0x141);
@@ -68,14 +72,15 @@ __device__ __forceinline__ float row_reduce_scatter10(const float* g, int lane, 
 // (e = pixel - c_t, |e| <= 7.5): sum w, sum w e, sum w e e^T, so the FP32
 // sums stay well conditioned even for a splat whose mean lies far off the
 // screen; the projection backward shifts them by c_t - mean in FP64.  Per
-// step, each row reduces these 10 values of its splat (moments, dL/do and the
-// colour gradient) over its lanes (only when some lane of the wave
+// step, each row reduces these NP values of its splat (moments, dL/do, the
+// colour gradient and, with NP = 11, the number of pixels it contributes to)
+// over its lanes (only when some lane of the wave
 // contributes) and adds them to its wave's LDS row of that splat, the rows in
 // order; the workgroup then sums the waves' rows in order and writes one
-// 10-float partial per (splat, tile) instance at the instance's emission
+// NP-float partial per (splat, tile) instance at the instance's emission
 // index, with zeros for instances that no pixel reached.  No atomics: the
 // result is deterministic.
-template <int PX>
+template <int PX, int NP>
 __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restrict__ vp,
                                                         const uint2* __restrict__ ranges,
                                                         const uint32_t* __restrict__ ival,
@@ -102,7 +107,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   // a row of acc per partial component; slot j's component c sits at column
   // j ^ c, so the ten lanes of a row adding one slot's components hit ten
   // banks (the rows are 128 words apart)
-  __shared__ float acc[NW][kPartial][NB];
+  __shared__ float acc[NW][NP][NB];
   const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, row = lane >> 4;
@@ -138,7 +143,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   const uint2 rg = ranges[tile];
   const uint32_t nr = (uint32_t)ctr->n_render;
   const float thr = 1.0f / 255.0f;
-  for (int t = threadIdx.x; t < NW * kPartial * NB; t += NT) (&acc[0][0][0])[t] = 0.0f;
+  for (int t = threadIdx.x; t < NW * NP * NB; t += NT) (&acc[0][0][0])[t] = 0.0f;
   // Thread j < NB holds batch slot j: the words (emission index, splat, event
   // word) of this batch and the next, and the splat record of this batch
   // (only for an instance with events: the others are never replayed), so the
@@ -215,7 +220,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
           act = act | live[p];
         }
         if (__any(any_con)) {  // wave-uniform
-          float g[kPartial] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+          float g[11] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
           for (int p = 0; p < PX; ++p) {
             const float alpha = als[p], Tp = T[p];
@@ -241,17 +246,18 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
             g[7] = __builtin_fmaf(G0[p], wc, g[7]);
             g[8] = __builtin_fmaf(G1[p], wc, g[8]);
             g[9] = __builtin_fmaf(G2[p], wc, g[9]);
+            if (NP == 11) g[10] += con ? 1.0f : 0.0f;  // contributing pixels
             GQ[p] = con ? gq : GQ[p];
             T[p] = con ? tts[p] : Tp;
           }
           int slot;
-          const float r = row_reduce_scatter10(g, lane, slot);
+          const float r = row_reduce_scatter<NP>(g, lane, slot);
           // the rows add into the wave's row of their splats in order (two
           // rows may be on the same splat)
           const uint64_t cm = __ballot(any_con);
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            if (row == q && slot < kPartial && ((cm >> (16 * q)) & 0xFFFFull) != 0ull) acc[wv][slot][j ^ slot] += r;
+            if (row == q && slot < NP && ((cm >> (16 * q)) & 0xFFFFull) != 0ull) acc[wv][slot][j ^ slot] += r;
         }
         return !__any(act);
       };
@@ -290,9 +296,9 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
-      float* dst = partial + kPartial * (int64_t)bid[threadIdx.x];
+      float* dst = partial + NP * (int64_t)bid[threadIdx.x];
 #pragma unroll
-      for (int c = 0; c < kPartial; ++c) {
+      for (int c = 0; c < NP; ++c) {
         const int col = (int)threadIdx.x ^ c;
         float r = acc[0][c][col];
         acc[0][c][col] = 0.0f;
@@ -313,9 +319,9 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   }
   // instances that no pixel of the tile reached
   for (uint32_t k = b0 + threadIdx.x; k < rg.y; k += NT) {
-    float* dst = partial + kPartial * (int64_t)ival[k];
+    float* dst = partial + NP * (int64_t)ival[k];
 #pragma unroll
-    for (int c = 0; c < kPartial; ++c) dst[c] = 0.0f;
+    for (int c = 0; c < NP; ++c) dst[c] = 0.0f;
   }
 }
 
@@ -380,8 +386,9 @@ __device__ __forceinline__ float sh_basis_value(int k, float x, float y, float z
 // gradient) as the splat's 2D sums in FP64: with D = c_t - mean,
 //   sum w d = m1 + D m0,  sum w d d^T = m2 + D m1^T + m1 D^T + D D^T m0,
 // added into g = [sum w dx, sum w dy, sum w dx^2, sum w dx dy, sum w dy^2,
-// dL/do, dL/dr, dL/dg, dL/db].  l is the instance's index within its splat,
+// dL/do, dL/dr, dL/dg, dL/db, contributing pixels].  l is the instance's index within its splat,
 // whose tiles it enumerates row by row over the rectangle q.
+template <int NP>
 __device__ __forceinline__ void add_instance(double* g, const float* P, uint32_t l, ushort4 q, double mx,
                                              double my) {
   const uint32_t w = (uint32_t)(q.y - q.x);
@@ -394,7 +401,7 @@ __device__ __forceinline__ void add_instance(double* g, const float* P, uint32_t
   g[3] += (double)P[4] + Dx * m1y + Dy * m1x + Dx * Dy * m0;
   g[4] += (double)P[5] + 2.0 * Dy * m1y + Dy * Dy * m0;
 #pragma unroll
-  for (int c = 5; c < 9; ++c) g[c] += (double)P[c + 1];
+  for (int c = 5; c < NP - 1; ++c) g[c] += (double)P[c + 1];
 }
 
 __device__ __forceinline__ void splat_mean64(const Splat* splats, int64_t i, double& mx, double& my) {
@@ -405,15 +412,16 @@ __device__ __forceinline__ void splat_mean64(const Splat* splats, int64_t i, dou
 
 // Splats with more than kLongSegment instances: one workgroup per splat turns
 // its instance partials into the splat's 2D sums (add_instance) in grad2d at
-// its selection position.  Per-thread FP64 sums over independent unrolled loads, a
+// its selection position (and its contributing pixels in contrib).  Per-thread FP64 sums over independent unrolled loads, a
 // butterfly over the wave, the waves in order: a fixed order, so
 // deterministic.
+template <int NP>
 __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, const uint32_t* long_list,
                                                       const uint32_t* order,
                                                       const uint32_t* inst_off, const float* __restrict__ partial,
                                                       const Splat* __restrict__ splats, const ushort4* rect,
-                                                      double* grad2d) {
-  __shared__ double part[kBlock / 64][9];
+                                                      double* grad2d, int32_t* contrib) {
+  __shared__ double part[kBlock / 64][10];
   const int64_t n = ctr->n_drawn, nl = ctr->n_long;
   const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -427,35 +435,36 @@ __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, 
     const ushort4 q = rect[i];
     double mx, my;
     splat_mean64(splats, i, mx, my);
-    double g[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double g[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t q0 = a + threadIdx.x; q0 < b; q0 += 4 * kBlock) {
-      float t[4][kPartial];
+      float t[4][NP];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int64_t k = q0 + (int64_t)u * kBlock;
 #pragma unroll
-        for (int c = 0; c < kPartial; ++c) t[u][c] = k < b ? partial[kPartial * k + c] : 0.0f;
+        for (int c = 0; c < NP; ++c) t[u][c] = k < b ? partial[NP * k + c] : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int64_t k = q0 + (int64_t)u * kBlock;
-        if (k < b) add_instance(g, t[u], (uint32_t)(k - a0), q, mx, my);
+        if (k < b) add_instance<NP>(g, t[u], (uint32_t)(k - a0), q, mx, my);
       }
     }
 #pragma unroll
-    for (int c = 0; c < 9; ++c)
+    for (int c = 0; c < 10; ++c)
 #pragma unroll
       for (int d = 32; d > 0; d >>= 1) g[c] += __shfl_xor(g[c], d, 64);
     if (lane == 0) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) part[wv][c] = g[c];
+      for (int c = 0; c < 10; ++c) part[wv][c] = g[c];
     }
     __syncthreads();
-    if (threadIdx.x < 9) {
+    if (threadIdx.x < 10) {
       double sum = part[0][threadIdx.x];
 #pragma unroll
       for (int w = 1; w < kBlock / 64; ++w) sum += part[w][threadIdx.x];
-      grad2d[9 * i + threadIdx.x] = sum;
+      if (threadIdx.x < 9) grad2d[9 * i + threadIdx.x] = sum;
+      else if (NP == 11) contrib[i] = (int32_t)sum;  // a count, exact in FP64
     }
     __syncthreads();
   }
@@ -466,12 +475,14 @@ __global__ void __launch_bounds__(kBlock) k_long_sums(const FrameCounters* ctr, 
 // one thread per splat, in depth order, so neighbouring threads read
 // neighbouring partials; FP64 sums in instance order (add_instance) into
 // grad2d at the splat's selection position (zero for a splat that an
-// instance overflow left without instances).
+// instance overflow left without instances), and its number of contributing
+// pixels into contrib.
+template <int NP>
 __global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr, const uint32_t* order,
                                                        const uint32_t* inst_off,
                                                        const float* __restrict__ partial,
                                                        const Splat* __restrict__ splats, const ushort4* rect,
-                                                       const uint4* rank_info, double* grad2d) {
+                                                       const uint4* rank_info, double* grad2d, int32_t* contrib) {
   const int64_t n = ctr->n_drawn;
   const int64_t n_inst = (uint32_t)ctr->n_instances, n_cl = ctr->n_inst_clamped;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
@@ -495,16 +506,17 @@ __global__ void __launch_bounds__(kBlock) k_splat_sums(const FrameCounters* ctr,
     int64_t b = r + 1 < n ? (int64_t)inst_off[r + 1] : n_inst;
     const int64_t a = a0 < n_cl ? a0 : n_cl;
     b = b < n_cl ? b : n_cl;
-    double g[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double g[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t k = a; k < b; ++k) {
-      float t[kPartial];
+      float t[NP];
 #pragma unroll
-      for (int c = 0; c < kPartial; ++c) t[c] = partial[kPartial * k + c];
-      add_instance(g, t, (uint32_t)(k - a0), q, mx, my);
+      for (int c = 0; c < NP; ++c) t[c] = partial[NP * k + c];
+      add_instance<NP>(g, t, (uint32_t)(k - a0), q, mx, my);
     }
     double* dst = grad2d + 9 * i;
 #pragma unroll
     for (int c = 0; c < 9; ++c) dst[c] = g[c];
+    if (NP == 11) contrib[i] = (int32_t)g[9];
   }
 }
 
@@ -602,12 +614,20 @@ template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewConst* __restrict__ vp, const int32_t* idx,
                                                         const FrameCounters* ctr, const uint32_t* drawn_list,
                                                         const double* grad2d, lodgs_grads sel, lodgs_grads nodes,
-                                                        float* max_grad2d) {
+                                                        float* max_grad2d, ContribStats cs) {
+  const int32_t iter = cs.last ? *cs.iteration : 0;
   const ViewConst v = *vp;
   const int64_t n = ctr->n_drawn;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = drawn_list[r];
     const int64_t node = idx[i];
+    if (cs.last) {  // pruning statistics: a drawn node is one splat of its view (no races)
+      const int32_t c = cs.contrib[i];
+      if (c > 0) {
+        cs.last[node] = iter;
+        if (cs.count) cs.count[node] += c;
+      }
+    }
     double g2[9];  // 2D sums of the splat (selection position i), see add_instance
 #pragma unroll
     for (int c = 0; c < 9; ++c) g2[c] = grad2d[9 * i + c];
@@ -701,39 +721,45 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewCo
   }
 }
 
-template <int DEG>
+template <int DEG, int NP>
 static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodgs_grads& sel,
                                    const lodgs_grads& nodes, hipStream_t st) {
-  // 16 splats per block: one pass covers 256k drawn splats, so each 16-lane
+  hipLaunchKernelGGL(k_long_sums<NP>, dim3(1024), dim3(kBlock), 0, st, f->ctr, f->long_list, f->sorted_order,
+                     f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d, f->contrib);
+  hipLaunchKernelGGL(k_splat_sums<NP>, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_order, f->inst_off,
+                     f->inst_grad, f->splats, f->rect, f->rank_info, f->grad2d, f->contrib);
+  // 16 lanes per splat: one pass covers 256k drawn splats, so each 16-lane
   // group runs its latency-bound chain of dependent loads once
-  hipLaunchKernelGGL(k_long_sums, dim3(1024), dim3(kBlock), 0, st, f->ctr, f->long_list, f->sorted_order,
-                     f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d);
-  hipLaunchKernelGGL(k_splat_sums, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_order, f->inst_off,
-                     f->inst_grad, f->splats, f->rect, f->rank_info, f->grad2d);
   hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, f->r_idx, f->ctr, f->drawn_list, f->dcol,
                      f->grad2d, sel.d_sh, nodes.d_sh);
+  ContribStats cs{f->contrib, nullptr, nullptr, nullptr};
+  if (NP == 11) cs = ContribStats{f->contrib, f->last_contrib, f->contrib_count, f->contrib_iteration};
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
-                     f->drawn_list, f->grad2d, sel, nodes, f->rows_mode ? (float*)nullptr : f->max_grad2d);
+                     f->drawn_list, f->grad2d, sel, nodes, f->rows_mode ? (float*)nullptr : f->max_grad2d, cs);
 }
 
-void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
-                     hipStream_t st) {
+template <int NP>
+static void launch_backward_np(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
+                               hipStream_t st) {
   const SceneDev& S = render_params(f);
   const ViewConst& v = f->view;
   stage_begin(f, LODGS_STAGE_BLEND_BWD, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   switch (f->blend_px_bwd) {
     case 1:
-      hipLaunchKernelGGL(k_blend_bwd<1>, dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->sorted_info, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
+      hipLaunchKernelGGL((k_blend_bwd<1, NP>), dim3(ntiles), dim3(256), 0, st, f->d_view_ren, f->ranges,
+                         f->sorted_ival, f->sorted_info, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event,
+                         f->tile_order, f->inst_grad);
       break;
     case 4:
-      hipLaunchKernelGGL(k_blend_bwd<4>, dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->sorted_info, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
+      hipLaunchKernelGGL((k_blend_bwd<4, NP>), dim3(ntiles), dim3(64), 0, st, f->d_view_ren, f->ranges,
+                         f->sorted_ival, f->sorted_info, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event,
+                         f->tile_order, f->inst_grad);
       break;
     default:
-      hipLaunchKernelGGL(k_blend_bwd<2>, dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges, f->sorted_ival,
-                         f->sorted_info, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event, f->tile_order, f->inst_grad);
+      hipLaunchKernelGGL((k_blend_bwd<2, NP>), dim3(ntiles), dim3(128), 0, st, f->d_view_ren, f->ranges,
+                         f->sorted_ival, f->sorted_info, f->splats, f->ctr, f->r_rgb, d_dL, f->inst_event,
+                         f->tile_order, f->inst_grad);
       break;
   }
   stage_end(f, st);
@@ -742,12 +768,20 @@ void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, 
   if (sel) hipLaunchKernelGGL(k_zero_sel, dim3(1024), dim3(kBlock), 0, st, f->ctr, S.n_coef, *sel);
   const lodgs_grads gs = sel ? *sel : none, gn = nodes ? *nodes : none;
   switch (S.sh_degree) {
-    case 0: launch_project_bwd_deg<0>(S, f, gs, gn, st); break;
-    case 1: launch_project_bwd_deg<1>(S, f, gs, gn, st); break;
-    case 2: launch_project_bwd_deg<2>(S, f, gs, gn, st); break;
-    default: launch_project_bwd_deg<3>(S, f, gs, gn, st); break;
+    case 0: launch_project_bwd_deg<0, NP>(S, f, gs, gn, st); break;
+    case 1: launch_project_bwd_deg<1, NP>(S, f, gs, gn, st); break;
+    case 2: launch_project_bwd_deg<2, NP>(S, f, gs, gn, st); break;
+    default: launch_project_bwd_deg<3, NP>(S, f, gs, gn, st); break;
   }
   stage_end(f, st);
+}
+
+// The per-instance partials carry the contributing-pixel count (11 values)
+// only while the pruning statistic is attached (and not in the rows form).
+void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
+                     hipStream_t st) {
+  if (f->last_contrib && !f->rows_mode) launch_backward_np<kPartial>(f, d_dL, sel, nodes, st);
+  else launch_backward_np<kPartial - 1>(f, d_dL, sel, nodes, st);
 }
 
 __device__ __forceinline__ float wave_sum(float x) {

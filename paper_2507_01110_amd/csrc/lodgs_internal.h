@@ -53,6 +53,14 @@ struct CacheDev {
   uint32_t* spt_sel;      // [n_spt] this view's selected nodes per SPT
 };
 
+// Pruning statistics handed to the projection backward (last == nullptr: off).
+struct ContribStats {
+  const int32_t* contrib;    // per selection position
+  int32_t* last;             // node-indexed
+  int32_t* count;            // node-indexed (optional)
+  const int32_t* iteration;  // device word
+};
+
 struct lodgs_scene {
   SceneDev dev;
   int32_t* anc_owned;
@@ -164,6 +172,10 @@ struct lodgs_frame {
   SceneDev rows_dev;         // the scene's view with the parameter pointers on the rows
   int32_t* iota;             // [max_selected] i at i
   float* max_grad2d;         // [n_nodes] densification statistic raised by each backward (borrowed; optional)
+  int32_t* contrib;          // [max_selected] contributing pixels of each drawn splat (selection position)
+  int32_t* last_contrib;     // [n_nodes] pruning statistic: iteration of the last contribution (borrowed; optional)
+  int32_t* contrib_count;    // [n_nodes] contributing pixels, accumulated (borrowed; optional)
+  const int32_t* contrib_iteration;  // the iteration stamped into last_contrib (borrowed device word)
   int blend_px_fwd;          // pixels per lane of the forward blend (1, 2 or 4)
   int blend_px_bwd;          // pixels per lane of the blend backward (1, 2 or 4)
 };
@@ -195,8 +207,9 @@ __device__ __forceinline__ int wave_hit_list(int m, uint32_t want, const uint32_
 }
 
 // Per-instance partial of the blend backward: sum w, sum w e (2), sum w e e^T
-// (3) about the tile centre, dL/do, dL/dRGB (3).
-constexpr int kPartial = 10;
+// (3) about the tile centre, dL/do, dL/dRGB (3), and (only while the pruning
+// statistic is attached) contributing pixels: at most kPartial floats.
+constexpr int kPartial = 11;
 
 // Floats of the colour backward's per-splat record (written by the forward).
 constexpr int kColorRec = 16;
@@ -297,6 +310,7 @@ void frame_arrays(lodgs_frame* f, const SceneDev& S, const lodgs_frame_caps& cap
   fn(f->info_k, ni);
   fn(f->rank_info, 2 * ns);
   fn(f->grad2d, 9 * ns);
+  fn(f->contrib, ns);
   fn(f->dcol, (size_t)kColorRec * ns);
   fn(f->long_list, ns);
   fn(f->ranges, nt);

@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_offsets(uint32_t* table, const
 // LDS in digit order; (3) consecutive threads write consecutive staged keys,
 // so a digit's keys go to consecutive global positions.  With XTRA an 8-byte
 // payload per key is read when the tile is staged (coalesced: input order)
-// and written beside it.
+// and staged and written with it.
 constexpr int kScatterRounds = 16;
 constexpr int kScatterTile = kScatterRounds * kBlock;
 
@@ -124,7 +124,8 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* kin, c
 #pragma unroll
     for (int u = 0; u < kScatterRounds; ++u) {
       if ((int64_t)u * kBlock + t < tn) {
-        const uint32_t pos = lstart[(kr[u] >> shift) & 255u] + lr[u];
+        const uint32_t d = (kr[u] >> shift) & 255u;
+        const uint32_t pos = lstart[d] + lr[u];
         sk[pos] = kr[u];
         sv[pos] = vr[u];
         if (XTRA) sx[pos] = xin[t0 + (int64_t)u * kBlock + t];

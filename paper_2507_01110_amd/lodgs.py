@@ -336,6 +336,16 @@ class Frame:
         self._densify = max_grad2d
         check(_lib.load().lodgs_frame_set_densify_stats(self._h, _ptr(max_grad2d)), "lodgs_frame_set_densify_stats")
 
+    def set_contrib_stats(self, last=None, count=None, iteration=None):
+        """Attaches the pruning statistic: node-indexed int32 `last` receives
+        the device int32 `iteration` for every node that contributes to a
+        pixel in a later backward; `count` (optional) accumulates the
+        contributing pixels.  last=None detaches."""
+        check(_lib.load().lodgs_frame_set_contrib_stats(self._h, _ptr(last), _ptr(count) if last is not None else None,
+                                                        _ptr(iteration) if last is not None else None),
+              "lodgs_frame_set_contrib_stats")
+        self._contrib = (last, count, iteration)
+
     def clear_status(self, stream=None):
         check(_lib.load().lodgs_frame_clear_status(self._h, _stream(stream)), "lodgs_frame_clear_status")
 

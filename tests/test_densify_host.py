@@ -99,3 +99,114 @@ def test_two_dead_siblings_respawn_only_the_right_one():
     _check_tree(t2)
     assert t2.left[l] < 0 and t2.parent[l] == t.parent[p]  # the left one took the parent's place
     assert t2.parent[r] == t2.parent[p]  # the right one and the parent were respawned together
+
+
+def _respawn_one_at_a_time(t, d, tgt):
+    """Reference edit for one respawn (the definition): the sibling takes the
+    parent's place, the dead leaf and its parent go under the chosen leaf."""
+    left, right, parent = t["left"], t["right"], t["parent"]
+    p = parent[d]
+    s = right[p] if left[p] == d else left[p]
+    g = parent[p]
+    parent[s] = g
+    if g >= 0:
+        if left[g] == p:
+            left[g] = s
+        else:
+            right[g] = s
+    else:
+        t["root"] = s
+    left[tgt], right[tgt] = d, p
+    parent[d] = parent[p] = tgt
+    left[p] = right[p] = -1
+
+
+def test_parallel_respawn_equals_the_edits_one_at_a_time():
+    # many dead leaves in one step: the parallel edit gives the tree that the
+    # planned respawns give applied one after another (they touch disjoint
+    # links), and the plan obeys both rules
+    from paper_2507_01110_amd.densify import respawn_plan
+    rng = np.random.default_rng(54)
+    for it in range(40):
+        t = random_tree(rng, int(rng.integers(8, 120)))
+        t.opacity_logits[:] = 2.0
+        leaves = np.flatnonzero(t.left < 0)
+        dead = rng.choice(leaves, size=max(1, len(leaves) // 4), replace=False)
+        t.opacity_logits[dead] = -10.0
+        stat = rng.random(t.n_nodes)
+        plan = respawn_plan(t.left, t.right, t.parent, np.sort(dead))
+        dead_set = set(dead.tolist())
+        planned = set(plan.tolist())
+        for d in plan:
+            p = t.parent[d]
+            s = t.right[p] if t.left[p] == d else t.left[p]
+            assert not (t.left[p] == d and s in dead_set), "the left one of two dead siblings"
+        sib = {int(t.right[t.parent[d]] if t.left[t.parent[d]] == d else t.left[t.parent[d]]) for d in plan}
+        assert not any(int(t.parent[d]) in sib for d in plan), "a parent that is another's sibling"
+        t2, info = densify(t, stat, n_spawn=0)
+        _check_tree(t2)
+        o = 1.0 / (1.0 + np.exp(-t.opacity_logits.astype(np.float64)))
+        cand = np.flatnonzero((t.left < 0) & (o >= 0.005))
+        targets = cand[np.lexsort((cand, -stat[cand]))][: len(plan)]
+        ref = {"left": t.left.copy(), "right": t.right.copy(), "parent": t.parent.copy(), "root": int(t.root)}
+        for d, tgt in zip(plan[: len(targets)], targets):
+            _respawn_one_at_a_time(ref, int(d), int(tgt))
+        assert info["respawned"] == min(len(plan), len(targets))
+        assert np.array_equal(t2.left, ref["left"]) and np.array_equal(t2.right, ref["right"])
+        assert np.array_equal(t2.parent, ref["parent"]) and int(t2.root) == ref["root"]
+        assert planned <= dead_set
+
+
+def test_chained_dead_leaves_wait_for_the_next_step():
+    # d1's sibling is the parent of d2: only d1 is respawned now; the next
+    # step respawns d2
+    from paper_2507_01110_amd.densify import respawn_plan
+    rng = np.random.default_rng(55)
+    found = 0
+    for it in range(200):
+        t = random_tree(rng, 24)
+        t.opacity_logits[:] = 2.0
+        for p1 in range(t.n_nodes):
+            l, r = int(t.left[p1]), int(t.right[p1])
+            if l < 0 or t.left[l] >= 0 or t.left[r] < 0:
+                continue
+            d1, s1 = l, r  # a leaf whose sibling s1 is interior
+            d2 = int(t.left[s1]) if t.left[t.left[s1]] < 0 else (int(t.right[s1]) if t.left[t.right[s1]] < 0 else -1)
+            if d2 < 0:
+                continue
+            other = int(t.right[s1]) if d2 == int(t.left[s1]) else int(t.left[s1])
+            if t.left[other] < 0:
+                continue  # keep the sibling rule out of it
+            t.opacity_logits[[d1, d2]] = -10.0
+            assert respawn_plan(t.left, t.right, t.parent, np.array([min(d1, d2), max(d1, d2)])).tolist() == [d1]
+            t2, info = densify(t, rng.random(t.n_nodes), n_spawn=0)
+            assert info["respawned"] == 1
+            _check_tree(t2)
+            t3, info3 = densify(t2, rng.random(t2.n_nodes), n_spawn=0)
+            assert info3["respawned"] >= 1
+            _check_tree(t3)
+            found += 1
+            break
+        if found >= 5:
+            break
+    assert found >= 5
+
+
+def test_prune_zeroes_the_leaves_idle_for_twice_the_training_set():
+    from paper_2507_01110_amd.densify import PRUNED_LOGIT, prune
+    rng = np.random.default_rng(56)
+    t = random_tree(rng, 50)
+    t.opacity_logits[:] = 1.0
+    last = rng.integers(0, 100, size=t.n_nodes)
+    n = prune(t, last, iteration=100, train_views=20)
+    leaf = t.left < 0
+    idle = (100 - last >= 40) & leaf
+    assert n == int(idle.sum()) > 0
+    assert np.all(t.opacity_logits[idle] == PRUNED_LOGIT)
+    assert np.all(t.opacity_logits[~idle] == 1.0)  # interior nodes and recent leaves untouched
+    assert 1.0 / (1.0 + np.exp(-PRUNED_LOGIT)) < 1e-12
+    assert prune(t, last, iteration=100, train_views=20) == 0  # already pruned
+    # a pruned leaf is dead: the next densification step respawns it
+    t2, info = densify(t, rng.random(t.n_nodes), n_spawn=0)
+    assert info["respawned"] >= 1
+    _check_tree(t2)

@@ -577,3 +577,79 @@ def test_densify_loop_statistic_edit_rebuild_render(torch_cuda):
     ids = _check_select(O2, f2, cam, 1.0, True)
     F = oracle.OracleFrame(t2, ids, cam)
     _check_image(f2.render(cam), F)
+
+
+def test_contribution_statistic_matches_the_oracle(torch_cuda):
+    # the pruning statistic over three views: every node the oracle composites
+    # into some pixel gets that view's iteration stamp and its exact number of
+    # contributing pixels (integer, bit-exact); nodes it composites nowhere
+    # keep their stamp
+    torch = torch_cuda
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    last = torch.full((S.n_nodes,), -1, dtype=torch.int32, device="cuda")
+    count = torch.zeros(S.n_nodes, dtype=torch.int32, device="cuda")
+    it = torch.zeros(1, dtype=torch.int32, device="cuda")
+    want_last = np.full(S.n_nodes, -1, np.int64)
+    want_count = np.zeros(S.n_nodes, np.int64)
+    cams = [configs.tiny_camera(256, 256), scenegen.camera_look_at((25, -8, 6), (3, 2, 0), (0, 0, 1), 320, 200),
+            scenegen.camera_look_at((-6, 14, 18), (0, 0, 0), (0, 0, 1), 300, 240)]
+    for k, cam in enumerate(cams):
+        it.fill_(10 + k)
+        f = _frame(S, cam)
+        f.set_contrib_stats(last, count, it)
+        f.lod_select(cam, 1.0)
+        f.render(cam)
+        ids, _ = O.select(cam, 1.0)
+        F = oracle.OracleFrame(tree, ids, cam)
+        _, dL = oracle.l1_loss_grad(F.image, scenegen.target_image(cam.height, cam.width, 50 + k))
+        f.backward(torch.from_numpy(dL.astype(np.float32)).cuda())
+        c = F.splat_contrib()
+        pos = O.pos_of[ids]
+        want_count[pos] += c
+        want_last[pos[c > 0]] = 10 + k
+        torch.cuda.synchronize()
+        assert np.array_equal(count.cpu().numpy(), want_count), k
+        assert np.array_equal(last.cpu().numpy(), want_last), k
+        _say(f"view {k}: {int((c > 0).sum())} of {len(ids)} selected nodes contribute, {int(c.sum())} pixels")
+
+
+def test_prune_loop_statistic_prune_respawn_render(torch_cuda):
+    # pruning: the statistic from GPU backwards over a two-view training set,
+    # the leaves idle for twice its size zeroed on the host, respawned by the
+    # next densification step, and the edited scene cut and rendered as the
+    # oracle does
+    torch = torch_cuda
+    from paper_2507_01110_amd.densify import densify, prune
+    tree = scenegen.build_tree(configs.tiny_spec(n=4096))
+    S = _scene(tree)
+    last = torch.zeros(S.n_nodes, dtype=torch.int32, device="cuda")
+    it = torch.zeros(1, dtype=torch.int32, device="cuda")
+    stat = torch.zeros(S.n_nodes, dtype=torch.float32, device="cuda")
+    cams = [configs.tiny_camera(160, 160), scenegen.camera_look_at((18, -6, 8), (0, 0, 0), (0, 0, 1), 160, 120)]
+    frames = [_frame(S, c) for c in cams]
+    for f in frames:
+        f.set_contrib_stats(last, None, it)
+        f.set_densify_stats(stat)
+    for step in range(1, 9):  # four passes over the training set
+        it.fill_(step)
+        f, cam = frames[step % 2], cams[step % 2]
+        f.lod_select(cam, 1.0)
+        img = f.render(cam)
+        f.backward(torch.sign(img - 0.5))
+    torch.cuda.synchronize()
+    by_id = np.zeros(S.n_nodes, np.int64)
+    by_id[S.perm] = last.cpu().numpy()
+    n_pruned = prune(tree, by_id, iteration=8, train_views=2)
+    _say("pruned", n_pruned, "of", int((tree.left < 0).sum()), "leaves")
+    assert n_pruned > 0
+    st = np.zeros(S.n_nodes)
+    st[S.perm] = stat.cpu().numpy()
+    t2, info = densify(tree, st, n_spawn=0)
+    assert info["respawned"] > 0
+    O2 = oracle.OracleScene(t2)
+    S2 = _scene(t2)
+    f2 = _frame(S2, cams[0])
+    ids = _check_select(O2, f2, cams[0], 1.0, True)
+    _check_image(f2.render(cams[0]), oracle.OracleFrame(t2, ids, cams[0]))

@@ -320,3 +320,45 @@ def test_directional_fd_matches_full_reevaluation_and_backward():
         full = (up - dn) / (2 * h)
         assert abs(local - full) <= 1e-7 * max(1.0, abs(full))
         assert abs(local - g[i] @ v) <= 1e-6 * max(1e-3, np.abs(g[i]).max() * np.abs(v).max())
+
+
+def test_splat_contribution_counts_closed_form():
+    # one splat: it is composited into exactly the pixels where o e^power >=
+    # 1/255 (nothing stops: 1 - alpha >= 0.01); two splats side by side along x
+    # do not overlap: each count is its own disc
+    cam = _cam64()
+    o, s = 0.3, 0.15
+    t = single_splat_tree([dict(mean=(0, 0, 0), log_scale=(math.log(s),) * 3, logit=math.log(o / (1 - o)),
+                                rgb=(0.5, 0.5, 0.5))])
+    F = oracle.OracleFrame(t, np.array([0]), cam)
+    se, oe, _ = _eff(s, o, (0.5, 0.5, 0.5))
+    a = _alpha_on_axis(oe, (cam.fx * se / 10.0) ** 2 + 0.3, (64, 64), (cam.cx, cam.cy))
+    assert np.all(np.abs(a - 1 / 255) > 1e-6), "no pixel centre on the threshold"
+    want = int((a >= 1 / 255).sum())
+    assert want > 20
+    assert F.splat_contrib().tolist() == [want]
+    assert int(F.pixel_counts().sum()) == want
+    # two splats 2.5 units apart on x (about 80 px): disjoint discs
+    t2 = single_splat_tree([dict(mean=(-1.25, 0, 0), log_scale=(math.log(s),) * 3, logit=math.log(o / (1 - o)),
+                                 rgb=(0.5, 0.5, 0.5)),
+                            dict(mean=(1.25, 0, 0), log_scale=(math.log(s),) * 3, logit=math.log(o / (1 - o)),
+                                 rgb=(0.5, 0.5, 0.5))])
+    cam2 = _cam64(w=256, h=64)
+    F2 = oracle.OracleFrame(t2, np.array([0, 1]), cam2)
+    var = (cam2.fx * se / 10.0) ** 2 + 0.3
+    counts = []
+    for mx in (-1.25, 1.25):
+        a = _alpha_on_axis(oe, var, (64, 256), (cam2.cx + cam2.fx * mx / 10.0, cam2.cy))
+        assert np.all(np.abs(a - 1 / 255) > 1e-6)
+        counts.append(int((a >= 1 / 255).sum()))
+    assert F2.splat_contrib().tolist() == counts
+
+
+def test_splat_contribution_counts_sum_to_the_contributor_lists(tiny_tree, tiny_oracle):
+    cam = configs.tiny_camera(128, 128)
+    ids, _ = tiny_oracle.select(cam, 1.0)
+    F = oracle.OracleFrame(tiny_tree, ids, cam)
+    c = F.splat_contrib()
+    assert int(c.sum()) == F.info()["n_contrib"] == int(F.pixel_counts().sum())
+    # a splat that is not drawn is composited nowhere
+    assert np.all(c[F.splats()["tiles"] == 0] == 0)
