@@ -286,6 +286,50 @@ typedef struct lodgs_grads {
 int lodgs_gather_rows(const lodgs_grads* host, const lodgs_grads* rows, int32_t sh_degree, const int32_t* d_idx,
                       const int32_t* d_count, int64_t capacity, int64_t n_nodes, lodgs_stream stream);
 
+/* A device pool of the rows of cached SPT cuts (Sec. 4.4 "Caching on the
+ * GPU": a cached cut's Gaussians stay in VRAM; Alg. 3: load from RAM, cache
+ * insert, write-back of evicted entries), over an SPT-cut cache and a host
+ * store in pinned memory (the layout of lodgs_gather_rows).  The upper
+ * hierarchy's rows are kept resident.  lodgs_gather_rows_pooled, called after
+ * a lodgs_lod_select_cached on the pool's cache with that call's d_idx and
+ * d_count, first gives back the slots of every entry that the select reloaded
+ * (a miss of the ratio test) or dropped, writing back to host memory the rows
+ * that lodgs_row_pool_store changed; then every cached, visible entry that is
+ * not pooled takes one slot per selected node of its cut; then writes row k
+ * of rows (k < min(*d_count, capacity)) for node d_idx[k] from the resident
+ * upper rows, the pool, or host memory (a node without a slot, or whose slot
+ * was just taken, which is filled on the way): a cache hit reads nothing over
+ * the host link.  lodgs_row_pool_store writes trained rows back: to the pool
+ * for pooled nodes (written to host memory when their entry leaves), to the
+ * resident upper rows and host memory for upper nodes, to host memory
+ * otherwise.  The pool's capacity (slots) must be at least the cache's
+ * max_nodes, so an entry always finds its slots.  One pool per cache; calls
+ * are stream-ordered after the select they follow.  Errors: LODGS_E_INVALID
+ * for a null or unpinned host array, a wrong sh_degree or a capacity below
+ * max_nodes; LODGS_E_OOM. */
+typedef struct lodgs_row_pool lodgs_row_pool;
+typedef struct lodgs_row_pool_stats {
+  int64_t capacity;         /* slots                                            */
+  int64_t pooled_rows;      /* slots in use                                     */
+  int64_t host_rows;        /* rows of the last gather read from host memory    */
+  int64_t inserted;         /* slots taken by the last gather                   */
+  int64_t released;         /* slots given back by the last gather              */
+  int64_t insert_failures;  /* nodes left without a slot (total; 0 by design)   */
+  int64_t written_back;     /* changed rows written back on release (total)     */
+} lodgs_row_pool_stats;
+
+int lodgs_row_pool_create(lodgs_cut_cache* cache, const lodgs_grads* host, int32_t sh_degree, int64_t capacity,
+                          lodgs_row_pool** out);
+void lodgs_row_pool_destroy(lodgs_row_pool* pool);
+int lodgs_gather_rows_pooled(lodgs_row_pool* pool, const int32_t* d_idx, const int32_t* d_count,
+                             const lodgs_grads* rows, int64_t capacity, lodgs_stream stream);
+int lodgs_row_pool_store(lodgs_row_pool* pool, const int32_t* d_idx, const int32_t* d_count, const lodgs_grads* rows,
+                         int64_t capacity, lodgs_stream stream);
+/* Counters (blocks on the stream); with d_node_slot (device int32 [n_nodes])
+ * not NULL, also copies each node's slot (-1: not pooled). */
+int lodgs_row_pool_stats_read(lodgs_row_pool* pool, lodgs_row_pool_stats* out, int32_t* d_node_slot,
+                              lodgs_stream stream);
+
 /* lodgs_render with the parameters of the i-th rendered node taken from row
  * i of rows (as lodgs_gather_rows writes them) instead of the scene: the
  * image, the instances and the frame state equal those of lodgs_render on

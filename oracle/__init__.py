@@ -393,6 +393,7 @@ class OracleCutCache:
                 counts[sp] = counts.get(sp, 0) + 1
         for r, d, X in loaded:
             self.entries[r] = [d, X, counts.get(r, 0), self.t]
+        self.last_loaded = [r for r, _, _ in loaded]  # SPT roots cut afresh by this select
         remaining = sum(e[2] for e in self.entries.values())
         for r in sorted(self.entries, key=lambda r: (self.entries[r][3], self.spt_index[r])):
             if remaining <= self.max_nodes:

@@ -75,6 +75,14 @@ class Timings(ctypes.Structure):
         return {name: (float(self.ms[k]), int(self.calls[k])) for k, name in enumerate(STAGES)}
 
 
+class RowPoolStats(ctypes.Structure):
+    _fields_ = [("capacity", i64), ("pooled_rows", i64), ("host_rows", i64), ("inserted", i64), ("released", i64),
+                ("insert_failures", i64), ("written_back", i64)]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
 SERVER_MAX_SIZES = 8
 
 
@@ -140,6 +148,11 @@ EXPORTS = {
     "lodgs_gather_rows": ([ctypes.POINTER(Grads), ctypes.POINTER(Grads), i32, c_p, c_p, i64, i64, c_p], ctypes.c_int),
     "lodgs_render_rows": ([c_p, ctypes.POINTER(Grads), c_p, ctypes.POINTER(Camera), c_p, c_p, c_p], ctypes.c_int),
     "lodgs_frame_set_densify_stats": ([c_p, c_p], ctypes.c_int),
+    "lodgs_row_pool_create": ([c_p, ctypes.POINTER(Grads), i32, i64, ctypes.POINTER(c_p)], ctypes.c_int),
+    "lodgs_row_pool_destroy": ([c_p], None),
+    "lodgs_gather_rows_pooled": ([c_p, c_p, c_p, ctypes.POINTER(Grads), i64, c_p], ctypes.c_int),
+    "lodgs_row_pool_store": ([c_p, c_p, c_p, ctypes.POINTER(Grads), i64, c_p], ctypes.c_int),
+    "lodgs_row_pool_stats_read": ([c_p, ctypes.POINTER(RowPoolStats), c_p, c_p], ctypes.c_int),
     "lodgs_frame_set_contrib_stats": ([c_p, c_p, c_p, c_p], ctypes.c_int),
     "lodgs_server_create": ([c_p, ctypes.POINTER(ServerCaps), ctypes.POINTER(c_p)], ctypes.c_int),
     "lodgs_server_destroy": ([c_p], None),

@@ -13,7 +13,7 @@ INC = os.path.join(ROOT, "include")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblodgs.so")
 
-HIP_SOURCES = ["lodgs_api.hip", "lodgs_prims.hip", "lodgs_select.hip", "lodgs_render.hip", "lodgs_backward.hip", "lodgs_optim.hip", "lodgs_cache.hip", "lodgs_rows.hip", "lodgs_noalloc.hip", "lodgs_server.hip"]
+HIP_SOURCES = ["lodgs_api.hip", "lodgs_prims.hip", "lodgs_select.hip", "lodgs_render.hip", "lodgs_backward.hip", "lodgs_optim.hip", "lodgs_cache.hip", "lodgs_rows.hip", "lodgs_noalloc.hip", "lodgs_server.hip", "lodgs_pool.hip"]
 CPP_SOURCES = ["lodgs_hspt.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -61,6 +61,26 @@ struct ContribStats {
   const int32_t* iteration;  // device word
 };
 
+// State of an SPT-cut cache (lodgs_cache.hip); per SPT unless noted.
+struct lodgs_cut_cache {
+  const lodgs_scene* scene;
+  lodgs_cut_cache_params prm;
+  int64_t iteration;
+  uint8_t* cached;
+  float* dc;
+  float* Xc;
+  uint32_t* size;
+  uint32_t* last_use;
+  uint8_t* vstate;
+  float* dcur;
+  uint32_t* spt_sel;
+  uint32_t* keys[2];
+  uint32_t* vals[2];
+  uint32_t* prefix;
+  unsigned long long* counters;  // hits, loads, evictions, cached SPTs, cached nodes
+  int32_t* total;                // node count of the entries before the drop
+};
+
 struct lodgs_scene {
   SceneDev dev;
   int32_t* anc_owned;

@@ -207,6 +207,45 @@ class CutCache:
 GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
+class RowPool:
+    """Device pool of the rows of a CutCache's cached SPT cuts over a pinned
+    host store (lodgs_row_pool_*): gather() after a cached lod_select fills
+    the rows from the resident upper rows, the pool and, for what neither
+    holds, host memory; store() writes trained rows back."""
+
+    def __init__(self, cache: "CutCache", host: "HostParams", capacity: int):
+        self.cache, self.host = cache, host
+        g = _lib.Grads(*[_ptr(host.params[k]) for k in GROUPS])
+        h = ctypes.c_void_p()
+        check(_lib.load().lodgs_row_pool_create(cache._h, ctypes.byref(g), host.sh_degree, int(capacity),
+                                                ctypes.byref(h)), "lodgs_row_pool_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.lodgs_row_pool_destroy(h)
+            self._h = None
+
+    def gather(self, idx, count, rows: dict, stream=None):
+        g = _lib.Grads(*[_ptr(rows[k]) for k in GROUPS])
+        check(_lib.load().lodgs_gather_rows_pooled(self._h, _ptr(idx), _ptr(count), ctypes.byref(g),
+                                                   int(rows["means"].shape[0]), _stream(stream)),
+              "lodgs_gather_rows_pooled")
+        return rows
+
+    def store(self, idx, count, rows: dict, stream=None):
+        g = _lib.Grads(*[_ptr(rows[k]) for k in GROUPS])
+        check(_lib.load().lodgs_row_pool_store(self._h, _ptr(idx), _ptr(count), ctypes.byref(g),
+                                               int(rows["means"].shape[0]), _stream(stream)), "lodgs_row_pool_store")
+
+    def stats(self, node_slot=None, stream=None) -> dict:
+        s = _lib.RowPoolStats()
+        check(_lib.load().lodgs_row_pool_stats_read(self._h, ctypes.byref(s), _ptr(node_slot), _stream(stream)),
+              "lodgs_row_pool_stats_read")
+        return s.as_dict()
+
+
 class AdamCut:
     """Adam on the cut set (lodgs_adam_cut): node-indexed first and second
     moments beside each parameter group; step() updates the rows of the

@@ -112,7 +112,7 @@ def test_ctypes_structs_match_the_header_layout(tmp_path):
                "lodgs_grads": L.Grads, "lodgs_adam": L.Adam, "lodgs_cut_cache_params": L.CutCacheParams,
                "lodgs_cut_cache_stats": L.CutCacheStats, "lodgs_stats": L.Stats, "lodgs_timings": L.Timings,
                "lodgs_server_caps": L.ServerCaps, "lodgs_request": L.Request, "lodgs_completion": L.Completion,
-               "lodgs_server_stats": L.ServerStats}
+               "lodgs_server_stats": L.ServerStats, "lodgs_row_pool_stats": L.RowPoolStats}
     lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "lodgs.h"', 'int main(void) {']
     for cname, cls in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -1,0 +1,129 @@
+"""The device pool of cached SPT cuts' rows (lodgs_row_pool_*, Sec. 4.4
+"Caching on the GPU", Alg. 3's load / insert / write-back) run beside the
+oracle's SPT-cut cache state machine: after every view the assembled rows
+equal the scene's rows of the selection bit for bit, the pooled nodes are
+exactly the nodes of the cached entries' cuts, and the rows read from host
+memory are exactly the selected nodes of the entries the view loaded.
+Trained rows stored into the pool reach host memory when their entry
+leaves."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from scenegen import configs
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _lockstep(torch, tree, cams, tau, max_nodes, d_min, d_max, flush, max_inst):
+    from paper_2507_01110_amd.lodgs import CutCache, Frame, HostParams, RowPool, Scene, rows_like
+    O = oracle.OracleScene(tree)
+    S = Scene(tree)
+    host = HostParams.from_scene(S)
+    f = Frame(S, S.n_nodes, max_inst, cams[0].width, cams[0].height)
+    G = CutCache(S, max_nodes, d_min, d_max, flush)
+    P = RowPool(G, host, max_nodes)
+    C = oracle.OracleCutCache(O, max_nodes, d_min, d_max, flush)
+    rows = rows_like(tree.sh_degree, S.n_nodes)
+    slot = torch.empty(S.n_nodes, dtype=torch.int32, device="cuda")
+    spt_of = O.spt_of  # tree id -> its SPT's root tree id, -1 for upper nodes
+    pooled = {}  # SPT root tree id -> layout positions of its cached cut
+    totals = {"host": 0, "selected": 0}
+    for it, cam in enumerate(cams):
+        idx, cnt = f.lod_select(cam, tau, cache=G)
+        P.gather(idx, cnt, rows)
+        ids, _ = C.select(cam, tau)
+        n = int(cnt.item())
+        assert f.stats()["status"] == 0
+        sel = idx[:n].long()
+        assert np.array_equal(sel.cpu().numpy(), O.pos_of[ids]), it
+        for k in GROUPS:
+            assert torch.equal(rows[k][:n], S.params[k][sel]), (it, k)
+        # the oracle's view of the pool: entries cut afresh now hold this view's
+        # nodes of their SPT; entries that left hold nothing
+        sp = spt_of[ids]
+        for r in C.last_loaded:
+            pooled.pop(r, None)
+        for r in list(pooled):
+            if r not in C.entries:
+                del pooled[r]
+        fresh_rows = 0
+        for r in C.last_loaded:
+            nodes = O.pos_of[ids[sp == r]]
+            fresh_rows += len(nodes)
+            if r in C.entries:
+                pooled[r] = set(nodes.tolist())
+        st = P.stats(node_slot=slot)
+        got = set(np.flatnonzero(slot.cpu().numpy() >= 0).tolist())
+        want = set().union(*pooled.values()) if pooled else set()
+        assert got == want, (it, len(got), len(want))
+        assert st["host_rows"] == fresh_rows, (it, st, fresh_rows)
+        assert st["pooled_rows"] == len(want) and st["insert_failures"] == 0
+        totals["host"] += st["host_rows"]
+        totals["selected"] += n
+        _say(f"  view {it}: {n} selected, {st['host_rows']} rows from host, {st['pooled_rows']} pooled")
+    return S, f, G, P, C, host, rows, totals
+
+
+def test_pool_tiny_lockstep(torch_cuda):
+    torch = torch_cuda
+    tree = scenegen.build_tree(configs.tiny_spec())
+    cams = [scenegen.camera_look_at((28 * np.cos(a), 28 * np.sin(a), 12.0), (0, 0, 0), (0, 0, 1), 256, 256)
+            for a in np.linspace(0.0, 1.2, 8)]
+    for prm in ((10 ** 6, 0.5, 1.5, 0), (6000, 0.6, 1.6, 5), (20000, 1.0, 1.0, 0)):
+        _, _, _, _, _, _, _, tot = _lockstep(torch, tree, cams, 1.0, *prm, max_inst=1 << 20)
+        _say("tiny", prm, tot)
+        if prm[0] == 10 ** 6:
+            assert tot["host"] < tot["selected"]  # hits read nothing over the host link
+
+
+def test_pool_medium_flyin_and_write_back(torch_cuda):
+    torch = torch_cuda
+    tree = scenegen.build_tree(configs.medium_spec(n=500_000, seed=14))
+    cams = [scenegen.camera_yaw_pitch((4.0 * k, 1.2 * k, 40.0 - 3.0 * k), 0.3, np.radians(-45.0), 1280, 720)
+            for k in range(6)]
+    # flush every 8th select: the 8th below drops every entry
+    S, f, G, P, C, host, rows, tot = _lockstep(torch, tree, cams, 1.0, 300000, 0.7, 1.4, 8, max_inst=1 << 23)
+    _say("medium", tot)
+    assert tot["host"] < tot["selected"]
+    # trained rows: +1 on every row of the last view, stored; upper and
+    # unpooled rows reach host memory at once, pooled ones when their entry
+    # leaves (the flush of the 8th select)
+    idx, cnt = f.idx.clone(), f.count.clone()
+    n = int(cnt.item())
+    for k in GROUPS:
+        rows[k][:n] += 1.0
+    P.store(idx, cnt, rows)
+    torch.cuda.synchronize()
+    before = {k: host.params[k].clone() for k in GROUPS}
+    far = scenegen.camera_yaw_pitch((-200.0, -200.0, 60.0), 2.5, np.radians(-30.0), 1280, 720)
+    for _ in range(2):  # selects 7 and 8
+        i2, c2 = f.lod_select(far, 1.0, cache=G)
+        P.gather(i2, c2, rows)
+    torch.cuda.synchronize()
+    st = P.stats()
+    _say("after the flush", st)
+    assert st["written_back"] > 0
+    changed = (host.params["means"] != before["means"]).any(dim=1).nonzero().flatten()
+    assert len(changed) == st["written_back"]
+    diff = host.params["means"][changed] - S.params["means"][changed.cuda()].cpu()
+    assert torch.allclose(diff, torch.ones_like(diff), atol=1e-4)  # the stored +1
+    assert bool(torch.isin(changed, idx[:n].long().cpu()).all())
