@@ -421,6 +421,9 @@ def main():
     ap.add_argument("--rows", action="store_true",
                     help="out-of-core parameters: gather each cut's rows from pinned host memory, render from the "
                          "rows, backward into selection-indexed gradients")
+    ap.add_argument("--pool", type=int, default=0,
+                    help="with --rows and --cache: keep the cached cuts' rows in a device pool of this many rows "
+                         "(at least the cache's max_nodes) and gather from it")
     ap.add_argument("--graph", action="store_true",
                     help="time the training step captured in one graph (lodgs_graph_capture_step) instead of plain "
                          "launches")
@@ -543,6 +546,13 @@ def main():
     if args.cache:
         mx, dmin, dmax, fl = args.cache.split(",")
         cache = CutCache(scene, int(mx), float(dmin), float(dmax), int(fl))
+    pool = None
+    if args.pool:
+        if not (args.rows and cache is not None):
+            raise SystemExit("--pool needs --rows and --cache")
+        from paper_2507_01110_amd.lodgs import RowPool
+        pool = RowPool(cache, host, args.pool)
+        log(f"row pool: {args.pool} rows in HBM")
 
     def step(i):
         cam, tau = cstructs[seq[i % K]], views[seq[i % K]][1]
@@ -551,7 +561,10 @@ def main():
         else:
             frame.lod_select(cam, tau, conservative=args.conservative, method=args.cut)
         if args.rows:
-            frame.gather_rows(host, rows)
+            if pool is not None:
+                pool.gather(frame.idx, frame.count, rows)
+            else:
+                frame.gather_rows(host, rows)
             frame.render_rows(cam, rows, out=img)
         else:
             frame.render(cam, out=img)
@@ -686,6 +699,9 @@ def main():
     if cache is not None:
         out["config"]["cut"] = "default through the SPT-cut cache " + args.cache
         out["cut_cache"] = cache.stats()
+    if pool is not None:
+        out["config"]["params"] = f"pinned host memory, rows through a device pool of {args.pool} rows"
+        out["row_pool"] = pool.stats()
     print(json.dumps(out), flush=True)
 
 

@@ -292,14 +292,17 @@ int lodgs_gather_rows(const lodgs_grads* host, const lodgs_grads* rows, int32_t 
  * store in pinned memory (the layout of lodgs_gather_rows).  The upper
  * hierarchy's rows are kept resident.  lodgs_gather_rows_pooled, called after
  * a lodgs_lod_select_cached on the pool's cache with that call's d_idx and
- * d_count, first gives back the slots of every entry that the select reloaded
- * (a miss of the ratio test) or dropped, writing back to host memory the rows
- * that lodgs_row_pool_store changed; then every cached, visible entry that is
- * not pooled takes one slot per selected node of its cut; then writes row k
- * of rows (k < min(*d_count, capacity)) for node d_idx[k] from the resident
- * upper rows, the pool, or host memory (a node without a slot, or whose slot
- * was just taken, which is filled on the way): a cache hit reads nothing over
- * the host link.  lodgs_row_pool_store writes trained rows back: to the pool
+ * d_count, first gives back the slots of every entry that the select dropped,
+ * and those of the nodes that the new cut of an entry it cut afresh (a miss of
+ * the ratio test) no longer holds, writing back to host memory the rows that
+ * lodgs_row_pool_store changed; then every selected node of a cached, visible
+ * entry that has no slot takes one, filled from host memory; then writes row
+ * k of rows (k < min(*d_count, capacity)) for node d_idx[k] from the resident
+ * upper rows, the pool, or host memory (a node without a slot): a cache hit
+ * reads nothing over the host link, a re-cut entry only its new nodes.  The
+ * selection marks carry a per-call 32-bit stamp; when it wraps the marks are
+ * cleared with hipMemsetAsync, so this call is not for graph capture.
+ * lodgs_row_pool_store writes trained rows back: to the pool
  * for pooled nodes (written to host memory when their entry leaves), to the
  * resident upper rows and host memory for upper nodes, to host memory
  * otherwise.  The pool's capacity (slots) must be at least the cache's
@@ -312,7 +315,7 @@ typedef struct lodgs_row_pool_stats {
   int64_t capacity;         /* slots                                            */
   int64_t pooled_rows;      /* slots in use                                     */
   int64_t host_rows;        /* rows of the last gather read from host memory    */
-  int64_t inserted;         /* slots taken by the last gather                   */
+  int64_t inserted;         /* slots taken (and filled) by the last gather      */
   int64_t released;         /* slots given back by the last gather              */
   int64_t insert_failures;  /* nodes left without a slot (total; 0 by design)   */
   int64_t written_back;     /* changed rows written back on release (total)     */

@@ -3,7 +3,8 @@
 oracle's SPT-cut cache state machine: after every view the assembled rows
 equal the scene's rows of the selection bit for bit, the pooled nodes are
 exactly the nodes of the cached entries' cuts, and the rows read from host
-memory are exactly the selected nodes of the entries the view loaded.
+memory are exactly the selected nodes of the entries the view loaded that
+their entry did not already hold.
 Trained rows stored into the pool reach host memory when their entry
 leaves."""
 import sys
@@ -57,20 +58,23 @@ def _lockstep(torch, tree, cams, tau, max_nodes, d_min, d_max, flush, max_inst):
         assert np.array_equal(sel.cpu().numpy(), O.pos_of[ids]), it
         for k in GROUPS:
             assert torch.equal(rows[k][:n], S.params[k][sel]), (it, k)
-        # the oracle's view of the pool: entries cut afresh now hold this view's
-        # nodes of their SPT; entries that left hold nothing
+        # the oracle's view of the pool: an entry cut afresh now holds this
+        # view's nodes of its SPT and reads from host memory only those it did
+        # not hold; entries that left hold nothing, and a loaded SPT that is
+        # not cached reads all its nodes from host memory
         sp = spt_of[ids]
+        fresh_rows = 0
         for r in C.last_loaded:
-            pooled.pop(r, None)
+            old = pooled.pop(r, set())
+            nodes = set(O.pos_of[ids[sp == r]].tolist())
+            if r in C.entries:
+                fresh_rows += len(nodes - old)
+                pooled[r] = nodes
+            else:
+                fresh_rows += len(nodes)
         for r in list(pooled):
             if r not in C.entries:
                 del pooled[r]
-        fresh_rows = 0
-        for r in C.last_loaded:
-            nodes = O.pos_of[ids[sp == r]]
-            fresh_rows += len(nodes)
-            if r in C.entries:
-                pooled[r] = set(nodes.tolist())
         st = P.stats(node_slot=slot)
         got = set(np.flatnonzero(slot.cpu().numpy() >= 0).tolist())
         want = set().union(*pooled.values()) if pooled else set()
@@ -93,6 +97,27 @@ def test_pool_tiny_lockstep(torch_cuda):
         _say("tiny", prm, tot)
         if prm[0] == 10 ** 6:
             assert tot["host"] < tot["selected"]  # hits read nothing over the host link
+
+
+@pytest.mark.parametrize("sh_degree", [0, 1, 2])
+def test_pool_lower_sh_degrees(torch_cuda, sh_degree):
+    """Rows of 3, 12 and 27 SH floats (float and float4 moves) through the
+    pool, stores and write-back included."""
+    torch = torch_cuda
+    tree = scenegen.build_tree(configs.tiny_spec(n=8192, seed=3, sh_degree=sh_degree))
+    cams = [scenegen.camera_look_at((26 * np.cos(a), 26 * np.sin(a), 10.0), (0, 0, 0), (0, 0, 1), 192, 160)
+            for a in np.linspace(0.0, 1.5, 6)]
+    S, f, G, P, C, host, rows, tot = _lockstep(torch, tree, cams, 1.0, 5000, 0.6, 1.6, 4, max_inst=1 << 19)
+    _say("sh degree", sh_degree, tot)
+    idx, cnt = f.idx.clone(), f.count.clone()
+    n = int(cnt.item())
+    for k in GROUPS:
+        rows[k][:n] = rows[k][:n] * 2.0 + 0.5
+    P.store(idx, cnt, rows)
+    rows_back = {k: torch.empty_like(v) for k, v in rows.items()}
+    P.gather(idx, cnt, rows_back)  # the same selection again: nothing moves, rows read back
+    for k in GROUPS:
+        assert torch.equal(rows_back[k][:n], rows[k][:n]), k  # stored rows read back from upper, pool or host
 
 
 def test_pool_medium_flyin_and_write_back(torch_cuda):
