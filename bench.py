@@ -116,6 +116,26 @@ def stored_traffic(stage):
     return None
 
 
+def stored_executed(stage):
+    """The executed-work figures of the stage's kernel from a committed SQ
+    counter summary (lines 'EXECUTED <stage> <kernel> <key=value> ... <source
+    hash>'), or None when none matches the current sources."""
+    import glob
+    here = os.path.dirname(os.path.abspath(__file__))
+    want = kernel_source_hash()
+    for f in sorted(glob.glob(os.path.join(here, "profiles", "*.txt"))):
+        with open(f) as fh:
+            for line in fh:
+                w = line.split()
+                if len(w) >= 4 and w[0] == "EXECUTED" and w[1] == stage and w[-1] == want:
+                    out = {"kernel": w[2], "source": os.path.basename(f)}
+                    for kv in w[3:-1]:
+                        k, _, v = kv.partition("=")
+                        out[k] = float(v)
+                    return out
+    return None
+
+
 def summarize_profiles(trace_csv, fetch_csv, write_csv, commands):
     """Text summary of a rocprofv3 kernel-trace run and two --pmc runs
     (FETCH_SIZE, WRITE_SIZE): per-kernel average duration and HBM KiB per
@@ -192,6 +212,7 @@ def summarize_counters(csvs, commands, trace_stats=None, kernels=("k_blend_q", "
                 continue
             sums[k][r["Counter_Name"]] += float(r["Counter_Value"])
             disp[k].add((path, r["Dispatch_Id"]))
+    executed = []
     out = ["rocprofv3 SQ counter summary, kernel sources at hash %s" % kernel_source_hash(), "", "commands:"]
     out += ["  " + c for c in commands] + ["", "counter sums over the kernel's dispatches:", ""]
     for k in sorted(sums):
@@ -210,17 +231,31 @@ def summarize_counters(csvs, commands, trace_stats=None, kernels=("k_blend_q", "
         if "SQ_LDS_BANK_CONFLICT" in c and "SQ_LDS_IDX_ACTIVE" in c:
             d.append("LDS bank-conflict / LDS-active cycles %.2f" % (c["SQ_LDS_BANK_CONFLICT"] / c["SQ_LDS_IDX_ACTIVE"]))
         nd = max(1, len(disp[k]) // max(1, len(csvs)))
+        ex = {}
         if "SQ_INSTS_VALU" in c:
             per = c["SQ_INSTS_VALU"] / nd
             d.append("VALU wave-instructions per dispatch %.4g" % per)
+            ex["valu_wave_instr_per_launch"] = per
             if k in avg_us:
                 # 1024 SIMDs at 2.4 GHz issue at most one wave64 FP32 instruction per 4 cycles each
                 # (the 78.6 TFLOP/s non-packed FMA peak)
-                d.append("issue utilisation at the traced %.1f us per dispatch %.2f"
-                         % (avg_us[k], per / (avg_us[k] * 1e-6 * 1024 * 2.4e9 / 4.0)))
+                util = per / (avg_us[k] * 1e-6 * 1024 * 2.4e9 / 4.0)
+                d.append("issue utilisation at the traced %.1f us per dispatch %.2f" % (avg_us[k], util))
+                ex["traced_us"] = avg_us[k]
+                ex["valu_issue_util"] = util
+        for n, key in (("SQ_ACTIVE_INST_VALU", "valu_active_share"), ("SQ_WAIT_ANY", "wait_any_share")):
+            if n in c and wc == wc:
+                ex[key] = c[n] / wc
+        if "SQ_LDS_BANK_CONFLICT" in c and "SQ_LDS_IDX_ACTIVE" in c:
+            ex["lds_conflict_share"] = c["SQ_LDS_BANK_CONFLICT"] / c["SQ_LDS_IDX_ACTIVE"]
         out.append("  derived: " + "; ".join(d))
         out.append("")
-    return "\n".join(out)
+        stage = "blend_bwd" if k.startswith("k_blend_bwd") else ("blend" if k.startswith("k_blend_q") else None)
+        if stage and ex:
+            executed.append("EXECUTED %s %s %s %s" % (stage, k.replace(" ", ""),
+                                                      " ".join("%s=%.6g" % kv for kv in sorted(ex.items())),
+                                                      kernel_source_hash()))
+    return "\n".join(out + executed)
 
 
 def configs_taus(workload):
@@ -650,7 +685,10 @@ def main():
         ach = flop / (dom_ms_total / 1000.0) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2), "peak": FP32_VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK_TFLOPS, 4), "traffic": stored_traffic(dom),
-                "evaluations_per_view": int(evals / K), "algorithmic_bytes_per_launch": int(tot_bytes[dom] / K)}
+                "evaluations_per_view": int(evals / K), "algorithmic_bytes_per_launch": int(tot_bytes[dom] / K),
+                # what the kernel executed (SQ counters of a committed run at these sources): the
+                # nominal figure above credits evaluations that the block masks and events skip
+                "executed": stored_executed(dom)}
     else:
         ach = tot_bytes[dom] / (dom_ms_total / 1000.0) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
