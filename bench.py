@@ -459,6 +459,9 @@ def main():
     ap.add_argument("--pool", type=int, default=0,
                     help="with --rows and --cache: keep the cached cuts' rows in a device pool of this many rows "
                          "(at least the cache's max_nodes) and gather from it")
+    ap.add_argument("--serial", action="store_true",
+                    help="one view at a time in the timed loop (the default keeps two views in flight: the select "
+                         "and forward of view i+1 on a second stream beside the L1 and backward of view i)")
     ap.add_argument("--graph", action="store_true",
                     help="time the training step captured in one graph (lodgs_graph_capture_step) instead of plain "
                          "launches")
@@ -635,19 +638,71 @@ def main():
             timed_step(i)
     else:
         timed_step = step
+    # Two views in flight (node-gradient accumulation only: the parameters do
+    # not change between views, so the forward of view i+1 may run while view
+    # i's backward does): frames alternate; the select and forward of a view go
+    # on stream F, its L1 and backward on stream B after the forward's event;
+    # backward passes stay in view order on B, so the node gradients are the
+    # serial loop's bit for bit; a frame is reused after its backward's event.
+    pipelined = not (args.serial or use_graph or args.adam or args.rows or cache is not None)
+    launch_desc = "one graph per step" if use_graph else (
+        "plain launches, two views in flight (select and forward of view i+1 on a second stream beside the L1 "
+        "and backward of view i)" if pipelined else "plain launches, one view at a time")
+    if pipelined:
+        frames = [frame, Frame(scene, cap_sel, cap_inst, W, H)]
+        imgs, dLs = [img, torch.empty_like(img)], [dL, torch.empty_like(dL)]
+        sF, sB = torch.cuda.Stream(), torch.cuda.current_stream()
+        fwd_done = [torch.cuda.Event(), torch.cuda.Event()]
+        bwd_done = [torch.cuda.Event(), torch.cuda.Event()]
+
+        def forward_on_F(i):
+            f, v = frames[i % 2], seq[i % K]
+            sF.wait_event(bwd_done[i % 2])  # the frame's previous view is done with it
+            f.lod_select(cstructs[v], views[v][1], conservative=args.conservative, method=args.cut, stream=sF)
+            f.render(cstructs[v], out=imgs[i % 2], stream=sF)
+            fwd_done[i % 2].record(sF)
+
+        def backward_on_B(i):
+            f, v = frames[i % 2], seq[i % K]
+            sB.wait_event(fwd_done[i % 2])
+            f.l1_loss(imgs[i % 2], targets[v % len(targets)], grad=dLs[i % 2], stream=sB)
+            f.backward(dLs[i % 2], nodes=grads, stream=sB)
+            bwd_done[i % 2].record(sB)
+
+        for i in range(args.warmup):  # the second frame's warm-up
+            forward_on_F(i)
+            backward_on_B(i)
     torch.cuda.synchronize()
-    # events around every view, on the stream the library launches on
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    # events on the stream the library launches on: around every view, or,
+    # with two views in flight, at every backward's end (per-view figures are
+    # then the intervals between consecutive completions)
+    ev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(K)]
     t0 = time.perf_counter()
-    for i in range(K):
-        ev[i][0].record(run_stream)
-        timed_step(i)
-        ev[i][1].record(run_stream)
+    if pipelined:
+        ev[0][0].record(sB)
+        forward_on_F(0)
+        for i in range(K):
+            if i + 1 < K:
+                forward_on_F(i + 1)
+            backward_on_B(i)
+            ev[i][1].record(sB)
+            if i + 1 < K:
+                ev[i + 1][0] = ev[i][1]
+    else:
+        for i in range(K):
+            ev[i][0].record(run_stream)
+            timed_step(i)
+            ev[i][1].record(run_stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     per_view = np.array([a.elapsed_time(b) for a, b in ev])
     ms_per_view = elapsed * 1000.0 / K
-    log(f"timed {K} views ({'one graph per step' if use_graph else 'plain launches'}): {ms_per_view:.3f} ms per view")
+    log(f"timed {K} views ({launch_desc}): {ms_per_view:.3f} ms per view")
+    if pipelined:
+        for f in frames:
+            st_p = f.stats()
+            assert st_p["status"] == 0, st_p
+        del frames[1]
     st_fin = frame.stats()
     assert st_fin["status"] == 0, st_fin
     # Stage split: the same views again with plain launches and events around
@@ -724,7 +779,7 @@ def main():
                        update="cut-set Adam" if args.adam else ("selection-indexed gradients" if args.rows
                                                                 else "node-gradient accumulation"),
                        params="pinned host memory, rows gathered per view" if args.rows else "resident in HBM"),
-        "launch": "one graph per step" if use_graph else "plain launches",
+        "launch": launch_desc,
         "hbm_fraction_whole_path": round(hbm_frac, 4),
         "algorithmic_GB_per_view": round(all_bytes / K / 1e9, 4),
         "stages": stages,
