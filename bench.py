@@ -459,9 +459,12 @@ def main():
     ap.add_argument("--pool", type=int, default=0,
                     help="with --rows and --cache: keep the cached cuts' rows in a device pool of this many rows "
                          "(at least the cache's max_nodes) and gather from it")
+    ap.add_argument("--in-flight", type=int, default=3,
+                    help="views in flight in the timed loop (frames taking turns, each on its own stream; the "
+                         "scatter into the node gradients in view order on one more)")
     ap.add_argument("--serial", action="store_true",
-                    help="one view at a time in the timed loop (the default keeps two views in flight: the select "
-                         "and forward of view i+1 on a second stream beside the L1 and backward of view i)")
+                    help="one view at a time in the timed loop (the default keeps several views in flight, "
+                         "see --in-flight)")
     ap.add_argument("--graph", action="store_true",
                     help="time the training step captured in one graph (lodgs_graph_capture_step) instead of plain "
                          "launches")
@@ -638,40 +641,47 @@ def main():
             timed_step(i)
     else:
         timed_step = step
-    # Two views in flight (node-gradient accumulation only: the parameters do
-    # not change between views, so the forward of view i+1 may run while view
-    # i's backward does): frames alternate; the select and forward of a view go
-    # on stream F, its L1 and backward on stream B after the forward's event;
-    # backward passes stay in view order on B, so the node gradients are the
-    # serial loop's bit for bit; a frame is reused after its backward's event.
-    pipelined = not (args.serial or use_graph or args.adam or args.rows or cache is not None)
+    # Several views in flight (node-gradient accumulation only: the parameters
+    # do not change between views, so the forward of a later view may run
+    # while an earlier view's backward does).  Frames take turns; each frame's
+    # stream runs a view's select, forward, L1 and the frame-local half of its
+    # backward (blend backward and per-splat sums); one more stream runs the
+    # other half (colour and projection backward into the node gradients) in
+    # view order, so the gradients are those of one view at a time bit for
+    # bit.  A frame takes its next view once the scatter of its last is done.
+    pipelined = not (args.serial or use_graph or args.adam or args.rows or cache is not None) and args.in_flight > 1
+    n_fl = max(2, args.in_flight)
     launch_desc = "one graph per step" if use_graph else (
-        "plain launches, two views in flight (select and forward of view i+1 on a second stream beside the L1 "
-        "and backward of view i)" if pipelined else "plain launches, one view at a time")
+        "plain launches, %d views in flight (select, forward, L1 and blend backward of each on its frame's stream; "
+        "the scatter into the node gradients in view order on one more stream)" % n_fl
+        if pipelined else "plain launches, one view at a time")
     if pipelined:
-        frames = [frame, Frame(scene, cap_sel, cap_inst, W, H)]
-        imgs, dLs = [img, torch.empty_like(img)], [dL, torch.empty_like(dL)]
-        sF, sB = torch.cuda.Stream(), torch.cuda.current_stream()
-        fwd_done = [torch.cuda.Event(), torch.cuda.Event()]
-        bwd_done = [torch.cuda.Event(), torch.cuda.Event()]
+        frames = [frame] + [Frame(scene, cap_sel, cap_inst, W, H) for _ in range(n_fl - 1)]
+        imgs = [img] + [torch.empty_like(img) for _ in range(n_fl - 1)]
+        dLs = [dL] + [torch.empty_like(dL) for _ in range(n_fl - 1)]
+        sFs, sB = [torch.cuda.Stream() for _ in range(n_fl)], torch.cuda.current_stream()
+        part_done = [torch.cuda.Event() for _ in range(n_fl)]
+        scat_done = [torch.cuda.Event() for _ in range(n_fl)]
 
-        def forward_on_F(i):
-            f, v = frames[i % 2], seq[i % K]
-            sF.wait_event(bwd_done[i % 2])  # the frame's previous view is done with it
+        def frame_work(i):  # on the frame's stream
+            k, v = i % n_fl, seq[i % K]
+            f, sF = frames[k], sFs[k]
+            sF.wait_event(scat_done[k])  # the frame's previous view is done with it
             f.lod_select(cstructs[v], views[v][1], conservative=args.conservative, method=args.cut, stream=sF)
-            f.render(cstructs[v], out=imgs[i % 2], stream=sF)
-            fwd_done[i % 2].record(sF)
+            f.render(cstructs[v], out=imgs[k], stream=sF)
+            f.l1_loss(imgs[k], targets[v % len(targets)], grad=dLs[k], stream=sF)
+            f.backward(dLs[k], stream=sF, phases="partials")
+            part_done[k].record(sF)
 
-        def backward_on_B(i):
-            f, v = frames[i % 2], seq[i % K]
-            sB.wait_event(fwd_done[i % 2])
-            f.l1_loss(imgs[i % 2], targets[v % len(targets)], grad=dLs[i % 2], stream=sB)
-            f.backward(dLs[i % 2], nodes=grads, stream=sB)
-            bwd_done[i % 2].record(sB)
+        def scatter_on_B(i):  # in view order
+            k = i % n_fl
+            sB.wait_event(part_done[k])
+            frames[k].backward(None, nodes=grads, stream=sB, phases="scatter")
+            scat_done[k].record(sB)
 
-        for i in range(args.warmup):  # the second frame's warm-up
-            forward_on_F(i)
-            backward_on_B(i)
+        for i in range(max(args.warmup, n_fl)):  # every frame's warm-up
+            frame_work(i)
+            scatter_on_B(i)
     torch.cuda.synchronize()
     # events on the stream the library launches on: around every view, or,
     # with two views in flight, at every backward's end (per-view figures are
@@ -680,14 +690,15 @@ def main():
     t0 = time.perf_counter()
     if pipelined:
         ev[0][0].record(sB)
-        forward_on_F(0)
-        for i in range(K):
-            if i + 1 < K:
-                forward_on_F(i + 1)
-            backward_on_B(i)
-            ev[i][1].record(sB)
-            if i + 1 < K:
-                ev[i + 1][0] = ev[i][1]
+        for t in range(K + n_fl - 1):
+            if t < K:
+                frame_work(t)
+            i = t - (n_fl - 1)
+            if i >= 0:
+                scatter_on_B(i)
+                ev[i][1].record(sB)
+                if i + 1 < K:
+                    ev[i + 1][0] = ev[i][1]
     else:
         for i in range(K):
             ev[i][0].record(run_stream)
@@ -702,7 +713,7 @@ def main():
         for f in frames:
             st_p = f.stats()
             assert st_p["status"] == 0, st_p
-        del frames[1]
+        del frames[1:]
     st_fin = frame.stats()
     assert st_fin["status"] == 0, st_fin
     # Stage split: the same views again with plain launches and events around

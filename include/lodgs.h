@@ -355,6 +355,25 @@ int lodgs_render_rows(lodgs_frame* frame, const lodgs_grads* rows, const int32_t
 int lodgs_render_backward(lodgs_frame* frame, const float* d_dL_drgb, const lodgs_grads* sel,
                           const lodgs_grads* nodes, lodgs_stream stream);
 
+/* lodgs_render_backward in two halves, for callers that keep several views
+ * in flight on several frames (Alg. 3 accumulating gradients over views):
+ *   LODGS_BWD_PARTIALS: the blend backward and the per-splat 2D sums, which
+ *                       write only this frame's state (d_dL_drgb needed;
+ *                       sel and nodes ignored);
+ *   LODGS_BWD_SCATTER:  the colour and projection backward into sel / nodes
+ *                       and the attached node statistics (needs a PARTIALS
+ *                       pass after the frame's last render; d_dL_drgb
+ *                       ignored).
+ * Both together equal lodgs_render_backward.  PARTIALS passes of different
+ * frames may run concurrently on different streams; SCATTER passes that write
+ * the same arrays must be ordered by the caller.  Errors: LODGS_E_INVALID for
+ * an unknown phase bit or a missing d_dL_drgb, LODGS_E_STATE for a SCATTER
+ * without its PARTIALS, and those of lodgs_render_backward. */
+#define LODGS_BWD_PARTIALS 1u
+#define LODGS_BWD_SCATTER 2u
+int lodgs_render_backward_phases(lodgs_frame* frame, const float* d_dL_drgb, const lodgs_grads* sel,
+                                 const lodgs_grads* nodes, uint32_t phases, lodgs_stream stream);
+
 /* Counters of the last calls on this frame (blocks on the stream). */
 typedef struct lodgs_stats {
   int32_t status;          /* LODGS_OK or LODGS_E_CAPACITY                  */

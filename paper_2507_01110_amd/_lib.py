@@ -12,6 +12,8 @@ LIB_PATH = os.path.join(_PKG, "liblodgs.so")
 OK, E_INVALID, E_CAPACITY, E_HIP, E_OOM, E_STATE = 0, -1, -2, -3, -4, -5
 CULL = 1
 CONSERVATIVE = 2
+BWD_PARTIALS = 1  # lodgs_render_backward_phases
+BWD_SCATTER = 2
 CUT_BFS = 4
 CUT_PARALLEL = 8
 
@@ -123,6 +125,8 @@ EXPORTS = {
                                  ctypes.c_int),
     "lodgs_render": ([c_p, c_p, c_p, ctypes.POINTER(Camera), c_p, c_p, c_p], ctypes.c_int),
     "lodgs_render_backward": ([c_p, c_p, ctypes.POINTER(Grads), ctypes.POINTER(Grads), c_p], ctypes.c_int),
+    "lodgs_render_backward_phases": ([c_p, c_p, ctypes.POINTER(Grads), ctypes.POINTER(Grads), ctypes.c_uint32, c_p],
+                                     ctypes.c_int),
     "lodgs_frame_stats": ([c_p, ctypes.POINTER(Stats), c_p], ctypes.c_int),
     "lodgs_frame_read_instances": ([c_p, c_p, c_p, i64, ctypes.POINTER(i64), c_p], ctypes.c_int),
     "lodgs_frame_clear_status": ([c_p, c_p], ctypes.c_int),

@@ -374,6 +374,7 @@ int lodgs_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, c
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "lodgs_render");
   f->rendered = true;
+  f->partials_ready = false;
   f->r_idx = d_idx;
   f->r_count = d_count;
   f->r_rgb = d_rgb;
@@ -408,6 +409,7 @@ int lodgs_render_rows(lodgs_frame* f, const lodgs_grads* rows, const int32_t* d_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "lodgs_render_rows");
   f->rendered = true;
+  f->partials_ready = false;
   f->r_idx = f->iota;
   f->r_count = d_count;
   f->r_rgb = d_rgb;
@@ -416,18 +418,30 @@ int lodgs_render_rows(lodgs_frame* f, const lodgs_grads* rows, const int32_t* d_
   return LODGS_OK;
 }
 
-int lodgs_render_backward(lodgs_frame* f, const float* d_dL_drgb, const lodgs_grads* sel, const lodgs_grads* nodes,
-                          lodgs_stream stream) {
-  if (!f || !d_dL_drgb) return set_error(LODGS_E_INVALID, "lodgs_render_backward: null argument");
+int lodgs_render_backward_phases(lodgs_frame* f, const float* d_dL_drgb, const lodgs_grads* sel,
+                                 const lodgs_grads* nodes, uint32_t phases, lodgs_stream stream) {
+  const bool part = (phases & LODGS_BWD_PARTIALS) != 0, scat = (phases & LODGS_BWD_SCATTER) != 0;
+  if (!f || (part && !d_dL_drgb) || (phases & ~(uint32_t)(LODGS_BWD_PARTIALS | LODGS_BWD_SCATTER)) != 0)
+    return set_error(LODGS_E_INVALID, "lodgs_render_backward: null argument or unknown phase");
   if (!f->rendered) return set_error(LODGS_E_STATE, "lodgs_render_backward: no render on this frame");
-  if (f->rows_mode && nodes)
+  if (scat && !part && !f->partials_ready)
+    return set_error(LODGS_E_STATE, "lodgs_render_backward: the scatter half needs the partials of the last render");
+  if (scat && f->rows_mode && nodes)
     return set_error(LODGS_E_INVALID, "lodgs_render_backward: after lodgs_render_rows only sel gradients are written");
-  if ((sel && (reinterpret_cast<uintptr_t>(sel->d_sh) & 15u)) || (nodes && (reinterpret_cast<uintptr_t>(nodes->d_sh) & 15u)))
+  if (scat &&
+      ((sel && (reinterpret_cast<uintptr_t>(sel->d_sh) & 15u)) || (nodes && (reinterpret_cast<uintptr_t>(nodes->d_sh) & 15u))))
     return set_error(LODGS_E_INVALID, "lodgs_render_backward: SH gradient arrays must be 16-byte aligned");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  lodgs::launch_backward(f, d_dL_drgb, sel, nodes, st);
+  lodgs::launch_backward(f, d_dL_drgb, sel, nodes, phases, st);
   hipError_t e = hipGetLastError();
-  return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_render_backward");
+  if (e != hipSuccess) return hip_fail(e, "lodgs_render_backward");
+  if (part) f->partials_ready = true;
+  return LODGS_OK;
+}
+
+int lodgs_render_backward(lodgs_frame* f, const float* d_dL_drgb, const lodgs_grads* sel, const lodgs_grads* nodes,
+                          lodgs_stream stream) {
+  return lodgs_render_backward_phases(f, d_dL_drgb, sel, nodes, LODGS_BWD_PARTIALS | LODGS_BWD_SCATTER, stream);
 }
 
 int lodgs_frame_stats(lodgs_frame* f, lodgs_stats* out, lodgs_stream stream) {
@@ -730,6 +744,7 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
     return rc;
   }
   f->rendered = true;
+  f->partials_ready = false;
   f->r_idx = d_idx;
   f->r_count = d_count;
   f->r_rgb = d_rgb;
@@ -775,7 +790,7 @@ int lodgs_graph_capture_step(lodgs_frame* f, const lodgs_camera* cam, float tau,
     f->r_rgb = d_rgb;
     f->view = vr;
     lodgs::launch_l1_loss(d_rgb, d_target, npx, d_dL, d_loss, st);
-    lodgs::launch_backward(f, d_dL, sel, nodes, st);
+    lodgs::launch_backward(f, d_dL, sel, nodes, LODGS_BWD_PARTIALS | LODGS_BWD_SCATTER, st);
   });
   if (rc == LODGS_OK && !g->node_l1) rc = set_error(LODGS_E_STATE, "lodgs_graph_capture_step: loss node not found");
   if (rc != LODGS_OK) {
@@ -783,6 +798,7 @@ int lodgs_graph_capture_step(lodgs_frame* f, const lodgs_camera* cam, float tau,
     return rc;
   }
   f->rendered = true;
+  f->partials_ready = false;
   f->r_idx = d_idx;
   f->r_count = d_count;
   f->r_rgb = d_rgb;

@@ -721,29 +721,33 @@ __global__ void __launch_bounds__(kBlock) k_project_bwd(SceneDev S, const ViewCo
   }
 }
 
-template <int DEG, int NP>
-static void launch_project_bwd_deg(const SceneDev& S, lodgs_frame* f, const lodgs_grads& sel,
-                                   const lodgs_grads& nodes, hipStream_t st) {
+// The per-splat 2D sums of the instance partials (frame-local outputs).
+template <int NP>
+static void launch_splat_sums(lodgs_frame* f, hipStream_t st) {
   hipLaunchKernelGGL(k_long_sums<NP>, dim3(1024), dim3(kBlock), 0, st, f->ctr, f->long_list, f->sorted_order,
                      f->inst_off, f->inst_grad, f->splats, f->rect, f->grad2d, f->contrib);
   hipLaunchKernelGGL(k_splat_sums<NP>, dim3(2048), dim3(kBlock), 0, st, f->ctr, f->sorted_order, f->inst_off,
                      f->inst_grad, f->splats, f->rect, f->rank_info, f->grad2d, f->contrib);
+}
+
+// Colour and projection backward into the gradient arrays (and the node
+// statistics).
+template <int DEG>
+static void launch_scatter_deg(const SceneDev& S, lodgs_frame* f, const lodgs_grads& sel, const lodgs_grads& nodes,
+                               bool contrib, hipStream_t st) {
   // 16 lanes per splat: one pass covers 256k drawn splats, so each 16-lane
   // group runs its latency-bound chain of dependent loads once
   hipLaunchKernelGGL(k_color_bwd<DEG>, dim3(16384), dim3(kBlock), 0, st, f->r_idx, f->ctr, f->drawn_list, f->dcol,
                      f->grad2d, sel.d_sh, nodes.d_sh);
   ContribStats cs{f->contrib, nullptr, nullptr, nullptr};
-  if (NP == 11) cs = ContribStats{f->contrib, f->last_contrib, f->contrib_count, f->contrib_iteration};
+  if (contrib) cs = ContribStats{f->contrib, f->last_contrib, f->contrib_count, f->contrib_iteration};
   hipLaunchKernelGGL(k_project_bwd<DEG>, dim3(1024), dim3(kBlock), 0, st, S, f->d_view_ren, f->r_idx, f->ctr,
                      f->drawn_list, f->grad2d, sel, nodes, f->rows_mode ? (float*)nullptr : f->max_grad2d, cs);
 }
 
 template <int NP>
-static void launch_backward_np(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
-                               hipStream_t st) {
-  const SceneDev& S = render_params(f);
+static void launch_blend_bwd_np(lodgs_frame* f, const float* d_dL, hipStream_t st) {
   const ViewConst& v = f->view;
-  stage_begin(f, LODGS_STAGE_BLEND_BWD, st);
   const int ntiles = v.tiles_x * v.tiles_y;
   switch (f->blend_px_bwd) {
     case 1:
@@ -762,26 +766,44 @@ static void launch_backward_np(lodgs_frame* f, const float* d_dL, const lodgs_gr
                          f->tile_order, f->inst_grad);
       break;
   }
-  stage_end(f, st);
-  stage_begin(f, LODGS_STAGE_PROJECT_BWD, st);
-  lodgs_grads none{nullptr, nullptr, nullptr, nullptr, nullptr};
-  if (sel) hipLaunchKernelGGL(k_zero_sel, dim3(1024), dim3(kBlock), 0, st, f->ctr, S.n_coef, *sel);
-  const lodgs_grads gs = sel ? *sel : none, gn = nodes ? *nodes : none;
-  switch (S.sh_degree) {
-    case 0: launch_project_bwd_deg<0, NP>(S, f, gs, gn, st); break;
-    case 1: launch_project_bwd_deg<1, NP>(S, f, gs, gn, st); break;
-    case 2: launch_project_bwd_deg<2, NP>(S, f, gs, gn, st); break;
-    default: launch_project_bwd_deg<3, NP>(S, f, gs, gn, st); break;
-  }
-  stage_end(f, st);
 }
 
-// The per-instance partials carry the contributing-pixel count (11 values)
-// only while the pruning statistic is attached (and not in the rows form).
+// LODGS_BWD_PARTIALS: the blend backward and the per-splat 2D sums, which
+// write only the frame's own state.  The per-instance partials carry the
+// contributing-pixel count (11 values) only while the pruning statistic is
+// attached (and not in the rows form).  LODGS_BWD_SCATTER: colour and
+// projection backward into the gradient arrays and the node statistics; it
+// stamps the pruning statistic only after partials that carried the count.
 void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
-                     hipStream_t st) {
-  if (f->last_contrib && !f->rows_mode) launch_backward_np<kPartial>(f, d_dL, sel, nodes, st);
-  else launch_backward_np<kPartial - 1>(f, d_dL, sel, nodes, st);
+                     uint32_t phases, hipStream_t st) {
+  const bool part = (phases & LODGS_BWD_PARTIALS) != 0, scat = (phases & LODGS_BWD_SCATTER) != 0;
+  if (part) {
+    f->partials_np = (f->last_contrib && !f->rows_mode) ? kPartial : kPartial - 1;
+    stage_begin(f, LODGS_STAGE_BLEND_BWD, st);
+    if (f->partials_np == kPartial) launch_blend_bwd_np<kPartial>(f, d_dL, st);
+    else launch_blend_bwd_np<kPartial - 1>(f, d_dL, st);
+    stage_end(f, st);
+  }
+  if (!part && !scat) return;
+  stage_begin(f, LODGS_STAGE_PROJECT_BWD, st);
+  if (part) {
+    if (f->partials_np == kPartial) launch_splat_sums<kPartial>(f, st);
+    else launch_splat_sums<kPartial - 1>(f, st);
+  }
+  if (scat) {
+    const SceneDev& S = render_params(f);
+    const bool contrib = f->partials_np == kPartial && f->last_contrib;
+    lodgs_grads none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (sel) hipLaunchKernelGGL(k_zero_sel, dim3(1024), dim3(kBlock), 0, st, f->ctr, S.n_coef, *sel);
+    const lodgs_grads gs = sel ? *sel : none, gn = nodes ? *nodes : none;
+    switch (S.sh_degree) {
+      case 0: launch_scatter_deg<0>(S, f, gs, gn, contrib, st); break;
+      case 1: launch_scatter_deg<1>(S, f, gs, gn, contrib, st); break;
+      case 2: launch_scatter_deg<2>(S, f, gs, gn, contrib, st); break;
+      default: launch_scatter_deg<3>(S, f, gs, gn, contrib, st); break;
+    }
+  }
+  stage_end(f, st);
 }
 
 __device__ __forceinline__ float wave_sum(float x) {

@@ -168,6 +168,8 @@ struct lodgs_frame {
   lodgs::ViewConst* d_view_ren;  // view constants of the last render (device)
   // state of the last render
   bool rendered;
+  bool partials_ready;  // a LODGS_BWD_PARTIALS pass ran since the last render
+  int partials_np;      // the values per instance partial of that pass
   const int32_t* r_idx;
   const int32_t* r_count;
   const float* r_rgb;
@@ -287,7 +289,7 @@ int blend_output_arg(const void* func, int* n_args);
 void launch_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, const ViewConst& v,
                    const float bg[3], float* d_rgb, hipStream_t st);
 void launch_backward(lodgs_frame* f, const float* d_dL, const lodgs_grads* sel, const lodgs_grads* nodes,
-                     hipStream_t st);
+                     uint32_t phases, hipStream_t st);
 
 }  // namespace lodgs
 

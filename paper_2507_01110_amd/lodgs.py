@@ -356,13 +356,20 @@ class Frame:
         self._last = (None, count, out)
         return out
 
-    def backward(self, dL_drgb, sel: dict | None = None, nodes: dict | None = None, stream=None):
+    def backward(self, dL_drgb, sel: dict | None = None, nodes: dict | None = None, stream=None,
+                 phases: str = "both"):
+        """The backward of the last render.  phases: "both", or "partials"
+        (blend backward and per-splat sums: frame-local) then "scatter"
+        (colour and projection backward into sel / nodes), for several views
+        in flight (lodgs_render_backward_phases)."""
         g = lambda d: _lib.Grads(*[_ptr(d.get(k)) if d else None for k in
                                    ("means", "log_scales", "quats", "opacity_logits", "sh")])
         gs, gn = g(sel), g(nodes)
-        check(_lib.load().lodgs_render_backward(self._h, _ptr(dL_drgb), ctypes.byref(gs) if sel else None,
-                                                ctypes.byref(gn) if nodes else None, _stream(stream)),
-              "lodgs_render_backward")
+        ph = {"both": _lib.BWD_PARTIALS | _lib.BWD_SCATTER, "partials": _lib.BWD_PARTIALS,
+              "scatter": _lib.BWD_SCATTER}[phases]
+        check(_lib.load().lodgs_render_backward_phases(self._h, _ptr(dL_drgb), ctypes.byref(gs) if sel else None,
+                                                       ctypes.byref(gn) if nodes else None, ph, _stream(stream)),
+              "lodgs_render_backward_phases")
 
     def stats(self, stream=None) -> dict:
         s = _lib.Stats()
