@@ -465,7 +465,8 @@ int lodgs_graph_launch_step(lodgs_graph* graph, const lodgs_camera* cam, float t
  * size class, so the requests of different slots overlap on the device.  The
  * scene and every per-request buffer stay on the device; the host only
  * queues, launches and polls events.
- * Admission: an idle slot whose capacities cover the request takes it;
+ * Admission: the largest idle slot whose capacities cover the request takes
+ * it (a request's size shows only after its first run);
  * otherwise a new slot is made if fewer than max_slots exist and free HBM
  * (hipMemGetInfo) is at least the slot's bytes plus hbm_reserve; otherwise
  * the request waits.  A request whose selection or instance list overflows

@@ -4,8 +4,8 @@
 // view graph per image-size class, a completion event and a small record in
 // mapped host memory through which its requests report their counters.
 //
-// Requests wait in a queue until a slot can take them: an idle slot whose
-// capacities cover the request, or a new slot when fewer than max_slots exist
+// Requests wait in a queue until a slot can take them: the largest idle slot
+// whose capacities cover the request, or a new slot when fewer than max_slots exist
 // and free HBM (hipMemGetInfo) covers the slot's bytes plus the caller's
 // reserve.  A launch updates the graph's view constants and output image and
 // replays it on the slot's stream, so the views of different slots overlap on
@@ -276,8 +276,10 @@ int pump(lodgs_server* sv) {
   for (auto it = sv->queue.begin(); it != sv->queue.end();) {
     Job& j = *it;
     Slot* best = nullptr;
+    // the largest idle slot that fits: a request's size is known only after
+    // its first run, so a heavy one overflows less often on a grown slot
     for (Slot* s : sv->slots)
-      if (!s->busy && fits(s, j) && (!best || s->bytes < best->bytes)) best = s;
+      if (!s->busy && fits(s, j) && (!best || s->bytes > best->bytes)) best = s;
     int rc = LODGS_OK;
     if (!best) best = grow(sv, j, &rc);
     if (rc != LODGS_OK) return rc;
