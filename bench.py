@@ -406,6 +406,20 @@ def ultra_bench(args):
     frames = [Frame(scene, 1 << 24, 1 << 26, 1920, 1080) for _ in range(B)]
     targets = [torch.from_numpy(scenegen.target_image(1080, 1920, 204 + k)).cuda() for k in range(B)]
 
+    # counting pass (untimed): per-view counts for the byte model of section S1-S11
+    counts = []
+    n_coef = 3 * (scene.sh_degree + 1) ** 2
+    for c in cams:
+        f = frames[0]
+        f.lod_select(c, 1.0)
+        f.render(c)
+        st = f.stats()
+        assert st["status"] == 0, st
+        st["n_spt_candidates"] = int(st["n_spt_candidates"])
+        st["n_upper"] = scene.n_upper
+        counts.append(st)
+    view_bytes = [sum(stage_bytes(c, 1080, 1920, n_coef).values()) for c in counts]
+
     def step(s):
         loss = 0.0
         for b in range(B):
@@ -427,6 +441,7 @@ def ultra_bench(args):
     el = time.perf_counter() - t0
     free, total = torch.cuda.mem_get_info()
     st = [f.stats() for f in frames]
+    timed_bytes = sum(view_bytes[(s * B + b) % len(cams)] for s in range(K) for b in range(B))
     out = {"metric": "ms per 8-view 1080p training step @150M Gaussians (LoD+splat fwd/bwd, autograd)",
            "value": round(el * 1000.0 / K, 3), "unit": "ms per step", "n_gpus": 1, "steps": K, "warmup": args.warmup,
            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
@@ -434,6 +449,9 @@ def ultra_bench(args):
            "views_per_s": round(B * K / el, 1), "param_GB": round(scene.param_bytes() / 1e9, 2),
            "peak_torch_allocated_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2),
            "device_used_GB": round((total - free) / 1e9, 2),
+           "algorithmic_GB_per_view": round(timed_bytes / (B * K) / 1e9, 4),
+           "achieved_GB_s": round(timed_bytes / el / 1e9, 1),
+           "hbm_fraction": round(timed_bytes / el / (HBM_PEAK_GBS * 1e9), 4),
            "last_batch": {k: int(np.mean([s[k] for s in st])) for k in ("n_selected", "n_drawn", "n_instances")}}
     print(json.dumps(out), flush=True)
 
