@@ -769,6 +769,9 @@ def main():
         ach = flop / (dom_ms_total / 1000.0) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(ach, 2), "peak": FP32_VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK_TFLOPS, 4), "traffic": stored_traffic(dom),
+                "basis": "algorithmic: every (pixel, splat) evaluation the method defines x %d FLOP, including "
+                         "those the block masks and events let the kernel skip" % (
+                             FLOP_PER_EVAL if dom == "blend" else FLOP_PER_EVAL_BWD),
                 "evaluations_per_view": int(evals / K), "algorithmic_bytes_per_launch": int(tot_bytes[dom] / K),
                 # what the kernel executed (SQ counters of a committed run at these sources): the
                 # nominal figure above credits evaluations that the block masks and events skip
