@@ -168,6 +168,10 @@ typedef struct lodgs_frame_caps {
 
 typedef struct lodgs_frame lodgs_frame;
 
+/* Errors: LODGS_E_INVALID for capacities out of range, LODGS_E_OOM when a
+ * device allocation fails (everything the call allocated is freed first).
+ * LODGS_FAIL_FRAME_ALLOC=k in the environment makes the k-th device
+ * allocation of the call report out of memory (a test of that path). */
 int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, lodgs_frame** out);
 void lodgs_frame_destroy(lodgs_frame* frame);
 

@@ -159,12 +159,12 @@ void free_frame(lodgs_frame* f) {
     (void)hipEventDestroy(r.b);
   }
   if (f->open_event) (void)hipEventDestroy(f->open_event);
-  void* ptrs[] = {f->work, f->ctr, f->block_sums, f->sort_table, f->sort_below, f->upper_sel, f->upper_test, f->spt_high, f->spt_X, f->spt_off, f->seg, f->chunk_owner,
-                  f->splats, f->depth_key, f->depth_key2, f->order, f->order2, f->tiles, f->inst_off, f->drawn_list, f->rect,
-                  f->ikey, f->ival, f->ikey2, f->ival2, f->inst_info, f->inst_grad, f->inst_event, f->info_k, f->rank_info, f->grad2d, f->contrib, f->dcol, f->long_list, f->ranges, f->tile_order, f->d_view_sel,
-                  f->d_view_ren, f->cut_bits, f->frontier[0], f->frontier[1], f->level_count, f->iota};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  // the arrays frame_create allocated (the same visitor; null ones skipped)
+  if (f->scene)
+    lodgs::frame_arrays(f, f->scene->dev, f->caps, [](auto*& ptr, size_t) {
+      if (ptr) (void)hipFree(ptr);
+      ptr = nullptr;
+    });
   delete f;
 }
 
@@ -291,8 +291,14 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   f->blend_px_fwd = lodgs::blend_pixels_per_lane(false);
   f->blend_px_bwd = lodgs::blend_pixels_per_lane(true);
   hipError_t e = hipSuccess;
-  lodgs::frame_arrays(f, scene->dev, *caps, [&e](auto*& ptr, size_t cnt) {
-    if (e == hipSuccess) e = dalloc(&ptr, cnt);
+  // LODGS_FAIL_FRAME_ALLOC=k (a test of the failure path): the k-th device
+  // allocation of this call reports out of memory instead of allocating
+  const char* fail_env = std::getenv("LODGS_FAIL_FRAME_ALLOC");
+  const long fail_at = fail_env ? std::strtol(fail_env, nullptr, 10) : 0;
+  long n_alloc = 0;
+  lodgs::frame_arrays(f, scene->dev, *caps, [&e, &n_alloc, fail_at](auto*& ptr, size_t cnt) {
+    if (e != hipSuccess) return;
+    e = ++n_alloc == fail_at ? hipErrorOutOfMemory : dalloc(&ptr, cnt);
   });
   if (scene->dev.parent) f->cut_height = scene->dev.height;
   if (e != hipSuccess) {
