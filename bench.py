@@ -700,13 +700,57 @@ def main():
         for i in range(max(args.warmup, n_fl)):  # every frame's warm-up
             frame_work(i)
             scatter_on_B(i)
+    # The out-of-core path through the row pool, views in flight: the cached
+    # select and the pool's gather change the cache's and the pool's state, so
+    # they run in view order on one stream; each view's render from its rows,
+    # L1 and backward (into selection-indexed gradients) then run on its
+    # frame's stream; a frame and its rows take the next view once that work is
+    # done.
+    pool_pipelined = not (args.serial or use_graph) and pool is not None and args.in_flight > 1
+    if pool_pipelined:
+        launch_desc = ("plain launches, %d views in flight (cached select and pool gather in view order on one "
+                       "stream; render, L1 and backward of each on its frame's stream)" % n_fl)
+        frames = [frame] + [Frame(scene, cap_sel, cap_inst, W, H) for _ in range(n_fl - 1)]
+        imgs = [img] + [torch.empty_like(img) for _ in range(n_fl - 1)]
+        dLs = [dL] + [torch.empty_like(dL) for _ in range(n_fl - 1)]
+        rowss = [rows] + [rows_like(tree.sh_degree, cap_sel) for _ in range(n_fl - 1)]
+        sels = [sel] + [{k: torch.zeros_like(t) for k, t in sel.items()} for _ in range(n_fl - 1)]
+        sS, sFs = torch.cuda.current_stream(), [torch.cuda.Stream() for _ in range(n_fl)]
+        gathered = [torch.cuda.Event() for _ in range(n_fl)]
+        done = [torch.cuda.Event() for _ in range(n_fl)]
+
+        def state_work(i):  # in view order
+            k, v = i % n_fl, seq[i % K]
+            sS.wait_event(done[k])  # the frame and its rows are free
+            frames[k].lod_select(cstructs[v], views[v][1], cache=cache, stream=sS)
+            pool.gather(frames[k].idx, frames[k].count, rowss[k], stream=sS)
+            gathered[k].record(sS)
+
+        def rows_work(i):  # on the frame's stream
+            k, v = i % n_fl, seq[i % K]
+            f, sF = frames[k], sFs[k]
+            sF.wait_event(gathered[k])
+            f.render_rows(cstructs[v], rowss[k], out=imgs[k], stream=sF)
+            f.l1_loss(imgs[k], targets[v % len(targets)], grad=dLs[k], stream=sF)
+            f.backward(dLs[k], sel=sels[k], stream=sF)
+            done[k].record(sF)
+
+        for i in range(max(args.warmup, n_fl)):  # every frame's warm-up
+            state_work(i)
+            rows_work(i)
     torch.cuda.synchronize()
     # events on the stream the library launches on: around every view, or,
     # with two views in flight, at every backward's end (per-view figures are
     # then the intervals between consecutive completions)
     ev = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(K)]
     t0 = time.perf_counter()
-    if pipelined:
+    if pool_pipelined:
+        ev[0][0].record(sS)
+        for i in range(K):
+            state_work(i)
+            rows_work(i)
+            ev[i][1].record(sFs[i % n_fl])
+    elif pipelined:
         ev[0][0].record(sB)
         for t in range(K + n_fl - 1):
             if t < K:
@@ -724,10 +768,14 @@ def main():
             ev[i][1].record(run_stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    per_view = np.array([a.elapsed_time(b) for a, b in ev])
+    if pool_pipelined:  # views may complete out of order: intervals between sorted completions
+        done_ms = np.sort([ev[0][0].elapsed_time(e[1]) for e in ev])
+        per_view = np.diff(np.concatenate([[0.0], done_ms]))
+    else:
+        per_view = np.array([a.elapsed_time(b) for a, b in ev])
     ms_per_view = elapsed * 1000.0 / K
     log(f"timed {K} views ({launch_desc}): {ms_per_view:.3f} ms per view")
-    if pipelined:
+    if pipelined or pool_pipelined:
         for f in frames:
             st_p = f.stats()
             assert st_p["status"] == 0, st_p

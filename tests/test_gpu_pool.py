@@ -152,3 +152,64 @@ def test_pool_medium_flyin_and_write_back(torch_cuda):
     diff = host.params["means"][changed] - S.params["means"][changed.cuda()].cpu()
     assert torch.allclose(diff, torch.ones_like(diff), atol=1e-4)  # the stored +1
     assert bool(torch.isin(changed, idx[:n].long().cpu()).all())
+
+
+def test_pool_views_in_flight_equal_one_at_a_time(torch_cuda):
+    """The cached select and the pooled gather in view order on one stream, each
+    view's render from its rows, L1 and backward on its frame's stream, three
+    frames taking turns: images and selection-indexed gradients equal those of
+    one view at a time bit for bit."""
+    torch = torch_cuda
+    from paper_2507_01110_amd.lodgs import CutCache, Frame, HostParams, RowPool, Scene, grads_like, rows_like
+    tree = scenegen.build_tree(configs.medium_spec(n=500_000, seed=15))
+    S = Scene(tree)
+    host = HostParams.from_scene(S)
+    W, H = 1280, 720
+    cams = [scenegen.camera_yaw_pitch((3.0 * k, 1.0 * k, 40.0 - 2.0 * k), 0.3 + 0.05 * k, np.radians(-45.0), W, H)
+            for k in range(8)]
+    targets = [torch.from_numpy(scenegen.target_image(H, W, 70 + k)).cuda() for k in range(len(cams))]
+    cap_sel, cap_inst = 1 << 21, 1 << 23
+
+    def run(n_fl):
+        G = CutCache(S, 300_000, 0.7, 1.4, 0)
+        P = RowPool(G, host, 300_000)
+        frames = [Frame(S, cap_sel, cap_inst, W, H) for _ in range(n_fl)]
+        rows = [rows_like(tree.sh_degree, cap_sel) for _ in range(n_fl)]
+        sels = [grads_like(S, cap_sel) for _ in range(n_fl)]
+        imgs = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(n_fl)]
+        dls = [torch.empty_like(imgs[0]) for _ in range(n_fl)]
+        sS = torch.cuda.Stream()
+        sF = [torch.cuda.Stream() for _ in range(n_fl)] if n_fl > 1 else [sS]
+        gathered = [torch.cuda.Event() for _ in range(n_fl)]
+        done = [torch.cuda.Event() for _ in range(n_fl)]
+        out = []
+        for i, cam in enumerate(cams):
+            k = i % n_fl
+            sS.wait_event(done[k])
+            frames[k].lod_select(cam, 1.0, cache=G, stream=sS)
+            P.gather(frames[k].idx, frames[k].count, rows[k], stream=sS)
+            gathered[k].record(sS)
+            s = sF[k]
+            s.wait_event(gathered[k])
+            frames[k].render_rows(cam, rows[k], out=imgs[k], stream=s)
+            frames[k].l1_loss(imgs[k], targets[i], grad=dls[k], stream=s)
+            frames[k].backward(dls[k], sel=sels[k], stream=s)
+            with torch.cuda.stream(s):
+                n = frames[k].count.clone()
+                out.append((imgs[k].clone(), n, {g: t.clone() for g, t in sels[k].items()}))
+            done[k].record(s)
+        torch.cuda.synchronize()
+        for f in frames:
+            assert f.stats()["status"] == 0
+        return out
+
+    serial = run(1)
+    flight = run(3)
+    for i in range(len(cams)):
+        (ia, na, ga), (ib, nb, gb) = serial[i], flight[i]
+        assert torch.equal(ia, ib), i
+        n = int(na.item())
+        assert n == int(nb.item()) and n > 0, i
+        for g in GROUPS:
+            assert torch.equal(ga[g][:n], gb[g][:n]), (i, g)
+        _say(f"  view {i}: {n} selected, equal")
