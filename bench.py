@@ -136,7 +136,7 @@ def stored_executed(stage):
     return None
 
 
-def summarize_profiles(trace_csv, fetch_csv, write_csv, commands):
+def summarize_profiles(trace_csv, fetch_csv, write_csv, commands, dispatch_csv=None, stage_views=768):
     """Text summary of a rocprofv3 kernel-trace run and two --pmc runs
     (FETCH_SIZE, WRITE_SIZE): per-kernel average duration and HBM KiB per
     dispatch, the copy-kernel calibration (the 1 GiB device copies of
@@ -181,6 +181,24 @@ def summarize_profiles(trace_csv, fetch_csv, write_csv, commands):
         out.append("%-52s %7d %14.0f %14.0f %14s" % (k[:52], len(fv), fa, wa,
                                                      "-" if scaled is None else "%.2f" % (scaled / 1e6)))
     out.append("")
+    if dispatch_csv:
+        # per dispatch, in time order: the stage pass (one view at a time, the
+        # durations bench.py's roofline divides by) is the last stage_views
+        # dispatches of a blend kernel, the timed loop the stage_views before
+        d = collections.defaultdict(list)
+        for r in csv.DictReader(open(dispatch_csv)):
+            k = short(r["Kernel_Name"]).replace("void ", "").replace(" ", "")
+            if k.startswith(("k_blend_bwd", "k_blend_q")):
+                d[k].append((int(r["Start_Timestamp"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+        out.append("blend kernels per dispatch (us): stage pass = the last %d dispatches (one view at a time), "
+                   "timed loop = the %d before them" % (stage_views, stage_views))
+        for k in sorted(d):
+            v = [x for _, x in sorted(d[k])]
+            if len(v) >= 2 * stage_views:
+                sp, tl = v[-stage_views:], v[-2 * stage_views:-stage_views]
+                out.append("DISPATCH %s stage_pass_avg_us=%.2f timed_loop_avg_us=%.2f" %
+                           (k, sum(sp) / len(sp), sum(tl) / len(tl)))
+        out.append("")
     h = kernel_source_hash()
     for stage, pats in (("blend_bwd", ("k_blend_bwd",)), ("blend", ("k_blend_q", "k_blend<false"))):
         ks = [k for k in hbm if k.replace("void ", "").startswith(pats)]
@@ -498,13 +516,18 @@ def main():
                     help="print a text summary of rocprofv3 --pmc SQ counter runs of the blend kernels (no GPU work)")
     ap.add_argument("--trace-stats", default=None,
                     help="with --summarize-counters: a rocprofv3 kernel-trace stats CSV for per-dispatch durations")
+    ap.add_argument("--trace-csv", default=None,
+                    help="with --summarize-profiles: the rocprofv3 kernel-trace CSV, for the blend kernels' "
+                         "averages over the stage pass (the last --stage-views dispatches) and the timed loop")
+    ap.add_argument("--stage-views", type=int, default=768,
+                    help="with --trace-csv: views of the run's stage pass (its --steps)")
     ap.add_argument("--profile-command", action="append", default=[],
                     help="command line that produced the profiles (repeatable; recorded in the summary)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy (HBM byte-counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.summarize_profiles:
-        print(summarize_profiles(*args.summarize_profiles, args.profile_command))
+        print(summarize_profiles(*args.summarize_profiles, args.profile_command, args.trace_csv, args.stage_views))
         return
     if args.summarize_counters:
         print(summarize_counters(args.summarize_counters, args.profile_command, args.trace_stats))
