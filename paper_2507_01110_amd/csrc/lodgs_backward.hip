@@ -75,11 +75,13 @@ __device__ __forceinline__ float row_reduce_scatter(const float* g, int lane, in
 // step, each row reduces these NP values of its splat (moments, dL/do, the
 // colour gradient and, with NP = 11, the number of pixels it contributes to)
 // over its lanes (only when some lane of the wave
-// contributes) and adds them to its wave's LDS row of that splat, the rows in
-// order; the workgroup then sums the waves' rows in order and writes one
-// NP-float partial per (splat, tile) instance at the instance's emission
-// index, with zeros for instances that no pixel reached.  No atomics: the
-// result is deterministic.
+// contributes) and adds them to its wave's LDS row of that splat, the four
+// rows with one LDS add instruction (the LDS applies the lanes of one
+// instruction in lane order, so two rows on the same splat add in row order,
+// as adding them one after another does); the workgroup then sums the waves'
+// rows in order and writes one NP-float partial per (splat, tile) instance at
+// the instance's emission index, with zeros for instances that no pixel
+// reached.  No order depends on timing: the result is deterministic.
 template <int PX, int NP>
 __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restrict__ vp,
                                                         const uint2* __restrict__ ranges,
@@ -252,12 +254,12 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
           }
           int slot;
           const float r = row_reduce_scatter<NP>(g, lane, slot);
-          // the rows add into the wave's row of their splats in order (two
-          // rows may be on the same splat)
+          // the rows add into the wave's row of their splats with one LDS
+          // add instruction (two rows may be on the same splat: the LDS
+          // applies the lanes of one instruction in a fixed order)
           const uint64_t cm = __ballot(any_con);
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if (row == q && slot < NP && ((cm >> (16 * q)) & 0xFFFFull) != 0ull) acc[wv][slot][j ^ slot] += r;
+          if (slot < NP && ((cm >> (16 * row)) & 0xFFFFull) != 0ull)
+            __hip_atomic_fetch_add(&acc[wv][slot][j ^ slot], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         return !__any(act);
       };
