@@ -495,9 +495,12 @@ def main():
     ap.add_argument("--pool", type=int, default=0,
                     help="with --rows and --cache: keep the cached cuts' rows in a device pool of this many rows "
                          "(at least the cache's max_nodes) and gather from it")
-    ap.add_argument("--in-flight", type=int, default=3,
+    ap.add_argument("--in-flight", type=int, default=4,
                     help="views in flight in the timed loop (frames taking turns, each on its own stream; the "
                          "scatter into the node gradients in view order on one more)")
+    ap.add_argument("--frame-streams", type=int, default=3,
+                    help="streams the frames' work is spread over (view i on stream i mod this; at most "
+                         "--in-flight)")
     ap.add_argument("--serial", action="store_true",
                     help="one view at a time in the timed loop (the default keeps several views in flight, "
                          "see --in-flight)")
@@ -684,29 +687,31 @@ def main():
         timed_step = step
     # Several views in flight (node-gradient accumulation only: the parameters
     # do not change between views, so the forward of a later view may run
-    # while an earlier view's backward does).  Frames take turns; each frame's
-    # stream runs a view's select, forward, L1 and the frame-local half of its
-    # backward (blend backward and per-splat sums); one more stream runs the
-    # other half (colour and projection backward into the node gradients) in
-    # view order, so the gradients are those of one view at a time bit for
-    # bit.  A frame takes its next view once the scatter of its last is done.
+    # while an earlier view's backward does).  Frames take turns; view i's
+    # select, forward, L1 and the frame-local half of its backward (blend
+    # backward and per-splat sums) run on stream i mod n_st; one more stream
+    # runs the other half (colour and projection backward into the node
+    # gradients) in view order, so the gradients are those of one view at a
+    # time bit for bit.  A frame takes its next view once the scatter of its
+    # last is done.
     pipelined = not (args.serial or use_graph or args.adam or args.rows or cache is not None) and args.in_flight > 1
     n_fl = max(2, args.in_flight)
+    n_st = max(1, min(args.frame_streams, n_fl))
     launch_desc = "one graph per step" if use_graph else (
-        "plain launches, %d views in flight (select, forward, L1 and blend backward of each on its frame's stream; "
-        "the scatter into the node gradients in view order on one more stream)" % n_fl
+        "plain launches, %d views in flight on %d frames (select, forward, L1 and blend backward of view i on "
+        "stream i mod %d; the scatter into the node gradients in view order on one more stream)" % (n_fl, n_fl, n_st)
         if pipelined else "plain launches, one view at a time")
     if pipelined:
         frames = [frame] + [Frame(scene, cap_sel, cap_inst, W, H) for _ in range(n_fl - 1)]
         imgs = [img] + [torch.empty_like(img) for _ in range(n_fl - 1)]
         dLs = [dL] + [torch.empty_like(dL) for _ in range(n_fl - 1)]
-        sFs, sB = [torch.cuda.Stream() for _ in range(n_fl)], torch.cuda.current_stream()
+        sFs, sB = [torch.cuda.Stream() for _ in range(n_st)], torch.cuda.current_stream()
         part_done = [torch.cuda.Event() for _ in range(n_fl)]
         scat_done = [torch.cuda.Event() for _ in range(n_fl)]
 
-        def frame_work(i):  # on the frame's stream
+        def frame_work(i):  # on stream i mod n_st
             k, v = i % n_fl, seq[i % K]
-            f, sF = frames[k], sFs[k]
+            f, sF = frames[k], sFs[i % n_st]
             sF.wait_event(scat_done[k])  # the frame's previous view is done with it
             f.lod_select(cstructs[v], views[v][1], conservative=args.conservative, method=args.cut, stream=sF)
             f.render(cstructs[v], out=imgs[k], stream=sF)

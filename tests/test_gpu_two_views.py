@@ -1,8 +1,8 @@
-"""Several views in flight (the timed loop of the benchmark): frames take
-turns, each frame's stream runs a view's select, forward, L1 and the
-frame-local half of its backward (lodgs_render_backward_phases, PARTIALS),
-one more stream runs the scatter half into the node gradients (SCATTER) in
-view order.  Also the two-frame form with the whole backward on one stream.
+"""Several views in flight (the timed loop of the benchmark): four frames
+take turns over three streams, view i's stream running its select, forward,
+L1 and the frame-local half of its backward (lodgs_render_backward_phases,
+PARTIALS), one more stream the scatter half into the node gradients (SCATTER)
+in view order.  Also the two-frame form with the whole backward on one stream.
 Images, dL/dimage and the accumulated node gradients equal those of one view
 at a time bit for bit: frames share no mutable state, and the writes to the
 node arrays stay in view order."""
@@ -62,19 +62,19 @@ def test_views_in_flight_with_split_backward_equal_one_at_a_time(setup):
     import torch
     from paper_2507_01110_amd.lodgs import Frame, grads_like
     S, cams, taus, targets = setup[:4]
-    n_fl = 3
+    n_fl, n_st = 4, 3  # four frames taking turns over three streams, as the benchmark's timed loop
     frames = [Frame(S, 1 << 22, 1 << 24, W, H) for _ in range(n_fl)]
     imgs = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for _ in range(n_fl)]
     dls = [torch.empty_like(imgs[0]) for _ in range(n_fl)]
     g_pipe = grads_like(S)
-    sF, sB = [torch.cuda.Stream() for _ in range(n_fl)], torch.cuda.Stream()
+    sF, sB = [torch.cuda.Stream() for _ in range(n_st)], torch.cuda.Stream()
     part_done = [torch.cuda.Event() for _ in range(n_fl)]
     scat_done = [torch.cuda.Event() for _ in range(n_fl)]
     got_imgs, got_dls = [None] * len(cams), [None] * len(cams)
 
     def frame_work(i):
         k = i % n_fl
-        f, s = frames[k], sF[k]
+        f, s = frames[k], sF[i % n_st]
         s.wait_event(scat_done[k])
         f.lod_select(cams[i], taus[i], stream=s)
         f.render(cams[i], out=imgs[k], stream=s)
