@@ -730,20 +730,20 @@ def main():
             scatter_on_B(i)
     # The out-of-core path through the row pool, views in flight: the cached
     # select and the pool's gather change the cache's and the pool's state, so
-    # they run in view order on one stream; each view's render from its rows,
-    # L1 and backward (into selection-indexed gradients) then run on its
-    # frame's stream; a frame and its rows take the next view once that work is
+    # they run in view order on one stream; view i's render from its rows, L1
+    # and backward (into selection-indexed gradients) then run on stream
+    # i mod n_st; a frame and its rows take the next view once that work is
     # done.
     pool_pipelined = not (args.serial or use_graph) and pool is not None and args.in_flight > 1
     if pool_pipelined:
-        launch_desc = ("plain launches, %d views in flight (cached select and pool gather in view order on one "
-                       "stream; render, L1 and backward of each on its frame's stream)" % n_fl)
+        launch_desc = ("plain launches, %d views in flight on %d frames (cached select and pool gather in view "
+                       "order on one stream; render, L1 and backward of view i on stream i mod %d)" % (n_fl, n_fl, n_st))
         frames = [frame] + [Frame(scene, cap_sel, cap_inst, W, H) for _ in range(n_fl - 1)]
         imgs = [img] + [torch.empty_like(img) for _ in range(n_fl - 1)]
         dLs = [dL] + [torch.empty_like(dL) for _ in range(n_fl - 1)]
         rowss = [rows] + [rows_like(tree.sh_degree, cap_sel) for _ in range(n_fl - 1)]
         sels = [sel] + [{k: torch.zeros_like(t) for k, t in sel.items()} for _ in range(n_fl - 1)]
-        sS, sFs = torch.cuda.current_stream(), [torch.cuda.Stream() for _ in range(n_fl)]
+        sS, sFs = torch.cuda.current_stream(), [torch.cuda.Stream() for _ in range(n_st)]
         gathered = [torch.cuda.Event() for _ in range(n_fl)]
         done = [torch.cuda.Event() for _ in range(n_fl)]
 
@@ -754,9 +754,9 @@ def main():
             pool.gather(frames[k].idx, frames[k].count, rowss[k], stream=sS)
             gathered[k].record(sS)
 
-        def rows_work(i):  # on the frame's stream
+        def rows_work(i):  # on stream i mod n_st
             k, v = i % n_fl, seq[i % K]
-            f, sF = frames[k], sFs[k]
+            f, sF = frames[k], sFs[i % n_st]
             sF.wait_event(gathered[k])
             f.render_rows(cstructs[v], rowss[k], out=imgs[k], stream=sF)
             f.l1_loss(imgs[k], targets[v % len(targets)], grad=dLs[k], stream=sF)
@@ -777,7 +777,7 @@ def main():
         for i in range(K):
             state_work(i)
             rows_work(i)
-            ev[i][1].record(sFs[i % n_fl])
+            ev[i][1].record(sFs[i % n_st])
     elif pipelined:
         ev[0][0].record(sB)
         for t in range(K + n_fl - 1):
