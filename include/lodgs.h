@@ -332,6 +332,10 @@ int lodgs_gather_rows_pooled(lodgs_row_pool* pool, const int32_t* d_idx, const i
                              const lodgs_grads* rows, int64_t capacity, lodgs_stream stream);
 int lodgs_row_pool_store(lodgs_row_pool* pool, const int32_t* d_idx, const int32_t* d_count, const lodgs_grads* rows,
                          int64_t capacity, lodgs_stream stream);
+/* Writes every changed pooled row back to host memory now (the rows stay
+ * pooled): at the end of training, or before lodgs_row_pool_destroy, which
+ * drops the pool without writing anything back.  Stream-ordered. */
+int lodgs_row_pool_write_back(lodgs_row_pool* pool, lodgs_stream stream);
 /* Counters (blocks on the stream); with d_node_slot (device int32 [n_nodes])
  * not NULL, also copies each node's slot (-1: not pooled). */
 int lodgs_row_pool_stats_read(lodgs_row_pool* pool, lodgs_row_pool_stats* out, int32_t* d_node_slot,

@@ -156,6 +156,7 @@ EXPORTS = {
     "lodgs_row_pool_destroy": ([c_p], None),
     "lodgs_gather_rows_pooled": ([c_p, c_p, c_p, ctypes.POINTER(Grads), i64, c_p], ctypes.c_int),
     "lodgs_row_pool_store": ([c_p, c_p, c_p, ctypes.POINTER(Grads), i64, c_p], ctypes.c_int),
+    "lodgs_row_pool_write_back": ([c_p, c_p], ctypes.c_int),
     "lodgs_row_pool_stats_read": ([c_p, ctypes.POINTER(RowPoolStats), c_p, c_p], ctypes.c_int),
     "lodgs_frame_set_contrib_stats": ([c_p, c_p, c_p, c_p], ctypes.c_int),
     "lodgs_server_create": ([c_p, ctypes.POINTER(ServerCaps), ctypes.POINTER(c_p)], ctypes.c_int),

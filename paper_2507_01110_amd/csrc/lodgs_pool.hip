@@ -458,6 +458,24 @@ __global__ void __launch_bounds__(kBlock) k_pool_store(const int32_t* idx, const
   }
 }
 
+// Every changed pooled row back to host memory (the rows stay pooled, no
+// longer marked changed): one thread per node below the upper hierarchy.
+__global__ void __launch_bounds__(kBlock) k_pool_write_back(int64_t n_upper, int64_t n_nodes,
+                                                            const int32_t* node_slot, uint8_t* dirty,
+                                                            unsigned long long* counters, Groups G) {
+  unsigned long long wb = 0;
+  for (int64_t node = n_upper + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; node < n_nodes;
+       node += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = node_slot[node];
+    if (s < 0 || !dirty[s]) continue;
+    rec_to_host(G, G.pool + (int64_t)s * G.rec, node);
+    dirty[s] = 0;
+    ++wb;
+  }
+  wb = wave_total(wb);
+  if ((threadIdx.x & 63) == 0 && wb) atomicAdd(&counters[kWritten], wb);
+}
+
 __global__ void __launch_bounds__(kBlock) k_pool_init(int32_t* node_slot, uint32_t* mark, int64_t n_nodes,
                                                       int32_t* free_slots, uint8_t* dirty, int64_t capacity) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -673,6 +691,17 @@ int lodgs_row_pool_store(lodgs_row_pool* p, const int32_t* d_idx, const int32_t*
 #undef LODGS_STORE
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_row_pool_store");
+}
+
+int lodgs_row_pool_write_back(lodgs_row_pool* p, lodgs_stream stream) {
+  using namespace lodgs;
+  if (!p) return set_error(LODGS_E_INVALID, "lodgs_row_pool_write_back: null argument");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const SceneDev& S = p->scene->dev;
+  hipLaunchKernelGGL(k_pool_write_back, dim3(4096), dim3(kBlock), 0, st, (int64_t)S.n_upper, (int64_t)S.n_nodes,
+                     p->node_slot, p->dirty, p->counters, groups_of(p));
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LODGS_OK : hip_fail(e, "lodgs_row_pool_write_back");
 }
 
 int lodgs_row_pool_stats_read(lodgs_row_pool* p, lodgs_row_pool_stats* out, int32_t* d_node_slot_copy,

@@ -239,6 +239,10 @@ class RowPool:
         check(_lib.load().lodgs_row_pool_store(self._h, _ptr(idx), _ptr(count), ctypes.byref(g),
                                                int(rows["means"].shape[0]), _stream(stream)), "lodgs_row_pool_store")
 
+    def write_back(self, stream=None):
+        """Every changed pooled row to host memory now (lodgs_row_pool_write_back)."""
+        check(_lib.load().lodgs_row_pool_write_back(self._h, _stream(stream)), "lodgs_row_pool_write_back")
+
     def stats(self, node_slot=None, stream=None) -> dict:
         s = _lib.RowPoolStats()
         check(_lib.load().lodgs_row_pool_stats_read(self._h, ctypes.byref(s), _ptr(node_slot), _stream(stream)),

@@ -154,6 +154,34 @@ def test_pool_medium_flyin_and_write_back(torch_cuda):
     assert bool(torch.isin(changed, idx[:n].long().cpu()).all())
 
 
+def test_pool_write_back_puts_every_stored_row_in_host_memory(torch_cuda):
+    """After lodgs_row_pool_store, lodgs_row_pool_write_back makes host memory
+    hold every stored row (pooled, upper or neither), the pool keeps its
+    slots, and a second write-back writes nothing."""
+    torch = torch_cuda
+    tree = scenegen.build_tree(configs.tiny_spec(n=8192, seed=4))
+    cams = [scenegen.camera_look_at((26 * np.cos(a), 26 * np.sin(a), 10.0), (0, 0, 0), (0, 0, 1), 192, 160)
+            for a in np.linspace(0.0, 1.0, 4)]
+    S, f, G, P, C, host, rows, tot = _lockstep(torch, tree, cams, 1.0, 10 ** 6, 0.5, 1.5, 0, max_inst=1 << 19)
+    idx, cnt = f.idx.clone(), f.count.clone()
+    n = int(cnt.item())
+    for k in GROUPS:
+        rows[k][:n] = rows[k][:n] * 3.0 - 0.25
+    P.store(idx, cnt, rows)
+    before = P.stats()
+    P.write_back()
+    torch.cuda.synchronize()
+    after = P.stats()
+    sel = idx[:n].long().cpu()
+    for k in GROUPS:
+        assert torch.equal(host.params[k][sel], rows[k][:n].cpu()), k
+    assert after["pooled_rows"] == before["pooled_rows"]
+    assert after["written_back"] > before["written_back"]
+    P.write_back()
+    torch.cuda.synchronize()
+    assert P.stats()["written_back"] == after["written_back"]  # nothing changed since
+
+
 def test_pool_views_in_flight_equal_one_at_a_time(torch_cuda):
     """The cached select and the pooled gather in view order on one stream, each
     view's render from its rows, L1 and backward on its frame's stream, three
