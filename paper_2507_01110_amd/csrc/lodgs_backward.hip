@@ -264,8 +264,14 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
         return !__any(act);
       };
       // two register sets, each loaded one list entry ahead of its use
+      static_assert((NB & (NB - 1)) == 0, "a power of two of list entries");
       const uint8_t* hl = hits[wv][row];
-      auto slot_at = [&](int t) -> int { return t < n ? (int)hl[t] : 0; };
+      // (an entry is read unconditionally, within the row's NB bytes, and
+      // replaced by 0 past the list's end, so every read is a plain LDS load)
+      auto slot_at = [&](int t) -> int {
+        const int e = (int)hl[t & (NB - 1)];
+        return t < n ? e : 0;
+      };
       auto rec = [&](int j) -> Splat {
         const BatchRec& q = batch[j];
         Splat sp;
@@ -284,16 +290,19 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
         sp.rect_x = sp.rect_y = sp.pad0 = sp.pad1 = 0u;
         return sp;
       };
-      Splat sa = rec(slot_at(0)), sb;
+      // (the list entries themselves two ahead, so a record's LDS read never
+      // waits for the read of its slot index)
+      int ja = slot_at(0), jb = slot_at(1);
+      Splat sa = rec(ja), sb;
       for (int t = 0;;) {
-        const int ja = slot_at(t);
-        const bool ha = t < n;
-        sb = rec(slot_at(t + 1));
-        if (step(sa, ja, ha) || ++t >= nmax) break;
-        const int jb = slot_at(t);
-        const bool hb = t < n;
-        sa = rec(slot_at(t + 1));
-        if (step(sb, jb, hb) || ++t >= nmax) break;
+        const int jc = slot_at(t + 2);
+        sb = rec(jb);
+        if (step(sa, ja, t < n) || ++t >= nmax) break;
+        const int jd = slot_at(t + 2);
+        sa = rec(jc);
+        if (step(sb, jb, t < n) || ++t >= nmax) break;
+        ja = jc;
+        jb = jd;
       }
     }
     __syncthreads();

@@ -505,7 +505,12 @@ __global__ void __launch_bounds__(256 / PX) k_blend(const ViewConst* __restrict_
     if (__any(active) && nmax > 0) {  // wave-uniform
       // two register sets, each loaded one list entry ahead of its use
       const uint8_t* hl = hits[wv][g];
-      auto slot = [&](int t) -> int { return t < n ? (int)hl[t] : 0; };
+      // (an entry is read unconditionally, within the row's 64 bytes, and
+      // replaced by 0 past the list's end, so every read is a plain LDS load)
+      auto slot = [&](int t) -> int {
+        const int e = (int)hl[t & 63];
+        return t < n ? e : 0;
+      };
       Splat sa = batch[slot(0)], sb;
       for (int t = 0;;) {
         const int ja = slot(t);
@@ -663,17 +668,25 @@ __global__ void __launch_bounds__(64) k_blend_q(const ViewConst* __restrict__ vp
     };
     if (nmax > 0) {
       const uint8_t* hl = hits[g];
-      auto slot = [&](int t) -> int { return t < n ? (int)hl[t] : 0; };
-      Splat sa = load(slot(0)), sb;
+      // (an entry is read unconditionally, within the row's 64 bytes, and
+      // replaced by 0 past the list's end, so every read is a plain LDS load)
+      auto slot = [&](int t) -> int {
+        const int e = (int)hl[t & 63];
+        return t < n ? e : 0;
+      };
+      // records one entry ahead of their use, list entries two ahead (so a
+      // record's LDS read never waits for the read of its slot index)
+      int ja = slot(0), jb = slot(1);
+      Splat sa = load(ja), sb;
       for (int t = 0;;) {
-        const int ja = slot(t);
-        const bool ha = t < n;
-        sb = load(slot(t + 1));
-        if (step(sa, ja, ha) || ++t >= nmax) break;
-        const int jb = slot(t);
-        const bool hb = t < n;
-        sa = load(slot(t + 1));
-        if (step(sb, jb, hb) || ++t >= nmax) break;
+        const int jc = slot(t + 2);
+        sb = load(jb);
+        if (step(sa, ja, t < n) || ++t >= nmax) break;
+        const int jd = slot(t + 2);
+        sa = load(jc);
+        if (step(sb, jb, t < n) || ++t >= nmax) break;
+        ja = jc;
+        jb = jd;
       }
     }
     __syncthreads();
