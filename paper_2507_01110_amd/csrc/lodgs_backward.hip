@@ -222,7 +222,10 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
           act = act | live[p];
         }
         if (__any(any_con)) {  // wave-uniform
-          float g[11] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+          // the first pixel's terms start the sums: only the sign of a zero
+          // sum differs from adding them to +0, and the LDS rows (never -0)
+          // absorb that
+          float g[11];
 #pragma unroll
           for (int p = 0; p < PX; ++p) {
             const float alpha = als[p], Tp = T[p];
@@ -238,17 +241,31 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
             const float dpow = unclamped ? dA * alpha : 0.0f;
             const float dop = unclamped ? dA * es[p] : 0.0f;
             const float wc = con ? w : 0.0f;
-            g[0] += dpow;
-            g[1] = __builtin_fmaf(dpow, ex, g[1]);
-            g[2] = __builtin_fmaf(dpow, ey[p], g[2]);
-            g[3] = __builtin_fmaf(dpow, exx[p], g[3]);
-            g[4] = __builtin_fmaf(dpow, exy[p], g[4]);
-            g[5] = __builtin_fmaf(dpow, eyy[p], g[5]);
-            g[6] += dop;
-            g[7] = __builtin_fmaf(G0[p], wc, g[7]);
-            g[8] = __builtin_fmaf(G1[p], wc, g[8]);
-            g[9] = __builtin_fmaf(G2[p], wc, g[9]);
-            if (NP == 11) g[10] += con ? 1.0f : 0.0f;  // contributing pixels
+            if (p == 0) {
+              g[0] = dpow;
+              g[1] = dpow * ex;
+              g[2] = dpow * ey[p];
+              g[3] = dpow * exx[p];
+              g[4] = dpow * exy[p];
+              g[5] = dpow * eyy[p];
+              g[6] = dop;
+              g[7] = G0[p] * wc;
+              g[8] = G1[p] * wc;
+              g[9] = G2[p] * wc;
+              g[10] = con ? 1.0f : 0.0f;  // contributing pixels (read only with NP = 11)
+            } else {
+              g[0] += dpow;
+              g[1] = __builtin_fmaf(dpow, ex, g[1]);
+              g[2] = __builtin_fmaf(dpow, ey[p], g[2]);
+              g[3] = __builtin_fmaf(dpow, exx[p], g[3]);
+              g[4] = __builtin_fmaf(dpow, exy[p], g[4]);
+              g[5] = __builtin_fmaf(dpow, eyy[p], g[5]);
+              g[6] += dop;
+              g[7] = __builtin_fmaf(G0[p], wc, g[7]);
+              g[8] = __builtin_fmaf(G1[p], wc, g[8]);
+              g[9] = __builtin_fmaf(G2[p], wc, g[9]);
+              if (NP == 11) g[10] += con ? 1.0f : 0.0f;
+            }
             GQ[p] = con ? gq : GQ[p];
             T[p] = con ? tts[p] : Tp;
           }
@@ -307,19 +324,31 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     }
     __syncthreads();
     if ((int)threadIdx.x < m) {
+      // Only the waves whose blocks hold one of the instance's events replayed
+      // it: the other waves' rows of this slot are still +0 and are neither
+      // read nor cleared.  Skipping them leaves the sums bit-identical (a row
+      // value is never -0: rows start at +0 and x + y is -0 only when both
+      // are), and an instance without events is written as zeros.
       float* dst = partial + NP * (int64_t)bid[threadIdx.x];
+      const uint32_t evb = ev[threadIdx.x];
+      float r[NP];
 #pragma unroll
-      for (int c = 0; c < NP; ++c) {
-        const int col = (int)threadIdx.x ^ c;
-        float r = acc[0][c][col];
-        acc[0][c][col] = 0.0f;
+      for (int c = 0; c < NP; ++c) r[c] = 0.0f;
 #pragma unroll
-        for (int w = 1; w < NW; ++w) {
-          r += acc[w][c][col];
+      for (int w = 0; w < NW; ++w) {
+        uint32_t wb = 0u;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) wb |= blend_row_blocks<PX, true>(w, g);
+        if ((evb & wb) == 0u) continue;
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+          const int col = (int)threadIdx.x ^ c;
+          r[c] += acc[w][c][col];
           acc[w][c][col] = 0.0f;
         }
-        dst[c] = r;
       }
+#pragma unroll
+      for (int c = 0; c < NP; ++c) dst[c] = r[c];
     }
     e0 = e1;
     i0 = i1;
