@@ -794,6 +794,7 @@ def main():
             ev[i][0].record(run_stream)
             timed_step(i)
             ev[i][1].record(run_stream)
+    t_enq = time.perf_counter() - t0  # the host's time to issue the loop's work
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     if pool_pipelined:  # views may complete out of order: intervals between sorted completions
@@ -802,7 +803,8 @@ def main():
     else:
         per_view = np.array([a.elapsed_time(b) for a, b in ev])
     ms_per_view = elapsed * 1000.0 / K
-    log(f"timed {K} views ({launch_desc}): {ms_per_view:.3f} ms per view")
+    log(f"timed {K} views ({launch_desc}): {ms_per_view:.3f} ms per view "
+        f"(the host issued the work in {t_enq * 1000.0 / K:.3f} ms per view)")
     if pipelined or pool_pipelined:
         for f in frames:
             st_p = f.stats()
