@@ -87,13 +87,19 @@ SERVE_RATES = (50.0, 200.0, 800.0, 1600.0)
 
 
 def kernel_source_hash():
-    """sha256 over the library's HIP sources: a stored counter reading applies
-    only to the kernels it was taken from."""
+    """sha256 over what the measured kernels (the blend forward and backward)
+    are compiled from: their two source files, every header they can include
+    and the build flags.  A stored counter reading applies only to the kernels
+    it was taken from; changes elsewhere in the library do not void it."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2507_01110_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+    pkg = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2507_01110_amd")
+    csrc = os.path.join(pkg, "csrc")
+    files = [os.path.join(csrc, "lodgs_render.hip"), os.path.join(csrc, "lodgs_backward.hip")]
+    files += sorted(glob.glob(os.path.join(csrc, "*.h")))
+    files += [os.path.join(os.path.dirname(pkg), "include", "lodgs.h"), os.path.join(pkg, "build.py")]
+    for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
