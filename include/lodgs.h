@@ -407,6 +407,20 @@ int lodgs_frame_read_instances(lodgs_frame* frame, int32_t* d_tile, int32_t* d_p
 /* Clears the recorded device error of the frame. */
 int lodgs_frame_clear_status(lodgs_frame* frame, lodgs_stream stream);
 
+/* The varying level of detail of training (implementation appendix: the
+ * distances to the SPT centres are multiplied by a random factor each
+ * iteration, against overfitting Gaussians of one scale to views from one
+ * distance): every later lodgs_lod_select and lodgs_lod_select_cached on this
+ * frame, and every replay of a graph captured on it, multiplies the FP32
+ * distance to each SPT root by factor before that SPT's cut (X = (d factor)
+ * tau / fx; with LODGS_CONSERVATIVE, max(0, d factor - R) tau / fx) and
+ * before the cut cache's ratio test, whose entries then hold that distance.
+ * Upper-hierarchy nodes keep their own distance; the comparator cuts
+ * (LODGS_CUT_BFS, LODGS_CUT_PARALLEL) have no SPTs and ignore it.  1 (the
+ * default) is no noise.  factor must be finite and > 0 (else
+ * LODGS_E_INVALID); the training loop draws 1 + 5 r^4, r ~ U(0, 1). */
+int lodgs_frame_set_lod_noise(lodgs_frame* frame, float factor);
+
 /* The densification criterion (Sec. 4.2: nodes are chosen for densification
  * by their largest screen-space gradient): with d_max_grad2d [n_nodes]
  * (device, node-indexed, borrowed) attached, every later

@@ -69,7 +69,7 @@ def lib():
         L.orc_hspt.restype = ctypes.c_int
         L.orc_layout.argtypes = [i64, P, P, i32, P, P, P, P, P, P, P, P, P]
         L.orc_layout.restype = ctypes.c_int
-        L.orc_select.argtypes = [i64, P, P, i32, P, P, P, P, P, P, P, P, ctypes.POINTER(OrcCamera), f32,
+        L.orc_select.argtypes = [i64, P, P, i32, P, P, P, P, P, P, P, P, ctypes.POINTER(OrcCamera), f32, f32,
                                  ctypes.c_uint32, ctypes.c_int, P, i64, P, ctypes.POINTER(SelectStats), P, P]
         L.orc_select.restype = ctypes.c_int
         for name in ("orc_select_bfs", "orc_select_parallel"):
@@ -169,10 +169,11 @@ class OracleScene:
         self.spt_begin = self.spt_begin[: self.n_spt + 1].copy()
 
     def select(self, cam, tau: float, cull: bool = True, mode: int = 0, conservative: bool = False,
-               spt_X: np.ndarray | None = None, spt_visible: np.ndarray | None = None):
+               spt_X: np.ndarray | None = None, spt_visible: np.ndarray | None = None, spt_scale: float = 1.0):
         """Tree ids of the cut, in layout order, and the decision statistics.
         spt_X (float32 [n_nodes], NaN = own): X of the SPT rooted at each tree id;
-        spt_visible (uint8 [n_nodes]): receives 1 at the visible SPT roots."""
+        spt_visible (uint8 [n_nodes]): receives 1 at the visible SPT roots;
+        spt_scale: the LoD noise factor on the distances to the SPT roots."""
         t = self.tree
         n = t.n_nodes
         out = np.zeros(n, np.int32)
@@ -181,7 +182,7 @@ class OracleScene:
         c = camera(cam)
         rc = lib().orc_select(n, _p(t.left), _p(t.right), t.root, _p(t.means), _p(self.g), _p(self.rho),
                               _p(self.role), _p(self.spt_of), _p(self.r_min), _p(self.r_max), _p(self.pos_of),
-                              ctypes.byref(c), float(np.float32(tau)),
+                              ctypes.byref(c), float(np.float32(tau)), float(np.float32(spt_scale)),
                               (CULL if cull else 0) | (CONSERVATIVE if conservative else 0), mode, _p(out), n,
                               ctypes.byref(cnt), ctypes.byref(st),
                               None if spt_X is None else _p(spt_X), None if spt_visible is None else _p(spt_visible))
@@ -346,7 +347,8 @@ class OracleCutCache:
     X = d tau / fx, then entered with (d, X) and size = the number of its
     nodes the cut selected.  Every visible SPT's last use becomes t.  Then,
     oldest last use first (ties by SPT index), entries are dropped while the
-    sizes of those left exceed max_nodes."""
+    sizes of those left exceed max_nodes.  With LoD noise (spt_scale), d is
+    the noisy root distance (the FP32 distance times the factor) throughout."""
 
     def __init__(self, scene: "OracleScene", max_nodes: int, d_min: float, d_max: float, flush_every: int = 0):
         self.S = scene
@@ -358,20 +360,21 @@ class OracleCutCache:
         roots = scene.perm[scene.spt_begin[:-1]]
         self.spt_index = {int(r): j for j, r in enumerate(roots)}
 
-    def select(self, cam, tau: float, cull: bool = True):
+    def select(self, cam, tau: float, cull: bool = True, spt_scale: float = 1.0):
         S = self.S
         tree = S.tree
+        s = np.float32(spt_scale)
         self.t += 1
         if self.flush_every > 0 and self.t % self.flush_every == 0:
             self.entries.clear()
         n = tree.n_nodes
         vis = np.zeros(n, np.uint8)
-        S.select(cam, tau, cull=cull, spt_visible=vis)
+        S.select(cam, tau, cull=cull, spt_visible=vis, spt_scale=s)
         k = np.float32(np.float32(tau) / np.float32(cam.fx))
         override = np.full(n, np.nan, np.float32)
         loaded = []
         for r in np.flatnonzero(vis).tolist():
-            d = dist32(tree.means[r], cam.pos)
+            d = np.float32(dist32(tree.means[r], cam.pos) * s)  # the root distance the cut uses
             e = self.entries.get(r)
             hit = False
             if e is not None:
@@ -386,7 +389,7 @@ class OracleCutCache:
             else:
                 loaded.append((r, d, np.float32(d * k)))
                 self.loads += 1
-        ids, st = S.select(cam, tau, cull=cull, spt_X=override)
+        ids, st = S.select(cam, tau, cull=cull, spt_X=override, spt_scale=s)
         counts = {}
         for sp in S.spt_of[ids].tolist():
             if sp >= 0:

@@ -334,11 +334,15 @@ static float spt_radius(const int32_t* left, const int32_t* right, const float* 
 
 /* spt_X (optional, [n] by tree id): a value that is not NaN at a visible SPT
  * root replaces that SPT's X (the SPT-cut cache reuses a cached cut this
- * way); spt_visible (optional, [n]): set to 1 at every visible SPT root. */
+ * way); spt_visible (optional, [n]): set to 1 at every visible SPT root.
+ * spt_scale: the varying level of detail of the implementation appendix
+ * multiplies the distances to the SPT centres by a per-iteration factor; the
+ * FP32 distance to an SPT root is multiplied by spt_scale (1: no noise)
+ * before it enters that SPT's cut, upper nodes keep their own distance. */
 int orc_select(int64_t n, const int32_t* left, const int32_t* right, int32_t root, const float* means,
                const float* g, const float* rho, const int8_t* role, const int32_t* spt_of,
                const float* r_min, const float* r_max, const int32_t* pos_of, const orc_camera* C,
-               float tau, uint32_t flags, int mode, int32_t* out, int64_t cap, int64_t* n_out,
+               float tau, float spt_scale, uint32_t flags, int mode, int32_t* out, int64_t cap, int64_t* n_out,
                orc_select_stats* st_out, const float* spt_X, uint8_t* spt_visible) {
   orc_select_stats st;
   memset(&st, 0, sizeof st);
@@ -373,8 +377,9 @@ int orc_select(int64_t n, const int32_t* left, const int32_t* right, int32_t roo
     if (cull && culled32(C, &F, mu, rho[u])) { st.spt_culled++; continue; }
     st.spt_visible++;
     if (spt_visible) spt_visible[u] = 1;
-    float X = dist32(mu, C->pos) * k;
-    if (flags & ORC_CONSERVATIVE) X = fmaxf(0.0f, dist32(mu, C->pos) - spt_radius(left, right, means, u, stk2)) * k;
+    const float d = dist32(mu, C->pos) * spt_scale;
+    float X = d * k;
+    if (flags & ORC_CONSERVATIVE) X = fmaxf(0.0f, d - spt_radius(left, right, means, u, stk2)) * k;
     if (spt_X && !isnan(spt_X[u])) X = spt_X[u];
     int64_t tp = 0;
     stk2[tp++] = u;

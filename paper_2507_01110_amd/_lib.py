@@ -151,6 +151,7 @@ EXPORTS = {
     "lodgs_cut_cache_stats_read": ([c_p, ctypes.POINTER(CutCacheStats), c_p], ctypes.c_int),
     "lodgs_gather_rows": ([ctypes.POINTER(Grads), ctypes.POINTER(Grads), i32, c_p, c_p, i64, i64, c_p], ctypes.c_int),
     "lodgs_render_rows": ([c_p, ctypes.POINTER(Grads), c_p, ctypes.POINTER(Camera), c_p, c_p, c_p], ctypes.c_int),
+    "lodgs_frame_set_lod_noise": ([c_p, ctypes.c_float], ctypes.c_int),
     "lodgs_frame_set_densify_stats": ([c_p, c_p], ctypes.c_int),
     "lodgs_row_pool_create": ([c_p, ctypes.POINTER(Grads), i32, i64, ctypes.POINTER(c_p)], ctypes.c_int),
     "lodgs_row_pool_destroy": ([c_p], None),

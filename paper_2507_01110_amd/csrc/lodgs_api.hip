@@ -46,6 +46,7 @@ ViewConst make_view(const lodgs_camera& c, float tau) {
   v.height = c.height;
   v.z_near = c.z_near;
   v.k = tau / c.fx;
+  v.spt_scale = 1.0f;
   v.hl = c.cx / c.fx;
   v.hr = ((float)c.width - c.cx) / c.fx;
   v.ht = c.cy / c.fy;
@@ -288,6 +289,7 @@ int lodgs_frame_create(const lodgs_scene* scene, const lodgs_frame_caps* caps, l
   if (!f) return set_error(LODGS_E_OOM, "lodgs_frame_create: out of host memory");
   f->scene = scene;
   f->caps = *caps;
+  f->spt_scale = 1.0f;
   f->blend_px_fwd = lodgs::blend_pixels_per_lane(false);
   f->blend_px_bwd = lodgs::blend_pixels_per_lane(true);
   hipError_t e = hipSuccess;
@@ -343,7 +345,8 @@ int lodgs_lod_select(lodgs_frame* f, const lodgs_camera* cam, float tau, uint32_
     return set_error(LODGS_E_INVALID, "lodgs_lod_select: LODGS_CUT_BFS, LODGS_CUT_PARALLEL and LODGS_CONSERVATIVE exclude each other");
   if (full && !f->cut_bits)
     return set_error(LODGS_E_STATE, "lodgs_lod_select: the frame was created before lodgs_scene_set_hierarchy");
-  const lodgs::ViewConst v = lodgs::make_view(*cam, tau);
+  lodgs::ViewConst v = lodgs::make_view(*cam, tau);
+  v.spt_scale = f->spt_scale;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (full) lodgs::launch_select_full(f, v, flags, d_idx, capacity, d_count, st);
   else lodgs::launch_select(f, v, flags, d_idx, capacity, d_count, st);
@@ -360,8 +363,9 @@ int lodgs_lod_select_cached(lodgs_frame* f, lodgs_cut_cache* c, const lodgs_came
   if (capacity < 0 || capacity > (int64_t)INT32_MAX)
     return set_error(LODGS_E_INVALID, "lodgs_lod_select_cached: capacity");
   if (flags & ~LODGS_CULL) return set_error(LODGS_E_INVALID, "lodgs_lod_select_cached: only LODGS_CULL is allowed");
-  return lodgs::cache_select(f, c, lodgs::make_view(*cam, tau), flags, d_idx, capacity, d_count,
-                             reinterpret_cast<hipStream_t>(stream));
+  lodgs::ViewConst v = lodgs::make_view(*cam, tau);
+  v.spt_scale = f->spt_scale;
+  return lodgs::cache_select(f, c, v, flags, d_idx, capacity, d_count, reinterpret_cast<hipStream_t>(stream));
 }
 
 int lodgs_render(lodgs_frame* f, const int32_t* d_idx, const int32_t* d_count, const lodgs_camera* cam,
@@ -610,6 +614,7 @@ int graph_launch(lodgs_graph* g, const lodgs_camera* cam, float tau, float* d_rg
     return set_error(LODGS_E_INVALID, "lodgs_graph_launch: image size differs from the captured one");
   if (!std::isfinite(tau) || tau < 0.0f) return set_error(LODGS_E_INVALID, "lodgs_graph_launch: bad tau");
   ViewConst vs = make_view(*cam, tau), vr = make_view(*cam, 0.0f);
+  vs.spt_scale = g->frame->spt_scale;  // the frame's LoD noise at this launch
   void* args_s[6] = {&vs, &g->dst_sel, &g->ctr_sel, &g->mode_sel, &g->count_sel, &g->cap_sel};
   void* args_r[6] = {&vr, &g->dst_ren, &g->ctr_ren, &g->mode_ren, &g->count_ren, &g->cap_ren};
   hipKernelNodeParams ps = g->p_sel, pr = g->p_ren;
@@ -739,7 +744,9 @@ int lodgs_graph_capture_view(lodgs_frame* f, const lodgs_camera* cam, float tau,
   float b[3] = {0.0f, 0.0f, 0.0f};
   if (bg)
     for (int k = 0; k < 3; ++k) b[k] = bg[k];
-  const lodgs::ViewConst vs = lodgs::make_view(*cam, tau), vr = lodgs::make_view(*cam, 0.0f);
+  lodgs::ViewConst vs = lodgs::make_view(*cam, tau);
+  vs.spt_scale = f->spt_scale;
+  const lodgs::ViewConst vr = lodgs::make_view(*cam, 0.0f);
   rc = lodgs::capture(g, st, "lodgs_graph_capture_view", [&] {
     lodgs::launch_select(f, vs, flags, d_idx, capacity, d_count, st);
     f->rows_mode = false;
@@ -784,7 +791,9 @@ int lodgs_graph_capture_step(lodgs_frame* f, const lodgs_camera* cam, float tau,
   float b[3] = {0.0f, 0.0f, 0.0f};
   if (bg)
     for (int k = 0; k < 3; ++k) b[k] = bg[k];
-  const lodgs::ViewConst vs = lodgs::make_view(*cam, tau), vr = lodgs::make_view(*cam, 0.0f);
+  lodgs::ViewConst vs = lodgs::make_view(*cam, tau);
+  vs.spt_scale = f->spt_scale;
+  const lodgs::ViewConst vr = lodgs::make_view(*cam, 0.0f);
   const int64_t npx = 3 * (int64_t)cam->width * cam->height;
   rc = lodgs::capture(g, st, "lodgs_graph_capture_step", [&] {
     lodgs::launch_select(f, vs, flags, d_idx, capacity, d_count, st);
@@ -834,6 +843,14 @@ int lodgs_frame_set_contrib_stats(lodgs_frame* f, int32_t* d_last, int32_t* d_co
   f->last_contrib = d_last;
   f->contrib_count = d_last ? d_count : nullptr;
   f->contrib_iteration = d_last ? d_iteration : nullptr;
+  return LODGS_OK;
+}
+
+int lodgs_frame_set_lod_noise(lodgs_frame* f, float factor) {
+  if (!f) return set_error(LODGS_E_INVALID, "lodgs_frame_set_lod_noise: null frame");
+  if (!std::isfinite(factor) || !(factor > 0.0f))
+    return set_error(LODGS_E_INVALID, "lodgs_frame_set_lod_noise: the factor must be finite and > 0");
+  f->spt_scale = factor;
   return LODGS_OK;
 }
 

@@ -26,6 +26,10 @@ struct ViewConst {
   float z_near;
   // LoD: X = d * k, k = tau / fx
   float k;
+  // LoD noise: the distance to an SPT root is multiplied by spt_scale before
+  // that SPT's cut and the cut cache's ratio test (1: no noise); upper nodes
+  // keep their own distance
+  float spt_scale;
   // frustum side planes x/z <= hr, -x/z <= hl, y/z <= hb, -y/z <= ht, with
   // normalisers n* = sqrt(1 + h*^2)
   float hl, hr, ht, hb, nl, nr, nt, nb;

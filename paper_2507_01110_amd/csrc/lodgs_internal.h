@@ -164,6 +164,7 @@ struct lodgs_frame {
   uint32_t* long_list;    // [max_selected] depth ranks of the splats with many instances
   uint2* ranges;          // [max tiles]
   uint32_t* tile_order;   // [max tiles] tiles, heaviest first
+  float spt_scale;        // LoD noise factor on the distances to SPT roots (lodgs_frame_set_lod_noise)
   lodgs::ViewConst* d_view_sel;  // view constants of the last lod_select (device)
   lodgs::ViewConst* d_view_ren;  // view constants of the last render (device)
   // state of the last render

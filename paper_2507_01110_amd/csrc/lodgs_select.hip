@@ -8,7 +8,9 @@
 // level-synchronous BFS.  Reached upper nodes that are not culled and fine
 // enough are selected; reached SPT roots that are not culled make their SPT
 // visible, and a binary search over the SPT's r_max (descending) gives the
-// candidate prefix length high_j = #{r_max > X_j}.
+// candidate prefix length high_j = #{r_max > X_j}.  X_j is taken at the root's
+// distance times the view's LoD noise factor (1 outside noisy training; the
+// upper nodes' own distances are never scaled).
 // Step 2: the candidates (upper nodes, then the prefixes of the visible SPTs)
 // are compacted in order with wave ballots, one wave per segment.
 #include "lodgs_internal.h"
@@ -163,7 +165,7 @@ __global__ void __launch_bounds__(kBlock) k_cut_upper(SceneDev S, const ViewCons
       if (reached(S, utest, e, total, S.spt_parent[j])) {
         const float mx = S.means[3 * (int64_t)b], my = S.means[3 * (int64_t)b + 1], mz = S.means[3 * (int64_t)b + 2];
         if (!(cull && sphere_culled(v, mx, my, mz, S.rho[b]))) {
-          const float d = view_distance(v, mx, my, mz);
+          const float d = view_distance(v, mx, my, mz) * v.spt_scale;  // the LoD noise (1: none)
           X = conservative ? fmaxf(0.0f, d - S.spt_radius[j]) * v.k : d * v.k;
           if (C.cached) {  // the cache's ratio test (squared, FP32)
             vst = 2;

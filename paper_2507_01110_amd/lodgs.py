@@ -380,6 +380,11 @@ class Frame:
         check(_lib.load().lodgs_frame_stats(self._h, ctypes.byref(s), _stream(stream)), "lodgs_frame_stats")
         return s.as_dict()
 
+    def set_lod_noise(self, factor: float = 1.0):
+        """The LoD noise of training: later selects on this frame multiply the
+        distance to every SPT root by factor (1: none); see training.lod_noise."""
+        check(_lib.load().lodgs_frame_set_lod_noise(self._h, float(factor)), "lodgs_frame_set_lod_noise")
+
     def set_densify_stats(self, max_grad2d=None):
         """Attach a node-indexed float32 array that every later backward raises
         to each drawn node's screen-space mean-gradient norm (None detaches)."""

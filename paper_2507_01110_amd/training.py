@@ -6,9 +6,10 @@
   the distance between the two views; every explore_every-th view is drawn
   uniformly from all views instead, against the bias of the local walk.
 * lod_noise: the varying level of detail of the implementation appendix: the
-  cut distances of an iteration are multiplied by 1 + 5 r^4, r ~ U(0, 1), so
-  most iterations train near the finest level and some train coarser ones.
-  The cut's X = d tau / fx is linear in d, so the factor is applied to tau.
+  distances to the SPT centres of an iteration are multiplied by 1 + 5 r^4,
+  r ~ U(0, 1), so most iterations train near the finest level and some train
+  coarser ones.  The factor goes to Frame.set_lod_noise, which applies it to
+  the SPT root distances only (the upper hierarchy keeps its own distances).
 """
 from __future__ import annotations
 

@@ -128,10 +128,12 @@ def bfs_cut(tree, condition):
     return cut
 
 
-def hspt_cut_reference(tree, cam, tau: float, cull: bool):
+def hspt_cut_reference(tree, cam, tau: float, cull: bool, spt_scale: float = 1.0):
     """Sec. 4.3 two-step cut in float64: BFS on the upper hierarchy (cull, or
     fine enough at the node's own distance), then each reached SPT cut at the
-    distance of its root (descend to the first node with g <= X; leaves always)."""
+    distance of its root (descend to the first node with g <= X; leaves always),
+    that distance multiplied by spt_scale (the LoD noise of the implementation
+    appendix, which scales the distances to the SPT centres only)."""
     role = hspt_roles(tree)
     g = g64(tree)
     rho = rho64(tree)
@@ -144,6 +146,8 @@ def hspt_cut_reference(tree, cam, tau: float, cull: bool):
         if cull and culled64(cam, tree.means[u], rho[u]):
             continue
         X = np.linalg.norm(tree.means[u].astype(np.float64) - pos) * k
+        if role[u] != 0:
+            X *= spt_scale
         if role[u] == 0:
             if g[u] <= X:
                 out.append(u)

@@ -28,16 +28,19 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def run_lockstep(tree, O, S, frame, cams, taus, max_nodes, d_min, d_max, flush_every, cull=True):
+def run_lockstep(tree, O, S, frame, cams, taus, max_nodes, d_min, d_max, flush_every, cull=True, noise=None):
+    """noise: per-iteration LoD noise factors (None: none)."""
     from paper_2507_01110_amd.lodgs import CutCache
     G = CutCache(S, max_nodes, d_min, d_max, flush_every)
     C = oracle.OracleCutCache(O, max_nodes, d_min, d_max, flush_every)
     for it, (cam, tau) in enumerate(zip(cams, taus)):
+        s = 1.0 if noise is None else float(noise[it])
+        frame.set_lod_noise(s)
         idx, cnt = frame.lod_select(cam, tau, cull=cull, cache=G)
         st = frame.stats()
         n = int(cnt.item())
         assert st["status"] == 0
-        ids, _ = C.select(cam, tau, cull=cull)
+        ids, _ = C.select(cam, tau, cull=cull, spt_scale=s)
         assert np.array_equal(idx[:n].cpu().numpy(), O.pos_of[ids]), (it, n, len(ids))
         g = G.stats()
         want = {"iterations": C.t, "hits": C.hits, "loads": C.loads, "evictions": C.evictions,
@@ -68,6 +71,11 @@ def test_cache_tiny_lockstep(torch_cuda):
         if prm[0] == 6000:
             assert s["evictions"] > 0
     run_lockstep(tree, O, S, f, cams[:6], taus[:6], 10 ** 9, 0.5, 1.5, 0, cull=False)
+    # with the LoD noise of training: 1 + 5 r^4 per iteration
+    noise = [float(np.float32(1.0 + 5.0 * r ** 4)) for r in rng.random(len(cams))]
+    s = run_lockstep(tree, O, S, f, cams, taus, 10 ** 9, 0.5, 1.5, 0, noise=noise)
+    assert s["hits"] > 0 and s["loads"] > 0
+    f.set_lod_noise(1.0)
 
 
 def test_cache_medium_lockstep(torch_cuda):

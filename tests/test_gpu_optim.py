@@ -123,6 +123,7 @@ def test_training_iterations_lower_the_loss(torch_cuda):
 
     def mean_loss():
         out = []
+        f.set_lod_noise(1.0)  # evaluation without the training noise
         for cam in cams:
             f.lod_select(cam, 1.0)
             f.l1_loss(f.render(cam, bg=bg), target, loss=loss)
@@ -132,7 +133,8 @@ def test_training_iterations_lower_the_loss(torch_cuda):
     before = mean_loss()
     for it in range(100):
         cam = cams[sched.next()]
-        f.lod_select(cam, 1.0 * lod_noise(rng))
+        f.set_lod_noise(lod_noise(rng))
+        f.lod_select(cam, 1.0)
         img = f.render(cam, bg=bg)
         dL = f.l1_loss(img, target)
         f.backward(dL, sel=sel)

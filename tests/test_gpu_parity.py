@@ -157,6 +157,32 @@ def test_select_conservative_bitexact(torch_cuda):
             _check_select(O, _frame(S, cam), cam, tau, cull=bool(it % 2), conservative=True)
 
 
+def test_select_lod_noise_bitexact(torch_cuda):
+    # the LoD noise of training (lodgs_frame_set_lod_noise): the distances to
+    # the SPT roots times the factor, the upper nodes at their own distance;
+    # the cut and the CONSERVATIVE cut agree with the oracle's bit for bit
+    tree = scenegen.build_tree(configs.tiny_spec())
+    O = oracle.OracleScene(tree)
+    S = _scene(tree)
+    rng = np.random.default_rng(33)
+    for cam in (configs.tiny_camera(), scenegen.camera_look_at((25, -8, 6), (3, 2, 0), (0, 0, 1), 320, 200)):
+        f = _frame(S, cam)
+        for factor in (1.0, 1.0001, 1.7, 4.2, 6.0, float(np.float32(1.0 + 5.0 * rng.uniform() ** 4))):
+            f.set_lod_noise(factor)
+            for tau, cull, cons in ((0.5, True, False), (1.0, False, False), (2.0, True, True)):
+                _say("select lod noise", factor, tau, cull, cons, cam.width)
+                ids, ost = O.select(cam, tau, cull=cull, conservative=cons, spt_scale=factor)
+                got, st = _gpu_select(f, cam, tau, cull, cons)
+                assert np.array_equal(got, O.pos_of[ids]), (factor, tau, len(got), len(ids))
+                assert st["n_spt_visible"] == ost["spt_visible"]
+        f.set_lod_noise(1.0)
+        _check_select(O, f, cam, 1.0, True)  # back to the plain cut
+    with pytest.raises(Exception):
+        f.set_lod_noise(0.0)
+    with pytest.raises(Exception):
+        f.set_lod_noise(float("nan"))
+
+
 def test_select_deep_upper_hierarchy_bitexact(torch_cuda):
     # an upper hierarchy deeper than the ancestor table holds: the cut walks the
     # parent array instead, with the same decisions

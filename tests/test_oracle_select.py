@@ -397,3 +397,26 @@ def test_parallel_cut_selects_an_ancestor_and_its_descendants_when_a_child_outgr
     tau = float(np.float32(2.0 / 10.0 * cam.fx))  # X = 2 at distance 10
     assert sorted(S.select_full(cam, tau, "parallel", cull=False).tolist()) == [0, 1, 4]
     assert S.select_full(cam, tau, "bfs", cull=False).tolist() == [4]
+
+
+@pytest.mark.parametrize("cull", [False, True])
+def test_lod_noise_scales_only_the_spt_root_distances(cull):
+    """Varying level of detail (implementation appendix): the distances to the
+    SPT centres are multiplied by the iteration's factor; the upper nodes keep
+    their own distances.  Against the float64 two-step reference with the same
+    rule; a factor on every distance (tau times the factor) gives a different
+    cut on some of these trees."""
+    rng = np.random.default_rng(71 + cull)
+    differs = 0
+    for _ in range(150):
+        t = random_tree(rng, int(rng.integers(2, 65)))
+        S = oracle.OracleScene(t)
+        cam = _random_camera(rng)
+        tau = float(np.float32(10 ** rng.uniform(-1, 2)))
+        s = float(np.float32(1.0 + 5.0 * rng.uniform() ** 4))
+        ref = hspt_cut_reference(t, cam, tau, cull, spt_scale=s)
+        for mode in (0, 1):
+            ids, _ = S.select(cam, tau, cull=cull, mode=mode, spt_scale=s)
+            assert sorted(ids.tolist()) == ref
+        differs += ref != hspt_cut_reference(t, cam, tau * s, cull)
+    assert differs > 0
