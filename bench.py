@@ -444,12 +444,29 @@ def ultra_bench(args):
         counts.append(st)
     view_bytes = [sum(stage_bytes(c, 1080, 1920, n_coef).values()) for c in counts]
 
+    # the batch's views on n_st streams (their forwards and the frame-local
+    # halves of their backwards overlap), the additions into the node
+    # gradients on one scatter stream in the autograd engine's order; with
+    # --serial every view on the current stream
+    main = torch.cuda.current_stream()
+    n_st = 1 if args.serial else max(1, min(args.frame_streams, B))
+    streams = [main] if args.serial else [torch.cuda.Stream() for _ in range(n_st)]
+    scat = None if args.serial else torch.cuda.Stream()
+
     def step(s):
-        loss = 0.0
+        losses = []
         for b in range(B):
-            img = render_lod(frames[b], cams[(s * B + b) % len(cams)], 1.0, accumulate_into=grads)
-            loss = loss + (img - targets[b]).abs().mean()
-        loss.backward()
+            st = streams[b % n_st]
+            st.wait_stream(main)
+            with torch.cuda.stream(st):
+                img = render_lod(frames[b], cams[(s * B + b) % len(cams)], 1.0, accumulate_into=grads,
+                                 scatter_stream=scat)
+                losses.append((img - targets[b]).abs().mean())
+        for st in streams:
+            main.wait_stream(st)
+        torch.stack(losses).sum().backward()
+        if scat is not None:
+            main.wait_stream(scat)
 
     for s in range(args.warmup):
         step(s)
@@ -469,7 +486,8 @@ def ultra_bench(args):
     out = {"metric": "ms per 8-view 1080p training step @150M Gaussians (LoD+splat fwd/bwd, autograd)",
            "value": round(el * 1000.0 / K, 3), "unit": "ms per step", "n_gpus": 1, "steps": K, "warmup": args.warmup,
            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "ultra-150M-8x1080p", "leaves": spec.n, "nodes": n_nodes, "batch": B},
+           "config": {"workload": "ultra-150M-8x1080p", "leaves": spec.n, "nodes": n_nodes, "batch": B,
+                      "streams": n_st, "scatter_stream": scat is not None},
            "views_per_s": round(B * K / el, 1), "param_GB": round(scene.param_bytes() / 1e9, 2),
            "peak_torch_allocated_GB": round(torch.cuda.max_memory_allocated() / 1e9, 2),
            "device_used_GB": round((total - free) / 1e9, 2),

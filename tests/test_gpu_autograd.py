@@ -85,6 +85,49 @@ def test_accumulate_mode_equals_dense_mode(torch_cuda):
         assert torch.allclose(acc[k], dense[k], rtol=1e-4, atol=1e-5 * scale), k
 
 
+def test_batch_on_streams_with_a_scatter_stream_equals_one_stream(torch_cuda):
+    # a batch of views on two streams, the node-array half of each backward on
+    # one scatter stream (in the autograd engine's order), two steps in a row
+    # with the frames reused: node gradients bit-identical to the same graph
+    # run on one stream
+    import torch
+    from paper_2507_01110_amd.autograd import render_lod
+    from paper_2507_01110_amd.lodgs import Frame, grads_like
+    tree = scenegen.build_tree(configs.medium_spec(n=200_000, seed=8))
+    rng = np.random.default_rng(12)
+    cams = [configs.random_pose_camera(rng, 200.0, 320, 240) for _ in range(8)]
+    S, _ = _setup(tree, cams[0])
+    frames = [Frame(S, S.n_nodes, 1 << 22, 320, 240) for _ in range(4)]
+    targets = [torch.rand(240, 320, 3, device="cuda") for _ in range(4)]
+
+    def run(streams, scat):
+        acc = grads_like(S)
+        main = torch.cuda.current_stream()
+        for step in range(2):
+            losses = []
+            for b in range(4):
+                st = streams[b % len(streams)]
+                st.wait_stream(main)
+                with torch.cuda.stream(st):
+                    img = render_lod(frames[b], cams[4 * step + b], 1.0, accumulate_into=acc, scatter_stream=scat)
+                    losses.append((img - targets[b]).abs().mean())
+            for st in streams:
+                main.wait_stream(st)
+            torch.stack(losses).sum().backward()
+            if scat is not None:
+                main.wait_stream(scat)
+        torch.cuda.synchronize()
+        for f in frames:
+            assert f.stats()["status"] == 0
+        return acc
+
+    one = run([torch.cuda.current_stream()], None)
+    many = run([torch.cuda.Stream(), torch.cuda.Stream()], torch.cuda.Stream())
+    for k in one:
+        assert float(one[k].abs().sum()) > 0.0, k
+        assert torch.equal(one[k], many[k]), k
+
+
 def test_autograd_vs_fp64_central_differences_medium_subset(torch_cuda):
     """Medium workload (2M leaves, 1080p): directional derivatives of 1,000 drawn
     nodes against FP64 central differences of the oracle with frozen decisions."""
