@@ -110,6 +110,7 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   // j ^ c, so the ten lanes of a row adding one slot's components hit ten
   // banks (the rows are 128 words apart)
   __shared__ float acc[NW][NP][NB];
+  __shared__ uint32_t wave_active[NW];  // per wave: some pixel still blends
   const int tile = (int)tile_order[blockIdx.x];
   const int tx = tile % v.tiles_x, ty = tile / v.tiles_x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, row = lane >> 4;
@@ -179,7 +180,10 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     bool active = false;
 #pragma unroll
     for (int p = 0; p < PX; ++p) active = active || live[p];
-    if (__syncthreads_count(active) == 0) break;
+    // each wave publishes whether a pixel of it still blends with the batch,
+    // behind the batch's barrier (no block-wide count, which takes three)
+    const bool wave_act = __any(active);
+    if (lane == 0) wave_active[wv] = wave_act ? 1u : 0u;
     if (loader) {
       bid[threadIdx.x] = e0;
       ev[threadIdx.x] = event_blocks(w0);
@@ -189,14 +193,44 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
       dst[2] = rc;
     }
     __syncthreads();
+    uint32_t block_act = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) block_act |= wave_active[w];
+    if (block_act == 0u) break;  // every pixel of the tile has stopped (the same flags for all threads)
     record(i1, w1, ra, rb, rc);
     uint32_t e2, i2, w2;
     words(b0 + 2 * NB, e2, i2, w2);
     const int m = (int)min((uint32_t)NB, rg.y - b0);
+    // every row's list of the batch slots whose events meet its blocks, in
+    // slot order (ballot ranks); each lane reads its slots' event words once
+    // for the four rows
+    static_assert(NB % 64 == 0, "whole waves of batch slots");
+    uint32_t evw[NB / 64];
+#pragma unroll
+    for (int c = 0; c < NB / 64; ++c) {
+      const int j = c * 64 + lane;
+      evw[c] = j < m ? ev[j] : 0u;
+    }
+    const uint64_t lt = lanemask_lt();
     int nh[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) nh[r] = wave_hit_list<NB, false>(m, blend_row_blocks<PX, true>(wv, r), ev, hits[wv][r]);
-    __syncthreads();
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t want = blend_row_blocks<PX, true>(wv, r);
+      int cnt = 0;
+#pragma unroll
+      for (int c = 0; c < NB / 64; ++c) {
+        const bool h = (evw[c] & want) != 0u;
+        const uint64_t hb = __ballot(h);
+        if (h) hits[wv][r][cnt + __popcll(hb & lt)] = (uint8_t)(c * 64 + lane);
+        cnt += __popcll(hb);
+      }
+      nh[r] = cnt;
+    }
+    // the hit lists are the wave's own (its LDS operations run in order): a
+    // wave-level fence and barrier order their writes before the reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int n = row == 0 ? nh[0] : (row == 1 ? nh[1] : (row == 2 ? nh[2] : nh[3]));  // this row's list
     const int nmax = max(max(nh[0], nh[1]), max(nh[2], nh[3]));
     if (__any(active) && nmax > 0) {  // wave-uniform
