@@ -147,13 +147,17 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
   const uint32_t nr = (uint32_t)ctr->n_render;
   const float thr = 1.0f / 255.0f;
   for (int t = threadIdx.x; t < NW * NP * NB; t += NT) (&acc[0][0][0])[t] = 0.0f;
-  // Thread j < NB holds batch slot j: the words (emission index, splat, event
-  // word) of this batch and the next, and the splat record of this batch
-  // (only for an instance with events: the others are never replayed), so the
-  // loads overlap the replay of the batch before.
-  const bool loader = (int)threadIdx.x < NB;
+  // The last NB threads load: thread NT - NB + j holds batch slot j, the
+  // words (emission index, splat, event word) of this batch and the next, and
+  // the splat record of this batch (only for an instance with events: the
+  // others are never replayed), so the loads overlap the replay of the batch
+  // before.  The first threads write the partials out after a replay, so with
+  // four waves the staging of the next batch and the write-out of the last
+  // run on different waves.
+  const int ld = (int)threadIdx.x - (NT - NB);  // the loaded slot (loaders only)
+  const bool loader = ld >= 0;
   auto words = [&](uint32_t b, uint32_t& e, uint32_t& i, uint32_t& w) {
-    const uint32_t k = b + threadIdx.x;
+    const uint32_t k = b + (uint32_t)ld;
     e = i = w = 0u;
     if (loader && k < rg.y) {
       e = ival[k];
@@ -185,9 +189,9 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
     const bool wave_act = __any(active);
     if (lane == 0) wave_active[wv] = wave_act ? 1u : 0u;
     if (loader) {
-      bid[threadIdx.x] = e0;
-      ev[threadIdx.x] = event_blocks(w0);
-      float4* dst = reinterpret_cast<float4*>(&batch[threadIdx.x]);  // mean, axis, power, opacity, colour
+      bid[ld] = e0;
+      ev[ld] = event_blocks(w0);
+      float4* dst = reinterpret_cast<float4*>(&batch[ld]);  // mean, axis, power, opacity, colour
       dst[0] = ra;
       dst[1] = rb;
       dst[2] = rc;
@@ -197,6 +201,9 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
 #pragma unroll
     for (int w = 0; w < NW; ++w) block_act |= wave_active[w];
     if (block_act == 0u) break;  // every pixel of the tile has stopped (the same flags for all threads)
+    // the words of the slot this thread writes out after the replay, read
+    // now: a loader may stage the next batch while the write-out runs
+    const uint32_t out_bid = bid[threadIdx.x % NB], out_ev = ev[threadIdx.x % NB];
     record(i1, w1, ra, rb, rc);
     uint32_t e2, i2, w2;
     words(b0 + 2 * NB, e2, i2, w2);
@@ -363,8 +370,8 @@ __global__ void __launch_bounds__(256 / PX) k_blend_bwd(const ViewConst* __restr
       // read nor cleared.  Skipping them leaves the sums bit-identical (a row
       // value is never -0: rows start at +0 and x + y is -0 only when both
       // are), and an instance without events is written as zeros.
-      float* dst = partial + NP * (int64_t)bid[threadIdx.x];
-      const uint32_t evb = ev[threadIdx.x];
+      float* dst = partial + NP * (int64_t)out_bid;
+      const uint32_t evb = out_ev;
       float r[NP];
 #pragma unroll
       for (int c = 0; c < NP; ++c) r[c] = 0.0f;
